@@ -1,0 +1,194 @@
+/* sparqs: sparse register-level quantum-state simulator, hot path on one AMD
+ * MI355X (gfx950).  C ABI.
+ *
+ * The method (SparQSim, arXiv 2503.15118) keeps a quantum state only as its
+ * nonzero branches: pairs (basis key, complex amplitude), where the key is the
+ * concatenation of register values (Sec. "Sparse state representation and data
+ * structure", its equation for |psi>).  Non-interference ops rewrite every
+ * branch independently (Sec. "Non-interference operations"); interference ops
+ * sort branches so coherent ones (equal idle qubits) sit together, combine each
+ * group with the gate matrix, and drop zero-amplitude branches (Sec.
+ * "Interference operations" and the supplementary details of Rot_Int and
+ * ClearZero).  QRAM is U|i>_A|j>_D = |i>_A|j xor d_i>_D (QRAM section, its
+ * equation); R = i(2|0><0|_anc - I) (x) I is the walk's reflection (QLSS
+ * section).
+ *
+ * Conventions used by every call:
+ *  - Qubit q of a register is bit q of its value (LSB = qubit 0).
+ *  - Registers (1..64 qubits each) are packed in creation order into 64-bit
+ *    key words, first fit, never straddling a word; W (1, 2 or 4) words per
+ *    key.  With ninst > 1 an instance-id field follows the registers (first
+ *    fit as well); keys handed out by ss_export have that field cleared.
+ *  - Keys order as unsigned integers with word W-1 most significant.
+ *  - Amplitudes are complex128, passed as interleaved (re, im) doubles.
+ *  - After every branching op (H, RY), never after a non-branching op, an
+ *    entry is removed when re*re + im*im < eps*eps or when it is exactly 0.
+ *
+ * Memory and threads: the caller owns the device arena (e.g. a torch uint8
+ * CUDA tensor) and the HIP stream; the library never allocates device memory
+ * (it allocates one small pinned host block per state for read-back).  Input
+ * arrays are copied before a call returns; no caller pointer is retained.  A
+ * state may be used by one host thread at a time; distinct states are
+ * independent.
+ *
+ * Errors: every call returns SS_OK (0) or a negative SS_E_* code; nothing is
+ * thrown across the ABI.  A state that hit SS_E_HIP is poisoned and further
+ * calls return SS_E_STATE.
+ */
+#ifndef SPARQS_H
+#define SPARQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum ss_status {
+  SS_OK = 0,
+  SS_E_ARG = -1,          /* bad register/qubit/instance, dst == src, control inside dst, empty mask */
+  SS_E_NOT_UNITARY = -2,  /* even MULC constant */
+  SS_E_QRAM = -3,         /* table length != 2^addr_bits, entry too wide, width mismatch */
+  SS_E_CAPACITY = -4,     /* an op would exceed the arena's entry capacity (state rolled back) */
+  SS_E_NOMEM = -5,        /* arena too small at creation */
+  SS_E_HIP = -6,          /* HIP runtime or kernel-side failure; the state is poisoned */
+  SS_E_STATE = -7         /* use of a poisoned or null state */
+};
+
+enum ss_kind {
+  SS_X = 0,           /* flip the qubits of qmask in reg (CNOT/Toffoli via controls) */
+  SS_H = 1,           /* Hadamard on each qubit of qmask, ascending */
+  SS_RY = 2,          /* Ry(theta) = [[cos t/2, -sin t/2], [sin t/2, cos t/2]] on each qubit of qmask */
+  SS_ADD = 3,         /* reg <- reg + reg2 mod 2^width(reg) */
+  SS_SUB = 4,         /* reg <- reg - reg2 mod 2^width(reg) */
+  SS_MULC = 5,        /* reg <- reg * imm mod 2^width(reg), imm odd */
+  SS_XOR = 6,         /* reg <- reg xor reg2 (truncated to width(reg)) */
+  SS_XORC = 7,        /* reg <- reg xor imm (truncated) */
+  SS_QRAM_LOAD = 8,   /* reg (data) <- reg xor table[reg2 (address)] */
+  SS_QRAM_UNLOAD = 9, /* the inverse, the same map */
+  SS_REFLECT0 = 10    /* amplitude *= +i if reg == 0 else -i */
+};
+
+typedef struct ss_reg {
+  uint32_t nqubits;       /* 1..64 */
+  const char* name;       /* may be NULL; informational only */
+} ss_reg;
+
+typedef struct ss_ctl {
+  uint32_t reg;
+  uint16_t qubit;
+  uint16_t value;         /* 0 or 1: the op acts where this qubit has this value */
+} ss_ctl;
+
+/* One register-level operation, 64 bytes. */
+typedef struct ss_op {
+  uint16_t kind;          /* enum ss_kind */
+  uint8_t nctl;           /* 0..3 controls */
+  uint8_t flags;          /* must be 0 */
+  uint32_t reg;           /* target / destination register */
+  uint32_t reg2;          /* source register (ADD/SUB/XOR) or address register (QRAM) */
+  uint32_t qram_id;       /* table id from ss_load_qram */
+  uint64_t qmask;         /* qubits of reg (X, H, RY) */
+  uint64_t imm;           /* MULC multiplier, XORC constant */
+  double theta;           /* RY angle */
+  ss_ctl ctl[3];
+} ss_op;
+
+typedef struct ss_result {
+  int32_t status;         /* last error, SS_OK if none */
+  uint32_t failed_inst;
+  uint64_t failed_op;     /* index of the op that failed (SS_E_CAPACITY: resume from here) */
+  uint64_t nnz;           /* entries after the call (all instances) */
+  uint64_t peak;          /* running maximum of nnz */
+} ss_result;
+
+typedef struct ss_state ss_state;
+
+/* Device bytes an arena needs for `cap_entries` entries of this layout plus
+ * `table_bytes` of QRAM tables.  Entries cost 2*(8W+16) bytes (state and its
+ * alternate buffer) plus look-back scratch. */
+int ss_required_bytes(const ss_reg* regs, uint32_t nregs, uint32_t ninst, uint64_t cap_entries,
+                      uint64_t table_bytes, size_t* bytes);
+
+/* Create a state of `ninst` instances, each |0...0> with amplitude 1, in the
+ * caller's device arena [arena, arena + arena_bytes) (256-byte aligned) on
+ * `hip_stream` (a hipStream_t, NULL = default stream).  `table_bytes` of the
+ * arena are reserved for QRAM tables.  Blocking.
+ * Errors: SS_E_ARG (bad registers, more than 256 key bits, ninst == 0),
+ * SS_E_NOMEM (arena too small for the instances), SS_E_HIP. */
+int ss_create_state(const ss_reg* regs, uint32_t nregs, uint32_t ninst, double eps, void* arena,
+                    size_t arena_bytes, uint64_t table_bytes, void* hip_stream, ss_state** out);
+
+/* Free host-side metadata; the arena stays the caller's. */
+int ss_destroy_state(ss_state* st);
+
+/* Entry capacity of the arena (all instances together). */
+int ss_capacity(const ss_state* st, uint64_t* cap);
+
+/* Where register `reg` sits in the key: word index, bit offset, width. */
+int ss_layout(const ss_state* st, uint32_t reg, uint32_t* word, uint32_t* offset, uint32_t* width);
+
+/* Key words per entry (1, 2 or 4). */
+int ss_key_words(const ss_state* st, uint32_t* w);
+
+/* Copy a QRAM table (host array of `len` words) into the arena.  Requires
+ * len == 2^addr_bits and every word < 2^word_bits (SS_E_QRAM otherwise). */
+int ss_load_qram(ss_state* st, const uint64_t* table, uint64_t len, uint32_t addr_bits,
+                 uint32_t word_bits, uint32_t* qram_id);
+
+/* Replace the entries of instance `inst` by n entries given as register values
+ * (host, row-major n x nregs) and amplitudes (host, 2n doubles).  Values are
+ * truncated to the register widths; keys must be distinct (not checked).
+ * Blocking. */
+int ss_set_entries(ss_state* st, uint32_t inst, const uint64_t* values, const double* amps, uint64_t n);
+
+/* Apply `nops` ops.  With inst_offsets == NULL every instance gets the same
+ * ops.  Returns when the work is done (the status is final).  On
+ * SS_E_CAPACITY the state holds the result of ops [0, res->failed_op) and the
+ * caller may rebind a larger arena and resume from failed_op. */
+int ss_apply_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst_offsets,
+                 ss_result* res);
+
+/* Remove entries with |a|^2 < eps^2 or a == 0.  Blocking. */
+int ss_prune(ss_state* st, double eps);
+
+/* Collapsing measurement of register `reg` of instance `inst` with the caller's
+ * uniform draw u in [0, 1): p(v) = sum of |a|^2 over entries with field v,
+ * P = sum over v; the outcome is the smallest v whose running sum (ascending
+ * v) exceeds u*P; the survivors are divided by sqrt(p(v)); *prob = p(v)/P.
+ * Blocking. */
+int ss_measure(ss_state* st, uint32_t inst, uint32_t reg, double u, uint64_t* outcome, double* prob);
+
+/* Entry count of instance `inst` (UINT32_MAX: all instances) and the running
+ * peak of the whole state.  Blocking. */
+int ss_nnz(ss_state* st, uint32_t inst, uint64_t* nnz, uint64_t* peak);
+
+/* Copy instance `inst`'s entries to host arrays in ascending key order:
+ * keys (W words per entry, instance field cleared) and amps (2 doubles per
+ * entry).  Writes min(cap, nnz) entries; *n gets nnz.  Blocking. */
+int ss_export(ss_state* st, uint32_t inst, uint64_t* keys, double* amps, uint64_t cap, uint64_t* n);
+
+/* Wait for the stream and report kernel-side errors. */
+int ss_sync(ss_state* st, ss_result* res);
+
+/* Move the state into another (larger) arena; the old one may be freed after
+ * the call returns.  Blocking. */
+int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
+
+/* Tuning/debug knobs: "sort_items" (8|16), "grouping" (1: reuse grouped
+ * order across ops, 0: always sort), "trace" (1: per-op timing records). */
+int ss_set_option(ss_state* st, const char* key, int64_t value);
+
+/* Counters since creation: [0] kernels launched, [1] sort passes, [2] sorts,
+ * [3] group launches, [4] expand launches, [5] permutation runs, [6] host
+ * syncs, [7] entries updated (sum over ops of input nnz). */
+int ss_stats(const ss_state* st, uint64_t* out8);
+
+const char* ss_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPARQS_H */

@@ -1,0 +1,785 @@
+// gfx950 kernels of the sparse register-level simulator.
+//
+// State layout in HBM (structure of arrays): key word w of entry i at
+// keys.w[w][i] (uint64), amplitude at amp[i] (double2 = re, im).  Register r
+// occupies bits [off_r, off_r + width_r) of one key word; qubit q of r is bit
+// off_r + q.
+//
+//  * k_perm     - a fused run of non-interference ops (X/CNOT/Toffoli, register
+//                 add/sub, multiply by an odd constant, XOR, QRAM load/unload,
+//                 the reflection R): every entry is updated in place while its
+//                 key sits in registers (Sec. "Non-interference operations";
+//                 QRAM equation; QLSS reflection R).
+//  * k_sort_hist / k_sort_scan / k_sort_pass
+//               - LSD radix sort over multi-word keys (one pass per 8-bit digit
+//                 of the bits that vary): LDS digit histograms, wave64 ballot
+//                 ranking, decoupled look-back for the global digit offsets,
+//                 LDS-staged scatter.  It puts coherent branches (equal idle
+//                 qubits) next to each other (Sec. "Interference operations",
+//                 first step).
+//  * k_group    - applies a branching op to each group of coherent branches
+//                 (second step of the same section), creating up to 2^k
+//                 children, merging contributions that land on the same key,
+//                 and removing entries whose |a|^2 falls below eps^2 (the
+//                 zero-clearing step), compacted with a look-back prefix.
+//  * k_filter   - threshold prune / measurement collapse with compaction.
+#include "kernels_common.hpp"
+
+namespace sparqs {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ uint64_t sel_word(const uint64_t (&k)[W], uint32_t w) {
+  uint64_t v = k[0];
+#pragma unroll
+  for (int i = 1; i < W; ++i)
+    if (w == (uint32_t)i) v = k[i];
+  return v;
+}
+
+template <int W>
+__device__ __forceinline__ void put_word(uint64_t (&k)[W], uint32_t w, uint64_t v) {
+#pragma unroll
+  for (int i = 0; i < W; ++i)
+    if (w == (uint32_t)i) k[i] = v;
+}
+
+template <int W>
+__device__ __forceinline__ bool controls_hold(const uint64_t (&k)[W], const uint64_t* cmask,
+                                              const uint64_t* cval) {
+  bool on = true;
+#pragma unroll
+  for (int w = 0; w < W; ++w) on = on && ((k[w] & cmask[w]) == cval[w]);
+  return on;
+}
+
+// Keep an amplitude unless |a|^2 < eps^2 or it is exactly zero.  The product
+// and sum are rounded separately (the file is built without contraction).
+__device__ __forceinline__ bool keep_amp(double re, double im, double eps2) {
+  const double n2 = re * re + im * im;
+  return !(n2 < eps2) && !(re == 0.0 && im == 0.0);
+}
+
+__device__ __forceinline__ void ring_reset(DevMeta* meta, uint32_t epoch) {
+  const uint32_t r = (epoch + kRing / 2) % kRing;
+  meta->counters[r] = 0;
+  meta->nnz_out[r] = 0;
+  for (int w = 0; w < kMaxW; ++w) {
+    meta->or_mask[r][w] = 0;
+    meta->and_mask[r][w] = ~0ull;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_perm: fused run of non-branching ops
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ void perm_apply(uint64_t (&k)[W], double2& a, const PermOp& op) {
+  if (op.nctl_words && !controls_hold<W>(k, op.cmask, op.cval)) return;
+  const uint64_t dw = sel_word<W>(k, op.dst_word);
+  const uint64_t dv = (dw >> op.dst_shift) & op.dst_mask;
+  uint64_t nv;
+  switch (op.kind) {
+    case PK_XMASK:
+    case PK_XORC:
+      nv = dv ^ op.imm;
+      break;
+    case PK_ADD:
+      nv = (dv + ((sel_word<W>(k, op.src_word) >> op.src_shift) & op.src_mask)) & op.dst_mask;
+      break;
+    case PK_SUB:
+      nv = (dv - ((sel_word<W>(k, op.src_word) >> op.src_shift) & op.src_mask)) & op.dst_mask;
+      break;
+    case PK_MULC:
+      nv = (dv * op.imm) & op.dst_mask;
+      break;
+    case PK_XOR:
+      nv = (dv ^ ((sel_word<W>(k, op.src_word) >> op.src_shift) & op.src_mask)) & op.dst_mask;
+      break;
+    case PK_QRAM: {
+      const uint64_t addr = (sel_word<W>(k, op.src_word) >> op.src_shift) & op.src_mask;
+      const uint64_t t = op.table_words32 ? (uint64_t)((const uint32_t*)op.table)[addr]
+                                          : ((const uint64_t*)op.table)[addr];
+      nv = (dv ^ t) & op.dst_mask;
+      break;
+    }
+    case PK_REFLECT0: {
+      // R = i(2|0><0| - I): +i on a zero field, -i otherwise (exact)
+      const double re = a.x, im = a.y;
+      if (dv == 0) {
+        a.x = -im;
+        a.y = re;
+      } else {
+        a.x = im;
+        a.y = -re;
+      }
+      return;
+    }
+    default:
+      return;
+  }
+  const uint64_t m = op.dst_mask << op.dst_shift;
+  put_word<W>(k, op.dst_word, (dw & ~m) | ((nv << op.dst_shift) & m));
+}
+
+template <int W, bool AMP>
+__global__ __launch_bounds__(kBlock) void k_perm(KeyPtrs<W> keys, double2* __restrict__ amp,
+                                                 uint64_t n, const PermOp* __restrict__ ops,
+                                                 uint32_t nops, uint32_t write_words,
+                                                 DevMeta* meta, uint32_t epoch) {
+  __shared__ uint64_t s_red[2 * kMaxW * 4];
+  if (blockIdx.x == 0 && threadIdx.x == 0) ring_reset(meta, epoch);
+  uint64_t orv[W], andv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    orv[w] = 0;
+    andv[w] = ~0ull;
+  }
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    uint64_t k[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) k[w] = keys.w[w][i];
+    double2 a = make_double2(0.0, 0.0);
+    if (AMP) a = amp[i];
+    for (uint32_t o = 0; o < nops; ++o) perm_apply<W>(k, a, ops[o]);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      if (write_words & (1u << w)) keys.w[w][i] = k[w];
+      orv[w] |= k[w];
+      andv[w] &= k[w];
+    }
+    if (AMP) amp[i] = a;
+  }
+  publish_masks<W>(meta, epoch, orv, andv, s_red);
+}
+
+// ---------------------------------------------------------------------------
+// radix sort
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ uint32_t digit_of(const uint64_t (&k)[W], const PassDesc& pd) {
+  uint32_t d = 0;
+  for (uint32_t j = 0; j < pd.nf; ++j) {
+    const uint32_t f = pd.f[j];
+    const uint32_t word = f & 3u, shift = (f >> 2) & 63u, width = (f >> 8) & 15u,
+                   ds = (f >> 12) & 15u;
+    const uint64_t v = sel_word<W>(k, word);
+    d |= (uint32_t)((v >> shift) & ((1ull << width) - 1ull)) << ds;
+  }
+  return d;
+}
+
+// Per-workgroup digit histograms of every pass in one read of the keys.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_sort_hist(KeyPtrs<W> keys, uint64_t n, SortPlan plan,
+                                                      uint32_t* __restrict__ partial) {
+  extern __shared__ uint32_t s_h[];  // npass * 256
+  const uint32_t np = plan.npass;
+  for (uint32_t i = threadIdx.x; i < np * kRadix; i += kBlock) s_h[i] = 0;
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    uint64_t k[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) k[w] = keys.w[w][i];
+    for (uint32_t p = 0; p < np; ++p) atomicAdd(&s_h[p * kRadix + digit_of<W>(k, plan.pass[p])], 1u);
+  }
+  __syncthreads();
+  uint32_t* out = partial + (uint64_t)blockIdx.x * np * kRadix;
+  for (uint32_t i = threadIdx.x; i < np * kRadix; i += kBlock) out[i] = s_h[i];
+}
+
+// Sum the per-workgroup histograms of pass blockIdx.x and scan them into the
+// first global position of every digit.
+__global__ __launch_bounds__(kBlock) void k_sort_scan(const uint32_t* __restrict__ partial,
+                                                      uint32_t nblk, uint32_t np,
+                                                      uint64_t* __restrict__ digit_start) {
+  __shared__ uint64_t s_tmp[4];
+  const uint32_t p = blockIdx.x, d = threadIdx.x;
+  uint64_t c = 0;
+  for (uint32_t b = 0; b < nblk; ++b) c += partial[((uint64_t)b * np + p) * kRadix + d];
+  uint64_t tot;
+  const uint64_t ex = block_excl_scan<uint64_t>(c, s_tmp, tot);
+  digit_start[p * kRadix + d] = ex;
+}
+
+// One LSD pass: stable scatter of (keys, amplitude) by the digit `pd`.
+template <int W, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_sort_pass(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
+                                                      KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
+                                                      uint64_t n, PassDesc pd,
+                                                      const uint64_t* __restrict__ digit_start,
+                                                      uint64_t* lb, DevMeta* meta, uint32_t epoch) {
+  constexpr int TILE = kBlock * ITEMS;
+  __shared__ uint32_t s_wcount[kBlock / 64][kRadix];
+  __shared__ uint32_t s_toff[kRadix];
+  __shared__ uint64_t s_gbase[kRadix];
+  __shared__ uint8_t s_digit[TILE];
+  __shared__ uint64_t s_stage[TILE];
+  __shared__ uint64_t s_scan[4];
+  __shared__ uint32_t s_tile;
+
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) s_wcount[w][tid] = 0;
+  const uint32_t tile = take_tile(meta, epoch, &s_tile);
+  if (tile_out_of_range(tile, (n + TILE - 1) / TILE, &meta->err)) return;
+  const uint64_t base = (uint64_t)tile * TILE;
+  const uint32_t tile_n = (uint32_t)min((uint64_t)TILE, n - base);
+
+  uint64_t k[ITEMS][W];
+  uint32_t dig[ITEMS], rank[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
+    if (le < tile_n) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) k[i][w] = in_keys.w[w][base + le];
+      dig[i] = digit_of<W>(k[i], pd);
+    } else {
+#pragma unroll
+      for (int w = 0; w < W; ++w) k[i][w] = 0;
+      dig[i] = 0;
+    }
+  }
+  // stable rank within the wave's chunk: ballot-match on the digit bits
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
+    const bool valid = le < tile_n;
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const bool bit = (dig[i] >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    const uint32_t below = mbcnt(m);
+    uint32_t prior = 0;
+    if (valid) prior = s_wcount[wave][dig[i]];
+    rank[i] = prior + below;
+    if (valid && below == 0) s_wcount[wave][dig[i]] = prior + (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  // per digit: exclusive offsets across waves, tile count, look-back
+  uint32_t cnt;
+  {
+    const uint32_t c0 = s_wcount[0][tid], c1 = s_wcount[1][tid], c2 = s_wcount[2][tid],
+                   c3 = s_wcount[3][tid];
+    s_wcount[0][tid] = 0;
+    s_wcount[1][tid] = c0;
+    s_wcount[2][tid] = c0 + c1;
+    s_wcount[3][tid] = c0 + c1 + c2;
+    cnt = c0 + c1 + c2 + c3;
+  }
+  const uint64_t prev = lookback_digit(lb, tile, tid, cnt, epoch, &meta->err);
+  uint64_t tot;
+  const uint64_t loc = block_excl_scan<uint64_t>((uint64_t)cnt, s_scan, tot);
+  s_toff[tid] = (uint32_t)loc;
+  s_gbase[tid] = digit_start[tid] + prev - loc;
+  __syncthreads();
+  uint32_t pos[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
+    if (le < tile_n) {
+      pos[i] = s_toff[dig[i]] + s_wcount[wave][dig[i]] + rank[i];
+      s_digit[pos[i]] = (uint8_t)dig[i];
+    }
+  }
+  // scatter one 8-byte column at a time through LDS
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
+      if (le < tile_n) s_stage[pos[i]] = k[i][w];
+    }
+    __syncthreads();
+    for (uint32_t j = tid; j < tile_n; j += kBlock) {
+      const uint64_t dst = s_gbase[s_digit[j]] + j;
+      if (dst < n) out_keys.w[w][dst] = s_stage[j];
+    }
+    __syncthreads();
+  }
+  double im_part[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
+    if (le < tile_n) {
+      const double2 a = in_amp[base + le];
+      s_stage[pos[i]] = __double_as_longlong(a.x);
+      im_part[i] = a.y;
+    }
+  }
+  __syncthreads();
+  double* out_d = reinterpret_cast<double*>(out_amp);
+  for (uint32_t j = tid; j < tile_n; j += kBlock) {
+    const uint64_t dst = s_gbase[s_digit[j]] + j;
+    if (dst < n) out_d[2 * dst] = __longlong_as_double(s_stage[j]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
+    if (le < tile_n) s_stage[pos[i]] = __double_as_longlong(im_part[i]);
+  }
+  __syncthreads();
+  for (uint32_t j = tid; j < tile_n; j += kBlock) {
+    const uint64_t dst = s_gbase[s_digit[j]] + j;
+    if (dst < n) out_d[2 * dst + 1] = __longlong_as_double(s_stage[j]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_group: apply a branching op to groups of coherent branches
+// ---------------------------------------------------------------------------
+// MODE_GROUP: members of a group (equal key outside the target bits) are
+// contiguous; the first member leads.  MODE_EXPAND: every entry is its own
+// group (no target bit varies over the state).
+enum { MODE_GROUP = 0, MODE_EXPAND = 1 };
+
+template <int W>
+__device__ __forceinline__ bool same_idle(const uint64_t (&a)[W], const uint64_t (&b)[W],
+                                          const uint64_t* tmask) {
+  bool eq = true;
+#pragma unroll
+  for (int w = 0; w < W; ++w) eq = eq && (((a[w] ^ b[w]) & ~tmask[w]) == 0);
+  return eq;
+}
+
+template <int W, int K>
+__device__ __forceinline__ uint32_t target_value(const uint64_t (&k)[W], const GroupOp& op) {
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) s |= (uint32_t)((sel_word<W>(k, op.tword[j]) >> op.tbit[j]) & 1ull) << j;
+  return s;
+}
+
+template <int W, int K>
+__device__ __forceinline__ void with_target_value(uint64_t (&k)[W], const GroupOp& op, uint32_t s) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) k[w] &= ~op.tmask[w];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    if ((s >> j) & 1u) {
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        if (op.tword[j] == (uint32_t)w) k[w] |= 1ull << op.tbit[j];
+    }
+  }
+}
+
+template <int W, int K, int MODE>
+__global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
+                                                  KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
+                                                  uint64_t n, uint64_t cap, GroupOp op, uint64_t* lb,
+                                                  DevMeta* meta, uint32_t epoch) {
+  constexpr uint32_t G = 1u << K;
+  __shared__ uint64_t s_scan[4];
+  __shared__ uint64_t s_off;
+  __shared__ uint64_t s_red[2 * kMaxW * 4];
+  __shared__ uint32_t s_tile;
+  const uint32_t tile = take_tile(meta, epoch, &s_tile);
+  if (tile_out_of_range(tile, (n + kBlock - 1) / kBlock, &meta->err)) return;
+  const uint64_t e = (uint64_t)tile * kBlock + threadIdx.x;
+  const bool valid = e < n;
+
+  uint64_t key[W];
+  double2 v[G];
+  uint32_t present = 0;
+#pragma unroll
+  for (uint32_t s = 0; s < G; ++s) v[s] = make_double2(0.0, 0.0);
+  bool lead = false, ctl = true;
+  if (valid) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) key[w] = in_keys.w[w][e];
+    lead = true;
+    if (MODE == MODE_GROUP && e > 0) {
+      uint64_t prv[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) prv[w] = in_keys.w[w][e - 1];
+      lead = !same_idle<W>(key, prv, op.tmask);
+    }
+    if (lead) {
+      ctl = !op.has_ctl || controls_hold<W>(key, op.cmask, op.cval);
+      const uint32_t s0 = target_value<W, K>(key, op);
+      const double2 a0 = in_amp[e];
+#pragma unroll
+      for (uint32_t t = 0; t < G; ++t)
+        if (t == s0) v[t] = a0;
+      present = 1u << s0;
+      if (MODE == MODE_GROUP) {
+        for (uint32_t j = 1; j < G && e + j < n; ++j) {
+          uint64_t nk[W];
+#pragma unroll
+          for (int w = 0; w < W; ++w) nk[w] = in_keys.w[w][e + j];
+          if (!same_idle<W>(key, nk, op.tmask)) break;
+          const uint32_t s = target_value<W, K>(nk, op);
+          if (present & (1u << s)) atomicOr(&meta->err, kErrGroup);
+          const double2 a = in_amp[e + j];
+#pragma unroll
+          for (uint32_t t = 0; t < G; ++t)
+            if (t == s) v[t] = a;
+          present |= 1u << s;
+        }
+      }
+      if (ctl) {
+        // one butterfly stage per target qubit, ascending; a child exists when
+        // some present parent reaches it through a nonzero matrix element
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+#pragma unroll
+          for (uint32_t s = 0; s < G; ++s) {
+            if ((s >> j) & 1u) continue;
+            const uint32_t s1 = s | (1u << j);
+            const double2 a0 = v[s], a1 = v[s1];
+            const bool p0 = (present >> s) & 1u, p1 = (present >> s1) & 1u;
+            double2 b0, b1;
+            b0.x = op.m[0][0] * a0.x + op.m[0][1] * a1.x;
+            b0.y = op.m[0][0] * a0.y + op.m[0][1] * a1.y;
+            b1.x = op.m[1][0] * a0.x + op.m[1][1] * a1.x;
+            b1.y = op.m[1][0] * a0.y + op.m[1][1] * a1.y;
+            const bool q0 = (p0 && op.m[0][0] != 0.0) || (p1 && op.m[0][1] != 0.0);
+            const bool q1 = (p0 && op.m[1][0] != 0.0) || (p1 && op.m[1][1] != 0.0);
+            v[s] = b0;
+            v[s1] = b1;
+            present = (present & ~((1u << s) | (1u << s1))) | ((uint32_t)q0 << s) | ((uint32_t)q1 << s1);
+          }
+        }
+      }
+    }
+  }
+  // survivors
+  uint32_t keepm = 0;
+  if (lead) {
+#pragma unroll
+    for (uint32_t s = 0; s < G; ++s)
+      if (((present >> s) & 1u) && keep_amp(v[s].x, v[s].y, op.eps2)) keepm |= 1u << s;
+  }
+  const uint64_t cnt = (uint64_t)__popc(keepm);
+  uint64_t tile_total;
+  const uint64_t loc = block_excl_scan<uint64_t>(cnt, s_scan, tile_total);
+  if (threadIdx.x < 64) {
+    const uint64_t ex = lookback_single(lb, tile, tile_total, epoch, &meta->err);
+    if (threadIdx.x == 0) {
+      s_off = ex;
+      const uint64_t ntiles = (n + kBlock - 1) / kBlock;
+      if (tile == ntiles - 1) {
+        meta->nnz_out[epoch % kRing] = ex + tile_total;
+        atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
+        if (ex + tile_total > cap) atomicOr(&meta->err, kErrCapacity);
+      }
+    }
+  }
+  __syncthreads();
+  uint64_t orv[W], andv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    orv[w] = 0;
+    andv[w] = ~0ull;
+  }
+  uint64_t p = s_off + loc;
+  if (keepm) {
+#pragma unroll
+    for (uint32_t s = 0; s < G; ++s) {
+      if (!((keepm >> s) & 1u)) continue;
+      uint64_t ok[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) ok[w] = key[w];
+      with_target_value<W, K>(ok, op, s);
+      if (p < cap) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) out_keys.w[w][p] = ok[w];
+        out_amp[p] = v[s];
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        orv[w] |= ok[w];
+        andv[w] &= ok[w];
+      }
+      ++p;
+    }
+  }
+  publish_masks<W>(meta, epoch, orv, andv, s_red);
+}
+
+// ---------------------------------------------------------------------------
+// k_filter: compaction with a keep predicate.
+//   FILTER_PRUNE:   keep unless |a|^2 < eps^2 or a == 0
+//   FILTER_COLLAPSE: entries of field value `fval` (on the given word/shift/mask)
+//                    within instance `inst` are kept and divided by `scale`;
+//                    other entries of that instance are dropped; entries of
+//                    other instances pass unchanged.
+//   FILTER_DROP_INST: drop every entry of instance `inst`.
+// ---------------------------------------------------------------------------
+enum { FILTER_PRUNE = 0, FILTER_COLLAPSE = 1, FILTER_DROP_INST = 2 };
+
+struct FilterOp {
+  uint32_t kind;
+  uint32_t fword, fshift, iword, ishift, has_inst;
+  uint32_t use_f, pad;
+  uint64_t fmask, fval, imask, inst;
+  double eps2, scale;
+};
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_filter(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
+                                                   KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
+                                                   uint64_t n, uint64_t cap, FilterOp f, uint64_t* lb,
+                                                   DevMeta* meta, uint32_t epoch) {
+  __shared__ uint64_t s_scan[4];
+  __shared__ uint64_t s_off;
+  __shared__ uint64_t s_red[2 * kMaxW * 4];
+  __shared__ uint32_t s_tile;
+  const uint32_t tile = take_tile(meta, epoch, &s_tile);
+  if (tile_out_of_range(tile, (n + kBlock - 1) / kBlock, &meta->err)) return;
+  const uint64_t e = (uint64_t)tile * kBlock + threadIdx.x;
+  uint64_t key[W];
+  double2 a = make_double2(0.0, 0.0);
+  bool keep = false;
+  if (e < n) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) key[w] = in_keys.w[w][e];
+    a = in_amp[e];
+    const bool mine = !f.has_inst || ((sel_word<W>(key, f.iword) >> f.ishift) & f.imask) == f.inst;
+    if (f.kind == FILTER_PRUNE) {
+      keep = !mine || keep_amp(a.x, a.y, f.eps2);
+    } else if (f.kind == FILTER_COLLAPSE) {
+      if (!mine) {
+        keep = true;
+      } else {
+        keep = ((sel_word<W>(key, f.fword) >> f.fshift) & f.fmask) == f.fval;
+        a.x = a.x / f.scale;
+        a.y = a.y / f.scale;
+      }
+    } else {
+      keep = !mine;
+    }
+  }
+  uint64_t tile_total;
+  const uint64_t loc = block_excl_scan<uint64_t>(keep ? 1ull : 0ull, s_scan, tile_total);
+  if (threadIdx.x < 64) {
+    const uint64_t ex = lookback_single(lb, tile, tile_total, epoch, &meta->err);
+    if (threadIdx.x == 0) {
+      s_off = ex;
+      const uint64_t ntiles = (n + kBlock - 1) / kBlock;
+      if (tile == ntiles - 1) meta->nnz_out[epoch % kRing] = ex + tile_total;
+    }
+  }
+  __syncthreads();
+  uint64_t orv[W], andv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    orv[w] = keep ? key[w] : 0ull;
+    andv[w] = keep ? key[w] : ~0ull;
+  }
+  if (keep) {
+    const uint64_t p = s_off + loc;
+    if (p < cap) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) out_keys.w[w][p] = key[w];
+      out_amp[p] = a;
+    }
+  }
+  publish_masks<W>(meta, epoch, orv, andv, s_red);
+}
+
+// ---------------------------------------------------------------------------
+// utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_ring_init(DevMeta* meta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    for (int r = 0; r < kRing; ++r) {
+      meta->counters[r] = 0;
+      meta->nnz_out[r] = 0;
+      for (int w = 0; w < kMaxW; ++w) {
+        meta->or_mask[r][w] = 0;
+        meta->and_mask[r][w] = ~0ull;
+      }
+    }
+  }
+}
+
+__global__ void k_clear_err(DevMeta* meta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) meta->err = 0;
+}
+
+__global__ void k_meta_init(DevMeta* meta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    for (int r = 0; r < kRing; ++r) {
+      meta->counters[r] = 0;
+      meta->nnz_out[r] = 0;
+      for (int w = 0; w < kMaxW; ++w) {
+        meta->or_mask[r][w] = 0;
+        meta->and_mask[r][w] = ~0ull;
+      }
+    }
+    meta->peak = 0;
+    meta->err = 0;
+  }
+}
+
+// Pack register values (n x nregs, row-major) into keys and append them at
+// position `at`; the instance field gets `inst`.
+struct PackDesc {
+  uint32_t nregs, has_inst, iword, ishift;
+  uint64_t inst;
+  uint32_t word[64], shift[64];
+  uint64_t mask[64];
+};
+
+template <int W>
+__global__ void k_pack(const uint64_t* __restrict__ values, const double2* __restrict__ amps, uint64_t n,
+                       KeyPtrs<W> keys, double2* __restrict__ amp, uint64_t at, PackDesc pd) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t k[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) k[w] = 0;
+  for (uint32_t r = 0; r < pd.nregs; ++r) {
+    const uint64_t v = values[i * pd.nregs + r] & pd.mask[r];
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+      if (pd.word[r] == (uint32_t)w) k[w] |= v << pd.shift[r];
+  }
+  if (pd.has_inst) {
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+      if (pd.iword == (uint32_t)w) k[w] |= pd.inst << pd.ishift;
+  }
+#pragma unroll
+  for (int w = 0; w < W; ++w) keys.w[w][at + i] = k[w];
+  amp[at + i] = amps[i];
+}
+
+// Copy entries [lo, hi) of instance-sorted keys into a W-interleaved export
+// buffer with the instance field cleared.
+template <int W>
+__global__ void k_export(KeyPtrs<W> keys, const double2* __restrict__ amp, uint64_t lo, uint64_t hi,
+                         uint64_t* __restrict__ out_keys, double2* __restrict__ out_amp,
+                         uint32_t iword, uint64_t iclear) {
+  const uint64_t i = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= hi) return;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    uint64_t v = keys.w[w][i];
+    if ((uint32_t)w == iword) v &= ~iclear;
+    out_keys[(i - lo) * W + w] = v;
+  }
+  out_amp[i - lo] = amp[i];
+}
+
+// Per-instance entry ranges of an instance-sorted state: bounds[inst] = first
+// index with instance >= inst (bounds has ninst + 1 slots, pre-filled with n).
+template <int W>
+__global__ void k_inst_bounds(KeyPtrs<W> keys, uint64_t n, uint32_t iword, uint32_t ishift,
+                              uint64_t imask, uint64_t* bounds, uint32_t ninst) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t k[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) k[w] = keys.w[w][i];
+  const uint64_t cur = (sel_word<W>(k, iword) >> ishift) & imask;
+  uint64_t prv = 0;
+  if (i > 0) {
+    uint64_t pk[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) pk[w] = keys.w[w][i - 1];
+    prv = (sel_word<W>(pk, iword) >> ishift) & imask;
+  } else {
+    prv = 0;
+    for (uint64_t j = 0; j <= cur && j < ninst; ++j) bounds[j] = 0;
+    return;
+  }
+  // instances prv+1 .. cur start here
+  for (uint64_t j = prv + 1; j <= cur && j < ninst; ++j) bounds[j] = i;
+}
+
+// ---------------------------------------------------------------------------
+// measurement support (a register field of one instance)
+// ---------------------------------------------------------------------------
+// Tile sums of w_i = |a_i|^2 over the entries of the instance (0 elsewhere),
+// in a fixed order per tile.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_prob_tiles(KeyPtrs<W> keys, const double2* __restrict__ amp,
+                                                       uint64_t n, FilterOp f, double* __restrict__ tile_sum) {
+  __shared__ double s_scan[4];
+  const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  double w = 0.0;
+  if (e < n) {
+    uint64_t k[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) k[j] = keys.w[j][e];
+    const bool mine = !f.has_inst || ((sel_word<W>(k, f.iword) >> f.ishift) & f.imask) == f.inst;
+    const bool pick = !f.use_f || ((sel_word<W>(k, f.fword) >> f.fshift) & f.fmask) == f.fval;
+    const double2 a = amp[e];
+    if (mine && pick) w = a.x * a.x + a.y * a.y;
+  }
+  double tot;
+  block_excl_scan<double>(w, s_scan, tot);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+// Sequential exclusive scan of the tile sums (one thread; fixed order).
+__global__ void k_prob_scan(double* tile_sum, uint64_t ntiles, double* total) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double run = 0.0;
+  for (uint64_t t = 0; t < ntiles; ++t) {
+    const double x = tile_sum[t];
+    tile_sum[t] = run;
+    run = run + x;
+  }
+  *total = run;
+}
+
+// Each entry of the instance gets its inclusive running sum (ascending field
+// order).  The entry whose running sum first exceeds u*P records its field
+// value; the first and last entries of every field run record their bounds.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_prob_find(KeyPtrs<W> keys, const double2* __restrict__ amp,
+                                                      uint64_t n, FilterOp f, const double* __restrict__ tile_pre,
+                                                      const double* __restrict__ total, double u,
+                                                      double* __restrict__ incl, unsigned long long* out) {
+  __shared__ double s_scan[4];
+  const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  double w = 0.0;
+  bool mine = false;
+  uint64_t fv = 0;
+  if (e < n) {
+    uint64_t k[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) k[j] = keys.w[j][e];
+    mine = !f.has_inst || ((sel_word<W>(k, f.iword) >> f.ishift) & f.imask) == f.inst;
+    fv = (sel_word<W>(k, f.fword) >> f.fshift) & f.fmask;
+    const double2 a = amp[e];
+    if (mine) w = a.x * a.x + a.y * a.y;
+  }
+  double tot;
+  const double ex = block_excl_scan<double>(w, s_scan, tot);
+  if (e < n) {
+    const double before = tile_pre[blockIdx.x] + ex;
+    const double after = before + w;
+    incl[e] = after;
+    const double target = u * (*total);
+    // out[0], out[1]: index and field value of the one entry whose running sum
+    // crosses u*P; out[2]: the largest field value with weight (fallback)
+    if (mine && w > 0.0) {
+      atomicMax(&out[2], (unsigned long long)fv);
+      if (before <= target && after > target) {
+        out[0] = e;
+        out[1] = fv;
+      }
+    }
+  }
+}
+
+}  // namespace sparqs

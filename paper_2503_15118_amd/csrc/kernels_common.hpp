@@ -1,0 +1,212 @@
+// Wave64 / workgroup primitives and decoupled look-back for gfx950.
+#pragma once
+
+#include "sparqs_internal.h"
+
+namespace sparqs {
+
+template <int W>
+struct KeyPtrs {
+  uint64_t* w[W];
+};
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Number of set bits of `m` in lanes below this one.
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T t = __shfl_up(v, d, 64);
+    if (lane >= (uint32_t)d) v += t;
+  }
+  return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_or(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v |= __shfl_xor(v, d, 64);
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_and(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v &= __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Exclusive scan over the 256 threads of a workgroup; `lds` holds 4 values.
+template <class T>
+__device__ __forceinline__ T block_excl_scan(T v, T* lds, T& total) {
+  T inc = wave_incl_scan(v);
+  const uint32_t w = threadIdx.x >> 6;
+  if (lane_id() == 63) lds[w] = inc;
+  __syncthreads();
+  T pre = 0, tot = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kBlock / 64; ++i) {
+    T x = lds[i];
+    if (i < w) pre += x;
+    tot += x;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + inc - v;
+}
+
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ bool lb_ready(uint64_t v, uint32_t epoch) {
+  return ((uint32_t)(v >> kLbEpochShift) == (epoch & kEpochMask)) && (v & kLbFlagMask);
+}
+
+// Decoupled look-back for one running total per tile, executed by every lane
+// of one wave.  Publishes `agg` for `tile`, returns the sum over all earlier
+// tiles (identical on every lane) and publishes the inclusive total.  A wait
+// that exceeds kSpinLimit polls raises kErrSpin and gives up (the result is
+// then wrong but every wave exits).
+__device__ uint64_t lookback_single(uint64_t* lb, uint32_t tile, uint64_t agg, uint32_t epoch,
+                                    unsigned int* err) {
+  const uint64_t ep = (uint64_t)(epoch & kEpochMask) << kLbEpochShift;
+  const uint32_t lane = lane_id();
+  if (tile == 0) {
+    if (lane == 0) st_agent(&lb[0], ep | kLbInc | agg);
+    return 0;
+  }
+  if (lane == 0) st_agent(&lb[tile], ep | kLbAgg | agg);
+  uint64_t excl = 0;
+  int64_t top = (int64_t)tile - 1;
+  uint32_t spins = 0;
+  while (true) {
+    const int64_t idx = top - (int64_t)lane;
+    const uint64_t v = idx >= 0 ? ld_agent(&lb[idx]) : (ep | kLbInc);
+    const bool rd = lb_ready(v, epoch);
+    const uint64_t rdy = __ballot(rd);
+    const uint64_t inc = __ballot(rd && (v & kLbInc));
+    const uint32_t first_nr = (~rdy) ? (uint32_t)__builtin_ctzll(~rdy) : 64u;
+    const uint32_t first_inc = inc ? (uint32_t)__builtin_ctzll(inc) : 64u;
+    if (first_inc < first_nr) {
+      excl += wave_sum<uint64_t>(lane <= first_inc ? (v & kLbValueMask) : 0ull);
+      break;
+    }
+    if (first_nr == 64u) {
+      excl += wave_sum<uint64_t>(v & kLbValueMask);
+      top -= 64;
+      continue;
+    }
+    if (++spins > kSpinLimit) {
+      if (lane == 0) atomicOr(err, kErrSpin);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  if (lane == 0) st_agent(&lb[tile], ep | kLbInc | (excl + agg));
+  return excl;
+}
+
+// Per-digit look-back: thread `d` of the workgroup walks its own chain.
+__device__ uint64_t lookback_digit(uint64_t* lb, uint32_t tile, uint32_t d, uint64_t cnt,
+                                   uint32_t epoch, unsigned int* err) {
+  const uint64_t ep = (uint64_t)(epoch & kEpochMask) << kLbEpochShift;
+  uint64_t* row = lb + (uint64_t)tile * kRadix;
+  if (tile == 0) {
+    st_agent(&row[d], ep | kLbInc | cnt);
+    return 0;
+  }
+  st_agent(&row[d], ep | kLbAgg | cnt);
+  uint64_t excl = 0;
+  int64_t j = (int64_t)tile - 1;
+  uint32_t spins = 0;
+  while (j >= 0) {
+    const uint64_t v = ld_agent(&lb[(uint64_t)j * kRadix + d]);
+    if (!lb_ready(v, epoch)) {
+      if (++spins > kSpinLimit) {
+        atomicOr(err, kErrSpin);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += v & kLbValueMask;
+    if (v & kLbInc) break;
+    --j;
+  }
+  st_agent(&row[d], ep | kLbInc | (excl + cnt));
+  return excl;
+}
+
+// Dynamic tile id from the launch's counter slot; the first workgroup to
+// arrive also clears the slot that a launch kRing/2 epochs later will use.
+__device__ __forceinline__ uint32_t take_tile(DevMeta* meta, uint32_t epoch, uint32_t* s_tile) {
+  if (threadIdx.x == 0) {
+    const uint32_t t = (uint32_t)atomicAdd(&meta->counters[epoch % kRing], 1ull);
+    *s_tile = t;
+    if (t == 0) {
+      const uint32_t r = (epoch + kRing / 2) % kRing;
+      meta->counters[r] = 0;
+      meta->nnz_out[r] = 0;
+      for (int w = 0; w < kMaxW; ++w) {
+        meta->or_mask[r][w] = 0;
+        meta->and_mask[r][w] = ~0ull;
+      }
+    }
+  }
+  __syncthreads();
+  return *s_tile;
+}
+
+// A tile id beyond the launch's tile count can only come from a corrupted
+// counter slot; such a workgroup flags the error and touches no data.
+__device__ __forceinline__ bool tile_out_of_range(uint32_t tile, uint64_t ntiles, unsigned int* err) {
+  if (tile < ntiles) return false;
+  if (threadIdx.x == 0) atomicOr(err, kErrSpin);
+  return true;
+}
+
+template <int W>
+__device__ __forceinline__ void publish_masks(DevMeta* meta, uint32_t epoch, const uint64_t (&orv)[W],
+                                              const uint64_t (&andv)[W], uint64_t* s_red) {
+  // s_red: 2*W*4 values of LDS
+  const uint32_t wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    uint64_t o = wave_or(orv[w]);
+    uint64_t a = wave_and(andv[w]);
+    if (lane_id() == 0) {
+      s_red[(2 * w) * 4 + wave] = o;
+      s_red[(2 * w + 1) * 4 + wave] = a;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < (uint32_t)W) {
+    const int w = threadIdx.x;
+    uint64_t o = 0, a = ~0ull;
+    for (int i = 0; i < kBlock / 64; ++i) {
+      o |= s_red[(2 * w) * 4 + i];
+      a &= s_red[(2 * w + 1) * 4 + i];
+    }
+    const uint32_t r = epoch % kRing;
+    if (o) atomicOr(&meta->or_mask[r][w], (unsigned long long)o);
+    if (~a) atomicAnd(&meta->and_mask[r][w], (unsigned long long)a);
+  }
+}
+
+}  // namespace sparqs

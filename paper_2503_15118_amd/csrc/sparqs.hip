@@ -1,0 +1,1204 @@
+// C ABI and host planner of the sparse register-level simulator (one MI355X).
+//
+// The planner turns a list of register-level ops into kernel launches:
+//  * consecutive non-branching ops form one fused k_perm launch;
+//  * a branching op (H / Ry on up to 5 qubits per launch) becomes
+//      - k_group in EXPAND mode when none of its target bits varies over the
+//        state (every group has one member),
+//      - k_group in GROUP mode directly when the entries are still grouped by
+//        the same target bits (members of a group contiguous), which the
+//        planner tracks through ops that cannot separate group members,
+//      - otherwise an LSD radix sort on (idle bits that vary, target bits)
+//        followed by k_group.
+// Control reaches the device once per launch; the host reads back the entry
+// count and key masks after each branching op (a pinned 2 KB block).
+#include "../../include/sparqs.h"
+#include "kernels.hip"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace sparqs;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+constexpr uint32_t kMaxOpsPerCall = 16384;  // device op ring (PermOp records)
+constexpr uint32_t kHistBlocksMax = 256;
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+struct RegInfo {
+  uint32_t word, shift, width;
+  uint64_t mask;
+};
+
+struct TableInfo {
+  void* dev;
+  uint32_t addr_bits, word_bits;
+  bool w32;
+};
+
+struct Buf {
+  uint64_t* key[kMaxW];
+  double2* amp;
+};
+
+struct Layout {
+  std::vector<RegInfo> regs;
+  uint32_t W = 1;
+  bool has_inst = false;
+  uint32_t iword = 0, ishift = 0, ibits = 0;
+  uint64_t imask = 0;
+};
+
+int make_layout(const ss_reg* regs, uint32_t nregs, uint32_t ninst, Layout& L) {
+  if (!regs || nregs == 0 || nregs > 64 || ninst == 0) return SS_E_ARG;
+  uint32_t fill[kMaxW] = {0, 0, 0, 0};
+  uint32_t used = 0;
+  auto place = [&](uint32_t width, uint32_t& word, uint32_t& shift) -> bool {
+    for (uint32_t w = 0; w < (uint32_t)kMaxW; ++w) {
+      if (fill[w] + width <= 64) {
+        word = w;
+        shift = fill[w];
+        fill[w] += width;
+        used = std::max(used, w + 1);
+        return true;
+      }
+    }
+    return false;
+  };
+  L.regs.clear();
+  for (uint32_t r = 0; r < nregs; ++r) {
+    const uint32_t w = regs[r].nqubits;
+    if (w < 1 || w > 64) return SS_E_ARG;
+    RegInfo ri;
+    if (!place(w, ri.word, ri.shift)) return SS_E_ARG;
+    ri.width = w;
+    ri.mask = w == 64 ? ~0ull : ((1ull << w) - 1);
+    L.regs.push_back(ri);
+  }
+  L.has_inst = ninst > 1;
+  if (L.has_inst) {
+    uint32_t b = 0;
+    while ((1ull << b) < ninst) ++b;
+    L.ibits = b;
+    L.imask = (1ull << b) - 1;
+    if (!place(b, L.iword, L.ishift)) return SS_E_ARG;
+  }
+  L.W = used <= 1 ? 1 : (used <= 2 ? 2 : 4);
+  return SS_OK;
+}
+
+uint64_t entry_bytes(uint32_t W) { return 8ull * W + 16; }
+
+struct Carve {
+  uint64_t meta, digit_start, dev_ops, uscr, hist, tables, lb, buf0, buf1, total;
+  uint64_t lb_words, hist_blocks;
+};
+
+Carve carve(uint32_t W, uint32_t ninst, uint64_t cap, uint64_t table_bytes) {
+  Carve c{};
+  uint64_t off = 0;
+  c.meta = off;
+  off = align_up(off + sizeof(DevMeta), kAlign);
+  c.digit_start = off;
+  off = align_up(off + (uint64_t)kMaxPasses * kRadix * 8, kAlign);
+  c.dev_ops = off;
+  off = align_up(off + (uint64_t)kMaxOpsPerCall * sizeof(PermOp), kAlign);
+  c.uscr = off;
+  off = align_up(off + (uint64_t)(ninst + 64) * 8, kAlign);
+  c.hist_blocks = std::min<uint64_t>(kHistBlocksMax, std::max<uint64_t>(1, cap / 16384));
+  c.hist = off;
+  off = align_up(off + c.hist_blocks * kMaxPasses * kRadix * 4, kAlign);
+  c.tables = off;
+  off = align_up(off + table_bytes, kAlign);
+  // look-back words: sort tiles (>= 2048 entries) x 256 digits, emit tiles (256 entries)
+  c.lb_words = std::max<uint64_t>(cap / 2048 + 2, 1) * kRadix + cap / kBlock + 64;
+  c.lb = off;
+  off = align_up(off + c.lb_words * 8, kAlign);
+  c.buf0 = off;
+  off = align_up(off + cap * entry_bytes(W), kAlign);
+  c.buf1 = off;
+  off = align_up(off + cap * entry_bytes(W), kAlign);
+  c.total = off;
+  return c;
+}
+
+}  // namespace
+
+struct ss_state {
+  Layout L;
+  uint32_t ninst = 1;
+  double eps = 0.0;
+  hipStream_t stream = nullptr;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  uint64_t table_bytes = 0;
+  uint64_t cap = 0;
+  Carve cv{};
+  Buf buf[2]{};
+  int cur = 0;
+  DevMeta* meta = nullptr;
+  uint64_t* lb = nullptr;
+  uint32_t* hist = nullptr;
+  uint64_t* digit_start = nullptr;
+  PermOp* dev_ops = nullptr;
+  uint64_t* uscr = nullptr;
+  char* tab_base = nullptr;
+  uint64_t tab_used = 0;
+  std::vector<TableInfo> tables;
+  // host mirrors
+  uint64_t n = 0, peak = 0;
+  uint64_t orm[kMaxW]{}, andm[kMaxW]{};
+  bool masks_stale = false;
+  uint32_t mask_epoch = 0;
+  uint32_t epoch = 0;
+  bool grouped = false;
+  uint64_t gmask[kMaxW]{};
+  bool poisoned = false;
+  DevMeta* hmeta = nullptr;       // pinned read-back block
+  PermOp* hops = nullptr;         // pinned op staging (kMaxOpsPerCall)
+  uint32_t ops_used = 0;
+  // options
+  int sort_items = 16;
+  int grouping = 1;
+  uint64_t stats[8]{};
+};
+
+namespace {
+
+Buf make_buf(char* base, uint32_t W, uint64_t cap) {
+  Buf b{};
+  for (uint32_t w = 0; w < W; ++w) b.key[w] = reinterpret_cast<uint64_t*>(base + (uint64_t)w * cap * 8);
+  b.amp = reinterpret_cast<double2*>(base + (uint64_t)W * cap * 8);
+  return b;
+}
+
+template <int W>
+KeyPtrs<W> kp(const Buf& b) {
+  KeyPtrs<W> p;
+  for (int w = 0; w < W; ++w) p.w[w] = b.key[w];
+  return p;
+}
+
+uint32_t next_epoch(ss_state* st) {
+  st->epoch = (st->epoch + 1) & kEpochMask;
+  if (st->epoch == 0) {
+    // the 24-bit tag wrapped: clear every look-back word before reuse
+    k_fill_u64<<<1024, 256, 0, st->stream>>>(st->lb, st->cv.lb_words, 0ull);
+    k_ring_init<<<1, 64, 0, st->stream>>>(st->meta);
+    st->epoch = 1;
+  }
+  st->stats[0]++;
+  return st->epoch;
+}
+
+int hip_fail(ss_state* st) {
+  st->poisoned = true;
+  return SS_E_HIP;
+}
+
+int check_launch(ss_state* st) {
+  if (hipGetLastError() != hipSuccess) return hip_fail(st);
+  return SS_OK;
+}
+
+// Wait for the stream and copy the device meta block to pinned memory.
+int readback(ss_state* st) {
+  if (hipMemcpyAsync(st->hmeta, st->meta, sizeof(DevMeta), hipMemcpyDeviceToHost, st->stream) != hipSuccess)
+    return hip_fail(st);
+  if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
+  st->stats[6]++;
+  st->ops_used = 0;
+  return SS_OK;
+}
+
+void take_masks(ss_state* st, uint32_t ep) {
+  const uint32_t r = ep % kRing;
+  for (int w = 0; w < kMaxW; ++w) {
+    st->orm[w] = st->hmeta->or_mask[r][w];
+    st->andm[w] = st->hmeta->and_mask[r][w];
+  }
+  st->masks_stale = false;
+}
+
+int ensure_masks(ss_state* st) {
+  if (!st->masks_stale) return SS_OK;
+  int rc = readback(st);
+  if (rc) return rc;
+  take_masks(st, st->mask_epoch);
+  return SS_OK;
+}
+
+int clear_err(ss_state* st) {
+  k_clear_err<<<1, 64, 0, st->stream>>>(st->meta);
+  return check_launch(st);
+}
+
+// ---------------------------------------------------------------------------
+// sort planning: virtual key = target bits (ascending qubit order) then the
+// varying idle bits from word 0 bit 0 upwards; 8 virtual bits per pass.
+// ---------------------------------------------------------------------------
+void build_plan(uint32_t W, const std::vector<std::pair<uint32_t, uint32_t>>& lowbits,
+                const uint64_t* skip, const uint64_t* var, SortPlan& plan) {
+  std::vector<std::pair<uint32_t, uint32_t>> vb = lowbits;
+  for (uint32_t w = 0; w < W; ++w)
+    for (uint32_t b = 0; b < 64; ++b)
+      if (((var[w] & ~skip[w]) >> b) & 1ull) vb.push_back({w, b});
+  plan.npass = (uint32_t)((vb.size() + kRadixBits - 1) / kRadixBits);
+  for (uint32_t p = 0; p < plan.npass; ++p) {
+    PassDesc& pd = plan.pass[p];
+    pd.nf = 0;
+    const size_t lo = (size_t)p * kRadixBits, hi = std::min(vb.size(), lo + kRadixBits);
+    size_t j = lo;
+    while (j < hi) {
+      const uint32_t w = vb[j].first, b = vb[j].second;
+      uint32_t width = 1;
+      while (j + width < hi && vb[j + width].first == w && vb[j + width].second == b + width) ++width;
+      pd.f[pd.nf++] = pack_field(w, b, width, (uint32_t)(j - lo));
+      j += width;
+    }
+  }
+}
+
+template <int W>
+int run_sort_w(ss_state* st, const SortPlan& plan) {
+  const uint64_t n = st->n;
+  if (plan.npass == 0 || n <= 1) return SS_OK;
+  const int items = (W == 4) ? 8 : st->sort_items;
+  const uint64_t tile = (uint64_t)kBlock * items;
+  const uint32_t nb = (uint32_t)std::min<uint64_t>(st->cv.hist_blocks, (n + 2047) / 2048);
+  k_sort_hist<W><<<nb, kBlock, plan.npass * kRadix * 4, st->stream>>>(kp<W>(st->buf[st->cur]), n, plan,
+                                                                       st->hist);
+  k_sort_scan<<<plan.npass, kBlock, 0, st->stream>>>(st->hist, nb, plan.npass, st->digit_start);
+  st->stats[0] += 2;
+  const uint32_t ntiles = (uint32_t)((n + tile - 1) / tile);
+  for (uint32_t p = 0; p < plan.npass; ++p) {
+    const uint32_t ep = next_epoch(st);
+    const Buf& in = st->buf[st->cur];
+    const Buf& out = st->buf[st->cur ^ 1];
+    if (items == 16)
+      k_sort_pass<W, 16><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, n,
+                                                             plan.pass[p], st->digit_start + p * kRadix,
+                                                             st->lb, st->meta, ep);
+    else
+      k_sort_pass<W, 8><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, n,
+                                                            plan.pass[p], st->digit_start + p * kRadix,
+                                                            st->lb, st->meta, ep);
+    st->cur ^= 1;
+    st->stats[1]++;
+  }
+  st->stats[2]++;
+  st->grouped = false;
+  return check_launch(st);
+}
+
+int run_sort(ss_state* st, const SortPlan& plan) {
+  switch (st->L.W) {
+    case 1: return run_sort_w<1>(st, plan);
+    case 2: return run_sort_w<2>(st, plan);
+    default: return run_sort_w<4>(st, plan);
+  }
+}
+
+// Canonical order: every varying bit, word 0 bit 0 least significant.
+int sort_canonical(ss_state* st) {
+  int rc = ensure_masks(st);
+  if (rc) return rc;
+  uint64_t var[kMaxW], skip[kMaxW] = {0, 0, 0, 0};
+  for (int w = 0; w < kMaxW; ++w) var[w] = st->orm[w] & ~st->andm[w];
+  SortPlan plan;
+  build_plan(st->L.W, {}, skip, var, plan);
+  return run_sort(st, plan);
+}
+
+// ---------------------------------------------------------------------------
+// emitting kernels (group / expand / filter): read buf[cur], write buf[cur^1]
+// ---------------------------------------------------------------------------
+template <int W, int K>
+void launch_group_wk(ss_state* st, int mode, const GroupOp& g, uint32_t ep) {
+  const Buf& in = st->buf[st->cur];
+  const Buf& out = st->buf[st->cur ^ 1];
+  const uint32_t ntiles = (uint32_t)((st->n + kBlock - 1) / kBlock);
+  if (mode == MODE_GROUP)
+    k_group<W, K, MODE_GROUP><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->n,
+                                                                  st->cap, g, st->lb, st->meta, ep);
+  else
+    k_group<W, K, MODE_EXPAND><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->n,
+                                                                   st->cap, g, st->lb, st->meta, ep);
+}
+
+template <int W>
+void launch_group_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep) {
+  switch (g.k) {
+    case 1: launch_group_wk<W, 1>(st, mode, g, ep); break;
+    case 2: launch_group_wk<W, 2>(st, mode, g, ep); break;
+    case 3: launch_group_wk<W, 3>(st, mode, g, ep); break;
+    case 4: launch_group_wk<W, 4>(st, mode, g, ep); break;
+    default: launch_group_wk<W, 5>(st, mode, g, ep); break;
+  }
+}
+
+// Finish an emitting launch: read back, check errors, swap buffers.
+int finish_emit(ss_state* st, uint32_t ep, bool check_cap) {
+  int rc = readback(st);
+  if (rc) return rc;
+  const DevMeta* hm = st->hmeta;
+  if (hm->err & (kErrSpin | kErrGroup)) return hip_fail(st);
+  const uint64_t nout = hm->nnz_out[ep % kRing];
+  if (check_cap && ((hm->err & kErrCapacity) || nout > st->cap)) {
+    clear_err(st);
+    return SS_E_CAPACITY;
+  }
+  st->cur ^= 1;
+  st->n = nout;
+  st->peak = std::max(st->peak, nout);
+  take_masks(st, ep);
+  return SS_OK;
+}
+
+template <int W>
+void launch_filter_w(ss_state* st, const FilterOp& f, uint32_t ep) {
+  const Buf& in = st->buf[st->cur];
+  const Buf& out = st->buf[st->cur ^ 1];
+  const uint32_t ntiles = (uint32_t)((st->n + kBlock - 1) / kBlock);
+  k_filter<W><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->n, st->cap, f,
+                                                 st->lb, st->meta, ep);
+}
+
+int run_filter(ss_state* st, const FilterOp& f) {
+  if (st->n == 0) return SS_OK;
+  const uint32_t ep = next_epoch(st);
+  switch (st->L.W) {
+    case 1: launch_filter_w<1>(st, f, ep); break;
+    case 2: launch_filter_w<2>(st, f, ep); break;
+    default: launch_filter_w<4>(st, f, ep); break;
+  }
+  int rc = check_launch(st);
+  if (rc) return rc;
+  return finish_emit(st, ep, false);
+}
+
+FilterOp base_filter(const ss_state* st, uint32_t inst) {
+  FilterOp f{};
+  f.has_inst = st->L.has_inst ? 1u : 0u;
+  f.iword = st->L.iword;
+  f.ishift = st->L.ishift;
+  f.imask = st->L.imask;
+  f.inst = inst;
+  return f;
+}
+
+// ---------------------------------------------------------------------------
+// op validation and conversion
+// ---------------------------------------------------------------------------
+bool is_branching(uint16_t kind) { return kind == SS_H || kind == SS_RY; }
+
+int validate_op(const ss_state* st, const ss_op& op) {
+  const uint32_t nr = (uint32_t)st->L.regs.size();
+  if (op.kind > SS_REFLECT0 || op.flags != 0 || op.nctl > 3) return SS_E_ARG;
+  if (op.reg >= nr) return SS_E_ARG;
+  const RegInfo& d = st->L.regs[op.reg];
+  for (uint32_t j = 0; j < op.nctl; ++j) {
+    const ss_ctl& c = op.ctl[j];
+    if (c.reg >= nr || c.qubit >= st->L.regs[c.reg].width || c.value > 1) return SS_E_ARG;
+  }
+  switch (op.kind) {
+    case SS_X:
+    case SS_H:
+    case SS_RY:
+      if (op.qmask == 0 || (op.qmask & ~d.mask)) return SS_E_ARG;
+      for (uint32_t j = 0; j < op.nctl; ++j)
+        if (op.ctl[j].reg == op.reg && ((op.qmask >> op.ctl[j].qubit) & 1ull)) return SS_E_ARG;
+      if (op.kind == SS_RY && !std::isfinite(op.theta)) return SS_E_ARG;
+      return SS_OK;
+    case SS_ADD:
+    case SS_SUB:
+    case SS_XOR:
+      if (op.reg2 >= nr || op.reg2 == op.reg) return SS_E_ARG;
+      break;
+    case SS_MULC:
+      if ((op.imm & 1ull) == 0) return SS_E_NOT_UNITARY;
+      break;
+    case SS_XORC:
+    case SS_REFLECT0:
+      break;
+    case SS_QRAM_LOAD:
+    case SS_QRAM_UNLOAD: {
+      if (op.reg2 >= nr || op.reg2 == op.reg) return SS_E_ARG;
+      if (op.qram_id >= st->tables.size()) return SS_E_QRAM;
+      const TableInfo& t = st->tables[op.qram_id];
+      if (st->L.regs[op.reg2].width != t.addr_bits || d.width != t.word_bits) return SS_E_QRAM;
+      break;
+    }
+  }
+  if (op.kind != SS_REFLECT0)
+    for (uint32_t j = 0; j < op.nctl; ++j)
+      if (op.ctl[j].reg == op.reg) return SS_E_ARG;
+  return SS_OK;
+}
+
+void ctl_masks(const ss_state* st, const ss_op& op, uint64_t* cmask, uint64_t* cval) {
+  for (int w = 0; w < kMaxW; ++w) cmask[w] = cval[w] = 0;
+  for (uint32_t j = 0; j < op.nctl; ++j) {
+    const RegInfo& r = st->L.regs[op.ctl[j].reg];
+    const uint64_t bit = 1ull << (r.shift + op.ctl[j].qubit);
+    cmask[r.word] |= bit;
+    if (op.ctl[j].value) cval[r.word] |= bit;
+  }
+}
+
+PermOp to_perm(const ss_state* st, const ss_op& op) {
+  PermOp p{};
+  const RegInfo& d = st->L.regs[op.reg];
+  p.dst_word = d.word;
+  p.dst_shift = d.shift;
+  p.dst_mask = d.mask;
+  p.src_word = 0;
+  p.src_shift = 0;
+  p.src_mask = 0;
+  switch (op.kind) {
+    case SS_X: p.kind = PK_XMASK; p.imm = op.qmask & d.mask; break;
+    case SS_XORC: p.kind = PK_XORC; p.imm = op.imm & d.mask; break;
+    case SS_MULC: p.kind = PK_MULC; p.imm = op.imm; break;
+    case SS_ADD: p.kind = PK_ADD; break;
+    case SS_SUB: p.kind = PK_SUB; break;
+    case SS_XOR: p.kind = PK_XOR; break;
+    case SS_QRAM_LOAD:
+    case SS_QRAM_UNLOAD: {
+      p.kind = PK_QRAM;
+      const TableInfo& t = st->tables[op.qram_id];
+      p.table = t.dev;
+      p.table_words32 = t.w32 ? 1u : 0u;
+      break;
+    }
+    case SS_REFLECT0: p.kind = PK_REFLECT0; break;
+  }
+  if (op.kind == SS_ADD || op.kind == SS_SUB || op.kind == SS_XOR || op.kind == SS_QRAM_LOAD ||
+      op.kind == SS_QRAM_UNLOAD) {
+    const RegInfo& s = st->L.regs[op.reg2];
+    p.src_word = s.word;
+    p.src_shift = s.shift;
+    p.src_mask = s.mask;
+  }
+  ctl_masks(st, op, p.cmask, p.cval);
+  p.nctl_words = op.nctl ? 1u : 0u;
+  return p;
+}
+
+// Does a non-branching op keep every group of the mask g contiguous and intact?
+bool keeps_grouping(const ss_state* st, const ss_op& op, const uint64_t* g) {
+  if (op.kind == SS_REFLECT0) return true;  // phase only, keys unchanged
+  uint64_t reads[kMaxW] = {0, 0, 0, 0}, writes[kMaxW] = {0, 0, 0, 0};
+  uint64_t cm[kMaxW], cv[kMaxW];
+  ctl_masks(st, op, cm, cv);
+  for (int w = 0; w < kMaxW; ++w) reads[w] |= cm[w];
+  const RegInfo& d = st->L.regs[op.reg];
+  writes[d.word] |= d.mask << d.shift;
+  if (op.kind == SS_ADD || op.kind == SS_SUB || op.kind == SS_XOR || op.kind == SS_QRAM_LOAD ||
+      op.kind == SS_QRAM_UNLOAD) {
+    const RegInfo& s = st->L.regs[op.reg2];
+    reads[s.word] |= s.mask << s.shift;
+  }
+  const bool xor_like = op.kind == SS_X || op.kind == SS_XORC || op.kind == SS_XOR ||
+                        op.kind == SS_QRAM_LOAD || op.kind == SS_QRAM_UNLOAD;
+  for (int w = 0; w < kMaxW; ++w) {
+    if (reads[w] & g[w]) return false;
+    if (!xor_like && (writes[w] & g[w])) return false;
+  }
+  return true;
+}
+
+template <int W>
+void launch_perm_w(ss_state* st, const PermOp* dev, uint32_t nops, uint32_t write_words, bool amp, uint32_t ep) {
+  const Buf& b = st->buf[st->cur];
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((st->n + kBlock - 1) / kBlock, 8192);
+  if (amp)
+    k_perm<W, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, dev, nops, write_words, st->meta, ep);
+  else
+    k_perm<W, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, dev, nops, write_words, st->meta, ep);
+}
+
+int flush_run(ss_state* st, std::vector<PermOp>& run, uint32_t write_words, bool amp) {
+  if (run.empty()) return SS_OK;
+  if (st->n == 0) {
+    run.clear();
+    return SS_OK;
+  }
+  size_t i = 0;
+  while (i < run.size()) {
+    uint32_t chunk = (uint32_t)std::min<size_t>(run.size() - i, kMaxOpsPerCall);
+    if (st->ops_used + chunk > kMaxOpsPerCall) {
+      // staging ring full: wait for the stream before reusing it
+      if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
+      st->stats[6]++;
+      st->ops_used = 0;
+    }
+    PermOp* h = st->hops + st->ops_used;
+    PermOp* d = st->dev_ops + st->ops_used;
+    std::memcpy(h, run.data() + i, chunk * sizeof(PermOp));
+    if (hipMemcpyAsync(d, h, chunk * sizeof(PermOp), hipMemcpyHostToDevice, st->stream) != hipSuccess)
+      return hip_fail(st);
+    st->ops_used += chunk;
+    const uint32_t ep = next_epoch(st);
+    switch (st->L.W) {
+      case 1: launch_perm_w<1>(st, d, chunk, write_words, amp, ep); break;
+      case 2: launch_perm_w<2>(st, d, chunk, write_words, amp, ep); break;
+      default: launch_perm_w<4>(st, d, chunk, write_words, amp, ep); break;
+    }
+    int rc = check_launch(st);
+    if (rc) return rc;
+    st->masks_stale = true;
+    st->mask_epoch = ep;
+    st->stats[5]++;
+    i += chunk;
+  }
+  run.clear();
+  return SS_OK;
+}
+
+// One branching op: chunks of at most kMaxGroupBits target qubits, ascending.
+int do_branching(ss_state* st, const ss_op& op) {
+  const RegInfo& d = st->L.regs[op.reg];
+  std::vector<uint32_t> qs;
+  for (uint32_t q = 0; q < d.width; ++q)
+    if ((op.qmask >> q) & 1ull) qs.push_back(q);
+  double m[2][2];
+  if (op.kind == SS_H) {
+    const double c = 0.70710678118654752440;  // nearest double to 1/sqrt(2)
+    m[0][0] = c; m[0][1] = c; m[1][0] = c; m[1][1] = -c;
+  } else {
+    const double h = op.theta / 2.0;
+    const double c = std::cos(h), s = std::sin(h);
+    m[0][0] = c; m[0][1] = -s; m[1][0] = s; m[1][1] = c;
+  }
+  // An op split over several launches cannot be rolled back once its first
+  // part has run, so it is admitted only if the worst case fits.
+  if (qs.size() > (size_t)kMaxGroupBits &&
+      (qs.size() >= 40 || (st->n << qs.size()) > st->cap || ((st->n << qs.size()) >> qs.size()) != st->n))
+    return SS_E_CAPACITY;
+  for (size_t c0 = 0; c0 < qs.size(); c0 += kMaxGroupBits) {
+    if (st->n == 0) return SS_OK;
+    const size_t c1 = std::min(qs.size(), c0 + kMaxGroupBits);
+    const bool last = c1 == qs.size();
+    GroupOp g{};
+    g.k = (uint32_t)(c1 - c0);
+    std::vector<std::pair<uint32_t, uint32_t>> tl;
+    for (size_t j = c0; j < c1; ++j) {
+      const uint32_t bit = d.shift + qs[j];
+      g.tword[j - c0] = d.word;
+      g.tbit[j - c0] = bit;
+      g.tmask[d.word] |= 1ull << bit;
+      tl.push_back({d.word, bit});
+    }
+    ctl_masks(st, op, g.cmask, g.cval);
+    g.has_ctl = op.nctl ? 1u : 0u;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) g.m[a][b] = m[a][b];
+    g.eps2 = last ? st->eps * st->eps : 0.0;
+
+    int mode;
+    bool same = st->grouped && st->grouping;
+    for (int w = 0; w < kMaxW && same; ++w) same = st->gmask[w] == g.tmask[w];
+    if (same) {
+      mode = MODE_GROUP;
+    } else {
+      int rc = ensure_masks(st);
+      if (rc) return rc;
+      bool tvar = false;
+      uint64_t var[kMaxW];
+      for (int w = 0; w < kMaxW; ++w) {
+        var[w] = st->orm[w] & ~st->andm[w];
+        if (var[w] & g.tmask[w]) tvar = true;
+      }
+      if (!tvar) {
+        mode = MODE_EXPAND;
+      } else {
+        SortPlan plan;
+        build_plan(st->L.W, tl, g.tmask, var, plan);
+        rc = run_sort(st, plan);
+        if (rc) return rc;
+        mode = MODE_GROUP;
+      }
+    }
+    const uint32_t ep = next_epoch(st);
+    switch (st->L.W) {
+      case 1: launch_group_w<1>(st, mode, g, ep); break;
+      case 2: launch_group_w<2>(st, mode, g, ep); break;
+      default: launch_group_w<4>(st, mode, g, ep); break;
+    }
+    int rc = check_launch(st);
+    if (rc) return rc;
+    st->stats[mode == MODE_GROUP ? 3 : 4]++;
+    rc = finish_emit(st, ep, true);
+    if (rc == SS_E_CAPACITY) {
+      // parents are intact in buf[cur] (possibly re-ordered by the sort)
+      st->grouped = (mode == MODE_GROUP);
+      for (int w = 0; w < kMaxW; ++w) st->gmask[w] = g.tmask[w];
+      return rc;
+    }
+    if (rc) return rc;
+    st->grouped = true;
+    for (int w = 0; w < kMaxW; ++w) st->gmask[w] = g.tmask[w];
+  }
+  return SS_OK;
+}
+
+int check_state(const ss_state* st) {
+  if (!st) return SS_E_STATE;
+  if (st->poisoned) return SS_E_STATE;
+  return SS_OK;
+}
+
+int setup_arena(ss_state* st, char* arena, size_t bytes) {
+  const uint32_t W = st->L.W;
+  // largest capacity (multiple of 256) whose carve fits
+  uint64_t lo = 0, hi = bytes / (2 * entry_bytes(W)) + 1;
+  while (lo + 1 < hi) {
+    const uint64_t mid = (lo + hi) / 2;
+    if (carve(W, st->ninst, mid * 256, st->table_bytes).total <= bytes) lo = mid;
+    else hi = mid;
+  }
+  const uint64_t cap = lo * 256;
+  if (cap < std::max<uint64_t>(256, st->ninst)) return SS_E_NOMEM;
+  st->cap = cap;
+  st->cv = carve(W, st->ninst, cap, st->table_bytes);
+  st->arena = arena;
+  st->arena_bytes = bytes;
+  st->meta = reinterpret_cast<DevMeta*>(arena + st->cv.meta);
+  st->digit_start = reinterpret_cast<uint64_t*>(arena + st->cv.digit_start);
+  st->dev_ops = reinterpret_cast<PermOp*>(arena + st->cv.dev_ops);
+  st->uscr = reinterpret_cast<uint64_t*>(arena + st->cv.uscr);
+  st->hist = reinterpret_cast<uint32_t*>(arena + st->cv.hist);
+  st->tab_base = arena + st->cv.tables;
+  st->lb = reinterpret_cast<uint64_t*>(arena + st->cv.lb);
+  st->buf[0] = make_buf(arena + st->cv.buf0, W, cap);
+  st->buf[1] = make_buf(arena + st->cv.buf1, W, cap);
+  return SS_OK;
+}
+
+int init_device(ss_state* st) {
+  k_meta_init<<<1, 64, 0, st->stream>>>(st->meta);
+  k_fill_u64<<<256, 256, 0, st->stream>>>(st->lb, st->cv.lb_words, 0ull);
+  st->stats[0] += 2;
+  return check_launch(st);
+}
+
+template <int W>
+void launch_pack(ss_state* st, const uint64_t* values, const double2* amps, uint64_t n, uint64_t at,
+                 const PackDesc& pd) {
+  const Buf& b = st->buf[st->cur];
+  k_pack<W><<<(uint32_t)((n + 255) / 256), 256, 0, st->stream>>>(values, amps, n, kp<W>(b), b.amp, at, pd);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ss_strerror(int code) {
+  switch (code) {
+    case SS_OK: return "ok";
+    case SS_E_ARG: return "invalid argument";
+    case SS_E_NOT_UNITARY: return "operation is not unitary (even multiplier)";
+    case SS_E_QRAM: return "invalid QRAM table or QRAM operands";
+    case SS_E_CAPACITY: return "entry capacity of the arena exceeded";
+    case SS_E_NOMEM: return "arena too small";
+    case SS_E_HIP: return "HIP runtime or kernel failure";
+    case SS_E_STATE: return "state is null or poisoned";
+    default: return "unknown error";
+  }
+}
+
+int ss_required_bytes(const ss_reg* regs, uint32_t nregs, uint32_t ninst, uint64_t cap_entries,
+                      uint64_t table_bytes, size_t* bytes) {
+  if (!bytes) return SS_E_ARG;
+  Layout L;
+  int rc = make_layout(regs, nregs, ninst, L);
+  if (rc) return rc;
+  const uint64_t cap = align_up(std::max<uint64_t>(cap_entries, 256), 256);
+  *bytes = carve(L.W, ninst, cap, table_bytes).total;
+  return SS_OK;
+}
+
+int ss_create_state(const ss_reg* regs, uint32_t nregs, uint32_t ninst, double eps, void* arena,
+                    size_t arena_bytes, uint64_t table_bytes, void* hip_stream, ss_state** out) {
+  if (!out || !arena || ((uintptr_t)arena % kAlign) || !(eps >= 0.0) || !std::isfinite(eps)) return SS_E_ARG;
+  *out = nullptr;
+  ss_state* st = new ss_state();
+  int rc = make_layout(regs, nregs, ninst, st->L);
+  if (rc) {
+    delete st;
+    return rc;
+  }
+  st->ninst = ninst;
+  st->eps = eps;
+  st->stream = static_cast<hipStream_t>(hip_stream);
+  st->table_bytes = align_up(table_bytes, kAlign);
+  rc = setup_arena(st, static_cast<char*>(arena), arena_bytes);
+  if (rc) {
+    delete st;
+    return rc;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&st->hmeta), sizeof(DevMeta), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&st->hops), (size_t)kMaxOpsPerCall * sizeof(PermOp),
+                    hipHostMallocDefault) != hipSuccess) {
+    if (st->hmeta) (void)hipHostFree(st->hmeta);
+    delete st;
+    return SS_E_HIP;
+  }
+  rc = init_device(st);
+  if (rc) {
+    ss_destroy_state(st);
+    return rc;
+  }
+  // every instance starts as |0...0> with amplitude 1
+  std::vector<uint64_t> vals((size_t)ninst * nregs, 0ull);
+  std::vector<double> amps(2 * (size_t)ninst, 0.0);
+  for (uint32_t i = 0; i < ninst; ++i) amps[2 * i] = 1.0;
+  st->n = 0;
+  for (uint32_t i = 0; i < ninst; ++i) {
+    rc = ss_set_entries(st, i, vals.data() + (size_t)i * nregs, amps.data() + 2 * i, 1);
+    if (rc) {
+      ss_destroy_state(st);
+      return rc;
+    }
+  }
+  *out = st;
+  return SS_OK;
+}
+
+int ss_destroy_state(ss_state* st) {
+  if (!st) return SS_E_STATE;
+  (void)hipStreamSynchronize(st->stream);
+  if (st->hmeta) (void)hipHostFree(st->hmeta);
+  if (st->hops) (void)hipHostFree(st->hops);
+  delete st;
+  return SS_OK;
+}
+
+int ss_capacity(const ss_state* st, uint64_t* cap) {
+  if (!st || !cap) return SS_E_ARG;
+  *cap = st->cap;
+  return SS_OK;
+}
+
+int ss_layout(const ss_state* st, uint32_t reg, uint32_t* word, uint32_t* offset, uint32_t* width) {
+  if (!st || reg >= st->L.regs.size()) return SS_E_ARG;
+  if (word) *word = st->L.regs[reg].word;
+  if (offset) *offset = st->L.regs[reg].shift;
+  if (width) *width = st->L.regs[reg].width;
+  return SS_OK;
+}
+
+int ss_key_words(const ss_state* st, uint32_t* w) {
+  if (!st || !w) return SS_E_ARG;
+  *w = st->L.W;
+  return SS_OK;
+}
+
+int ss_load_qram(ss_state* st, const uint64_t* table, uint64_t len, uint32_t addr_bits, uint32_t word_bits,
+                 uint32_t* qram_id) {
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (!table || !qram_id || addr_bits > 40 || word_bits < 1 || word_bits > 64) return SS_E_QRAM;
+  if (len != (1ull << addr_bits)) return SS_E_QRAM;
+  const bool w32 = word_bits <= 32;
+  std::vector<uint32_t> t32;
+  for (uint64_t i = 0; i < len; ++i)
+    if (word_bits < 64 && (table[i] >> word_bits)) return SS_E_QRAM;
+  const uint64_t bytes = align_up(len * (w32 ? 4 : 8), kAlign);
+  if (st->tab_used + bytes > st->table_bytes) return SS_E_NOMEM;
+  void* dev = st->tab_base + st->tab_used;
+  if (w32) {
+    t32.resize(len);
+    for (uint64_t i = 0; i < len; ++i) t32[i] = (uint32_t)table[i];
+    if (hipMemcpyAsync(dev, t32.data(), len * 4, hipMemcpyHostToDevice, st->stream) != hipSuccess)
+      return hip_fail(st);
+  } else {
+    if (hipMemcpyAsync(dev, table, len * 8, hipMemcpyHostToDevice, st->stream) != hipSuccess)
+      return hip_fail(st);
+  }
+  if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
+  st->tab_used += bytes;
+  st->tables.push_back({dev, addr_bits, word_bits, w32});
+  *qram_id = (uint32_t)st->tables.size() - 1;
+  return SS_OK;
+}
+
+int ss_set_entries(ss_state* st, uint32_t inst, const uint64_t* values, const double* amps, uint64_t n) {
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (inst >= st->ninst || (n && (!values || !amps))) return SS_E_ARG;
+  // drop the instance's current entries
+  if (st->L.has_inst) {
+    FilterOp f = base_filter(st, inst);
+    f.kind = FILTER_DROP_INST;
+    rc = run_filter(st, f);
+    if (rc) return rc;
+  } else {
+    st->n = 0;
+  }
+  if (st->n + n > st->cap) return SS_E_CAPACITY;
+  const uint32_t nr = (uint32_t)st->L.regs.size();
+  PackDesc pd{};
+  pd.nregs = nr;
+  pd.has_inst = st->L.has_inst ? 1u : 0u;
+  pd.iword = st->L.iword;
+  pd.ishift = st->L.ishift;
+  pd.inst = inst;
+  for (uint32_t r = 0; r < nr; ++r) {
+    pd.word[r] = st->L.regs[r].word;
+    pd.shift[r] = st->L.regs[r].shift;
+    pd.mask[r] = st->L.regs[r].mask;
+  }
+  // stage through the alternate buffer in chunks
+  const Buf& alt = st->buf[st->cur ^ 1];
+  char* stage = reinterpret_cast<char*>(alt.key[0]);
+  const uint64_t stage_bytes = st->cap * entry_bytes(st->L.W);
+  const uint64_t per = (uint64_t)nr * 8 + 16;
+  const uint64_t chunk = std::max<uint64_t>(1, stage_bytes / per - 1);
+  uint64_t done = 0;
+  while (done < n) {
+    const uint64_t c = std::min(chunk, n - done);
+    uint64_t* dv = reinterpret_cast<uint64_t*>(stage);
+    double2* da = reinterpret_cast<double2*>(stage + align_up(c * nr * 8, 16));
+    if (hipMemcpyAsync(dv, values + done * nr, c * nr * 8, hipMemcpyHostToDevice, st->stream) != hipSuccess ||
+        hipMemcpyAsync(da, amps + 2 * done, c * 16, hipMemcpyHostToDevice, st->stream) != hipSuccess)
+      return hip_fail(st);
+    switch (st->L.W) {
+      case 1: launch_pack<1>(st, dv, da, c, st->n + done, pd); break;
+      case 2: launch_pack<2>(st, dv, da, c, st->n + done, pd); break;
+      default: launch_pack<4>(st, dv, da, c, st->n + done, pd); break;
+    }
+    rc = check_launch(st);
+    if (rc) return rc;
+    if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
+    done += c;
+  }
+  st->n += n;
+  st->peak = std::max(st->peak, st->n);
+  st->grouped = false;
+  // masks of the whole state: a no-op filter recomputes them
+  FilterOp f = base_filter(st, 0);
+  f.kind = FILTER_PRUNE;
+  f.has_inst = 1;
+  f.iword = 0;
+  f.ishift = 0;
+  f.imask = 0;
+  f.inst = 1;  // never matches: every entry passes unchanged
+  rc = run_filter(st, f);
+  if (rc) return rc;
+  return SS_OK;
+}
+
+int ss_apply_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst_offsets, ss_result* res) {
+  int rc = check_state(st);
+  if (rc) return rc;
+  ss_result local{};
+  if (!res) res = &local;
+  *res = ss_result{};
+  if (nops && !ops) return SS_E_ARG;
+  if (inst_offsets) return SS_E_ARG;  // per-instance op lists: see the batch runner
+  for (uint64_t i = 0; i < nops; ++i) {
+    rc = validate_op(st, ops[i]);
+    if (rc) {
+      res->status = rc;
+      res->failed_op = i;
+      return rc;
+    }
+  }
+  std::vector<PermOp> run;
+  uint32_t write_words = 0;
+  bool amp = false;
+  for (uint64_t i = 0; i < nops; ++i) {
+    const ss_op& op = ops[i];
+    st->stats[7] += st->n;
+    if (is_branching(op.kind)) {
+      rc = flush_run(st, run, write_words, amp);
+      write_words = 0;
+      amp = false;
+      if (!rc) rc = do_branching(st, op);
+      if (rc) {
+        res->status = rc;
+        res->failed_op = i;
+        res->nnz = st->n;
+        res->peak = st->peak;
+        return rc;
+      }
+    } else {
+      if (st->grouped && !keeps_grouping(st, op, st->gmask)) st->grouped = false;
+      PermOp p = to_perm(st, op);
+      if (op.kind == SS_REFLECT0) amp = true;
+      else write_words |= 1u << p.dst_word;
+      run.push_back(p);
+    }
+  }
+  rc = flush_run(st, run, write_words, amp);
+  if (!rc) rc = ensure_masks(st);
+  if (!rc && (st->hmeta->err & (kErrSpin | kErrGroup))) rc = hip_fail(st);
+  res->status = rc;
+  res->nnz = st->n;
+  res->peak = st->peak;
+  return rc;
+}
+
+int ss_prune(ss_state* st, double eps) {
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (!(eps >= 0.0)) return SS_E_ARG;
+  FilterOp f = base_filter(st, 0);
+  f.has_inst = 0;
+  f.kind = FILTER_PRUNE;
+  f.eps2 = eps * eps;
+  return run_filter(st, f);
+}
+
+int ss_nnz(ss_state* st, uint32_t inst, uint64_t* nnz, uint64_t* peak) {
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (peak) *peak = st->peak;
+  if (!nnz) return SS_OK;
+  if (inst == UINT32_MAX || !st->L.has_inst) {
+    *nnz = st->n;
+    return SS_OK;
+  }
+  if (inst >= st->ninst) return SS_E_ARG;
+  // count by sorting on the instance field and reading two bounds
+  uint64_t lo = 0, hi = 0;
+  if (st->n) {
+    rc = sort_canonical(st);
+    if (rc) return rc;
+    const uint32_t W = st->L.W;
+    k_fill_u64<<<1, 256, 0, st->stream>>>(st->uscr, st->ninst + 1, st->n);
+    const uint32_t g = (uint32_t)((st->n + 255) / 256);
+    const Buf& b = st->buf[st->cur];
+    if (W == 1) k_inst_bounds<1><<<g, 256, 0, st->stream>>>(kp<1>(b), st->n, st->L.iword, st->L.ishift, st->L.imask, st->uscr, st->ninst);
+    else if (W == 2) k_inst_bounds<2><<<g, 256, 0, st->stream>>>(kp<2>(b), st->n, st->L.iword, st->L.ishift, st->L.imask, st->uscr, st->ninst);
+    else k_inst_bounds<4><<<g, 256, 0, st->stream>>>(kp<4>(b), st->n, st->L.iword, st->L.ishift, st->L.imask, st->uscr, st->ninst);
+    rc = check_launch(st);
+    if (rc) return rc;
+    uint64_t bnd[2];
+    if (hipMemcpyAsync(bnd, st->uscr + inst, 16, hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
+        hipStreamSynchronize(st->stream) != hipSuccess)
+      return hip_fail(st);
+    lo = bnd[0];
+    hi = bnd[1];
+    if (lo > hi || hi > st->n) return hip_fail(st);
+  }
+  *nnz = hi - lo;
+  return SS_OK;
+}
+
+int ss_export(ss_state* st, uint32_t inst, uint64_t* keys, double* amps, uint64_t cap, uint64_t* n_out) {
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (inst >= st->ninst || !n_out || (cap && (!keys || !amps))) return SS_E_ARG;
+  *n_out = 0;
+  if (st->n == 0) return SS_OK;
+  rc = sort_canonical(st);
+  if (rc) return rc;
+  const uint32_t W = st->L.W;
+  uint64_t lo = 0, hi = st->n;
+  const Buf& b = st->buf[st->cur];
+  if (st->L.has_inst) {
+    k_fill_u64<<<1, 256, 0, st->stream>>>(st->uscr, st->ninst + 1, st->n);
+    const uint32_t g = (uint32_t)((st->n + 255) / 256);
+    if (W == 1) k_inst_bounds<1><<<g, 256, 0, st->stream>>>(kp<1>(b), st->n, st->L.iword, st->L.ishift, st->L.imask, st->uscr, st->ninst);
+    else if (W == 2) k_inst_bounds<2><<<g, 256, 0, st->stream>>>(kp<2>(b), st->n, st->L.iword, st->L.ishift, st->L.imask, st->uscr, st->ninst);
+    else k_inst_bounds<4><<<g, 256, 0, st->stream>>>(kp<4>(b), st->n, st->L.iword, st->L.ishift, st->L.imask, st->uscr, st->ninst);
+    rc = check_launch(st);
+    if (rc) return rc;
+    uint64_t bnd[2];
+    if (hipMemcpyAsync(bnd, st->uscr + inst, 16, hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
+        hipStreamSynchronize(st->stream) != hipSuccess)
+      return hip_fail(st);
+    lo = bnd[0];
+    hi = bnd[1];
+    if (lo > hi || hi > st->n) return hip_fail(st);
+  }
+  const uint64_t cnt = hi - lo;
+  *n_out = cnt;
+  const uint64_t m = std::min(cnt, cap);
+  if (m == 0) return SS_OK;
+  const Buf& alt = st->buf[st->cur ^ 1];
+  uint64_t* ok = alt.key[0];
+  double2* oa = alt.amp;
+  const uint64_t iclear = st->L.has_inst ? (st->L.imask << st->L.ishift) : 0ull;
+  const uint32_t iword = st->L.has_inst ? st->L.iword : 99u;
+  const uint32_t g = (uint32_t)((m + 255) / 256);
+  if (W == 1) k_export<1><<<g, 256, 0, st->stream>>>(kp<1>(b), b.amp, lo, lo + m, ok, oa, iword, iclear);
+  else if (W == 2) k_export<2><<<g, 256, 0, st->stream>>>(kp<2>(b), b.amp, lo, lo + m, ok, oa, iword, iclear);
+  else k_export<4><<<g, 256, 0, st->stream>>>(kp<4>(b), b.amp, lo, lo + m, ok, oa, iword, iclear);
+  rc = check_launch(st);
+  if (rc) return rc;
+  if (hipMemcpyAsync(keys, ok, m * W * 8, hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
+      hipMemcpyAsync(amps, oa, m * 16, hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
+      hipStreamSynchronize(st->stream) != hipSuccess)
+    return hip_fail(st);
+  return SS_OK;
+}
+
+int ss_measure(ss_state* st, uint32_t inst, uint32_t reg, double u, uint64_t* outcome, double* prob) {
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (inst >= st->ninst || reg >= st->L.regs.size() || !(u >= 0.0 && u < 1.0) || !outcome || !prob)
+    return SS_E_ARG;
+  if (st->n == 0) return SS_E_ARG;
+  rc = ensure_masks(st);
+  if (rc) return rc;
+  const RegInfo& r = st->L.regs[reg];
+  const uint32_t W = st->L.W;
+  // sort by (instance, field) so the running sum visits field values in ascending order
+  uint64_t var[kMaxW] = {0, 0, 0, 0}, skip[kMaxW] = {0, 0, 0, 0};
+  var[r.word] |= (r.mask << r.shift) & (st->orm[r.word] & ~st->andm[r.word]);
+  std::vector<std::pair<uint32_t, uint32_t>> low;
+  for (uint32_t b = 0; b < 64; ++b)
+    if ((var[r.word] >> b) & 1ull) low.push_back({r.word, b});
+  uint64_t ivar[kMaxW] = {0, 0, 0, 0};
+  if (st->L.has_inst) ivar[st->L.iword] = (st->L.imask << st->L.ishift) & (st->orm[st->L.iword] & ~st->andm[st->L.iword]);
+  SortPlan plan;
+  build_plan(W, low, skip, ivar, plan);
+  rc = run_sort(st, plan);
+  if (rc) return rc;
+  FilterOp f = base_filter(st, inst);
+  f.fword = r.word;
+  f.fshift = r.shift;
+  f.fmask = r.mask;
+  const Buf& b = st->buf[st->cur];
+  const Buf& alt = st->buf[st->cur ^ 1];
+  const uint64_t n = st->n;
+  const uint32_t ntiles = (uint32_t)((n + kBlock - 1) / kBlock);
+  double* tile_sum = reinterpret_cast<double*>(alt.amp);
+  double* incl = tile_sum + align_up(ntiles, 64);
+  double* dtot = st->meta->dscratch;
+  unsigned long long* out = reinterpret_cast<unsigned long long*>(st->uscr);
+  auto tiles = [&](const FilterOp& fo) {
+    if (W == 1) k_prob_tiles<1><<<ntiles, kBlock, 0, st->stream>>>(kp<1>(b), b.amp, n, fo, tile_sum);
+    else if (W == 2) k_prob_tiles<2><<<ntiles, kBlock, 0, st->stream>>>(kp<2>(b), b.amp, n, fo, tile_sum);
+    else k_prob_tiles<4><<<ntiles, kBlock, 0, st->stream>>>(kp<4>(b), b.amp, n, fo, tile_sum);
+  };
+  f.use_f = 0;
+  tiles(f);
+  k_prob_scan<<<1, 64, 0, st->stream>>>(tile_sum, ntiles, dtot);
+  k_fill_u64<<<1, 64, 0, st->stream>>>(st->uscr, 1, ~0ull);
+  k_fill_u64<<<1, 64, 0, st->stream>>>(st->uscr + 1, 3, 0ull);
+  if (W == 1) k_prob_find<1><<<ntiles, kBlock, 0, st->stream>>>(kp<1>(b), b.amp, n, f, tile_sum, dtot, u, incl, out);
+  else if (W == 2) k_prob_find<2><<<ntiles, kBlock, 0, st->stream>>>(kp<2>(b), b.amp, n, f, tile_sum, dtot, u, incl, out);
+  else k_prob_find<4><<<ntiles, kBlock, 0, st->stream>>>(kp<4>(b), b.amp, n, f, tile_sum, dtot, u, incl, out);
+  rc = check_launch(st);
+  if (rc) return rc;
+  unsigned long long hout[4];
+  double P = 0.0;
+  if (hipMemcpyAsync(hout, out, 32, hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
+      hipMemcpyAsync(&P, dtot, 8, hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
+      hipStreamSynchronize(st->stream) != hipSuccess)
+    return hip_fail(st);
+  if (!(P > 0.0)) return SS_E_ARG;  // the instance holds no entries
+  uint64_t v;
+  if (hout[0] != ~0ull) {
+    v = hout[1];
+  } else {
+    // u*P at or beyond the total (rounding): the largest field value present
+    v = hout[2];
+  }
+  f.use_f = 1;
+  f.fval = v;
+  tiles(f);
+  k_prob_scan<<<1, 64, 0, st->stream>>>(tile_sum, ntiles, dtot + 1);
+  double pv = 0.0;
+  if (hipMemcpyAsync(&pv, dtot + 1, 8, hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
+      hipStreamSynchronize(st->stream) != hipSuccess)
+    return hip_fail(st);
+  FilterOp c = f;
+  c.kind = FILTER_COLLAPSE;
+  c.scale = std::sqrt(pv);
+  rc = run_filter(st, c);
+  if (rc) return rc;
+  st->grouped = false;
+  *outcome = v;
+  *prob = pv / P;
+  return SS_OK;
+}
+
+int ss_sync(ss_state* st, ss_result* res) {
+  if (!st) return SS_E_STATE;
+  int rc = st->poisoned ? SS_E_STATE : readback(st);
+  if (!rc && (st->hmeta->err & (kErrSpin | kErrGroup))) rc = hip_fail(st);
+  if (res) {
+    res->status = rc;
+    res->nnz = st->n;
+    res->peak = st->peak;
+  }
+  return rc;
+}
+
+int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes) {
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (!arena || ((uintptr_t)arena % kAlign)) return SS_E_ARG;
+  if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
+  ss_state old = *st;
+  rc = setup_arena(st, static_cast<char*>(arena), arena_bytes);
+  if (rc || st->cap < old.n || st->table_bytes < old.tab_used) {
+    // restore the old carve
+    st->cap = old.cap;
+    st->cv = old.cv;
+    st->arena = old.arena;
+    st->arena_bytes = old.arena_bytes;
+    st->meta = old.meta;
+    st->digit_start = old.digit_start;
+    st->dev_ops = old.dev_ops;
+    st->uscr = old.uscr;
+    st->hist = old.hist;
+    st->tab_base = old.tab_base;
+    st->lb = old.lb;
+    st->buf[0] = old.buf[0];
+    st->buf[1] = old.buf[1];
+    return rc ? rc : SS_E_NOMEM;
+  }
+  st->cur = 0;
+  const uint32_t W = st->L.W;
+  const Buf& src = old.buf[old.cur];
+  for (uint32_t w = 0; w < W; ++w)
+    if (old.n && hipMemcpyAsync(st->buf[0].key[w], src.key[w], old.n * 8, hipMemcpyDeviceToDevice, st->stream) != hipSuccess)
+      return hip_fail(st);
+  if (old.n && hipMemcpyAsync(st->buf[0].amp, src.amp, old.n * 16, hipMemcpyDeviceToDevice, st->stream) != hipSuccess)
+    return hip_fail(st);
+  if (old.tab_used && hipMemcpyAsync(st->tab_base, old.tab_base, old.tab_used, hipMemcpyDeviceToDevice, st->stream) != hipSuccess)
+    return hip_fail(st);
+  for (auto& t : st->tables) t.dev = st->tab_base + (static_cast<char*>(t.dev) - old.tab_base);
+  rc = init_device(st);
+  if (rc) return rc;
+  if (hipMemcpyAsync(&st->meta->peak, &old.peak, 8, hipMemcpyHostToDevice, st->stream) != hipSuccess ||
+      hipStreamSynchronize(st->stream) != hipSuccess)
+    return hip_fail(st);
+  st->epoch = 0;
+  return SS_OK;
+}
+
+int ss_set_option(ss_state* st, const char* key, int64_t value) {
+  if (!st || !key) return SS_E_ARG;
+  const std::string k(key);
+  if (k == "sort_items") {
+    if (value != 8 && value != 16) return SS_E_ARG;
+    st->sort_items = (int)value;
+  } else if (k == "grouping") {
+    st->grouping = value ? 1 : 0;
+  } else {
+    return SS_E_ARG;
+  }
+  return SS_OK;
+}
+
+int ss_stats(const ss_state* st, uint64_t* out8) {
+  if (!st || !out8) return SS_E_ARG;
+  for (int i = 0; i < 8; ++i) out8[i] = st->stats[i];
+  return SS_OK;
+}
+
+}  // extern "C"

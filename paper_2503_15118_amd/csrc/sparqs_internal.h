@@ -1,0 +1,108 @@
+// Internal structures shared by the host planner and the gfx950 kernels of
+// the sparse register-level simulator.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sparqs {
+
+constexpr int kMaxW = 4;            // 64-bit key words per entry (up to 256 key bits)
+constexpr int kBlock = 256;         // threads per workgroup (4 wave64)
+constexpr int kRadixBits = 8;       // digit width of one radix-sort pass
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kMaxFields = 8;       // contiguous bit runs that make up one digit
+constexpr int kMaxPasses = 40;      // up to 256 key bits + 5 target bits, 8 bits per pass
+constexpr int kMaxGroupBits = 5;    // targets fused into one interference op (2^5 group)
+constexpr int kRing = 16;           // per-launch slots (tile counter, count, key masks)
+
+// Lookback words: [epoch:24 | flag:2 | value:38].
+constexpr uint64_t kLbValueBits = 38;
+constexpr uint64_t kLbValueMask = (1ull << kLbValueBits) - 1;
+constexpr uint64_t kLbAgg = 1ull << kLbValueBits;
+constexpr uint64_t kLbInc = 2ull << kLbValueBits;
+constexpr uint64_t kLbFlagMask = 3ull << kLbValueBits;
+constexpr int kLbEpochShift = 40;
+constexpr uint32_t kEpochMask = (1u << 24) - 1;
+
+// Error bits raised by kernels (meta->err).
+constexpr uint32_t kErrCapacity = 1u << 0;   // outputs would exceed the buffer capacity
+constexpr uint32_t kErrSpin = 1u << 1;       // a lookback wait exceeded its bound
+constexpr uint32_t kErrGroup = 1u << 2;      // two group members share a target value
+constexpr uint32_t kErrCollision = 1u << 3;  // reserved: duplicate key detected
+
+// Device-side bookkeeping.  Every kernel launch that counts tiles, produces an
+// entry count or key masks owns ring slot (epoch % kRing); the first
+// workgroup of launch e clears slot (e + kRing/2) % kRing for a later launch.
+struct DevMeta {
+  unsigned long long counters[kRing];        // dynamic tile ids
+  unsigned long long nnz_out[kRing];         // entry count written by an emitting kernel
+  unsigned long long or_mask[kRing][kMaxW];  // OR of the produced keys, per word
+  unsigned long long and_mask[kRing][kMaxW]; // AND of the produced keys, per word
+  unsigned long long peak;                   // running maximum of nnz
+  unsigned int err;                          // kErr* bits, sticky until the host clears them
+  unsigned int pad;
+  double dscratch[16];
+  unsigned long long uscratch[16];
+};
+
+// A run of non-branching ops is executed from an array of these (uniform per op).
+// Field positions are precomputed on the host; `dst_*` is the written register,
+// `src_*` the read register (ADD/SUB/XOR source, QRAM address).
+enum PermKind : uint32_t {
+  PK_XMASK = 0,     // key[w] ^= imm (the qubit mask, shifted) on dst word
+  PK_ADD = 1,
+  PK_SUB = 2,
+  PK_MULC = 3,
+  PK_XOR = 4,
+  PK_XORC = 5,      // same as XMASK but kept distinct for statistics
+  PK_QRAM = 6,
+  PK_REFLECT0 = 7,
+};
+
+struct PermOp {
+  uint32_t kind;
+  uint32_t nctl_words;          // 0: uncontrolled
+  uint32_t dst_word, dst_shift;
+  uint32_t src_word, src_shift;
+  uint32_t table_words32;       // 1 if the QRAM table is stored as uint32
+  uint32_t pad;
+  uint64_t dst_mask;            // (1 << width) - 1, unshifted
+  uint64_t src_mask;
+  uint64_t imm;                 // X mask / XOR constant / multiplier (already shifted for X)
+  const void* table;            // QRAM words
+  uint64_t cmask[kMaxW];        // control bits per word
+  uint64_t cval[kMaxW];         // required values of those bits
+};
+
+// One branching (interference) op as seen by the group/expand kernel.
+struct GroupOp {
+  uint32_t k;                   // number of target qubits (1..kMaxGroupBits); 0 = plain filter
+  uint32_t has_ctl;
+  uint32_t tword[kMaxGroupBits];  // target j: key word and bit, ascending qubit order
+  uint32_t tbit[kMaxGroupBits];
+  uint64_t tmask[kMaxW];        // all target bits per word
+  uint64_t cmask[kMaxW];
+  uint64_t cval[kMaxW];
+  double m[2][2];               // real matrix, m[out][in]
+  double eps2;                  // prune below this |a|^2 (strict)
+};
+
+// A digit of one radix pass = sum of up to kMaxFields bit runs of the key:
+//   digit |= ((key[word] >> shift) & ((1 << width) - 1)) << dshift
+struct PassDesc {
+  uint32_t nf;
+  uint32_t f[kMaxFields];       // word:2 | shift:6 | width:4 | dshift:4  (packed)
+};
+
+__host__ __device__ inline uint32_t pack_field(uint32_t word, uint32_t shift, uint32_t width,
+                                               uint32_t dshift) {
+  return word | (shift << 2) | (width << 8) | (dshift << 12);
+}
+
+struct SortPlan {
+  uint32_t npass;
+  PassDesc pass[kMaxPasses];
+};
+
+}  // namespace sparqs

@@ -1,0 +1,245 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Keys outside the band |a| <= eps + 1e-9 must match word for word; shared keys
+within 1e-12 (complex modulus); export must be strictly ascending.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle.oracle import OracleState, run_circuit
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+
+C = 0.70710678118654752440
+
+
+@pytest.fixture(scope="module")
+def abi():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2503_15118_amd import _abi
+    return _abi
+
+
+def _gpu(abi, c, cap=None, opts=None, ops=None):
+    st = abi.state_for_circuit(c, cap_entries=cap)
+    for k, v in (opts or {}).items():
+        st.set_option(k, v)
+    st.apply(c.ops if ops is None else ops)
+    return st
+
+
+def _check(abi, c, cap=None, opts=None, atol=1e-12):
+    print(f"[case] {c.name} nops={len(c.ops)} opts={opts}", flush=True)
+    st = _gpu(abi, c, cap, opts)
+    gk, ga = st.export()
+    ora, _, _ = run_circuit(c)
+    ok, _, oa = ora.export()
+    s = compare(gk, ga, ok, oa, c.eps, atol=atol)
+    assert st.nnz() == len(gk)
+    st.close()
+    return s
+
+
+def test_permutation_only_bit_exact(abi):
+    """Minimum slice: non-branching ops on an imported superposition are
+    bit-exact in keys and amplitudes."""
+    kinds = ("X", "ADD", "SUB", "MULC", "XOR", "XORC", "QRAM_LOAD", "QRAM_UNLOAD", "REFLECT0")
+    for seed in range(4):
+        c = wl.random_small_circuit(seed, kinds=kinds, nops=80, with_init=True)
+        s = _check(abi, c)
+        assert s["bit_exact"] == s["shared"] == s["n_oracle"]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_small_circuits_all_kinds(abi, seed):
+    c = wl.random_small_circuit(seed, with_init=bool(seed % 2), eps=(0.0 if seed % 4 == 3 else 1e-14))
+    _check(abi, c)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_c1_form(abi, seed):
+    c = wl.c1_circuit(seed)
+    s = _check(abi, c)
+    assert s["n_oracle"] > 1
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_c1_form_always_sort(abi, seed):
+    """The plain method (sort before every interference op) gives the same state."""
+    c = wl.c1_circuit(100 + seed)
+    _check(abi, c, opts={"grouping": 0})
+    _check(abi, c, opts={"grouping": 0, "sort_items": 8})
+
+
+@pytest.mark.parametrize("nq", [23, 40, 255])
+def test_ghz_two_branches(abi, nq):
+    c = wl.ghz_circuit(nq)
+    st = _gpu(abi, c)
+    k, a = st.export()
+    assert len(k) == 2
+    assert np.all(a == C)
+    _check(abi, c)
+
+
+@pytest.mark.parametrize("ab,wb", [(4, 6), (10, 10), (12, 32)])
+def test_qram_closed_form(abi, ab, wb):
+    c = wl.qram_circuit(ab, ab, wb)
+    _check(abi, c)
+    st = _gpu(abi, c)
+    k, a = st.export()
+    assert len(k) == 2 ** ab
+    expect = 1.0
+    for _ in range(ab):
+        expect = C * expect
+    assert np.all(a == expect)
+
+
+def test_c2_form_small(abi):
+    c = wl.c2_circuit(3, nops=300, n_ry=5, h_qubits=10)
+    _check(abi, c)
+    _check(abi, c, opts={"grouping": 0})
+
+
+def test_c4_form_batched_instances(abi):
+    circ = wl.c4_batch(2, nrhs=4, steps=4, n=64)
+    c0 = circ[0]
+    st = abi.State(c0.regs, ninst=len(circ), eps=c0.eps, cap_entries=1 << 14, table_bytes=1 << 16)
+    st.load_qram(c0.tables[0])
+    for i, c in enumerate(circ):
+        st.set_entries(i, c.init_values, c.init_amps)
+    st.apply(c0.ops)
+    for i, c in enumerate(circ):
+        gk, ga = st.export(i)
+        ora, _, _ = run_circuit(c)
+        ok, _, oa = ora.export()
+        compare(gk, ga, ok, oa, c.eps)
+    st.close()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_measure_matches_oracle(abi, seed):
+    c = wl.random_small_circuit(seed, nops=30, with_init=True)
+    reg = seed % len(c.regs)
+    u = [0.13, 0.37, 0.61, 0.89][seed]
+    st = _gpu(abi, c)
+    ora, _, _ = run_circuit(c)
+    v_g, p_g = st.measure(0, reg, u)
+    v_o, p_o = ora.measure(reg, u)
+    assert v_g == v_o
+    assert abs(p_g - p_o) < 1e-12
+    gk, ga = st.export()
+    ok, _, oa = ora.export()
+    compare(gk, ga, ok, oa, c.eps)
+
+
+def test_prune_matches_oracle(abi):
+    c = wl.random_small_circuit(5, nops=40, with_init=True, eps=0.0)
+    st = _gpu(abi, c)
+    ora, _, _ = run_circuit(c)
+    for eps in (1e-3, 1e-2, 0.05):
+        st.prune(eps)
+        ora.prune(eps)
+        gk, ga = st.export()
+        ok, _, oa = ora.export()
+        compare(gk, ga, ok, oa, eps)
+
+
+def test_empty_state_and_noop(abi):
+    c = wl.random_small_circuit(7, nops=20, with_init=True)
+    st = _gpu(abi, c)
+    st.prune(10.0)
+    assert st.nnz() == 0
+    st.apply(c.ops)
+    assert st.nnz() == 0
+    k, a = st.export()
+    assert len(k) == 0
+
+
+def test_capacity_error_rolls_back(abi):
+    """An op whose survivors exceed the capacity fails with SS_E_CAPACITY and
+    leaves the state as it was after the ops before it."""
+    c = wl.c2_circuit(1, nops=10, n_ry=1, h_qubits=12)
+    st = abi.State(c.regs, eps=c.eps, cap_entries=4096, table_bytes=0)
+    assert 4096 <= st.capacity < 8192
+    res = st.apply(c.ops, raise_on_error=False)
+    assert res.status == abi.SS_E_CAPACITY
+    assert wl.KINDS[int(c.ops[res.failed_op]["kind"])] == "RY"
+    gk, ga = st.export()
+    ora, _, _ = run_circuit(c, ops=c.ops[:res.failed_op])
+    ok, _, oa = ora.export()
+    s = compare(gk, ga, ok, oa, c.eps)
+    assert s["n_gpu"] == 4096
+    # an op split over several launches is refused before it starts
+    st2 = abi.State(c.regs, eps=c.eps, cap_entries=4096, table_bytes=0)
+    res = st2.apply(wl.ops_array([wl.make_op("H", 0, qmask=(1 << 14) - 1)]), raise_on_error=False)
+    assert res.status == abi.SS_E_CAPACITY and res.failed_op == 0
+    k, a = st2.export()
+    assert len(k) == 1 and a[0] == 1.0
+
+
+def test_deterministic_reruns(abi):
+    c = wl.c1_circuit(9)
+    k1, a1 = _gpu(abi, c).export()
+    k2, a2 = _gpu(abi, c).export()
+    assert np.array_equal(k1, k2)
+    assert np.array_equal(a1.view(np.uint64), a2.view(np.uint64))
+
+
+def test_invalid_ops_rejected(abi):
+    st = abi.State([("a", 4), ("b", 4)], cap_entries=1024)
+    bad = [
+        wl.make_op("X", 0, qmask=1 << 5),                      # qubit outside the register
+        wl.make_op("ADD", 0, reg2=0),                          # dst == src
+        wl.make_op("MULC", 0, imm=4),                          # even multiplier
+        wl.make_op("X", 0, qmask=1, ctls=[(0, 0, 1)]),         # control on the target
+        wl.make_op("ADD", 0, reg2=1, ctls=[(0, 2, 1)]),        # control inside dst
+    ]
+    codes = [abi.SS_E_ARG, abi.SS_E_ARG, abi.SS_E_NOT_UNITARY, abi.SS_E_ARG, abi.SS_E_ARG]
+    for op, code in zip(bad, codes):
+        res = st.apply(wl.ops_array([op]), raise_on_error=False)
+        assert res.status == code
+    assert st.nnz() == 1
+
+
+def _c2_sample_check(abi, c, st, nsamp=48, seed=0):
+    """Sampled parity at full size: the oracle evolves single trajectories
+    (each C2-form branch only ever meets its flag partner)."""
+    gk, ga = st.export()
+    hop = c.ops[:1]
+    ora0 = OracleState(c.regs, c.eps)
+    ora0.apply(hop)
+    _, v0, a0 = ora0.export()
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(len(v0), size=nsamp, replace=False)
+    w1 = gk[:, 1]
+    checked = 0
+    for i in idx:
+        o = OracleState(c.regs, c.eps, init_values=v0[i:i + 1], init_amps=a0[i:i + 1])
+        o.apply(c.ops[1:])
+        ok, _, oa = o.export()
+        for key, amp in zip(ok, oa):
+            lo = np.searchsorted(w1, key[1], side="left")
+            hi = np.searchsorted(w1, key[1], side="right")
+            j = lo + np.searchsorted(gk[lo:hi, 0], key[0])
+            assert j < hi and gk[j, 0] == key[0] and gk[j, 1] == key[1], "sampled key missing on GPU"
+            assert abs(ga[j] - amp) <= 1e-12
+            checked += 1
+    return checked
+
+
+@pytest.mark.slow
+def test_c2_full_size_sampled(abi):
+    """C2 at its full size (2^20 -> 2^21 entries, 1000 ops) in the benchmark's
+    launch configuration: nnz exact, norm 1, sampled trajectories vs oracle."""
+    c = wl.c2_circuit(0)
+    print(f"[case] {c.name} full size", flush=True)
+    st = abi.state_for_circuit(c, cap_entries=1 << 22)
+    st.apply(c.ops)
+    assert st.nnz() == 2 ** 21
+    gk, ga = st.export()
+    norm = float(np.sum(ga.real ** 2 + ga.imag ** 2))
+    assert abs(norm - 1.0) < 1e-10
+    assert _c2_sample_check(abi, c, st) >= 48
