@@ -1,0 +1,159 @@
+"""Benchmark: the sparse simulator hot path on one MI355X.
+
+Workload (one "step"): the arithmetic-heavy sparse circuit -- registers a, b,
+c of 32 qubits and a 1-qubit flag (97-bit key in two 64-bit words), H on 20
+seeded qubits of a (2^20 branches), then 1000 seeded ops: register add/sub
+mod 2^32, multiply by odd constants, XOR (register or constant), CNOT,
+Toffoli and 10 Ry on the flag (2^21 branches from the first one).  Each step
+resets the state to |0> and runs the whole op list through the C ABI.
+
+value = sparse entries updated per second = (sum over ops of the entry count
+the op reads) / wall time of the timed steps.  The dominant kernel's achieved
+bandwidth comes from HIP events recorded around every launch on the state's
+stream during the timed steps.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published peak
+
+
+def cpu_baseline(circ, nops_sample):
+    """The oracle (std::map, one core) on a bounded sample of the same circuit:
+    the H prelude and the first `nops_sample` ops after it."""
+    from oracle.oracle import OracleState
+    o = OracleState(circ.regs, circ.eps)
+    s0, e0 = o.apply(circ.ops[:1])
+    s1, e1 = o.apply(circ.ops[1:1 + nops_sample])
+    sec, ent = s0 + s1, e0 + e1
+    return {"value": ent / sec, "unit": "entries/s", "cores": 1, "kind": "oracle",
+            "sample": f"prelude H on 20 qubits + first {nops_sample} ops of the same circuit "
+                      f"({ent} entry updates in {sec:.1f} s, std::map oracle, one thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-ops", type=int, default=16)
+    ap.add_argument("--grouping", type=int, default=1, help="0: sort before every interference op")
+    ap.add_argument("--group-items", type=int, default=4)
+    ap.add_argument("--sort-items", type=int, default=16)
+    ap.add_argument("--perm-entries", type=int, default=8)
+    ap.add_argument("--tile-order", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding is a design note, not an implemented path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2503_15118_amd import _abi
+
+    circ = wl.c2_circuit(args.seed)
+    ops = _abi.to_ss_ops(circ.ops)
+    st = _abi.State(circ.regs, eps=circ.eps, cap_entries=1 << 22, table_bytes=0)
+    st.set_option("grouping", args.grouping)
+    st.set_option("group_items", args.group_items)
+    st.set_option("sort_items", args.sort_items)
+    st.set_option("perm_entries", args.perm_entries)
+    st.set_option("tile_order", args.tile_order)
+    zero = np.zeros((1, len(circ.regs)), dtype=np.uint64)
+    one = np.array([1.0 + 0j])
+
+    def step():
+        st.set_entries(0, zero, one)
+        st.apply(ops)
+
+    for _ in range(args.warmup):
+        step()
+    s0 = st.stats()["entries_updated"]
+    step()
+    entries_per_step = st.stats()["entries_updated"] - s0
+    nnz_final = st.nnz()
+
+    st.set_option("trace", 1)
+    st.set_option("trace_reset", 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tr = st.trace()
+    st.set_option("trace", 0)
+
+    elapsed = t1 - t0
+    value = entries_per_step * args.steps / elapsed
+    kernels = {}
+    for name, r in tr.items():
+        if r["launches"] == 0:
+            continue
+        kernels[name] = {"launches_per_step": r["launches"] / args.steps,
+                         "avg_us": 1e6 * r["seconds"] / r["launches"],
+                         "ms_per_step": 1e3 * r["seconds"] / args.steps,
+                         "GBps": r["bytes"] / r["seconds"] / 1e9 if r["seconds"] > 0 else None}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    d = tr[dom]
+    achieved = d["bytes"] / d["seconds"] / 1e9
+    gpu_kernel_ms = sum(k["ms_per_step"] for k in kernels.values())
+
+    out = {
+        "metric": "sparse entries updated/s + HBM GB/s; batched-vs-plain speedup; p99 latency",
+        "value": value,
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "arithmetic-heavy sparse circuit: registers a,b,c (32 qubits) + flag, 97-bit key "
+                        "in 2 words; H on 20 qubits of a, then 1000 ops (add/sub/mulc/xor/CNOT/Toffoli, "
+                        "10 Ry on flag); nnz 2^20 -> 2^21; complex128; seed %d" % args.seed,
+            "nnz_final": nnz_final,
+            "ops": int(len(ops)),
+            "entries_per_step": int(entries_per_step),
+            "grouping": args.grouping,
+            "group_items": args.group_items,
+            "sort_items": args.sort_items,
+            "perm_entries": args.perm_entries,
+            "tile_order": args.tile_order,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+        "hbm_gbps": achieved,
+        "gpu_kernel_ms_per_step": gpu_kernel_ms,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(circ, args.cpu_ops)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -177,13 +177,38 @@ int ss_sync(ss_state* st, ss_result* res);
 int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
 
 /* Tuning/debug knobs: "sort_items" (8|16), "grouping" (1: reuse grouped
- * order across ops, 0: always sort), "trace" (1: per-op timing records). */
+ * order across ops, 0: always sort), "trace" (1: time every kernel launch
+ * with a HIP event pair on the state's stream), "trace_reset". */
 int ss_set_option(ss_state* st, const char* key, int64_t value);
+
+/* Kernel categories of the trace. */
+enum ss_trace_cat {
+  SS_TRACE_PERM = 0,       /* fused non-branching run */
+  SS_TRACE_SORT_HIST = 1,  /* radix-sort digit histograms (all passes) */
+  SS_TRACE_SORT_PASS = 2,  /* one LSD scatter pass */
+  SS_TRACE_GROUP = 3,      /* interference op on grouped entries */
+  SS_TRACE_EXPAND = 4,     /* interference op where every group has one member */
+  SS_TRACE_FILTER = 5,     /* prune / collapse compaction */
+  SS_TRACE_NCAT = 6
+};
+
+/* Totals of the traced launches of one category since the last
+ * "trace_reset": launch count, summed event durations (s), algorithmic bytes
+ * (entries read and written at 8W+16 bytes each; a permutation run reads W
+ * words and writes the touched ones, plus 32 bytes when it has a phase op)
+ * and entries processed.  Blocks until pending events have completed. */
+int ss_trace_read(ss_state* st, uint32_t cat, uint64_t* launches, double* seconds, uint64_t* bytes,
+                  uint64_t* entries);
 
 /* Counters since creation: [0] kernels launched, [1] sort passes, [2] sorts,
  * [3] group launches, [4] expand launches, [5] permutation runs, [6] host
  * syncs, [7] entries updated (sum over ops of input nnz). */
 int ss_stats(const ss_state* st, uint64_t* out8);
+
+/* Kernel-side error bits seen so far (diagnostics after SS_E_HIP): 1 = a
+ * branching op's survivors exceeded the capacity, 2 = a tile wait gave up,
+ * 4 = two entries of one group shared a target value. */
+int ss_device_error(const ss_state* st, uint32_t* bits);
 
 const char* ss_strerror(int code);
 

@@ -75,6 +75,8 @@ def _load():
         "ss_rebind_arena": [vp, vp, ctypes.c_size_t],
         "ss_set_option": [vp, ctypes.c_char_p, i64],
         "ss_stats": [vp, P(u64)],
+        "ss_trace_read": [vp, u32, P(u64), P(f64), P(u64), P(u64)],
+        "ss_device_error": [vp, P(u32)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -90,7 +92,9 @@ lib = _load()
 EXPORTED = ("ss_required_bytes", "ss_create_state", "ss_destroy_state", "ss_capacity", "ss_layout",
             "ss_key_words", "ss_load_qram", "ss_set_entries", "ss_apply_ops", "ss_prune", "ss_measure",
             "ss_nnz", "ss_export", "ss_sync", "ss_rebind_arena", "ss_set_option", "ss_stats",
-            "ss_strerror")
+            "ss_trace_read", "ss_device_error", "ss_strerror")
+
+TRACE_CATS = ("perm", "sort_hist", "sort_pass", "group", "expand", "filter")
 
 
 def strerror(code: int) -> str:
@@ -214,7 +218,9 @@ class State:
         res = _Result()
         rc = lib.ss_apply_ops(self.h, ctypes.c_void_p(rec.ctypes.data), len(rec), None, ctypes.byref(res))
         if rc != SS_OK and raise_on_error:
-            raise SSError(rc, f"ss_apply_ops (op {res.failed_op})")
+            bits = ctypes.c_uint32(0)
+            lib.ss_device_error(self.h, ctypes.byref(bits))
+            raise SSError(rc, f"ss_apply_ops (op {res.failed_op}, device error bits {bits.value})")
         res.status = rc
         return res
 
@@ -258,6 +264,18 @@ class State:
 
     def set_option(self, key: str, value: int):
         _check(lib.ss_set_option(self.h, key.encode(), int(value)), "ss_set_option")
+
+    def trace(self) -> dict:
+        """Per kernel category: launches, seconds (HIP events), algorithmic bytes, entries."""
+        out = {}
+        for i, name in enumerate(TRACE_CATS):
+            n, b, e = ctypes.c_uint64(0), ctypes.c_uint64(0), ctypes.c_uint64(0)
+            sec = ctypes.c_double(0.0)
+            _check(lib.ss_trace_read(self.h, i, ctypes.byref(n), ctypes.byref(sec), ctypes.byref(b),
+                                     ctypes.byref(e)), "ss_trace_read")
+            out[name] = {"launches": int(n.value), "seconds": float(sec.value), "bytes": int(b.value),
+                         "entries": int(e.value)}
+        return out
 
     def stats(self) -> dict:
         a = (ctypes.c_uint64 * 8)()

@@ -65,6 +65,7 @@ __device__ __forceinline__ bool keep_amp(double re, double im, double eps2) {
 __device__ __forceinline__ void ring_reset(DevMeta* meta, uint32_t epoch) {
   const uint32_t r = (epoch + kRing / 2) % kRing;
   meta->counters[r] = 0;
+  for (int x = 0; x < kXcds; ++x) meta->xcd_ctr[r][x * kXcdStride] = 0;
   meta->nnz_out[r] = 0;
   for (int w = 0; w < kMaxW; ++w) {
     meta->or_mask[r][w] = 0;
@@ -157,6 +158,287 @@ __global__ __launch_bounds__(kBlock) void k_perm(KeyPtrs<W> keys, double2* __res
 }
 
 // ---------------------------------------------------------------------------
+// k_perm_fast: the same ops in 32-bit form for keys of 1 or 2 words.  One
+// switch case per (kind, half indices), so every case is straight-line code;
+// each thread carries E entries so the per-op scalar decode is shared.
+// ---------------------------------------------------------------------------
+#define SQ_E for (int j = 0; j < E; ++j)
+template <int W, int E, bool AMP>
+__device__ __forceinline__ void fast_step(uint32_t (&h)[E][4], double2 (&a)[E], const FastOp& op,
+                                          const PermOp* __restrict__ gops) {
+  switch (op.code) {
+    case F_XM + 0: SQ_E h[j][0] ^= op.imm; break;
+    case F_XM + 1: SQ_E h[j][1] ^= op.imm; break;
+    case F_XM + 2: SQ_E h[j][2] ^= op.imm; break;
+    case F_XM + 3: SQ_E h[j][3] ^= op.imm; break;
+    case F_XC1 + 0: SQ_E h[j][0] ^= (((h[j][0] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 1: SQ_E h[j][0] ^= (((h[j][1] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 2: SQ_E h[j][0] ^= (((h[j][2] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 3: SQ_E h[j][0] ^= (((h[j][3] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 4: SQ_E h[j][1] ^= (((h[j][0] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 5: SQ_E h[j][1] ^= (((h[j][1] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 6: SQ_E h[j][1] ^= (((h[j][2] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 7: SQ_E h[j][1] ^= (((h[j][3] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 8: SQ_E h[j][2] ^= (((h[j][0] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 9: SQ_E h[j][2] ^= (((h[j][1] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 10: SQ_E h[j][2] ^= (((h[j][2] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 11: SQ_E h[j][2] ^= (((h[j][3] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 12: SQ_E h[j][3] ^= (((h[j][0] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 13: SQ_E h[j][3] ^= (((h[j][1] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 14: SQ_E h[j][3] ^= (((h[j][2] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC1 + 15: SQ_E h[j][3] ^= (((h[j][3] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
+    case F_XC2 + 0: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 1: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 2: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 3: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 4: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 5: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 6: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 7: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 8: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 9: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 10: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 11: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 12: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 13: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 14: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 15: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 16: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 17: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 18: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 19: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 20: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 21: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 22: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 23: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 24: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 25: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 26: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 27: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 28: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 29: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 30: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 31: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 32: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 33: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 34: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 35: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 36: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 37: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 38: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 39: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 40: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 41: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 42: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 43: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 44: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 45: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 46: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 47: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 48: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 49: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 50: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 51: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 52: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 53: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 54: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 55: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 56: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 57: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 58: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 59: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 60: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 61: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 62: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 63: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_ADDA + 0: SQ_E h[j][0] += h[j][0]; break;
+    case F_ADDA + 1: SQ_E h[j][0] += h[j][1]; break;
+    case F_ADDA + 2: SQ_E h[j][0] += h[j][2]; break;
+    case F_ADDA + 3: SQ_E h[j][0] += h[j][3]; break;
+    case F_ADDA + 4: SQ_E h[j][1] += h[j][0]; break;
+    case F_ADDA + 5: SQ_E h[j][1] += h[j][1]; break;
+    case F_ADDA + 6: SQ_E h[j][1] += h[j][2]; break;
+    case F_ADDA + 7: SQ_E h[j][1] += h[j][3]; break;
+    case F_ADDA + 8: SQ_E h[j][2] += h[j][0]; break;
+    case F_ADDA + 9: SQ_E h[j][2] += h[j][1]; break;
+    case F_ADDA + 10: SQ_E h[j][2] += h[j][2]; break;
+    case F_ADDA + 11: SQ_E h[j][2] += h[j][3]; break;
+    case F_ADDA + 12: SQ_E h[j][3] += h[j][0]; break;
+    case F_ADDA + 13: SQ_E h[j][3] += h[j][1]; break;
+    case F_ADDA + 14: SQ_E h[j][3] += h[j][2]; break;
+    case F_ADDA + 15: SQ_E h[j][3] += h[j][3]; break;
+    case F_ADDF + 0: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) + ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 1: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) + ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 2: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) + ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 3: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) + ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 4: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) + ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 5: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) + ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 6: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) + ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 7: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) + ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 8: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) + ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 9: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) + ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 10: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) + ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 11: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) + ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 12: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) + ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 13: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) + ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 14: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) + ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_ADDF + 15: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) + ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBA + 0: SQ_E h[j][0] -= h[j][0]; break;
+    case F_SUBA + 1: SQ_E h[j][0] -= h[j][1]; break;
+    case F_SUBA + 2: SQ_E h[j][0] -= h[j][2]; break;
+    case F_SUBA + 3: SQ_E h[j][0] -= h[j][3]; break;
+    case F_SUBA + 4: SQ_E h[j][1] -= h[j][0]; break;
+    case F_SUBA + 5: SQ_E h[j][1] -= h[j][1]; break;
+    case F_SUBA + 6: SQ_E h[j][1] -= h[j][2]; break;
+    case F_SUBA + 7: SQ_E h[j][1] -= h[j][3]; break;
+    case F_SUBA + 8: SQ_E h[j][2] -= h[j][0]; break;
+    case F_SUBA + 9: SQ_E h[j][2] -= h[j][1]; break;
+    case F_SUBA + 10: SQ_E h[j][2] -= h[j][2]; break;
+    case F_SUBA + 11: SQ_E h[j][2] -= h[j][3]; break;
+    case F_SUBA + 12: SQ_E h[j][3] -= h[j][0]; break;
+    case F_SUBA + 13: SQ_E h[j][3] -= h[j][1]; break;
+    case F_SUBA + 14: SQ_E h[j][3] -= h[j][2]; break;
+    case F_SUBA + 15: SQ_E h[j][3] -= h[j][3]; break;
+    case F_SUBF + 0: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) - ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 1: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) - ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 2: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) - ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 3: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) - ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 4: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) - ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 5: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) - ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 6: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) - ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 7: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) - ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 8: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) - ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 9: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) - ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 10: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) - ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 11: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) - ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 12: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) - ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 13: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) - ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 14: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) - ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_SUBF + 15: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) - ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORA + 0: SQ_E h[j][0] ^= h[j][0]; break;
+    case F_XORA + 1: SQ_E h[j][0] ^= h[j][1]; break;
+    case F_XORA + 2: SQ_E h[j][0] ^= h[j][2]; break;
+    case F_XORA + 3: SQ_E h[j][0] ^= h[j][3]; break;
+    case F_XORA + 4: SQ_E h[j][1] ^= h[j][0]; break;
+    case F_XORA + 5: SQ_E h[j][1] ^= h[j][1]; break;
+    case F_XORA + 6: SQ_E h[j][1] ^= h[j][2]; break;
+    case F_XORA + 7: SQ_E h[j][1] ^= h[j][3]; break;
+    case F_XORA + 8: SQ_E h[j][2] ^= h[j][0]; break;
+    case F_XORA + 9: SQ_E h[j][2] ^= h[j][1]; break;
+    case F_XORA + 10: SQ_E h[j][2] ^= h[j][2]; break;
+    case F_XORA + 11: SQ_E h[j][2] ^= h[j][3]; break;
+    case F_XORA + 12: SQ_E h[j][3] ^= h[j][0]; break;
+    case F_XORA + 13: SQ_E h[j][3] ^= h[j][1]; break;
+    case F_XORA + 14: SQ_E h[j][3] ^= h[j][2]; break;
+    case F_XORA + 15: SQ_E h[j][3] ^= h[j][3]; break;
+    case F_XORF + 0: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 1: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 2: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 3: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 4: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 5: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 6: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 7: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 8: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 9: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 10: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 11: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 12: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 13: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 14: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_XORF + 15: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_MULA + 0: SQ_E h[j][0] *= op.imm; break;
+    case F_MULA + 1: SQ_E h[j][1] *= op.imm; break;
+    case F_MULA + 2: SQ_E h[j][2] *= op.imm; break;
+    case F_MULA + 3: SQ_E h[j][3] *= op.imm; break;
+    case F_MULF + 0: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) * op.imm) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_MULF + 1: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) * op.imm) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_MULF + 2: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) * op.imm) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_MULF + 3: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) * op.imm) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 0: SQ_E { const uint32_t t = op.table[(h[j][0] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 1: SQ_E { const uint32_t t = op.table[(h[j][1] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 2: SQ_E { const uint32_t t = op.table[(h[j][2] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 3: SQ_E { const uint32_t t = op.table[(h[j][3] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 4: SQ_E { const uint32_t t = op.table[(h[j][0] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 5: SQ_E { const uint32_t t = op.table[(h[j][1] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 6: SQ_E { const uint32_t t = op.table[(h[j][2] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 7: SQ_E { const uint32_t t = op.table[(h[j][3] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 8: SQ_E { const uint32_t t = op.table[(h[j][0] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 9: SQ_E { const uint32_t t = op.table[(h[j][1] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 10: SQ_E { const uint32_t t = op.table[(h[j][2] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 11: SQ_E { const uint32_t t = op.table[(h[j][3] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 12: SQ_E { const uint32_t t = op.table[(h[j][0] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 13: SQ_E { const uint32_t t = op.table[(h[j][1] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 14: SQ_E { const uint32_t t = op.table[(h[j][2] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_QRAM + 15: SQ_E { const uint32_t t = op.table[(h[j][3] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
+    case F_REFL + 0: SQ_E { const double re = a[j].x, im = a[j].y; if (((h[j][0] >> op.dsh) & op.dm) == 0u) { a[j].x = -im; a[j].y = re; } else { a[j].x = im; a[j].y = -re; } } break;
+    case F_REFL + 1: SQ_E { const double re = a[j].x, im = a[j].y; if (((h[j][1] >> op.dsh) & op.dm) == 0u) { a[j].x = -im; a[j].y = re; } else { a[j].x = im; a[j].y = -re; } } break;
+    case F_REFL + 2: SQ_E { const double re = a[j].x, im = a[j].y; if (((h[j][2] >> op.dsh) & op.dm) == 0u) { a[j].x = -im; a[j].y = re; } else { a[j].x = im; a[j].y = -re; } } break;
+    case F_REFL + 3: SQ_E { const double re = a[j].x, im = a[j].y; if (((h[j][3] >> op.dsh) & op.dm) == 0u) { a[j].x = -im; a[j].y = re; } else { a[j].x = im; a[j].y = -re; } } break;
+    case F_GEN: SQ_E {
+      uint64_t k[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) k[w] = (uint64_t)h[j][2 * w] | ((uint64_t)h[j][2 * w + 1] << 32);
+      perm_apply<W>(k, a[j], gops[op.gi]);
+#pragma unroll
+      for (int w = 0; w < W; ++w) { h[j][2 * w] = (uint32_t)k[w]; h[j][2 * w + 1] = (uint32_t)(k[w] >> 32); }
+    } break;
+    default: break;
+  }
+}
+#undef SQ_E
+
+template <int W, int E, bool AMP>
+__global__ __launch_bounds__(kBlock) void k_perm_fast(KeyPtrs<W> keys, double2* __restrict__ amp, uint64_t n,
+                                                      const FastOp* __restrict__ ops, uint32_t nops,
+                                                      const PermOp* __restrict__ gops, uint32_t write_words,
+                                                      DevMeta* meta, uint32_t epoch) {
+  __shared__ uint64_t s_red[2 * kMaxW * 4];
+  if (blockIdx.x == 0 && threadIdx.x == 0) ring_reset(meta, epoch);
+  uint32_t h[E][4];
+  double2 a[E];
+  const uint64_t base = (uint64_t)blockIdx.x * kBlock * E + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const uint64_t i = base + (uint64_t)j * kBlock;
+    h[j][2] = h[j][3] = 0u;
+    a[j] = make_double2(0.0, 0.0);
+    if (i < n) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const uint64_t v = keys.w[w][i];
+        h[j][2 * w] = (uint32_t)v;
+        h[j][2 * w + 1] = (uint32_t)(v >> 32);
+      }
+      if (AMP) a[j] = amp[i];
+    } else {
+      h[j][0] = h[j][1] = 0u;
+    }
+  }
+  for (uint32_t o = 0; o < nops; ++o) fast_step<W, E, AMP>(h, a, ops[o], gops);
+  uint64_t orv[W], andv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    orv[w] = 0;
+    andv[w] = ~0ull;
+  }
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const uint64_t i = base + (uint64_t)j * kBlock;
+    if (i >= n) continue;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint64_t v = (uint64_t)h[j][2 * w] | ((uint64_t)h[j][2 * w + 1] << 32);
+      if (write_words & (1u << w)) keys.w[w][i] = v;
+      orv[w] |= v;
+      andv[w] &= v;
+    }
+    if (AMP) amp[i] = a[j];
+  }
+  publish_masks<W>(meta, epoch, orv, andv, s_red);
+}
+
+// ---------------------------------------------------------------------------
 // radix sort
 // ---------------------------------------------------------------------------
 template <int W>
@@ -212,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(KeyPtrs<W> in_keys, const 
                                                       KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
                                                       uint64_t n, PassDesc pd,
                                                       const uint64_t* __restrict__ digit_start,
-                                                      uint64_t* lb, DevMeta* meta, uint32_t epoch) {
+                                                      uint64_t* lb, DevMeta* meta, uint32_t epoch, uint32_t xo) {
   constexpr int TILE = kBlock * ITEMS;
   __shared__ uint32_t s_wcount[kBlock / 64][kRadix];
   __shared__ uint32_t s_toff[kRadix];
@@ -225,7 +507,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(KeyPtrs<W> in_keys, const 
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 #pragma unroll
   for (int w = 0; w < kBlock / 64; ++w) s_wcount[w][tid] = 0;
-  const uint32_t tile = take_tile(meta, epoch, &s_tile);
+  const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   if (tile_out_of_range(tile, (n + TILE - 1) / TILE, &meta->err)) return;
   const uint64_t base = (uint64_t)tile * TILE;
   const uint32_t tile_n = (uint32_t)min((uint64_t)TILE, n - base);
@@ -373,57 +655,94 @@ __device__ __forceinline__ void with_target_value(uint64_t (&k)[W], const GroupO
   }
 }
 
-template <int W, int K, int MODE>
+// Offsets of ITEMS counts per thread in element order (item-major, then
+// thread): ITEMS wave scans and one barrier.  Returns the tile total.
+template <int ITEMS>
+__device__ __forceinline__ uint64_t tile_offsets(const uint32_t (&cnt)[ITEMS], uint32_t (&off)[ITEMS],
+                                                 uint32_t (*s_wtot)[kBlock / 64]) {
+  const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
+  uint32_t inc[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    inc[i] = wave_incl_scan<uint32_t>(cnt[i]);
+    if (lane == 63) s_wtot[i][wave] = inc[i];
+  }
+  __syncthreads();
+  uint64_t run = 0;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    uint32_t pre = 0, row = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kBlock / 64; ++w) {
+      const uint32_t x = s_wtot[i][w];
+      if (w < wave) pre += x;
+      row += x;
+    }
+    off[i] = (uint32_t)run + pre + inc[i] - cnt[i];
+    run += row;
+  }
+  return run;
+}
+
+template <int W, int K, int MODE, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                   KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
                                                   uint64_t n, uint64_t cap, GroupOp op, uint64_t* lb,
-                                                  DevMeta* meta, uint32_t epoch) {
+                                                  DevMeta* meta, uint32_t epoch, uint32_t xo) {
   constexpr uint32_t G = 1u << K;
-  __shared__ uint64_t s_scan[4];
+  constexpr uint32_t TILE = kBlock * ITEMS;
+  __shared__ uint32_t s_wtot[ITEMS][kBlock / 64];
   __shared__ uint64_t s_off;
+  __shared__ uint64_t s_lb[12];
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
-  const uint32_t tile = take_tile(meta, epoch, &s_tile);
-  if (tile_out_of_range(tile, (n + kBlock - 1) / kBlock, &meta->err)) return;
-  const uint64_t e = (uint64_t)tile * kBlock + threadIdx.x;
-  const bool valid = e < n;
+  const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
+  const uint64_t ntiles = (n + TILE - 1) / TILE;
+  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
 
-  uint64_t key[W];
-  double2 v[G];
-  uint32_t present = 0;
+  uint64_t key[ITEMS][W];
+  double2 v[ITEMS][G];
+  uint32_t keepm[ITEMS], cnt[ITEMS];
 #pragma unroll
-  for (uint32_t s = 0; s < G; ++s) v[s] = make_double2(0.0, 0.0);
-  bool lead = false, ctl = true;
-  if (valid) {
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t e = (uint64_t)tile * TILE + (uint64_t)it * kBlock + threadIdx.x;
+    uint32_t present = 0;
 #pragma unroll
-    for (int w = 0; w < W; ++w) key[w] = in_keys.w[w][e];
-    lead = true;
-    if (MODE == MODE_GROUP && e > 0) {
-      uint64_t prv[W];
+    for (uint32_t s = 0; s < G; ++s) v[it][s] = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int w = 0; w < W; ++w) prv[w] = in_keys.w[w][e - 1];
-      lead = !same_idle<W>(key, prv, op.tmask);
+    for (int w = 0; w < W; ++w) key[it][w] = 0;
+    bool lead = false;
+    if (e < n) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) key[it][w] = in_keys.w[w][e];
+      lead = true;
+      if (MODE == MODE_GROUP && e > 0) {
+        uint64_t prv[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) prv[w] = in_keys.w[w][e - 1];
+        lead = !same_idle<W>(key[it], prv, op.tmask);
+      }
     }
     if (lead) {
-      ctl = !op.has_ctl || controls_hold<W>(key, op.cmask, op.cval);
-      const uint32_t s0 = target_value<W, K>(key, op);
+      const bool ctl = !op.has_ctl || controls_hold<W>(key[it], op.cmask, op.cval);
+      const uint32_t s0 = target_value<W, K>(key[it], op);
       const double2 a0 = in_amp[e];
 #pragma unroll
       for (uint32_t t = 0; t < G; ++t)
-        if (t == s0) v[t] = a0;
+        if (t == s0) v[it][t] = a0;
       present = 1u << s0;
       if (MODE == MODE_GROUP) {
         for (uint32_t j = 1; j < G && e + j < n; ++j) {
           uint64_t nk[W];
 #pragma unroll
           for (int w = 0; w < W; ++w) nk[w] = in_keys.w[w][e + j];
-          if (!same_idle<W>(key, nk, op.tmask)) break;
+          if (!same_idle<W>(key[it], nk, op.tmask)) break;
           const uint32_t s = target_value<W, K>(nk, op);
           if (present & (1u << s)) atomicOr(&meta->err, kErrGroup);
           const double2 a = in_amp[e + j];
 #pragma unroll
           for (uint32_t t = 0; t < G; ++t)
-            if (t == s) v[t] = a;
+            if (t == s) v[it][t] = a;
           present |= 1u << s;
         }
       }
@@ -436,7 +755,7 @@ __global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const doub
           for (uint32_t s = 0; s < G; ++s) {
             if ((s >> j) & 1u) continue;
             const uint32_t s1 = s | (1u << j);
-            const double2 a0 = v[s], a1 = v[s1];
+            const double2 a0 = v[it][s], a1 = v[it][s1];
             const bool p0 = (present >> s) & 1u, p1 = (present >> s1) & 1u;
             double2 b0, b1;
             b0.x = op.m[0][0] * a0.x + op.m[0][1] * a1.x;
@@ -445,29 +764,27 @@ __global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const doub
             b1.y = op.m[1][0] * a0.y + op.m[1][1] * a1.y;
             const bool q0 = (p0 && op.m[0][0] != 0.0) || (p1 && op.m[0][1] != 0.0);
             const bool q1 = (p0 && op.m[1][0] != 0.0) || (p1 && op.m[1][1] != 0.0);
-            v[s] = b0;
-            v[s1] = b1;
+            v[it][s] = b0;
+            v[it][s1] = b1;
             present = (present & ~((1u << s) | (1u << s1))) | ((uint32_t)q0 << s) | ((uint32_t)q1 << s1);
           }
         }
       }
     }
-  }
-  // survivors
-  uint32_t keepm = 0;
-  if (lead) {
+    keepm[it] = 0;
+    if (lead) {
 #pragma unroll
-    for (uint32_t s = 0; s < G; ++s)
-      if (((present >> s) & 1u) && keep_amp(v[s].x, v[s].y, op.eps2)) keepm |= 1u << s;
+      for (uint32_t s = 0; s < G; ++s)
+        if (((present >> s) & 1u) && keep_amp(v[it][s].x, v[it][s].y, op.eps2)) keepm[it] |= 1u << s;
+    }
+    cnt[it] = (uint32_t)__popc(keepm[it]);
   }
-  const uint64_t cnt = (uint64_t)__popc(keepm);
-  uint64_t tile_total;
-  const uint64_t loc = block_excl_scan<uint64_t>(cnt, s_scan, tile_total);
-  if (threadIdx.x < 64) {
-    const uint64_t ex = lookback_single(lb, tile, tile_total, epoch, &meta->err);
+  uint32_t off[ITEMS];
+  const uint64_t tile_total = tile_offsets<ITEMS>(cnt, off, s_wtot);
+  {
+    const uint64_t ex = lookback_block(lb, tile, tile_total, epoch, &meta->err, s_lb);
     if (threadIdx.x == 0) {
       s_off = ex;
-      const uint64_t ntiles = (n + kBlock - 1) / kBlock;
       if (tile == ntiles - 1) {
         meta->nnz_out[epoch % kRing] = ex + tile_total;
         atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
@@ -482,19 +799,159 @@ __global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const doub
     orv[w] = 0;
     andv[w] = ~0ull;
   }
-  uint64_t p = s_off + loc;
-  if (keepm) {
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    uint64_t p = s_off + off[it];
+    if (!keepm[it]) continue;
 #pragma unroll
     for (uint32_t s = 0; s < G; ++s) {
-      if (!((keepm >> s) & 1u)) continue;
+      if (!((keepm[it] >> s) & 1u)) continue;
       uint64_t ok[W];
 #pragma unroll
-      for (int w = 0; w < W; ++w) ok[w] = key[w];
+      for (int w = 0; w < W; ++w) ok[w] = key[it][w];
       with_target_value<W, K>(ok, op, s);
       if (p < cap) {
 #pragma unroll
         for (int w = 0; w < W; ++w) out_keys.w[w][p] = ok[w];
-        out_amp[p] = v[s];
+        out_amp[p] = v[it][s];
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        orv[w] |= ok[w];
+        andv[w] &= ok[w];
+      }
+      ++p;
+    }
+  }
+  publish_masks<W>(meta, epoch, orv, andv, s_red);
+}
+
+// ---------------------------------------------------------------------------
+// k_pair: a branching op on one target qubit, one thread per entry.  In a
+// full pair (the two members adjacent, in either order) each member writes the
+// child with its own target value; a member without partner writes both children;
+// where the controls fail the entry passes through.  Children of one group
+// stay adjacent, in target-value order, and every child is computed with the
+// same expression as in k_group (m[r][0] * a0 + m[r][1] * a1, absent = 0).
+// ---------------------------------------------------------------------------
+template <int W, int MODE, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
+                                                 KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
+                                                 uint64_t n, uint64_t cap, GroupOp op, uint64_t* lb,
+                                                 DevMeta* meta, uint32_t epoch, uint32_t xo) {
+  constexpr uint32_t TILE = kBlock * ITEMS;
+  __shared__ uint32_t s_wtot[ITEMS][kBlock / 64];
+  __shared__ uint64_t s_off;
+  __shared__ uint64_t s_lb[12];
+  __shared__ uint64_t s_red[2 * kMaxW * 4];
+  __shared__ uint32_t s_tile;
+  const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
+  const uint64_t ntiles = (n + TILE - 1) / TILE;
+  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
+  const uint32_t tw = op.tword[0], tb = op.tbit[0];
+  uint64_t key[ITEMS][W];
+  double2 out[ITEMS][2];
+  uint32_t keepm[ITEMS], cnt[ITEMS];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t e = (uint64_t)tile * TILE + (uint64_t)it * kBlock + threadIdx.x;
+    keepm[it] = 0;
+    out[it][0] = out[it][1] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int w = 0; w < W; ++w) key[it][w] = 0;
+    if (e < n) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) key[it][w] = in_keys.w[w][e];
+      const double2 a = in_amp[e];
+      const uint32_t b = (uint32_t)((sel_word<W>(key[it], tw) >> tb) & 1ull);
+      const bool ctl = !op.has_ctl || controls_hold<W>(key[it], op.cmask, op.cval);
+      if (!ctl) {
+        // pass through (selects, not a runtime index: keeps `out` in registers)
+        if (b) out[it][1] = a;
+        else out[it][0] = a;
+        if (keep_amp(a.x, a.y, op.eps2)) keepm[it] = 1u << b;
+      } else {
+        bool has_p = false;
+        double2 ap = make_double2(0.0, 0.0);
+        if (MODE == MODE_GROUP) {
+          // the partner is a neighbour on either side: grouped order keeps the
+          // two members adjacent but not necessarily bit 0 first
+          uint64_t c = 0;
+          if (e > 0) {
+            uint64_t pk[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) pk[w] = in_keys.w[w][e - 1];
+            if (same_idle<W>(key[it], pk, op.tmask)) {
+              has_p = true;
+              c = e - 1;
+            }
+          }
+          if (!has_p && e + 1 < n) {
+            uint64_t pk[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) pk[w] = in_keys.w[w][e + 1];
+            if (same_idle<W>(key[it], pk, op.tmask)) {
+              has_p = true;
+              c = e + 1;
+            }
+          }
+          if (has_p) ap = in_amp[c];
+        }
+        const double2 a0 = b == 0 ? a : ap;
+        const double2 a1 = b == 0 ? ap : a;
+#pragma unroll
+        for (uint32_t r = 0; r < 2; ++r) {
+          // a member of a full pair writes only the child with its own value
+          if (has_p && r != b) continue;
+          double2 v;
+          v.x = op.m[r][0] * a0.x + op.m[r][1] * a1.x;
+          v.y = op.m[r][0] * a0.y + op.m[r][1] * a1.y;
+          const double mrb = b ? op.m[r][1] : op.m[r][0];
+          const bool exists = has_p ? (op.m[r][0] != 0.0 || op.m[r][1] != 0.0) : (mrb != 0.0);
+          out[it][r] = v;
+          if (exists && keep_amp(v.x, v.y, op.eps2)) keepm[it] |= 1u << r;
+        }
+      }
+    }
+    cnt[it] = (uint32_t)__popc(keepm[it]);
+  }
+  uint32_t off[ITEMS];
+  const uint64_t tile_total = tile_offsets<ITEMS>(cnt, off, s_wtot);
+  {
+    const uint64_t ex = lookback_block(lb, tile, tile_total, epoch, &meta->err, s_lb);
+    if (threadIdx.x == 0) {
+      s_off = ex;
+      if (tile == ntiles - 1) {
+        meta->nnz_out[epoch % kRing] = ex + tile_total;
+        atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
+        if (ex + tile_total > cap) atomicOr(&meta->err, kErrCapacity);
+      }
+    }
+  }
+  __syncthreads();
+  uint64_t orv[W], andv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    orv[w] = 0;
+    andv[w] = ~0ull;
+  }
+  const uint64_t tbit = 1ull << tb;
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    uint64_t p = s_off + off[it];
+#pragma unroll
+    for (uint32_t r = 0; r < 2; ++r) {
+      if (!((keepm[it] >> r) & 1u)) continue;
+      uint64_t ok[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        ok[w] = key[it][w];
+        if ((uint32_t)w == tw) ok[w] = r ? (ok[w] | tbit) : (ok[w] & ~tbit);
+      }
+      if (p < cap) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) out_keys.w[w][p] = ok[w];
+        out_amp[p] = out[it][r];
       }
 #pragma unroll
       for (int w = 0; w < W; ++w) {
@@ -526,47 +983,57 @@ struct FilterOp {
   double eps2, scale;
 };
 
-template <int W>
+template <int W, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_filter(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                    KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
                                                    uint64_t n, uint64_t cap, FilterOp f, uint64_t* lb,
-                                                   DevMeta* meta, uint32_t epoch) {
-  __shared__ uint64_t s_scan[4];
+                                                   DevMeta* meta, uint32_t epoch, uint32_t xo) {
+  constexpr uint32_t TILE = kBlock * ITEMS;
+  __shared__ uint32_t s_wtot[ITEMS][kBlock / 64];
   __shared__ uint64_t s_off;
+  __shared__ uint64_t s_lb[12];
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
-  const uint32_t tile = take_tile(meta, epoch, &s_tile);
-  if (tile_out_of_range(tile, (n + kBlock - 1) / kBlock, &meta->err)) return;
-  const uint64_t e = (uint64_t)tile * kBlock + threadIdx.x;
-  uint64_t key[W];
-  double2 a = make_double2(0.0, 0.0);
-  bool keep = false;
-  if (e < n) {
+  const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
+  const uint64_t ntiles = (n + TILE - 1) / TILE;
+  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
+  uint64_t key[ITEMS][W];
+  double2 a[ITEMS];
+  uint32_t cnt[ITEMS];
 #pragma unroll
-    for (int w = 0; w < W; ++w) key[w] = in_keys.w[w][e];
-    a = in_amp[e];
-    const bool mine = !f.has_inst || ((sel_word<W>(key, f.iword) >> f.ishift) & f.imask) == f.inst;
-    if (f.kind == FILTER_PRUNE) {
-      keep = !mine || keep_amp(a.x, a.y, f.eps2);
-    } else if (f.kind == FILTER_COLLAPSE) {
-      if (!mine) {
-        keep = true;
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t e = (uint64_t)tile * TILE + (uint64_t)it * kBlock + threadIdx.x;
+    bool keep = false;
+    a[it] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int w = 0; w < W; ++w) key[it][w] = 0;
+    if (e < n) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) key[it][w] = in_keys.w[w][e];
+      a[it] = in_amp[e];
+      const bool mine = !f.has_inst || ((sel_word<W>(key[it], f.iword) >> f.ishift) & f.imask) == f.inst;
+      if (f.kind == FILTER_PRUNE) {
+        keep = !mine || keep_amp(a[it].x, a[it].y, f.eps2);
+      } else if (f.kind == FILTER_COLLAPSE) {
+        if (!mine) {
+          keep = true;
+        } else {
+          keep = ((sel_word<W>(key[it], f.fword) >> f.fshift) & f.fmask) == f.fval;
+          a[it].x = a[it].x / f.scale;
+          a[it].y = a[it].y / f.scale;
+        }
       } else {
-        keep = ((sel_word<W>(key, f.fword) >> f.fshift) & f.fmask) == f.fval;
-        a.x = a.x / f.scale;
-        a.y = a.y / f.scale;
+        keep = !mine;
       }
-    } else {
-      keep = !mine;
     }
+    cnt[it] = keep ? 1u : 0u;
   }
-  uint64_t tile_total;
-  const uint64_t loc = block_excl_scan<uint64_t>(keep ? 1ull : 0ull, s_scan, tile_total);
-  if (threadIdx.x < 64) {
-    const uint64_t ex = lookback_single(lb, tile, tile_total, epoch, &meta->err);
+  uint32_t off[ITEMS];
+  const uint64_t tile_total = tile_offsets<ITEMS>(cnt, off, s_wtot);
+  {
+    const uint64_t ex = lookback_block(lb, tile, tile_total, epoch, &meta->err, s_lb);
     if (threadIdx.x == 0) {
       s_off = ex;
-      const uint64_t ntiles = (n + kBlock - 1) / kBlock;
       if (tile == ntiles - 1) meta->nnz_out[epoch % kRing] = ex + tile_total;
     }
   }
@@ -574,15 +1041,22 @@ __global__ __launch_bounds__(kBlock) void k_filter(KeyPtrs<W> in_keys, const dou
   uint64_t orv[W], andv[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    orv[w] = keep ? key[w] : 0ull;
-    andv[w] = keep ? key[w] : ~0ull;
+    orv[w] = 0;
+    andv[w] = ~0ull;
   }
-  if (keep) {
-    const uint64_t p = s_off + loc;
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    if (!cnt[it]) continue;
+    const uint64_t p = s_off + off[it];
     if (p < cap) {
 #pragma unroll
-      for (int w = 0; w < W; ++w) out_keys.w[w][p] = key[w];
-      out_amp[p] = a;
+      for (int w = 0; w < W; ++w) out_keys.w[w][p] = key[it][w];
+      out_amp[p] = a[it];
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      orv[w] |= key[it][w];
+      andv[w] &= key[it][w];
     }
   }
   publish_masks<W>(meta, epoch, orv, andv, s_red);
@@ -600,6 +1074,7 @@ __global__ void k_ring_init(DevMeta* meta) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     for (int r = 0; r < kRing; ++r) {
       meta->counters[r] = 0;
+      for (int x = 0; x < kXcds; ++x) meta->xcd_ctr[r][x * kXcdStride] = 0;
       meta->nnz_out[r] = 0;
       for (int w = 0; w < kMaxW; ++w) {
         meta->or_mask[r][w] = 0;
@@ -607,6 +1082,11 @@ __global__ void k_ring_init(DevMeta* meta) {
       }
     }
   }
+}
+
+// XCD of each of the first gridDim.x workgroups (checks the round-robin spread).
+__global__ void k_xcc_probe(uint64_t* out) {
+  if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
 __global__ void k_clear_err(DevMeta* meta) {
@@ -617,6 +1097,7 @@ __global__ void k_meta_init(DevMeta* meta) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     for (int r = 0; r < kRing; ++r) {
       meta->counters[r] = 0;
+      for (int x = 0; x < kXcds; ++x) meta->xcd_ctr[r][x * kXcdStride] = 0;
       meta->nnz_out[r] = 0;
       for (int w = 0; w < kMaxW; ++w) {
         meta->or_mask[r][w] = 0;

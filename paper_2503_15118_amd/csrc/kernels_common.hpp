@@ -122,9 +122,77 @@ __device__ uint64_t lookback_single(uint64_t* lb, uint32_t tile, uint64_t agg, u
   return excl;
 }
 
-// Per-digit look-back: thread `d` of the workgroup walks its own chain.
+// Decoupled look-back for one running total per tile, executed by all 256
+// threads: each step reads the flags of 256 predecessors at once, so when
+// many tiles start together (only a few carry an inclusive total yet) the
+// walk back reaches one in few round trips.  `s` holds 12 LDS words.
+__device__ uint64_t lookback_block(uint64_t* lb, uint32_t tile, uint64_t agg, uint32_t epoch,
+                                   unsigned int* err, uint64_t* s) {
+  const uint64_t ep = (uint64_t)(epoch & kEpochMask) << kLbEpochShift;
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  if (tile == 0) {
+    if (tid == 0) st_agent(&lb[0], ep | kLbInc | agg);
+    return 0;
+  }
+  if (tid == 0) st_agent(&lb[tile], ep | kLbAgg | agg);
+  uint64_t excl = 0;
+  int64_t top = (int64_t)tile - 1;
+  uint32_t spins = 0;
+  while (true) {
+    const int64_t idx = top - (int64_t)tid;
+    const uint64_t v = idx >= 0 ? ld_agent(&lb[idx]) : (ep | kLbInc);
+    const bool rd = lb_ready(v, epoch);
+    const uint64_t rdy = __ballot(rd);
+    const uint64_t inc = __ballot(rd && (v & kLbInc));
+    // per wave: first not-ready lane and first inclusive lane (64 = none)
+    const uint32_t fnr = (~rdy) ? (uint32_t)__builtin_ctzll(~rdy) : 64u;
+    const uint32_t finc = inc ? (uint32_t)__builtin_ctzll(inc) : 64u;
+    if (lane == 0) {
+      s[wave] = fnr == 64u ? 256u : wave * 64u + fnr;
+      s[4 + wave] = finc == 64u ? 256u : wave * 64u + finc;
+    }
+    __syncthreads();
+    uint32_t first_nr = 256u, first_inc = 256u;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      first_nr = min(first_nr, (uint32_t)s[w]);
+      first_inc = min(first_inc, (uint32_t)s[4 + w]);
+    }
+    const bool done = first_inc < first_nr;
+    const bool step = !done && first_nr == 256u;
+    uint64_t part = 0;
+    if (done) part = tid <= first_inc ? (v & kLbValueMask) : 0ull;
+    else if (step) part = v & kLbValueMask;
+    part = wave_sum<uint64_t>(part);
+    __syncthreads();
+    if (lane == 0) s[8 + wave] = part;
+    __syncthreads();
+    const uint64_t sum = s[8] + s[9] + s[10] + s[11];
+    __syncthreads();
+    if (done) {
+      excl += sum;
+      break;
+    }
+    if (step) {
+      excl += sum;
+      top -= 256;
+      continue;
+    }
+    if (++spins > kSpinLimit) {
+      if (tid == 0) atomicOr(err, kErrSpin);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  if (tid == 0) st_agent(&lb[tile], ep | kLbInc | (excl + agg));
+  return excl;
+}
+
+// Per-digit look-back: thread `d` of the workgroup walks its own chain,
+// reading 8 predecessors per round trip.
 __device__ uint64_t lookback_digit(uint64_t* lb, uint32_t tile, uint32_t d, uint64_t cnt,
                                    uint32_t epoch, unsigned int* err) {
+  constexpr int B = 8;
   const uint64_t ep = (uint64_t)(epoch & kEpochMask) << kLbEpochShift;
   uint64_t* row = lb + (uint64_t)tile * kRadix;
   if (tile == 0) {
@@ -135,33 +203,69 @@ __device__ uint64_t lookback_digit(uint64_t* lb, uint32_t tile, uint32_t d, uint
   uint64_t excl = 0;
   int64_t j = (int64_t)tile - 1;
   uint32_t spins = 0;
-  while (j >= 0) {
-    const uint64_t v = ld_agent(&lb[(uint64_t)j * kRadix + d]);
-    if (!lb_ready(v, epoch)) {
+  while (true) {
+    uint64_t v[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int64_t k = j - b;
+      v[b] = k >= 0 ? ld_agent(&lb[(uint64_t)k * kRadix + d]) : (ep | kLbInc);
+    }
+    // accept the longest ready prefix; stop at the first inclusive total
+    int used = 0;
+    bool found = false;
+    uint64_t part = 0;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (found || used < b) continue;
+      if (!lb_ready(v[b], epoch)) continue;
+      part += v[b] & kLbValueMask;
+      used = b + 1;
+      if (v[b] & kLbInc) found = true;
+    }
+    excl += part;
+    j -= used;
+    if (found) break;
+    if (used == 0) {
       if (++spins > kSpinLimit) {
         atomicOr(err, kErrSpin);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
-      continue;
     }
-    excl += v & kLbValueMask;
-    if (v & kLbInc) break;
-    --j;
   }
   st_agent(&row[d], ep | kLbInc | (excl + cnt));
   return excl;
 }
 
-// Dynamic tile id from the launch's counter slot; the first workgroup to
-// arrive also clears the slot that a launch kRing/2 epochs later will use.
-__device__ __forceinline__ uint32_t take_tile(DevMeta* meta, uint32_t epoch, uint32_t* s_tile) {
+__device__ __forceinline__ uint32_t xcc_id() {
+  // HW_REG_XCC_ID (id 20), bits [3:0]
+  return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 15u;
+}
+
+// Dynamic tile id.  With `xcd_order` (one stream; the device sends workgroups
+// with equal blockIdx % 8 to one XCD and distinct residues to distinct XCDs,
+// checked when the state is created) residue class x has its own counter and
+// its k-th workgroup to start takes tile 8k + x: the counters see 8x less
+// contention, and a tile waits only on lower tiles, each taken by a running
+// workgroup or by one that its XCD will still start.  Otherwise one counter
+// hands out tiles in start order.  The first workgroup of a launch clears the
+// ring slot that a launch kRing/2 epochs later will use.
+__device__ __forceinline__ uint32_t take_tile(DevMeta* meta, uint32_t epoch, uint32_t* s_tile,
+                                              uint32_t xcd_order) {
   if (threadIdx.x == 0) {
-    const uint32_t t = (uint32_t)atomicAdd(&meta->counters[epoch % kRing], 1ull);
+    const uint32_t slot = epoch % kRing;
+    uint32_t t;
+    if (xcd_order) {
+      const uint32_t x = blockIdx.x % kXcds;
+      t = (uint32_t)atomicAdd(&meta->xcd_ctr[slot][x * kXcdStride], 1ull) * kXcds + x;
+    } else {
+      t = (uint32_t)atomicAdd(&meta->counters[slot], 1ull);
+    }
     *s_tile = t;
     if (t == 0) {
       const uint32_t r = (epoch + kRing / 2) % kRing;
       meta->counters[r] = 0;
+      for (int x = 0; x < kXcds; ++x) meta->xcd_ctr[r][x * kXcdStride] = 0;
       meta->nnz_out[r] = 0;
       for (int w = 0; w < kMaxW; ++w) {
         meta->or_mask[r][w] = 0;
@@ -203,9 +307,15 @@ __device__ __forceinline__ void publish_masks(DevMeta* meta, uint32_t epoch, con
       o |= s_red[(2 * w) * 4 + i];
       a &= s_red[(2 * w + 1) * 4 + i];
     }
+    // OR only gains bits and AND only loses them, so a workgroup whose values
+    // are already folded in (read back, possibly stale: a stale value has
+    // fewer OR bits / more AND bits, which only causes an extra atomic)
+    // skips its atomic; after the first few workgroups almost all do.
     const uint32_t r = epoch % kRing;
-    if (o) atomicOr(&meta->or_mask[r][w], (unsigned long long)o);
-    if (~a) atomicAnd(&meta->and_mask[r][w], (unsigned long long)a);
+    const uint64_t co = ld_agent(reinterpret_cast<const uint64_t*>(&meta->or_mask[r][w]));
+    const uint64_t ca = ld_agent(reinterpret_cast<const uint64_t*>(&meta->and_mask[r][w]));
+    if ((co | o) != co) atomicOr(&meta->or_mask[r][w], (unsigned long long)o);
+    if ((ca & a) != ca) atomicAnd(&meta->and_mask[r][w], (unsigned long long)a);
   }
 }
 

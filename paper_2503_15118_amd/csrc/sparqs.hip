@@ -27,7 +27,9 @@ using namespace sparqs;
 namespace {
 
 constexpr uint64_t kAlign = 256;
-constexpr uint32_t kMaxOpsPerCall = 16384;  // device op ring (PermOp records)
+constexpr uint32_t kMaxOpsPerCall = 16384;  // device op ring, in PermOp records
+constexpr uint64_t kOpRingBytes = (uint64_t)kMaxOpsPerCall * sizeof(PermOp);
+constexpr uint32_t kRunChunk = 4096;        // ops per fused launch
 constexpr uint32_t kHistBlocksMax = 256;
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
@@ -161,13 +163,29 @@ struct ss_state {
   bool grouped = false;
   uint64_t gmask[kMaxW]{};
   bool poisoned = false;
+  uint32_t dev_err = 0;           // kernel-side error bits seen at the last read-back
   DevMeta* hmeta = nullptr;       // pinned read-back block
   PermOp* hops = nullptr;         // pinned op staging (kMaxOpsPerCall)
   uint32_t ops_used = 0;
   // options
   int sort_items = 16;
   int grouping = 1;
+  int group_items = 4;
+  int perm_entries = 8;
+  uint32_t xcd_order = 0;        // 1 when workgroups spread round-robin over 8 XCDs
+  int tile_order_opt = 1;        // option: 1 use XCD tickets when possible, 0 one counter
   uint64_t stats[8]{};
+  // per-launch HIP-event timing (option "trace")
+  bool trace = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct TraceRec {
+    uint32_t cat;
+    hipEvent_t a, b;
+    uint64_t bytes, entries;
+  };
+  std::vector<TraceRec> pending;
+  double tr_sec[SS_TRACE_NCAT]{};
+  uint64_t tr_cnt[SS_TRACE_NCAT]{}, tr_bytes[SS_TRACE_NCAT]{}, tr_entries[SS_TRACE_NCAT]{};
 };
 
 namespace {
@@ -203,9 +221,52 @@ int hip_fail(ss_state* st) {
   return SS_E_HIP;
 }
 
+uint32_t xo(const ss_state* st) { return (st->xcd_order && st->tile_order_opt) ? 1u : 0u; }
+
 int check_launch(ss_state* st) {
   if (hipGetLastError() != hipSuccess) return hip_fail(st);
   return SS_OK;
+}
+
+// Event pair around one launch when tracing; returns the record index or -1.
+int trace_begin(ss_state* st, uint32_t cat) {
+  if (!st->trace) return -1;
+  hipEvent_t ev[2];
+  for (int i = 0; i < 2; ++i) {
+    if (!st->ev_pool.empty()) {
+      ev[i] = st->ev_pool.back();
+      st->ev_pool.pop_back();
+    } else if (hipEventCreate(&ev[i]) != hipSuccess) {
+      return -1;
+    }
+  }
+  (void)hipEventRecord(ev[0], st->stream);
+  st->pending.push_back({cat, ev[0], ev[1], 0, 0});
+  return (int)st->pending.size() - 1;
+}
+
+void trace_end(ss_state* st, int idx, uint64_t bytes, uint64_t entries) {
+  if (idx < 0) return;
+  auto& r = st->pending[(size_t)idx];
+  r.bytes = bytes;
+  r.entries = entries;
+  (void)hipEventRecord(r.b, st->stream);
+}
+
+// After a stream synchronisation: fold finished event pairs into the totals.
+void trace_flush(ss_state* st) {
+  for (auto& r : st->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      st->tr_sec[r.cat] += ms * 1e-3;
+      st->tr_cnt[r.cat] += 1;
+      st->tr_bytes[r.cat] += r.bytes;
+      st->tr_entries[r.cat] += r.entries;
+    }
+    st->ev_pool.push_back(r.a);
+    st->ev_pool.push_back(r.b);
+  }
+  st->pending.clear();
 }
 
 // Wait for the stream and copy the device meta block to pinned memory.
@@ -213,8 +274,10 @@ int readback(ss_state* st) {
   if (hipMemcpyAsync(st->hmeta, st->meta, sizeof(DevMeta), hipMemcpyDeviceToHost, st->stream) != hipSuccess)
     return hip_fail(st);
   if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
+  st->dev_err |= st->hmeta->err;
   st->stats[6]++;
   st->ops_used = 0;
+  trace_flush(st);
   return SS_OK;
 }
 
@@ -273,23 +336,27 @@ int run_sort_w(ss_state* st, const SortPlan& plan) {
   const int items = (W == 4) ? 8 : st->sort_items;
   const uint64_t tile = (uint64_t)kBlock * items;
   const uint32_t nb = (uint32_t)std::min<uint64_t>(st->cv.hist_blocks, (n + 2047) / 2048);
+  int tr = trace_begin(st, SS_TRACE_SORT_HIST);
   k_sort_hist<W><<<nb, kBlock, plan.npass * kRadix * 4, st->stream>>>(kp<W>(st->buf[st->cur]), n, plan,
                                                                        st->hist);
   k_sort_scan<<<plan.npass, kBlock, 0, st->stream>>>(st->hist, nb, plan.npass, st->digit_start);
+  trace_end(st, tr, n * 8 * W, n);
   st->stats[0] += 2;
   const uint32_t ntiles = (uint32_t)((n + tile - 1) / tile);
   for (uint32_t p = 0; p < plan.npass; ++p) {
     const uint32_t ep = next_epoch(st);
     const Buf& in = st->buf[st->cur];
     const Buf& out = st->buf[st->cur ^ 1];
+    tr = trace_begin(st, SS_TRACE_SORT_PASS);
     if (items == 16)
       k_sort_pass<W, 16><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, n,
                                                              plan.pass[p], st->digit_start + p * kRadix,
-                                                             st->lb, st->meta, ep);
+                                                             st->lb, st->meta, ep, xo(st));
     else
       k_sort_pass<W, 8><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, n,
                                                             plan.pass[p], st->digit_start + p * kRadix,
-                                                            st->lb, st->meta, ep);
+                                                            st->lb, st->meta, ep, xo(st));
+    trace_end(st, tr, 2 * n * entry_bytes(W), n);
     st->cur ^= 1;
     st->stats[1]++;
   }
@@ -320,17 +387,36 @@ int sort_canonical(ss_state* st) {
 // ---------------------------------------------------------------------------
 // emitting kernels (group / expand / filter): read buf[cur], write buf[cur^1]
 // ---------------------------------------------------------------------------
-template <int W, int K>
-void launch_group_wk(ss_state* st, int mode, const GroupOp& g, uint32_t ep) {
+template <int W, int K, int ITEMS>
+void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
-  const uint32_t ntiles = (uint32_t)((st->n + kBlock - 1) / kBlock);
+  const uint32_t ntiles = (uint32_t)((st->n + kBlock * ITEMS - 1) / (kBlock * ITEMS));
+  if (K == 1) {
+    if (mode == MODE_GROUP)
+      k_pair<W, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
+                                                                       st->n, st->cap, g, st->lb, st->meta, ep, xo(st));
+    else
+      k_pair<W, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
+                                                                        st->n, st->cap, g, st->lb, st->meta, ep, xo(st));
+    return;
+  }
   if (mode == MODE_GROUP)
-    k_group<W, K, MODE_GROUP><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->n,
-                                                                  st->cap, g, st->lb, st->meta, ep);
+    k_group<W, K, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
+                                                                         st->n, st->cap, g, st->lb, st->meta, ep, xo(st));
   else
-    k_group<W, K, MODE_EXPAND><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->n,
-                                                                   st->cap, g, st->lb, st->meta, ep);
+    k_group<W, K, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
+                                                                          st->n, st->cap, g, st->lb, st->meta, ep, xo(st));
+}
+
+// Items per thread: several for one or two targets (bigger tiles, fewer
+// tile-id atomics), one for 8..32-member groups (register budget).
+template <int W, int K>
+void launch_group_wk(ss_state* st, int mode, const GroupOp& g, uint32_t ep) {
+  const int items = K <= 2 ? st->group_items : 1;
+  if (K <= 2 && items >= 4) launch_group_wki<W, K, (K <= 2 ? 4 : 1)>(st, mode, g, ep);
+  else if (K <= 2 && items == 2) launch_group_wki<W, K, (K <= 2 ? 2 : 1)>(st, mode, g, ep);
+  else launch_group_wki<W, K, 1>(st, mode, g, ep);
 }
 
 template <int W>
@@ -362,26 +448,37 @@ int finish_emit(ss_state* st, uint32_t ep, bool check_cap) {
   return SS_OK;
 }
 
+// Output bytes of an emitting launch are known only after it finished.
+void trace_add_output(ss_state* st, uint32_t cat, uint64_t nout) {
+  st->tr_bytes[cat] += nout * entry_bytes(st->L.W);
+}
+
 template <int W>
 void launch_filter_w(ss_state* st, const FilterOp& f, uint32_t ep) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
-  const uint32_t ntiles = (uint32_t)((st->n + kBlock - 1) / kBlock);
-  k_filter<W><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->n, st->cap, f,
-                                                 st->lb, st->meta, ep);
+  constexpr int ITEMS = 4;
+  const uint32_t ntiles = (uint32_t)((st->n + kBlock * ITEMS - 1) / (kBlock * ITEMS));
+  k_filter<W, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->n, st->cap,
+                                                        f, st->lb, st->meta, ep, xo(st));
 }
 
 int run_filter(ss_state* st, const FilterOp& f) {
   if (st->n == 0) return SS_OK;
   const uint32_t ep = next_epoch(st);
+  const uint64_t n_in = st->n;
+  const int tr = trace_begin(st, SS_TRACE_FILTER);
   switch (st->L.W) {
     case 1: launch_filter_w<1>(st, f, ep); break;
     case 2: launch_filter_w<2>(st, f, ep); break;
     default: launch_filter_w<4>(st, f, ep); break;
   }
+  trace_end(st, tr, n_in * entry_bytes(st->L.W), n_in);
   int rc = check_launch(st);
   if (rc) return rc;
-  return finish_emit(st, ep, false);
+  rc = finish_emit(st, ep, false);
+  if (rc == SS_OK && tr >= 0) trace_add_output(st, SS_TRACE_FILTER, st->n);
+  return rc;
 }
 
 FilterOp base_filter(const ss_state* st, uint32_t inst) {
@@ -514,43 +611,199 @@ bool keeps_grouping(const ss_state* st, const ss_op& op, const uint64_t* g) {
   return true;
 }
 
-template <int W>
-void launch_perm_w(ss_state* st, const PermOp* dev, uint32_t nops, uint32_t write_words, bool amp, uint32_t ep) {
-  const Buf& b = st->buf[st->cur];
-  const uint32_t grid = (uint32_t)std::min<uint64_t>((st->n + kBlock - 1) / kBlock, 8192);
-  if (amp)
-    k_perm<W, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, dev, nops, write_words, st->meta, ep);
-  else
-    k_perm<W, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, dev, nops, write_words, st->meta, ep);
+// Position of a key bit range inside the 32-bit halves of the key words.
+struct HalfField {
+  bool ok;            // the range lies inside one half
+  uint32_t half, sh;  // half index (word*2 + upper) and shift within it
+  uint32_t mask;      // width mask (unshifted)
+};
+
+HalfField half_of(const RegInfo& r) {
+  HalfField f{};
+  const uint32_t lo = r.shift % 32;
+  f.ok = r.width <= 32 && lo + r.width <= 32;
+  f.half = r.word * 2 + (r.shift >= 32 ? 1u : 0u);
+  f.sh = lo;
+  f.mask = r.width >= 32 ? 0xFFFFFFFFu : ((1u << r.width) - 1u);
+  return f;
 }
 
-int flush_run(ss_state* st, std::vector<PermOp>& run, uint32_t write_words, bool amp) {
+// 32-bit encoding of a non-branching op, or F_GEN when it has no such form.
+FastOp encode_fast(const ss_state* st, const ss_op& op, uint32_t gi) {
+  FastOp f{};
+  f.code = F_GEN;
+  f.gi = gi;
+  const RegInfo& d = st->L.regs[op.reg];
+  const HalfField hd = half_of(d);
+  auto ctl_bit = [&](const ss_ctl& c, uint32_t& half, uint32_t& bit) {
+    const RegInfo& r = st->L.regs[c.reg];
+    const uint32_t b = r.shift + c.qubit;
+    half = r.word * 2 + (b >= 32 ? 1u : 0u);
+    bit = b % 32;
+  };
+  switch (op.kind) {
+    case SS_X:
+    case SS_XORC: {
+      const uint64_t m64 = ((op.kind == SS_X ? op.qmask : op.imm) & d.mask) << d.shift;
+      uint32_t half, imm;
+      if ((m64 >> 32) == 0) {
+        half = d.word * 2;
+        imm = (uint32_t)m64;
+      } else if ((m64 & 0xFFFFFFFFull) == 0) {
+        half = d.word * 2 + 1;
+        imm = (uint32_t)(m64 >> 32);
+      } else {
+        return f;
+      }
+      f.imm = imm;
+      if (op.nctl == 0) {
+        f.code = F_XM + half;
+      } else if (op.nctl == 1) {
+        uint32_t hc, cb;
+        ctl_bit(op.ctl[0], hc, cb);
+        f.cb = cb;
+        f.cv = op.ctl[0].value;
+        f.code = F_XC1 + half * 4 + hc;
+      } else if (op.nctl == 2) {
+        uint32_t hc, cb, hc2, cb2;
+        ctl_bit(op.ctl[0], hc, cb);
+        ctl_bit(op.ctl[1], hc2, cb2);
+        f.cb = cb;
+        f.cv = op.ctl[0].value;
+        f.cb2 = cb2;
+        f.cv2 = op.ctl[1].value;
+        f.code = F_XC2 + half * 16 + hc * 4 + hc2;
+      }
+      return f;
+    }
+    default:
+      break;
+  }
+  if (op.nctl != 0 || !hd.ok) return f;
+  f.dsh = hd.sh;
+  f.dm = hd.mask;
+  f.dms = hd.mask << hd.sh;
+  const bool dwhole = hd.mask == 0xFFFFFFFFu;
+  switch (op.kind) {
+    case SS_ADD:
+    case SS_SUB:
+    case SS_XOR: {
+      const HalfField hs = half_of(st->L.regs[op.reg2]);
+      if (!hs.ok) return f;
+      f.ssh = hs.sh;
+      f.sm = hs.mask;
+      const bool whole = dwhole && hs.mask == 0xFFFFFFFFu;
+      const uint32_t idx = hd.half * 4 + hs.half;
+      if (op.kind == SS_ADD) f.code = (whole ? F_ADDA : F_ADDF) + idx;
+      else if (op.kind == SS_SUB) f.code = (whole ? F_SUBA : F_SUBF) + idx;
+      else f.code = (whole ? F_XORA : F_XORF) + idx;
+      return f;
+    }
+    case SS_MULC:
+      f.imm = (uint32_t)op.imm;
+      f.code = (dwhole ? F_MULA : F_MULF) + hd.half;
+      return f;
+    case SS_QRAM_LOAD:
+    case SS_QRAM_UNLOAD: {
+      const TableInfo& t = st->tables[op.qram_id];
+      const HalfField hs = half_of(st->L.regs[op.reg2]);
+      if (!t.w32 || !hs.ok) return f;
+      f.ssh = hs.sh;
+      f.sm = hs.mask;
+      f.table = static_cast<const uint32_t*>(t.dev);
+      f.code = F_QRAM + hd.half * 4 + hs.half;
+      return f;
+    }
+    case SS_REFLECT0:
+      f.code = F_REFL + hd.half;
+      return f;
+    default:
+      return f;
+  }
+}
+
+template <int W, int E>
+void launch_perm_fast(ss_state* st, const FastOp* f, uint32_t nfast, const PermOp* gops, uint32_t write_words,
+                      bool amp, uint32_t ep) {
+  const Buf& b = st->buf[st->cur];
+  const uint32_t grid = (uint32_t)((st->n + kBlock * E - 1) / (kBlock * E));
+  if (amp)
+    k_perm_fast<W, E, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, f, nfast, gops, write_words,
+                                                             st->meta, ep);
+  else
+    k_perm_fast<W, E, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, f, nfast, gops, write_words,
+                                                              st->meta, ep);
+}
+
+template <int W>
+void launch_perm_w(ss_state* st, const void* dev, uint32_t nfast, const PermOp* gops, uint32_t write_words,
+                   bool amp, uint32_t ep) {
+  if (W <= 2) {
+    const FastOp* f = static_cast<const FastOp*>(dev);
+    if (st->perm_entries == 8) launch_perm_fast<W, 8>(st, f, nfast, gops, write_words, amp, ep);
+    else launch_perm_fast<W, 4>(st, f, nfast, gops, write_words, amp, ep);
+  } else {
+    const Buf& b = st->buf[st->cur];
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((st->n + kBlock - 1) / kBlock, 8192);
+    if (amp)
+      k_perm<W, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, gops, nfast, write_words, st->meta, ep);
+    else
+      k_perm<W, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, gops, nfast, write_words, st->meta, ep);
+  }
+}
+
+// Launch the pending run of non-branching ops (one fused kernel per chunk).
+int flush_run(ss_state* st, std::vector<ss_op>& run) {
   if (run.empty()) return SS_OK;
   if (st->n == 0) {
     run.clear();
     return SS_OK;
   }
+  const uint32_t W = st->L.W;
   size_t i = 0;
   while (i < run.size()) {
-    uint32_t chunk = (uint32_t)std::min<size_t>(run.size() - i, kMaxOpsPerCall);
-    if (st->ops_used + chunk > kMaxOpsPerCall) {
+    const uint32_t chunk = (uint32_t)std::min<size_t>(run.size() - i, kRunChunk);
+    std::vector<FastOp> fast;
+    std::vector<PermOp> gen;
+    uint32_t write_words = 0;
+    bool amp = false;
+    for (uint32_t j = 0; j < chunk; ++j) {
+      const ss_op& op = run[i + j];
+      if (op.kind == SS_REFLECT0) amp = true;
+      else write_words |= 1u << st->L.regs[op.reg].word;
+      if (W <= 2) {
+        FastOp f = encode_fast(st, op, (uint32_t)gen.size());
+        if (f.code == F_GEN) gen.push_back(to_perm(st, op));
+        fast.push_back(f);
+      } else {
+        gen.push_back(to_perm(st, op));
+      }
+    }
+    const uint64_t fbytes = align_up(fast.size() * sizeof(FastOp), kAlign);
+    const uint64_t bytes = fbytes + gen.size() * sizeof(PermOp);
+    if (st->ops_used + bytes > kOpRingBytes) {
       // staging ring full: wait for the stream before reusing it
       if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
       st->stats[6]++;
       st->ops_used = 0;
+      trace_flush(st);
     }
-    PermOp* h = st->hops + st->ops_used;
-    PermOp* d = st->dev_ops + st->ops_used;
-    std::memcpy(h, run.data() + i, chunk * sizeof(PermOp));
-    if (hipMemcpyAsync(d, h, chunk * sizeof(PermOp), hipMemcpyHostToDevice, st->stream) != hipSuccess)
-      return hip_fail(st);
-    st->ops_used += chunk;
+    char* h = reinterpret_cast<char*>(st->hops) + st->ops_used;
+    char* d = reinterpret_cast<char*>(st->dev_ops) + st->ops_used;
+    if (!fast.empty()) std::memcpy(h, fast.data(), fast.size() * sizeof(FastOp));
+    if (!gen.empty()) std::memcpy(h + fbytes, gen.data(), gen.size() * sizeof(PermOp));
+    if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st->stream) != hipSuccess) return hip_fail(st);
+    st->ops_used += align_up(bytes, kAlign);
     const uint32_t ep = next_epoch(st);
-    switch (st->L.W) {
-      case 1: launch_perm_w<1>(st, d, chunk, write_words, amp, ep); break;
-      case 2: launch_perm_w<2>(st, d, chunk, write_words, amp, ep); break;
-      default: launch_perm_w<4>(st, d, chunk, write_words, amp, ep); break;
+    const int tr = trace_begin(st, SS_TRACE_PERM);
+    const PermOp* gops = reinterpret_cast<const PermOp*>(d + fbytes);
+    switch (W) {
+      case 1: launch_perm_w<1>(st, d, chunk, gops, write_words, amp, ep); break;
+      case 2: launch_perm_w<2>(st, d, chunk, gops, write_words, amp, ep); break;
+      default: launch_perm_w<4>(st, d, chunk, gops, write_words, amp, ep); break;
     }
+    trace_end(st, tr, st->n * (8ull * W + 8ull * (uint64_t)__builtin_popcount(write_words) + (amp ? 32ull : 0ull)),
+              st->n * chunk);
     int rc = check_launch(st);
     if (rc) return rc;
     st->masks_stale = true;
@@ -627,15 +880,19 @@ int do_branching(ss_state* st, const ss_op& op) {
       }
     }
     const uint32_t ep = next_epoch(st);
+    const uint32_t cat = mode == MODE_GROUP ? SS_TRACE_GROUP : SS_TRACE_EXPAND;
+    const int tr = trace_begin(st, cat);
     switch (st->L.W) {
       case 1: launch_group_w<1>(st, mode, g, ep); break;
       case 2: launch_group_w<2>(st, mode, g, ep); break;
       default: launch_group_w<4>(st, mode, g, ep); break;
     }
+    trace_end(st, tr, st->n * entry_bytes(st->L.W), st->n);
     int rc = check_launch(st);
     if (rc) return rc;
     st->stats[mode == MODE_GROUP ? 3 : 4]++;
     rc = finish_emit(st, ep, true);
+    if (rc == SS_OK && tr >= 0) trace_add_output(st, cat, st->n);
     if (rc == SS_E_CAPACITY) {
       // parents are intact in buf[cur] (possibly re-ordered by the sort)
       st->grouped = (mode == MODE_GROUP);
@@ -685,8 +942,23 @@ int setup_arena(ss_state* st, char* arena, size_t bytes) {
 int init_device(ss_state* st) {
   k_meta_init<<<1, 64, 0, st->stream>>>(st->meta);
   k_fill_u64<<<256, 256, 0, st->stream>>>(st->lb, st->cv.lb_words, 0ull);
-  st->stats[0] += 2;
-  return check_launch(st);
+  // Which XCD runs each of 64 workgroups: per-XCD tile tickets are used only
+  // when equal residues of blockIdx % 8 share an XCD and residues differ by XCD.
+  k_xcc_probe<<<64, 64, 0, st->stream>>>(st->uscr);
+  st->stats[0] += 3;
+  int rc = check_launch(st);
+  if (rc) return rc;
+  uint64_t ids[64];
+  if (hipMemcpyAsync(ids, st->uscr, sizeof(ids), hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
+      hipStreamSynchronize(st->stream) != hipSuccess)
+    return hip_fail(st);
+  // residue classes of blockIdx % 8 map one-to-one onto XCDs
+  bool rr = true;
+  for (int i = 0; i < 64; ++i) rr = rr && ids[i] == ids[i % kXcds];
+  for (int i = 0; i < kXcds; ++i)
+    for (int j = 0; j < i; ++j) rr = rr && ids[i] != ids[j];
+  st->xcd_order = rr ? 1u : 0u;
+  return SS_OK;
 }
 
 template <int W>
@@ -775,6 +1047,8 @@ int ss_create_state(const ss_reg* regs, uint32_t nregs, uint32_t ninst, double e
 int ss_destroy_state(ss_state* st) {
   if (!st) return SS_E_STATE;
   (void)hipStreamSynchronize(st->stream);
+  trace_flush(st);
+  for (hipEvent_t e : st->ev_pool) (void)hipEventDestroy(e);
   if (st->hmeta) (void)hipHostFree(st->hmeta);
   if (st->hops) (void)hipHostFree(st->hops);
   delete st;
@@ -912,16 +1186,12 @@ int ss_apply_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* 
       return rc;
     }
   }
-  std::vector<PermOp> run;
-  uint32_t write_words = 0;
-  bool amp = false;
+  std::vector<ss_op> run;
   for (uint64_t i = 0; i < nops; ++i) {
     const ss_op& op = ops[i];
     st->stats[7] += st->n;
     if (is_branching(op.kind)) {
-      rc = flush_run(st, run, write_words, amp);
-      write_words = 0;
-      amp = false;
+      rc = flush_run(st, run);
       if (!rc) rc = do_branching(st, op);
       if (rc) {
         res->status = rc;
@@ -932,13 +1202,10 @@ int ss_apply_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* 
       }
     } else {
       if (st->grouped && !keeps_grouping(st, op, st->gmask)) st->grouped = false;
-      PermOp p = to_perm(st, op);
-      if (op.kind == SS_REFLECT0) amp = true;
-      else write_words |= 1u << p.dst_word;
-      run.push_back(p);
+      run.push_back(op);
     }
   }
-  rc = flush_run(st, run, write_words, amp);
+  rc = flush_run(st, run);
   if (!rc) rc = ensure_masks(st);
   if (!rc && (st->hmeta->err & (kErrSpin | kErrGroup))) rc = hip_fail(st);
   res->status = rc;
@@ -1187,11 +1454,49 @@ int ss_set_option(ss_state* st, const char* key, int64_t value) {
   if (k == "sort_items") {
     if (value != 8 && value != 16) return SS_E_ARG;
     st->sort_items = (int)value;
+  } else if (k == "tile_order") {
+    // 1: per-XCD tickets when the device spreads workgroups round-robin (one
+    // stream); 0: one ticket counter (states driven concurrently on several
+    // streams of one GPU must use 0)
+    st->tile_order_opt = value ? 1 : 0;
+  } else if (k == "perm_entries") {
+    if (value != 4 && value != 8) return SS_E_ARG;
+    st->perm_entries = (int)value;
+  } else if (k == "group_items") {
+    if (value != 1 && value != 2 && value != 4) return SS_E_ARG;
+    st->group_items = (int)value;
   } else if (k == "grouping") {
     st->grouping = value ? 1 : 0;
+  } else if (k == "trace") {
+    st->trace = value != 0;
+  } else if (k == "trace_reset") {
+    for (int c = 0; c < SS_TRACE_NCAT; ++c) {
+      st->tr_sec[c] = 0.0;
+      st->tr_cnt[c] = st->tr_bytes[c] = st->tr_entries[c] = 0;
+    }
   } else {
     return SS_E_ARG;
   }
+  return SS_OK;
+}
+
+int ss_trace_read(ss_state* st, uint32_t cat, uint64_t* launches, double* seconds, uint64_t* bytes,
+                  uint64_t* entries) {
+  if (!st || cat >= SS_TRACE_NCAT) return SS_E_ARG;
+  if (!st->pending.empty()) {
+    if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
+    trace_flush(st);
+  }
+  if (launches) *launches = st->tr_cnt[cat];
+  if (seconds) *seconds = st->tr_sec[cat];
+  if (bytes) *bytes = st->tr_bytes[cat];
+  if (entries) *entries = st->tr_entries[cat];
+  return SS_OK;
+}
+
+int ss_device_error(const ss_state* st, uint32_t* bits) {
+  if (!st || !bits) return SS_E_ARG;
+  *bits = st->dev_err;
   return SS_OK;
 }
 

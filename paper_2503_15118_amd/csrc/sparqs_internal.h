@@ -34,8 +34,12 @@ constexpr uint32_t kErrCollision = 1u << 3;  // reserved: duplicate key detected
 // Device-side bookkeeping.  Every kernel launch that counts tiles, produces an
 // entry count or key masks owns ring slot (epoch % kRing); the first
 // workgroup of launch e clears slot (e + kRing/2) % kRing for a later launch.
+constexpr int kXcds = 8;            // XCDs of an MI355X; workgroup i runs on XCD i % 8
+constexpr int kXcdStride = 16;      // counters 128 bytes apart
+
 struct DevMeta {
-  unsigned long long counters[kRing];        // dynamic tile ids
+  unsigned long long counters[kRing];        // dynamic tile ids (one ticket per launch)
+  unsigned long long xcd_ctr[kRing][kXcds * kXcdStride];  // per-XCD tickets
   unsigned long long nnz_out[kRing];         // entry count written by an emitting kernel
   unsigned long long or_mask[kRing][kMaxW];  // OR of the produced keys, per word
   unsigned long long and_mask[kRing][kMaxW]; // AND of the produced keys, per word
@@ -73,6 +77,39 @@ struct PermOp {
   const void* table;            // QRAM words
   uint64_t cmask[kMaxW];        // control bits per word
   uint64_t cval[kMaxW];         // required values of those bits
+};
+
+// Fast form of a non-branching op for keys of at most 2 words, every field
+// inside one 32-bit half of a word (halves numbered word*2 + upper).  `code`
+// fixes the op kind and the half indices, so each case of the interpreter is
+// straight-line code on named registers.
+enum FastBase : uint32_t {
+  F_XM = 0,       // + h          : h ^= imm                     (X / XORC, uncontrolled)
+  F_XC1 = 4,      // + t*4 + c    : h[t] ^= imm if bit cb of h[c] == cv        (CNOT)
+  F_XC2 = 20,     // + t*16+c*4+c2: two controls                               (Toffoli)
+  F_ADDA = 84,    // + d*4 + s    : h[d] += h[s]   (both whole halves)
+  F_ADDF = 100,   // + d*4 + s    : field form
+  F_SUBA = 116,
+  F_SUBF = 132,
+  F_XORA = 148,
+  F_XORF = 164,
+  F_MULA = 180,   // + d
+  F_MULF = 184,   // + d
+  F_QRAM = 188,   // + d*4 + s    : data field ^= table32[address field]
+  F_REFL = 204,   // + d          : amplitude *= +i / -i by field == 0
+  F_GEN = 208,    // generic 64-bit form: gops[gi]
+  F_NCODES = 209
+};
+
+struct FastOp {
+  uint32_t code;
+  uint32_t dsh, dm;             // dst shift within its half, width mask
+  uint32_t ssh, sm;             // src shift within its half, width mask
+  uint32_t imm;                 // X/XORC mask (shifted into place), multiplier
+  uint32_t cb, cv, cb2, cv2;    // control bit positions and required values
+  uint32_t gi;                  // index into the generic op array (F_GEN)
+  uint32_t dms;                 // dm << dsh
+  const uint32_t* table;        // QRAM words (uint32)
 };
 
 // One branching (interference) op as seen by the group/expand kernel.

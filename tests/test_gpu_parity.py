@@ -243,3 +243,20 @@ def test_c2_full_size_sampled(abi):
     norm = float(np.sum(ga.real ** 2 + ga.imag ** 2))
     assert abs(norm - 1.0) < 1e-10
     assert _c2_sample_check(abi, c, st) >= 48
+
+
+def test_reversed_pairs_after_flip(abi):
+    """Grouped order survives an X on the target qubit with each pair reversed
+    (bit 1 before bit 0); the next interference op on that qubit must find the
+    partner on either side."""
+    for ctl in ([], [(1, 0, 1)]):
+        ops = wl.ops_array([
+            wl.make_op("H", 1, qmask=0b111),
+            wl.make_op("RY", 0, qmask=1 << 2, theta=0.9),
+            wl.make_op("X", 0, qmask=1 << 2, ctls=ctl),
+            wl.make_op("RY", 0, qmask=1 << 2, theta=2.1),
+            wl.make_op("X", 0, qmask=(1 << 2) | 1),
+            wl.make_op("H", 0, qmask=1 << 2),
+        ])
+        c = wl.Circuit(regs=[("a", 4), ("b", 3)], ops=ops, name=f"reversed-pairs-ctl{len(ctl)}")
+        _check(abi, c)
