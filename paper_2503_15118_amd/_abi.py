@@ -212,11 +212,19 @@ class State:
         _check(lib.ss_set_entries(self.h, inst, _p(v, ctypes.c_uint64), _p(a, ctypes.c_double), len(v)),
                "ss_set_entries")
 
-    def apply(self, ops: np.ndarray, raise_on_error: bool = True) -> _Result:
+    def apply(self, ops: np.ndarray, inst_offsets=None, raise_on_error: bool = True) -> _Result:
+        """Apply ops to every instance, or with ``inst_offsets`` (ninst + 1
+        CSR offsets into ``ops``) instance i runs ops[off[i]:off[i+1]]."""
         rec = ops if ops.dtype == SS_OP else to_ss_ops(ops)
         rec = np.ascontiguousarray(rec)
         res = _Result()
-        rc = lib.ss_apply_ops(self.h, ctypes.c_void_p(rec.ctypes.data), len(rec), None, ctypes.byref(res))
+        offp = None
+        if inst_offsets is not None:
+            off = np.ascontiguousarray(inst_offsets, dtype=np.uint64)
+            if len(off) != self.ninst + 1:
+                raise ValueError("inst_offsets needs ninst + 1 entries")
+            offp = _p(off, ctypes.c_uint64)
+        rc = lib.ss_apply_ops(self.h, ctypes.c_void_p(rec.ctypes.data), len(rec), offp, ctypes.byref(res))
         if rc != SS_OK and raise_on_error:
             bits = ctypes.c_uint32(0)
             lib.ss_device_error(self.h, ctypes.byref(bits))

@@ -1063,6 +1063,260 @@ __global__ __launch_bounds__(kBlock) void k_filter(KeyPtrs<W> in_keys, const dou
 }
 
 // ---------------------------------------------------------------------------
+// Batched rounds: every instance follows its own op list.
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ uint32_t inst_of(const uint64_t (&k)[W], uint32_t iword, uint32_t ishift, uint64_t imask) {
+  return (uint32_t)((sel_word<W>(k, iword) >> ishift) & imask);
+}
+
+// Each entry runs its own instance's run of non-branching ops.  A wave takes
+// the distinct instances among its lanes one at a time, so the op index stays
+// uniform and the interpreter's dispatch stays scalar.
+template <int W, bool AMP>
+__global__ __launch_bounds__(kBlock) void k_perm_batched(KeyPtrs<W> keys, double2* __restrict__ amp, uint64_t n,
+                                                         const FastOp* __restrict__ ops,
+                                                         const PermOp* __restrict__ gops,
+                                                         const RunRange* __restrict__ runs, uint32_t iword,
+                                                         uint32_t ishift, uint64_t imask, uint32_t write_words,
+                                                         DevMeta* meta, uint32_t epoch) {
+  __shared__ uint64_t s_red[2 * kMaxW * 4];
+  if (blockIdx.x == 0 && threadIdx.x == 0) ring_reset(meta, epoch);
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = i < n;
+  uint32_t h[1][4] = {{0u, 0u, 0u, 0u}};
+  double2 a[1] = {make_double2(0.0, 0.0)};
+  uint64_t k[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) k[w] = valid ? keys.w[w][i] : 0ull;
+  const uint32_t inst = valid ? inst_of<W>(k, iword, ishift, imask) : 0u;
+  const RunRange rr = valid ? runs[inst] : RunRange{0u, 0u};
+  if (W <= 2) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      h[0][2 * w] = (uint32_t)k[w];
+      h[0][2 * w + 1] = (uint32_t)(k[w] >> 32);
+    }
+  }
+  if (AMP && valid) a[0] = amp[i];
+  uint64_t pending = __ballot(valid && rr.len > 0);
+  while (pending) {
+    const uint32_t lead = (uint32_t)__builtin_ctzll(pending);
+    const uint32_t u = __builtin_amdgcn_readfirstlane(__shfl(inst, (int)lead, 64));
+    const bool mine = valid && rr.len > 0 && inst == u;
+    pending &= ~__ballot(mine);
+    if (mine) {
+      const uint32_t start = __builtin_amdgcn_readfirstlane(rr.start);
+      const uint32_t len = __builtin_amdgcn_readfirstlane(rr.len);
+      for (uint32_t o = start; o < start + len; ++o) {
+        if (W <= 2) fast_step<W, 1, AMP>(h, a, ops[o], gops);
+        else perm_apply<W>(k, a[0], gops[ops[o].gi]);
+      }
+    }
+  }
+  if (W <= 2) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) k[w] = (uint64_t)h[0][2 * w] | ((uint64_t)h[0][2 * w + 1] << 32);
+  }
+  uint64_t orv[W], andv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    orv[w] = valid ? k[w] : 0ull;
+    andv[w] = valid ? k[w] : ~0ull;
+    if (valid && (write_words & (1u << w))) keys.w[w][i] = k[w];
+  }
+  if (AMP && valid) amp[i] = a[0];
+  publish_masks<W>(meta, epoch, orv, andv, s_red);
+}
+
+// Branch expansion: every parent emits the children of its instance's op
+// (target bits set to s, amplitude multiplied by the matrix elements stage by
+// stage in ascending qubit order), skipping children reached through an exact
+// 0.0 element; where the controls fail, or the instance has no branching op
+// this round, the parent is copied.  Output offsets come from a look-back
+// prefix of the per-parent child counts.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
+                                                           KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
+                                                           uint64_t n, uint64_t cap, const BatchOp* __restrict__ bops,
+                                                           uint32_t iword, uint32_t ishift, uint64_t imask,
+                                                           uint64_t* lb, DevMeta* meta, uint32_t epoch, uint32_t xo) {
+  __shared__ uint32_t s_wtot[1][kBlock / 64];
+  __shared__ uint64_t s_off;
+  __shared__ uint64_t s_lb[12];
+  __shared__ uint64_t s_red[2 * kMaxW * 4];
+  __shared__ uint32_t s_tile;
+  const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
+  const uint64_t ntiles = (n + kBlock - 1) / kBlock;
+  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
+  const uint64_t e = (uint64_t)tile * kBlock + threadIdx.x;
+  uint64_t key[W];
+  double2 a = make_double2(0.0, 0.0);
+  uint32_t k = 0, b = 0, cnt = 0;
+  bool copy = true;
+  const BatchOp* op = nullptr;
+#pragma unroll
+  for (int w = 0; w < W; ++w) key[w] = 0;
+  if (e < n) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) key[w] = in_keys.w[w][e];
+    a = in_amp[e];
+    op = &bops[inst_of<W>(key, iword, ishift, imask)];
+    k = op->k;
+    copy = k == 0 || (op->has_ctl && !controls_hold<W>(key, op->cmask, op->cval));
+    if (copy) {
+      cnt = 1;
+    } else {
+      for (uint32_t j = 0; j < k; ++j) b |= (uint32_t)((sel_word<W>(key, op->tword[j]) >> op->tbit[j]) & 1ull) << j;
+      // children reachable through nonzero elements: product over stages of
+      // the number of nonzero entries in column b_j
+      cnt = 1;
+      for (uint32_t j = 0; j < k; ++j) {
+        const uint32_t bj = (b >> j) & 1u;
+        const double e0 = bj ? op->m[0][1] : op->m[0][0];
+        const double e1 = bj ? op->m[1][1] : op->m[1][0];
+        cnt *= (uint32_t)(e0 != 0.0) + (uint32_t)(e1 != 0.0);
+      }
+    }
+  }
+  uint32_t cnta[1] = {cnt}, offa[1];
+  const uint64_t tile_total = tile_offsets<1>(cnta, offa, s_wtot);
+  {
+    const uint64_t ex = lookback_block(lb, tile, tile_total, epoch, &meta->err, s_lb);
+    if (threadIdx.x == 0) {
+      s_off = ex;
+      if (tile == ntiles - 1) {
+        meta->nnz_out[epoch % kRing] = ex + tile_total;
+        if (ex + tile_total > cap) atomicOr(&meta->err, kErrCapacity);
+      }
+    }
+  }
+  __syncthreads();
+  uint64_t orv[W], andv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    orv[w] = 0;
+    andv[w] = ~0ull;
+  }
+  uint64_t p = s_off + offa[0];
+  if (e < n) {
+    const uint32_t nchild = copy ? 1u : (1u << k);
+    for (uint32_t s = 0; s < nchild; ++s) {
+      uint64_t ok[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) ok[w] = key[w];
+      double2 v = a;
+      bool exists = true;
+      if (!copy) {
+        for (uint32_t j = 0; j < k; ++j) {
+          const uint32_t sj = (s >> j) & 1u, bj = (b >> j) & 1u;
+          const double c = sj ? (bj ? op->m[1][1] : op->m[1][0]) : (bj ? op->m[0][1] : op->m[0][0]);
+          if (c == 0.0) exists = false;
+          v.x = c * v.x;
+          v.y = c * v.y;
+          const uint64_t bit = 1ull << op->tbit[j];
+#pragma unroll
+          for (int w = 0; w < W; ++w)
+            if ((uint32_t)w == op->tword[j]) ok[w] = sj ? (ok[w] | bit) : (ok[w] & ~bit);
+        }
+      }
+      if (!exists) continue;
+      if (p < cap) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) out_keys.w[w][p] = ok[w];
+        out_amp[p] = v;
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        orv[w] |= ok[w];
+        andv[w] &= ok[w];
+      }
+      ++p;
+    }
+  }
+  publish_masks<W>(meta, epoch, orv, andv, s_red);
+}
+
+// Reduce-by-key over sorted candidates: the first entry of each run of equal
+// keys sums the run left to right; instances that branched this round drop
+// sums with |a|^2 < eps^2 or a == 0.  One output per run, compacted.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
+                                                           KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
+                                                           uint64_t n, uint64_t cap, const BatchOp* __restrict__ bops,
+                                                           uint32_t iword, uint32_t ishift, uint64_t imask,
+                                                           uint64_t* lb, DevMeta* meta, uint32_t epoch, uint32_t xo) {
+  __shared__ uint32_t s_wtot[1][kBlock / 64];
+  __shared__ uint64_t s_off;
+  __shared__ uint64_t s_lb[12];
+  __shared__ uint64_t s_red[2 * kMaxW * 4];
+  __shared__ uint32_t s_tile;
+  const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
+  const uint64_t ntiles = (n + kBlock - 1) / kBlock;
+  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
+  const uint64_t e = (uint64_t)tile * kBlock + threadIdx.x;
+  uint64_t key[W];
+  double2 sum = make_double2(0.0, 0.0);
+  bool keep = false;
+#pragma unroll
+  for (int w = 0; w < W; ++w) key[w] = 0;
+  if (e < n) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) key[w] = in_keys.w[w][e];
+    bool head = true;
+    if (e > 0) {
+      bool eq = true;
+#pragma unroll
+      for (int w = 0; w < W; ++w) eq = eq && in_keys.w[w][e - 1] == key[w];
+      head = !eq;
+    }
+    if (head) {
+      sum = in_amp[e];
+      uint64_t j = e + 1;
+      for (uint32_t m = 1; j < n && m < 64; ++m, ++j) {
+        bool eq = true;
+#pragma unroll
+        for (int w = 0; w < W; ++w) eq = eq && in_keys.w[w][j] == key[w];
+        if (!eq) break;
+        const double2 x = in_amp[j];
+        sum.x = sum.x + x.x;
+        sum.y = sum.y + x.y;
+      }
+      const BatchOp* op = &bops[inst_of<W>(key, iword, ishift, imask)];
+      keep = op->prune ? keep_amp(sum.x, sum.y, op->eps2) : true;
+    }
+  }
+  uint32_t cnta[1] = {keep ? 1u : 0u}, offa[1];
+  const uint64_t tile_total = tile_offsets<1>(cnta, offa, s_wtot);
+  {
+    const uint64_t ex = lookback_block(lb, tile, tile_total, epoch, &meta->err, s_lb);
+    if (threadIdx.x == 0) {
+      s_off = ex;
+      if (tile == ntiles - 1) {
+        meta->nnz_out[epoch % kRing] = ex + tile_total;
+        atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
+      }
+    }
+  }
+  __syncthreads();
+  uint64_t orv[W], andv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    orv[w] = keep ? key[w] : 0ull;
+    andv[w] = keep ? key[w] : ~0ull;
+  }
+  if (keep) {
+    const uint64_t p = s_off + offa[0];
+    if (p < cap) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) out_keys.w[w][p] = key[w];
+      out_amp[p] = sum;
+    }
+  }
+  publish_masks<W>(meta, epoch, orv, andv, s_red);
+}
+
+// ---------------------------------------------------------------------------
 // utility kernels
 // ---------------------------------------------------------------------------
 __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {

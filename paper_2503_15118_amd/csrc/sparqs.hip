@@ -968,6 +968,232 @@ void launch_pack(ss_state* st, const uint64_t* values, const double2* amps, uint
   k_pack<W><<<(uint32_t)((n + 255) / 256), 256, 0, st->stream>>>(values, amps, n, kp<W>(b), b.amp, at, pd);
 }
 
+// ---------------------------------------------------------------------------
+// Batched rounds (per-instance op lists)
+// ---------------------------------------------------------------------------
+// Upload `bytes` from `src` into the op ring; returns the device address.
+char* ring_upload(ss_state* st, const void* src, uint64_t bytes) {
+  const uint64_t need = align_up(std::max<uint64_t>(bytes, 1), kAlign);
+  if (st->ops_used + need > kOpRingBytes) {
+    if (hipStreamSynchronize(st->stream) != hipSuccess) return nullptr;
+    st->stats[6]++;
+    st->ops_used = 0;
+    trace_flush(st);
+  }
+  if (need > kOpRingBytes) return nullptr;
+  char* h = reinterpret_cast<char*>(st->hops) + st->ops_used;
+  char* d = reinterpret_cast<char*>(st->dev_ops) + st->ops_used;
+  if (bytes) std::memcpy(h, src, bytes);
+  if (bytes && hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st->stream) != hipSuccess) return nullptr;
+  st->ops_used += need;
+  return d;
+}
+
+template <int W>
+void launch_perm_batched_w(ss_state* st, const FastOp* f, const PermOp* g, const RunRange* runs, uint32_t ww,
+                           bool amp, uint32_t ep) {
+  const Buf& b = st->buf[st->cur];
+  const uint32_t grid = (uint32_t)((st->n + kBlock - 1) / kBlock);
+  if (amp)
+    k_perm_batched<W, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, f, g, runs, st->L.iword,
+                                                             st->L.ishift, st->L.imask, ww, st->meta, ep);
+  else
+    k_perm_batched<W, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, f, g, runs, st->L.iword,
+                                                              st->L.ishift, st->L.imask, ww, st->meta, ep);
+}
+
+template <int W>
+void launch_expand_batched_w(ss_state* st, const BatchOp* bops, uint32_t ep) {
+  const Buf& in = st->buf[st->cur];
+  const Buf& out = st->buf[st->cur ^ 1];
+  const uint32_t ntiles = (uint32_t)((st->n + kBlock - 1) / kBlock);
+  k_expand_batched<W><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->n, st->cap,
+                                                         bops, st->L.iword, st->L.ishift, st->L.imask, st->lb,
+                                                         st->meta, ep, xo(st));
+}
+
+template <int W>
+void launch_reduce_batched_w(ss_state* st, const BatchOp* bops, uint32_t ep) {
+  const Buf& in = st->buf[st->cur];
+  const Buf& out = st->buf[st->cur ^ 1];
+  const uint32_t ntiles = (uint32_t)((st->n + kBlock - 1) / kBlock);
+  k_reduce_batched<W><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->n, st->cap,
+                                                         bops, st->L.iword, st->L.ishift, st->L.imask, st->lb,
+                                                         st->meta, ep, xo(st));
+}
+
+// Every instance i runs ops[off[i] .. off[i+1]).  Round r: one fused launch
+// advances each instance through its non-branching ops up to its next
+// branching op; then one expansion applies each instance's branching op (up to
+// five target qubits; wider ops take several rounds), one LSD sort orders the
+// candidates by (instance, key) and one reduce-by-key merges equal keys.
+int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* off, ss_result* res) {
+  const uint32_t NI = st->ninst;
+  if (off[0] != 0 || off[NI] > nops) return SS_E_ARG;
+  for (uint32_t i = 0; i < NI; ++i)
+    if (off[i] > off[i + 1]) return SS_E_ARG;
+  std::vector<uint64_t> cur(off, off + NI), end(off + 1, off + NI + 1);
+  std::vector<uint32_t> chunk(NI, 0);
+  const uint32_t W = st->L.W;
+  uint64_t round = 0;
+  std::vector<RunRange> runs(NI);
+  std::vector<BatchOp> bops(NI);
+  while (true) {
+    // --- non-branching runs -------------------------------------------------
+    bool any_run = false;
+    uint32_t i0 = 0;
+    while (i0 < NI) {
+      std::vector<FastOp> fast;
+      std::vector<PermOp> gen;
+      uint32_t ww = 0;
+      bool amp = false;
+      std::fill(runs.begin(), runs.end(), RunRange{0u, 0u});
+      uint32_t i = i0;
+      for (; i < NI; ++i) {
+        if (chunk[i] != 0) continue;
+        uint64_t j = cur[i];
+        uint64_t len = 0;
+        while (j + len < end[i] && !is_branching(ops[j + len].kind)) ++len;
+        if (len == 0) continue;
+        // keep one launch's op tables well inside the staging ring
+        const uint64_t bytes = (fast.size() + len) * sizeof(FastOp) + (gen.size() + len) * sizeof(PermOp);
+        if (!fast.empty() && bytes > kOpRingBytes / 2) break;
+        runs[i].start = (uint32_t)fast.size();
+        runs[i].len = (uint32_t)len;
+        for (uint64_t q = 0; q < len; ++q) {
+          const ss_op& op = ops[j + q];
+          if (op.kind == SS_REFLECT0) amp = true;
+          else ww |= 1u << st->L.regs[op.reg].word;
+          FastOp f = W <= 2 ? encode_fast(st, op, (uint32_t)gen.size()) : FastOp{};
+          if (W > 2) {
+            f.code = F_GEN;
+            f.gi = (uint32_t)gen.size();
+          }
+          if (f.code == F_GEN) gen.push_back(to_perm(st, op));
+          fast.push_back(f);
+        }
+        cur[i] = j + len;
+      }
+      if (!fast.empty() && st->n > 0) {
+        char* dr = ring_upload(st, runs.data(), NI * sizeof(RunRange));
+        char* df = ring_upload(st, fast.data(), fast.size() * sizeof(FastOp));
+        char* dg = ring_upload(st, gen.data(), gen.size() * sizeof(PermOp));
+        if (!dr || !df || !dg) return hip_fail(st);
+        const uint32_t ep = next_epoch(st);
+        const int tr = trace_begin(st, SS_TRACE_PERM);
+        const FastOp* f = reinterpret_cast<const FastOp*>(df);
+        const PermOp* g = reinterpret_cast<const PermOp*>(dg);
+        const RunRange* r = reinterpret_cast<const RunRange*>(dr);
+        if (W == 1) launch_perm_batched_w<1>(st, f, g, r, ww, amp, ep);
+        else if (W == 2) launch_perm_batched_w<2>(st, f, g, r, ww, amp, ep);
+        else launch_perm_batched_w<4>(st, f, g, r, ww, amp, ep);
+        trace_end(st, tr, st->n * (8ull * W + 8ull * (uint64_t)__builtin_popcount(ww) + (amp ? 32ull : 0ull)), st->n);
+        int rc = check_launch(st);
+        if (rc) return rc;
+        st->masks_stale = true;
+        st->mask_epoch = ep;
+        st->stats[5]++;
+        any_run = true;
+      }
+      i0 = i;
+    }
+    // --- branching ops --------------------------------------------------------
+    bool any_branch = false;
+    for (uint32_t i = 0; i < NI; ++i) {
+      BatchOp& b = bops[i];
+      b = BatchOp{};
+      if (cur[i] >= end[i]) continue;
+      const ss_op& op = ops[cur[i]];
+      const RegInfo& d = st->L.regs[op.reg];
+      std::vector<uint32_t> qs;
+      for (uint32_t q = 0; q < d.width; ++q)
+        if ((op.qmask >> q) & 1ull) qs.push_back(q);
+      const size_t c0 = (size_t)chunk[i] * kMaxGroupBits, c1 = std::min(qs.size(), c0 + kMaxGroupBits);
+      const bool last = c1 == qs.size();
+      b.k = (uint32_t)(c1 - c0);
+      for (size_t j = c0; j < c1; ++j) {
+        b.tword[j - c0] = d.word;
+        b.tbit[j - c0] = d.shift + qs[j];
+      }
+      ctl_masks(st, op, b.cmask, b.cval);
+      b.has_ctl = op.nctl ? 1u : 0u;
+      if (op.kind == SS_H) {
+        const double c = 0.70710678118654752440;
+        b.m[0][0] = c; b.m[0][1] = c; b.m[1][0] = c; b.m[1][1] = -c;
+      } else {
+        const double h = op.theta / 2.0;
+        const double c = std::cos(h), s2 = std::sin(h);
+        b.m[0][0] = c; b.m[0][1] = -s2; b.m[1][0] = s2; b.m[1][1] = c;
+      }
+      b.prune = 1;
+      b.eps2 = last ? st->eps * st->eps : 0.0;
+      if (last) {
+        chunk[i] = 0;
+        cur[i]++;
+      } else {
+        chunk[i]++;
+      }
+      any_branch = true;
+    }
+    if (!any_branch) {
+      if (!any_run) break;
+      bool left = false;
+      for (uint32_t i = 0; i < NI; ++i) left = left || cur[i] < end[i];
+      if (!left) break;
+      continue;
+    }
+    ++round;
+    if (st->n == 0) continue;
+    char* db = ring_upload(st, bops.data(), NI * sizeof(BatchOp));
+    if (!db) return hip_fail(st);
+    const BatchOp* bo = reinterpret_cast<const BatchOp*>(db);
+    // expand
+    uint32_t ep = next_epoch(st);
+    int tr = trace_begin(st, SS_TRACE_EXPAND);
+    if (W == 1) launch_expand_batched_w<1>(st, bo, ep);
+    else if (W == 2) launch_expand_batched_w<2>(st, bo, ep);
+    else launch_expand_batched_w<4>(st, bo, ep);
+    trace_end(st, tr, st->n * entry_bytes(W), st->n);
+    int rc = check_launch(st);
+    if (rc) return rc;
+    const uint64_t n_par = st->n;
+    rc = finish_emit(st, ep, true);
+    if (rc == SS_E_CAPACITY) {
+      res->failed_op = round;
+      return rc;
+    }
+    if (rc) return rc;
+    if (tr >= 0) trace_add_output(st, SS_TRACE_EXPAND, st->n);
+    (void)n_par;
+    // sort candidates by (instance, key)
+    uint64_t var[kMaxW], skip[kMaxW] = {0, 0, 0, 0};
+    for (int w = 0; w < kMaxW; ++w) var[w] = st->orm[w] & ~st->andm[w];
+    SortPlan plan;
+    build_plan(W, {}, skip, var, plan);
+    rc = run_sort(st, plan);
+    if (rc) return rc;
+    // reduce by key + prune
+    ep = next_epoch(st);
+    tr = trace_begin(st, SS_TRACE_FILTER);
+    if (W == 1) launch_reduce_batched_w<1>(st, bo, ep);
+    else if (W == 2) launch_reduce_batched_w<2>(st, bo, ep);
+    else launch_reduce_batched_w<4>(st, bo, ep);
+    trace_end(st, tr, st->n * entry_bytes(W), st->n);
+    rc = check_launch(st);
+    if (rc) return rc;
+    rc = finish_emit(st, ep, false);
+    if (rc) return rc;
+    if (tr >= 0) trace_add_output(st, SS_TRACE_FILTER, st->n);
+  }
+  st->grouped = false;
+  int rc = ensure_masks(st);
+  if (!rc && (st->hmeta->err & (kErrSpin | kErrGroup))) rc = hip_fail(st);
+  res->status = rc;
+  res->nnz = st->n;
+  res->peak = st->peak;
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1177,7 +1403,6 @@ int ss_apply_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* 
   if (!res) res = &local;
   *res = ss_result{};
   if (nops && !ops) return SS_E_ARG;
-  if (inst_offsets) return SS_E_ARG;  // per-instance op lists: see the batch runner
   for (uint64_t i = 0; i < nops; ++i) {
     rc = validate_op(st, ops[i]);
     if (rc) {
@@ -1185,6 +1410,11 @@ int ss_apply_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* 
       res->failed_op = i;
       return rc;
     }
+  }
+  if (inst_offsets) {
+    rc = apply_batched(st, ops, nops, inst_offsets, res);
+    res->status = rc;
+    return rc;
   }
   std::vector<ss_op> run;
   for (uint64_t i = 0; i < nops; ++i) {

@@ -125,6 +125,22 @@ struct GroupOp {
   double eps2;                  // prune below this |a|^2 (strict)
 };
 
+// Per-instance tables of a batched round (instances with their own op lists).
+struct RunRange {
+  uint32_t start, len;          // FastOp range of the instance's non-branching run
+};
+
+struct BatchOp {
+  uint32_t k;                   // target qubits this round (0: the entry passes through)
+  uint32_t has_ctl;
+  uint32_t prune;               // 1: the instance branched this round; apply eps2 after merging
+  uint32_t pad;
+  uint32_t tword[kMaxGroupBits], tbit[kMaxGroupBits];
+  uint64_t cmask[kMaxW], cval[kMaxW];
+  double m[2][2];
+  double eps2;
+};
+
 // A digit of one radix pass = sum of up to kMaxFields bit runs of the key:
 //   digit |= ((key[word] >> shift) & ((1 << width) - 1)) << dshift
 struct PassDesc {

@@ -260,3 +260,39 @@ def test_reversed_pairs_after_flip(abi):
         ])
         c = wl.Circuit(regs=[("a", 4), ("b", 3)], ops=ops, name=f"reversed-pairs-ctl{len(ctl)}")
         _check(abi, c)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_batched_instances_match_oracle_and_plain(abi, seed):
+    """Per-instance op lists in one state: each instance equals the oracle and
+    its own plain single-instance run."""
+    from paper_2503_15118_amd import batch
+    circ = wl.c3_batch(seed, ninst=12, lo_bits=4.0, hi_bits=11.0, len_lo=40, len_hi=160)
+    print(f"[case] batched c3-form seed {seed}: {len(circ)} instances", flush=True)
+    st, res = batch.run_batched(circ, cap_entries=1 << 18)
+    plain = batch.run_sequential(circ, cap_entries=1 << 14)
+    for i, c in enumerate(circ):
+        gk, ga = st.export(i)
+        ora, _, _ = run_circuit(c)
+        ok, _, oa = ora.export()
+        compare(gk, ga, ok, oa, c.eps)
+        pk, pa = plain[i]
+        compare(gk, ga, pk, pa, c.eps)
+
+
+def test_batched_mixed_kinds(abi):
+    """Batched rounds with every op kind (random small circuits, QRAM table
+    shared), uneven lengths including an empty op list."""
+    from paper_2503_15118_amd import batch
+    base = wl.random_small_circuit(3, nops=1)
+    circ = []
+    for i in range(6):
+        c = wl.random_small_circuit(100 + i, nops=[30, 0, 55, 12, 41, 25][i], max_h=5)
+        c.tables = base.tables
+        circ.append(c)
+    st, res = batch.run_batched(circ, cap_entries=1 << 16)
+    for i, c in enumerate(circ):
+        gk, ga = st.export(i)
+        ora, _, _ = run_circuit(c)
+        ok, _, oa = ora.export()
+        compare(gk, ga, ok, oa, c.eps)
