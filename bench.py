@@ -26,6 +26,27 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published peak
 
 
+def counter_traffic(kernel_label):
+    """HBM bytes per launch of `kernel_label` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy of known size),
+    or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "c2_hbm_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2503_15118_amd", "csrc")
+    sha = hashlib.sha256(open(os.path.join(src, "kernels.hip"), "rb").read()
+                         + open(os.path.join(src, "kernels_common.hpp"), "rb").read()).hexdigest()[:16]
+    if kv.get("sources_sha") != sha or kernel_label not in kv.get("traffic_kernel", ""):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(circ, nops_sample):
     """The oracle (std::map, one core) on a bounded sample of the same circuit:
     the H prelude and the first `nops_sample` ops after it."""
@@ -37,6 +58,69 @@ def cpu_baseline(circ, nops_sample):
     return {"value": ent / sec, "unit": "entries/s", "cores": 1, "kind": "oracle",
             "sample": f"prelude H on 20 qubits + first {nops_sample} ops of the same circuit "
                       f"({ent} entry updates in {sec:.1f} s, std::map oracle, one thread)"}
+
+
+def bench_batched(args):
+    """Batching: many C1-form instances (per-instance caps log-uniform in
+    [2^6, 2^18], 200..1000 ops each) in one state, against the same instances
+    run one at a time through the plain path on the same GPU."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2503_15118_amd import _abi, batch
+
+    t0 = time.perf_counter()
+    circ = wl.c3_batch(args.seed, ninst=args.ninst)
+    gen_s = time.perf_counter() - t0
+    ops, off = batch.concat_ops(circ)
+    # plain path, one instance at a time (apply calls timed)
+    st = _abi.State(circ[0].regs, eps=circ[0].eps, cap_entries=1 << 20, table_bytes=0)
+    zero = np.zeros((1, len(circ[0].regs)), dtype=np.uint64)
+    one = np.array([1.0 + 0j])
+    seq_s = 0.0
+    entries = 0
+    peak_sum = 0
+    plain_ops = [_abi.to_ss_ops(c.ops) for c in circ]
+    st.apply(plain_ops[0])  # warm-up
+    for c, o in zip(circ, plain_ops):
+        st.set_entries(0, zero, one)
+        e0 = st.stats()["entries_updated"]
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        st.apply(o)
+        torch.cuda.synchronize()
+        seq_s += time.perf_counter() - ta
+        entries += st.stats()["entries_updated"] - e0
+        peak_sum += st.nnz()
+    st.close()
+    # batched
+    cap = 1 << args.batch_cap_log2
+    bs = batch.batch_state(circ, cap_entries=cap, table_bytes=0)
+    bs.set_option("trace", 1)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    res = bs.apply(ops, inst_offsets=off)
+    torch.cuda.synchronize()
+    bat_s = time.perf_counter() - tb
+    tr = bs.trace()
+    stats = bs.stats()
+    out = {
+        "workload": f"batching: {args.ninst} C1-form instances (20-bit key, caps 2^6..2^18 log-uniform, "
+                    f"200..1000 ops), seed {args.seed}",
+        "entries_updated": int(entries),
+        "sequential_plain_s": seq_s,
+        "batched_s": bat_s,
+        "batched_vs_plain": seq_s / bat_s,
+        "sequential_entries_per_s": entries / seq_s,
+        "batched_entries_per_s": entries / bat_s,
+        "final_nnz_sum": int(res.nnz),
+        "rounds_sorts": stats["sorts"],
+        "kernels": {k: {"launches": v["launches"], "ms": 1e3 * v["seconds"],
+                        "GBps": v["bytes"] / v["seconds"] / 1e9 if v["seconds"] else None}
+                    for k, v in tr.items() if v["launches"]},
+        "generation_s": gen_s,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -52,16 +136,33 @@ def main():
     ap.add_argument("--sort-items", type=int, default=16)
     ap.add_argument("--perm-entries", type=int, default=8)
     ap.add_argument("--tile-order", type=int, default=1)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 64 MiB device copy first (reference for HBM counters)")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
+    ap.add_argument("--ninst", type=int, default=1024)
+    ap.add_argument("--batch-cap-log2", type=int, default=28)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding is a design note, not an implemented path", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "c3":
+        bench_batched(args)
+        return
+
     import numpy as np
     import torch
     import workloads as wl
     from paper_2503_15118_amd import _abi
+
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     circ = wl.c2_circuit(args.seed)
     ops = _abi.to_ss_ops(circ.ops)
@@ -109,6 +210,7 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     d = tr[dom]
     achieved = d["bytes"] / d["seconds"] / 1e9
+    traffic = counter_traffic("k_perm_fast") if dom == "perm" else None
     gpu_kernel_ms = sum(k["ms_per_step"] for k in kernels.values())
 
     out = {
@@ -144,7 +246,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
         },
         "hbm_gbps": achieved,
         "gpu_kernel_ms_per_step": gpu_kernel_ms,
