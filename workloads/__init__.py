@@ -444,3 +444,56 @@ def qram_circuit(seed, addr_bits: int, word_bits: int, superpose: bool = True) -
     return Circuit(regs=regs, ops=ops_array(ops),
                    tables=[Table(values=values, addr_bits=addr_bits, word_bits=word_bits)],
                    name=f"qram{addr_bits}x{word_bits}")
+
+
+# ---------------------------------------------------------------------------
+# C5: a Poisson request stream mixing the C1..C4 forms
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class TraceItem:
+    arrival: float
+    kind: str                     # "c1" | "c2" | "c3" | "c4"
+    circuits: List[Circuit]       # one circuit, or C4-form right-hand sides sharing one op list
+    peak: int                     # the generator's bound on the peak entry count
+
+
+def c5_trace(seed, rate: float = 200.0, duration: float = 30.0, lo_bits: float = 8.0,
+             hi_bits: float = 24.0, c4_steps: int = 200, c4_matrix_n: int = 1024,
+             max_requests: Optional[int] = None) -> List[TraceItem]:
+    """Poisson arrivals at `rate` per second for `duration` seconds.  Kind is
+    uniform over the four forms; the target peak is P = 2^u, u ~ U[lo, hi]:
+    C1/C3 forms (one C1-form circuit) need P <= 2^18, else the kind is redrawn
+    among C2/C4; a C2-form request runs H on log2(P) - 1 qubits of a; a
+    C4-form request carries max(1, P / 2^14) right-hand sides."""
+    rng = _rng(seed)
+    t = 0.0
+    items: List[TraceItem] = []
+    A = None
+    words = None
+    k = 0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t > duration or (max_requests is not None and len(items) >= max_requests):
+            break
+        kind = ("c1", "c2", "c3", "c4")[int(rng.integers(0, 4))]
+        u = float(rng.uniform(lo_bits, hi_bits))
+        if kind in ("c1", "c3") and u > 18.0:
+            kind = ("c2", "c4")[int(rng.integers(0, 2))]
+        sub = int(rng.integers(0, 2 ** 31))
+        if kind in ("c1", "c3"):
+            cb = max(2, int(np.floor(u)))
+            circs = [c1_circuit(sub, nops=300, cap_bits=cb)]
+            peak = 2 ** cb
+        elif kind == "c2":
+            h = max(1, int(np.floor(u)) - 1)
+            circs = [c2_circuit(sub, nops=1000, n_ry=10, h_qubits=h)]
+            peak = 2 ** (h + 1)
+        else:
+            if A is None:
+                A = c4_matrix(seed, n=c4_matrix_n)
+            nrhs = max(1, int(2 ** np.floor(u)) // (c4_matrix_n * 16))
+            circs = c4_batch(sub, nrhs=nrhs, steps=c4_steps, n=c4_matrix_n, A=A)
+            peak = nrhs * c4_matrix_n * 16
+        items.append(TraceItem(arrival=t, kind=kind, circuits=circs, peak=peak))
+        k += 1
+    return items
