@@ -241,12 +241,14 @@ def main():
 
     st.set_option("trace", 1)
     st.set_option("trace_reset", 1)
+    sy0 = st.stats()["host_syncs"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    syncs = (st.stats()["host_syncs"] - sy0) / args.steps
     tr = st.trace()
     st.set_option("trace", 0)
 
@@ -305,6 +307,7 @@ def main():
         },
         "hbm_gbps": achieved,
         "gpu_kernel_ms_per_step": gpu_kernel_ms,
+        "host_syncs_per_step": syncs,
         "kernels": kernels,
     }
     if not args.no_cpu_baseline:

@@ -167,6 +167,14 @@ class State:
                "ss_create_state")
         self.h = h
         self.table_ids = []
+        self.table_bytes = int(table_bytes)
+
+    def rebind(self, cap_entries: int):
+        """Move the state into a new arena sized for `cap_entries` entries."""
+        nb = required_bytes(self.regs, self.ninst, cap_entries, self.table_bytes)
+        arena = self.torch.empty(int(nb), dtype=self.torch.uint8, device=self.device)
+        _check(lib.ss_rebind_arena(self.h, ctypes.c_void_p(arena.data_ptr()), int(nb)), "ss_rebind_arena")
+        self.arena = arena
 
     def close(self):
         if getattr(self, "h", None):

@@ -62,17 +62,6 @@ __device__ __forceinline__ bool keep_amp(double re, double im, double eps2) {
   return !(n2 < eps2) && !(re == 0.0 && im == 0.0);
 }
 
-__device__ __forceinline__ void ring_reset(DevMeta* meta, uint32_t epoch) {
-  const uint32_t r = (epoch + kRing / 2) % kRing;
-  meta->counters[r] = 0;
-  for (int x = 0; x < kXcds; ++x) meta->xcd_ctr[r][x * kXcdStride] = 0;
-  meta->nnz_out[r] = 0;
-  for (int w = 0; w < kMaxW; ++w) {
-    meta->or_mask[r][w] = 0;
-    meta->and_mask[r][w] = ~0ull;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // k_perm: fused run of non-branching ops
 // ---------------------------------------------------------------------------
@@ -127,11 +116,13 @@ __device__ __forceinline__ void perm_apply(uint64_t (&k)[W], double2& a, const P
 
 template <int W, bool AMP>
 __global__ __launch_bounds__(kBlock) void k_perm(KeyPtrs<W> keys, double2* __restrict__ amp,
-                                                 uint64_t n, const PermOp* __restrict__ ops,
+                                                 uint32_t ns, const PermOp* __restrict__ ops,
                                                  uint32_t nops, uint32_t write_words,
                                                  DevMeta* meta, uint32_t epoch) {
   __shared__ uint64_t s_red[2 * kMaxW * 4];
-  if (blockIdx.x == 0 && threadIdx.x == 0) ring_reset(meta, epoch);
+  if (launch_prologue(meta, epoch)) return;
+  const uint64_t n = meta->nring[ns & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) meta->upd += n * nops;
   uint64_t orv[W], andv[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) {
@@ -389,12 +380,19 @@ __device__ __forceinline__ void fast_step(uint32_t (&h)[E][4], double2 (&a)[E], 
 #undef SQ_E
 
 template <int W, int E, bool AMP>
-__global__ __launch_bounds__(kBlock) void k_perm_fast(KeyPtrs<W> keys, double2* __restrict__ amp, uint64_t n,
+__global__ __launch_bounds__(kBlock) void k_perm_fast(KeyPtrs<W> keys, double2* __restrict__ amp, uint32_t ns,
                                                       const FastOp* __restrict__ ops, uint32_t nops,
                                                       const PermOp* __restrict__ gops, uint32_t write_words,
                                                       DevMeta* meta, uint32_t epoch) {
   __shared__ uint64_t s_red[2 * kMaxW * 4];
-  if (blockIdx.x == 0 && threadIdx.x == 0) ring_reset(meta, epoch);
+  if (launch_prologue(meta, epoch)) return;
+  const uint64_t n = meta->nring[ns & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    meta->upd += n * nops;
+    if ((uint64_t)gridDim.x * kBlock * E < n) raise_error(meta, kErrGrid, epoch);
+  }
+  // the grid comes from an upper bound of the count
+  if ((uint64_t)blockIdx.x * kBlock * E >= n) return;
   uint32_t h[E][4];
   double2 a[E];
   const uint64_t base = (uint64_t)blockIdx.x * kBlock * E + threadIdx.x;
@@ -505,6 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(KeyPtrs<W> in_keys, const 
   __shared__ uint32_t s_tile;
 
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (launch_prologue(meta, epoch)) return;
 #pragma unroll
   for (int w = 0; w < kBlock / 64; ++w) s_wcount[w][tid] = 0;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
@@ -687,7 +686,7 @@ __device__ __forceinline__ uint64_t tile_offsets(const uint32_t (&cnt)[ITEMS], u
 template <int W, int K, int MODE, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                   KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
-                                                  uint64_t n, uint64_t cap, GroupOp op, uint64_t* lb,
+                                                  uint32_t ns, uint64_t cap, GroupOp op, uint64_t* lb,
                                                   DevMeta* meta, uint32_t epoch, uint32_t xo) {
   constexpr uint32_t G = 1u << K;
   constexpr uint32_t TILE = kBlock * ITEMS;
@@ -696,6 +695,9 @@ __global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const doub
   __shared__ uint64_t s_lb[12];
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
+  uint64_t n;
+  if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
+  if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) meta->upd += n;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + TILE - 1) / TILE;
   if (tile_out_of_range(tile, ntiles, &meta->err)) return;
@@ -787,8 +789,9 @@ __global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const doub
       s_off = ex;
       if (tile == ntiles - 1) {
         meta->nnz_out[epoch % kRing] = ex + tile_total;
-        atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
-        if (ex + tile_total > cap) atomicOr(&meta->err, kErrCapacity);
+        meta->nring[(ns & 1) ^ 1] = ex + tile_total;
+        if (ex + tile_total > cap) raise_error(meta, kErrCapacity, epoch);
+        else atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
       }
     }
   }
@@ -837,7 +840,7 @@ __global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const doub
 template <int W, int MODE, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                  KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
-                                                 uint64_t n, uint64_t cap, GroupOp op, uint64_t* lb,
+                                                 uint32_t ns, uint64_t cap, GroupOp op, uint64_t* lb,
                                                  DevMeta* meta, uint32_t epoch, uint32_t xo) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   __shared__ uint32_t s_wtot[ITEMS][kBlock / 64];
@@ -845,6 +848,9 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
   __shared__ uint64_t s_lb[12];
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
+  uint64_t n;
+  if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
+  if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) meta->upd += n;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + TILE - 1) / TILE;
   if (tile_out_of_range(tile, ntiles, &meta->err)) return;
@@ -923,8 +929,9 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
       s_off = ex;
       if (tile == ntiles - 1) {
         meta->nnz_out[epoch % kRing] = ex + tile_total;
-        atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
-        if (ex + tile_total > cap) atomicOr(&meta->err, kErrCapacity);
+        meta->nring[(ns & 1) ^ 1] = ex + tile_total;
+        if (ex + tile_total > cap) raise_error(meta, kErrCapacity, epoch);
+        else atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
       }
     }
   }
@@ -986,7 +993,7 @@ struct FilterOp {
 template <int W, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_filter(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                    KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
-                                                   uint64_t n, uint64_t cap, FilterOp f, uint64_t* lb,
+                                                   uint32_t ns, uint64_t cap, FilterOp f, uint64_t* lb,
                                                    DevMeta* meta, uint32_t epoch, uint32_t xo) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   __shared__ uint32_t s_wtot[ITEMS][kBlock / 64];
@@ -994,6 +1001,8 @@ __global__ __launch_bounds__(kBlock) void k_filter(KeyPtrs<W> in_keys, const dou
   __shared__ uint64_t s_lb[12];
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
+  uint64_t n;
+  if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + TILE - 1) / TILE;
   if (tile_out_of_range(tile, ntiles, &meta->err)) return;
@@ -1034,7 +1043,10 @@ __global__ __launch_bounds__(kBlock) void k_filter(KeyPtrs<W> in_keys, const dou
     const uint64_t ex = lookback_block(lb, tile, tile_total, epoch, &meta->err, s_lb);
     if (threadIdx.x == 0) {
       s_off = ex;
-      if (tile == ntiles - 1) meta->nnz_out[epoch % kRing] = ex + tile_total;
+      if (tile == ntiles - 1) {
+        meta->nnz_out[epoch % kRing] = ex + tile_total;
+        meta->nring[(ns & 1) ^ 1] = ex + tile_total;
+      }
     }
   }
   __syncthreads();
@@ -1074,14 +1086,17 @@ __device__ __forceinline__ uint32_t inst_of(const uint64_t (&k)[W], uint32_t iwo
 // the distinct instances among its lanes one at a time, so the op index stays
 // uniform and the interpreter's dispatch stays scalar.
 template <int W, bool AMP>
-__global__ __launch_bounds__(kBlock) void k_perm_batched(KeyPtrs<W> keys, double2* __restrict__ amp, uint64_t n,
+__global__ __launch_bounds__(kBlock) void k_perm_batched(KeyPtrs<W> keys, double2* __restrict__ amp, uint32_t ns,
                                                          const FastOp* __restrict__ ops,
                                                          const PermOp* __restrict__ gops,
                                                          const RunRange* __restrict__ runs, uint32_t iword,
                                                          uint32_t ishift, uint64_t imask, uint32_t write_words,
                                                          DevMeta* meta, uint32_t epoch) {
   __shared__ uint64_t s_red[2 * kMaxW * 4];
-  if (blockIdx.x == 0 && threadIdx.x == 0) ring_reset(meta, epoch);
+  if (launch_prologue(meta, epoch)) return;
+  const uint64_t n = meta->nring[ns & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (uint64_t)gridDim.x * kBlock < n) raise_error(meta, kErrGrid, epoch);
+  if ((uint64_t)blockIdx.x * kBlock >= n) return;
   const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool valid = i < n;
   uint32_t h[1][4] = {{0u, 0u, 0u, 0u}};
@@ -1138,7 +1153,7 @@ __global__ __launch_bounds__(kBlock) void k_perm_batched(KeyPtrs<W> keys, double
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                            KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
-                                                           uint64_t n, uint64_t cap, const BatchOp* __restrict__ bops,
+                                                           uint32_t ns, uint64_t cap, const BatchOp* __restrict__ bops,
                                                            uint32_t iword, uint32_t ishift, uint64_t imask,
                                                            uint64_t* lb, DevMeta* meta, uint32_t epoch, uint32_t xo) {
   __shared__ uint32_t s_wtot[1][kBlock / 64];
@@ -1146,6 +1161,8 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
   __shared__ uint64_t s_lb[12];
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
+  uint64_t n;
+  if (!emit_begin(meta, ns, epoch, kBlock, &n)) return;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + kBlock - 1) / kBlock;
   if (tile_out_of_range(tile, ntiles, &meta->err)) return;
@@ -1187,7 +1204,8 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
       s_off = ex;
       if (tile == ntiles - 1) {
         meta->nnz_out[epoch % kRing] = ex + tile_total;
-        if (ex + tile_total > cap) atomicOr(&meta->err, kErrCapacity);
+        meta->nring[(ns & 1) ^ 1] = ex + tile_total;
+        if (ex + tile_total > cap) raise_error(meta, kErrCapacity, epoch);
       }
     }
   }
@@ -1243,7 +1261,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                            KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
-                                                           uint64_t n, uint64_t cap, const BatchOp* __restrict__ bops,
+                                                           uint32_t ns, uint64_t cap, const BatchOp* __restrict__ bops,
                                                            uint32_t iword, uint32_t ishift, uint64_t imask,
                                                            uint64_t* lb, DevMeta* meta, uint32_t epoch, uint32_t xo) {
   __shared__ uint32_t s_wtot[1][kBlock / 64];
@@ -1251,6 +1269,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
   __shared__ uint64_t s_lb[12];
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
+  uint64_t n;
+  if (!emit_begin(meta, ns, epoch, kBlock, &n)) return;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + kBlock - 1) / kBlock;
   if (tile_out_of_range(tile, ntiles, &meta->err)) return;
@@ -1294,6 +1314,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
       s_off = ex;
       if (tile == ntiles - 1) {
         meta->nnz_out[epoch % kRing] = ex + tile_total;
+        meta->nring[(ns & 1) ^ 1] = ex + tile_total;
         atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
       }
     }
@@ -1344,7 +1365,44 @@ __global__ void k_xcc_probe(uint64_t* out) {
 }
 
 __global__ void k_clear_err(DevMeta* meta) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) meta->err = 0;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    meta->err = 0;
+    meta->err_epoch = 0;
+  }
+}
+
+// Host-known entry count into ring slot `ns` (after imports and rebinds).
+__global__ void k_set_n(DevMeta* meta, uint32_t ns, uint64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    meta->nring[ns & 1] = n;
+    if (n > meta->peak) meta->peak = n;
+  }
+}
+
+// OR / AND of all keys, for when the masks of the launch that produced the
+// entries have left the ring.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_masks(KeyPtrs<W> keys, uint32_t ns, uint64_t cap, DevMeta* meta,
+                                                  uint32_t epoch) {
+  __shared__ uint64_t s_red[2 * kMaxW * 4];
+  if (launch_prologue(meta, epoch)) return;
+  const uint64_t nr = meta->nring[ns & 1];
+  const uint64_t n = nr < cap ? nr : cap;
+  uint64_t orv[W], andv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    orv[w] = 0;
+    andv[w] = ~0ull;
+  }
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint64_t v = keys.w[w][i];
+      orv[w] |= v;
+      andv[w] &= v;
+    }
+  }
+  publish_masks<W>(meta, epoch, orv, andv, s_red);
 }
 
 __global__ void k_meta_init(DevMeta* meta) {
@@ -1359,12 +1417,16 @@ __global__ void k_meta_init(DevMeta* meta) {
       }
     }
     meta->peak = 0;
+    meta->upd = 0;
+    meta->nring[0] = meta->nring[1] = 0;
     meta->err = 0;
+    meta->err_epoch = 0;
   }
 }
 
 // Pack register values (n x nregs, row-major) into keys and append them at
-// position `at`; the instance field gets `inst`.
+// position `at`; the instance field gets `inst` (has_inst == 1) or `inst`
+// plus the row index (has_inst == 2).
 struct PackDesc {
   uint32_t nregs, has_inst, iword, ishift;
   uint64_t inst;
@@ -1387,9 +1449,10 @@ __global__ void k_pack(const uint64_t* __restrict__ values, const double2* __res
       if (pd.word[r] == (uint32_t)w) k[w] |= v << pd.shift[r];
   }
   if (pd.has_inst) {
+    const uint64_t iv = pd.has_inst == 2 ? pd.inst + i : pd.inst;
 #pragma unroll
     for (int w = 0; w < W; ++w)
-      if (pd.iword == (uint32_t)w) k[w] |= pd.inst << pd.ishift;
+      if (pd.iword == (uint32_t)w) k[w] |= iv << pd.ishift;
   }
 #pragma unroll
   for (int w = 0; w < W; ++w) keys.w[w][at + i] = k[w];

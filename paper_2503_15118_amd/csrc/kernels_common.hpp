@@ -248,8 +248,7 @@ __device__ __forceinline__ uint32_t xcc_id() {
 // its k-th workgroup to start takes tile 8k + x: the counters see 8x less
 // contention, and a tile waits only on lower tiles, each taken by a running
 // workgroup or by one that its XCD will still start.  Otherwise one counter
-// hands out tiles in start order.  The first workgroup of a launch clears the
-// ring slot that a launch kRing/2 epochs later will use.
+// hands out tiles in start order.
 __device__ __forceinline__ uint32_t take_tile(DevMeta* meta, uint32_t epoch, uint32_t* s_tile,
                                               uint32_t xcd_order) {
   if (threadIdx.x == 0) {
@@ -262,7 +261,20 @@ __device__ __forceinline__ uint32_t take_tile(DevMeta* meta, uint32_t epoch, uin
       t = (uint32_t)atomicAdd(&meta->counters[slot], 1ull);
     }
     *s_tile = t;
-    if (t == 0) {
+  }
+  __syncthreads();
+  return *s_tile;
+}
+
+// Launch prologue of every kernel that owns an epoch: workgroup 0 clears the
+// ring slot a launch kRing/2 epochs later will use.  Returns true (the same
+// value in every thread of the workgroup) when an earlier launch raised an
+// error: the kernel then changes nothing, and the host rolls the state back to
+// the input of the failing launch.
+__device__ __forceinline__ bool launch_prologue(DevMeta* meta, uint32_t epoch) {
+  __shared__ unsigned int s_err;
+  if (threadIdx.x == 0) {
+    if (blockIdx.x == 0) {
       const uint32_t r = (epoch + kRing / 2) % kRing;
       meta->counters[r] = 0;
       for (int x = 0; x < kXcds; ++x) meta->xcd_ctr[r][x * kXcdStride] = 0;
@@ -272,16 +284,44 @@ __device__ __forceinline__ uint32_t take_tile(DevMeta* meta, uint32_t epoch, uin
         meta->and_mask[r][w] = ~0ull;
       }
     }
+    s_err = *reinterpret_cast<volatile unsigned int*>(&meta->err);
   }
   __syncthreads();
-  return *s_tile;
+  return s_err != 0u;
 }
 
-// A tile id beyond the launch's tile count can only come from a corrupted
-// counter slot; such a workgroup flags the error and touches no data.
+__device__ __forceinline__ void raise_error(DevMeta* meta, uint32_t bits, uint32_t epoch) {
+  atomicOr(&meta->err, bits);
+  atomicCAS(&meta->err_epoch, 0u, epoch);
+}
+
+// Start of an emitting launch that reads its entry count from ring slot `ns`
+// and writes the output count to the other slot.  Grids are sized from an
+// upper bound of the count: a workgroup past the count's tiles leaves before
+// taking a tile ticket, so tickets go to exactly ceil(n / tile) workgroups.
+// Returns false when the workgroup has nothing to do (an earlier error, an
+// empty input: workgroup 0 then records an empty output, or excess).  A grid
+// smaller than the count is flagged rather than leaving entries behind.
+__device__ __forceinline__ bool emit_begin(DevMeta* meta, uint32_t ns, uint32_t epoch, uint64_t tile_entries,
+                                           uint64_t* n_out) {
+  if (launch_prologue(meta, epoch)) return false;
+  const uint64_t n = meta->nring[ns & 1];
+  *n_out = n;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (n == 0) {
+      meta->nring[(ns & 1) ^ 1] = 0;
+      meta->nnz_out[epoch % kRing] = 0;
+    }
+    if ((uint64_t)gridDim.x * tile_entries < n) raise_error(meta, kErrGrid, epoch);
+  }
+  return (uint64_t)blockIdx.x * tile_entries < n;
+}
+
+// A tile id at or past the tile count cannot be handed out when only
+// workgroups inside the count take tickets; such a workgroup touches nothing.
 __device__ __forceinline__ bool tile_out_of_range(uint32_t tile, uint64_t ntiles, unsigned int* err) {
   if (tile < ntiles) return false;
-  if (threadIdx.x == 0) atomicOr(err, kErrSpin);
+  if (threadIdx.x == 0) atomicOr(err, kErrGrid);
   return true;
 }
 

@@ -154,15 +154,33 @@ struct ss_state {
   char* tab_base = nullptr;
   uint64_t tab_used = 0;
   std::vector<TableInfo> tables;
-  // host mirrors
-  uint64_t n = 0, peak = 0;
+  // Host view of the entry count.  The count itself lives on the device in
+  // meta->nring[nslot]: an emitting launch reads slot nslot and writes the
+  // other one.  Between synchronisations the host knows an upper bound only.
+  uint32_t nslot = 0;
+  uint64_t n = 0;                 // exact count (valid when n_known)
+  bool n_known = true;
+  uint64_t n_ub = 0;              // upper bound of the count (== n when known)
+  uint32_t n_src_ep = 0;          // launch whose output count is current (0: n is exact)
+  uint64_t peak = 0;
+  // key masks: OR / AND over all keys, per word
   uint64_t orm[kMaxW]{}, andm[kMaxW]{};
-  bool masks_stale = false;
-  uint32_t mask_epoch = 0;
+  bool masks_valid = false;       // orm/andm describe the current entries
+  uint32_t mask_ep = 0;           // launch whose ring slot holds them (0: none, recompute)
   uint32_t epoch = 0;
   bool grouped = false;
   uint64_t gmask[kMaxW]{};
   bool poisoned = false;
+  // capacity-checked launches since the last synchronisation, for rollback
+  struct EmitLog {
+    uint32_t ep;
+    int cur;
+    uint32_t nslot;
+    uint64_t op;
+  };
+  std::vector<EmitLog> emits;
+  bool rolled_back = false;       // the last synchronisation rolled back a launch
+  uint64_t rb_op = 0;             // ... whose op index (batched: round) this is
   uint32_t dev_err = 0;           // kernel-side error bits seen at the last read-back
   DevMeta* hmeta = nullptr;       // pinned read-back block
   PermOp* hops = nullptr;         // pinned op staging (kMaxOpsPerCall)
@@ -178,12 +196,17 @@ struct ss_state {
   // per-launch HIP-event timing (option "trace")
   bool trace = false;
   std::vector<hipEvent_t> ev_pool;
+  // Bytes and entries of a traced launch depend on counts that the host
+  // learns at the next synchronisation: input count n_in (exact, or the
+  // output of launch in_ep), output count (of launch out_ep, if it emits).
   struct TraceRec {
     uint32_t cat;
     hipEvent_t a, b;
-    uint64_t bytes, entries;
+    uint32_t in_ep, out_ep;
+    uint64_t in_n, in_per, out_per, ent_mult;
   };
   std::vector<TraceRec> pending;
+  uint32_t trace_old_ep = 0;      // oldest launch a pending record refers to
   double tr_sec[SS_TRACE_NCAT]{};
   uint64_t tr_cnt[SS_TRACE_NCAT]{}, tr_bytes[SS_TRACE_NCAT]{}, tr_entries[SS_TRACE_NCAT]{};
 };
@@ -202,18 +225,6 @@ KeyPtrs<W> kp(const Buf& b) {
   KeyPtrs<W> p;
   for (int w = 0; w < W; ++w) p.w[w] = b.key[w];
   return p;
-}
-
-uint32_t next_epoch(ss_state* st) {
-  st->epoch = (st->epoch + 1) & kEpochMask;
-  if (st->epoch == 0) {
-    // the 24-bit tag wrapped: clear every look-back word before reuse
-    k_fill_u64<<<1024, 256, 0, st->stream>>>(st->lb, st->cv.lb_words, 0ull);
-    k_ring_init<<<1, 64, 0, st->stream>>>(st->meta);
-    st->epoch = 1;
-  }
-  st->stats[0]++;
-  return st->epoch;
 }
 
 int hip_fail(ss_state* st) {
@@ -241,44 +252,57 @@ int trace_begin(ss_state* st, uint32_t cat) {
     }
   }
   (void)hipEventRecord(ev[0], st->stream);
-  st->pending.push_back({cat, ev[0], ev[1], 0, 0});
+  ss_state::TraceRec r{};
+  r.cat = cat;
+  r.a = ev[0];
+  r.b = ev[1];
+  st->pending.push_back(r);
   return (int)st->pending.size() - 1;
 }
 
-void trace_end(ss_state* st, int idx, uint64_t bytes, uint64_t entries) {
+// Close a record: input bytes/entries per input entry, output bytes per
+// output entry of the emitting launch `out_ep` (0: none).
+void trace_end(ss_state* st, int idx, uint64_t in_per, uint64_t ent_mult, uint32_t out_ep, uint64_t out_per) {
   if (idx < 0) return;
   auto& r = st->pending[(size_t)idx];
-  r.bytes = bytes;
-  r.entries = entries;
+  r.in_ep = st->n_src_ep;
+  r.in_n = st->n;
+  r.in_per = in_per;
+  r.ent_mult = ent_mult;
+  r.out_ep = out_ep;
+  r.out_per = out_per;
+  for (uint32_t e : {r.in_ep, r.out_ep})
+    if (e && (st->trace_old_ep == 0 || e < st->trace_old_ep)) st->trace_old_ep = e;
   (void)hipEventRecord(r.b, st->stream);
 }
 
-// After a stream synchronisation: fold finished event pairs into the totals.
+// After a read-back of the meta block: fold finished records into the totals.
 void trace_flush(ss_state* st) {
+  const DevMeta* hm = st->hmeta;
   for (auto& r : st->pending) {
     float ms = 0.f;
+    const uint64_t n_in = r.in_ep ? hm->nnz_out[r.in_ep % kRing] : r.in_n;
+    const uint64_t n_out = r.out_ep ? hm->nnz_out[r.out_ep % kRing] : 0;
     if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
       st->tr_sec[r.cat] += ms * 1e-3;
       st->tr_cnt[r.cat] += 1;
-      st->tr_bytes[r.cat] += r.bytes;
-      st->tr_entries[r.cat] += r.entries;
+      st->tr_bytes[r.cat] += n_in * r.in_per + n_out * r.out_per;
+      st->tr_entries[r.cat] += n_in * r.ent_mult;
     }
     st->ev_pool.push_back(r.a);
     st->ev_pool.push_back(r.b);
   }
   st->pending.clear();
+  st->trace_old_ep = 0;
 }
 
-// Wait for the stream and copy the device meta block to pinned memory.
-int readback(ss_state* st) {
-  if (hipMemcpyAsync(st->hmeta, st->meta, sizeof(DevMeta), hipMemcpyDeviceToHost, st->stream) != hipSuccess)
-    return hip_fail(st);
-  if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
-  st->dev_err |= st->hmeta->err;
-  st->stats[6]++;
-  st->ops_used = 0;
-  trace_flush(st);
-  return SS_OK;
+void drop_trace(ss_state* st) {
+  for (auto& r : st->pending) {
+    st->ev_pool.push_back(r.a);
+    st->ev_pool.push_back(r.b);
+  }
+  st->pending.clear();
+  st->trace_old_ep = 0;
 }
 
 void take_masks(ss_state* st, uint32_t ep) {
@@ -287,20 +311,140 @@ void take_masks(ss_state* st, uint32_t ep) {
     st->orm[w] = st->hmeta->or_mask[r][w];
     st->andm[w] = st->hmeta->and_mask[r][w];
   }
-  st->masks_stale = false;
+  st->masks_valid = true;
 }
 
-int ensure_masks(ss_state* st) {
-  if (!st->masks_stale) return SS_OK;
-  int rc = readback(st);
-  if (rc) return rc;
-  take_masks(st, st->mask_epoch);
+void set_known(ss_state* st, uint64_t n) {
+  st->n = n;
+  st->n_known = true;
+  st->n_ub = n;
+  st->n_src_ep = 0;
+}
+
+// Synchronise: wait for the stream, copy the status part of the device meta
+// block to pinned memory and bring the host view up to date.  A launch that
+// ran out of capacity made every later launch a no-op; the state returns to
+// that launch's input (buffer and count), and SS_E_CAPACITY is returned with
+// rolled_back / rb_op set.  Any other kernel-side error poisons the state.
+int sync_state(ss_state* st) {
+  st->rolled_back = false;
+  if (st->poisoned) return SS_E_STATE;
+  if (hipMemcpyAsync(st->hmeta, st->meta, offsetof(DevMeta, dscratch), hipMemcpyDeviceToHost, st->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(st->stream) != hipSuccess)
+    return hip_fail(st);
+  st->stats[6]++;
+  st->ops_used = 0;
+  const DevMeta* hm = st->hmeta;
+  st->dev_err |= hm->err;
+  trace_flush(st);
+  st->peak = hm->peak;
+  st->stats[7] = hm->upd;
+  if (hm->err & ~kErrCapacity) {
+    st->emits.clear();
+    return hip_fail(st);
+  }
+  if (hm->err & kErrCapacity) {
+    const ss_state::EmitLog* e = nullptr;
+    for (const auto& x : st->emits)
+      if (x.ep == hm->err_epoch) e = &x;
+    if (!e) {
+      st->emits.clear();
+      return hip_fail(st);
+    }
+    st->cur = e->cur;
+    st->nslot = e->nslot;
+    st->rb_op = e->op;
+    st->rolled_back = true;
+    set_known(st, hm->nring[e->nslot]);
+    st->masks_valid = false;
+    st->mask_ep = 0;
+    st->grouped = false;
+    st->emits.clear();
+    k_clear_err<<<1, 64, 0, st->stream>>>(st->meta);
+    if (check_launch(st)) return SS_E_HIP;
+    return SS_E_CAPACITY;
+  }
+  st->emits.clear();
+  set_known(st, hm->nring[st->nslot]);
+  if (!st->masks_valid && st->mask_ep && st->epoch - st->mask_ep < (uint32_t)kRing / 2) take_masks(st, st->mask_ep);
+  if (st->epoch >= kEpochMask - 4096) {
+    // the 24-bit look-back tag is about to wrap: start over with clean words
+    k_fill_u64<<<1024, 256, 0, st->stream>>>(st->lb, st->cv.lb_words, 0ull);
+    k_ring_init<<<1, 64, 0, st->stream>>>(st->meta);
+    st->stats[0] += 2;
+    st->epoch = 0;
+    st->mask_ep = 0;
+    if (check_launch(st)) return SS_E_HIP;
+  }
   return SS_OK;
 }
 
-int clear_err(ss_state* st) {
-  k_clear_err<<<1, 64, 0, st->stream>>>(st->meta);
-  return check_launch(st);
+// Before a launch that takes an epoch: synchronise when a pending trace
+// record or the current count's source is about to leave the ring, or when
+// the epoch nears its wrap (handled inside sync_state).
+int begin_launch(ss_state* st, uint32_t* ep) {
+  const uint32_t lim = kRing / 2 - 8;
+  bool need = st->epoch >= kEpochMask - 4096;
+  if (st->trace) {
+    need = need || (st->trace_old_ep && st->epoch - st->trace_old_ep >= lim);
+    need = need || (st->n_src_ep && st->epoch - st->n_src_ep >= lim);
+  }
+  if (need) {
+    const int rc = sync_state(st);
+    if (rc) return rc;
+  }
+  st->epoch++;
+  st->stats[0]++;
+  *ep = st->epoch;
+  return SS_OK;
+}
+
+// After an emitting launch: the output is in the other buffer and slot.
+// `logged`: the launch checks capacity, so a failure can roll back to here.
+void after_emit(ss_state* st, uint32_t ep, uint64_t bound, bool logged, uint64_t op) {
+  if (logged) st->emits.push_back({ep, st->cur, st->nslot, op});
+  st->cur ^= 1;
+  st->nslot ^= 1;
+  st->n_known = false;
+  st->n_ub = std::min(st->cap, bound);
+  st->n_src_ep = ep;
+  st->masks_valid = false;
+  st->mask_ep = ep;
+}
+
+int ensure_n(ss_state* st) {
+  if (st->n_known) return SS_OK;
+  return sync_state(st);
+}
+
+template <int W>
+void launch_masks_w(ss_state* st, uint32_t ep) {
+  const Buf& b = st->buf[st->cur];
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((st->n_ub + kBlock - 1) / kBlock, 2048));
+  k_masks<W><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), st->nslot, st->cap, st->meta, ep);
+}
+
+// Exact key masks of the current entries (synchronises unless known).
+int ensure_masks(ss_state* st) {
+  if (st->masks_valid) return SS_OK;
+  if (st->mask_ep == 0 || st->epoch - st->mask_ep >= (uint32_t)kRing / 2 - 8) {
+    uint32_t ep;
+    int rc = begin_launch(st, &ep);
+    if (rc) return rc;
+    switch (st->L.W) {
+      case 1: launch_masks_w<1>(st, ep); break;
+      case 2: launch_masks_w<2>(st, ep); break;
+      default: launch_masks_w<4>(st, ep); break;
+    }
+    rc = check_launch(st);
+    if (rc) return rc;
+    st->mask_ep = ep;
+  }
+  int rc = sync_state(st);
+  if (rc) return rc;
+  if (!st->masks_valid) return hip_fail(st);
+  return SS_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -340,11 +484,13 @@ int run_sort_w(ss_state* st, const SortPlan& plan) {
   k_sort_hist<W><<<nb, kBlock, plan.npass * kRadix * 4, st->stream>>>(kp<W>(st->buf[st->cur]), n, plan,
                                                                        st->hist);
   k_sort_scan<<<plan.npass, kBlock, 0, st->stream>>>(st->hist, nb, plan.npass, st->digit_start);
-  trace_end(st, tr, n * 8 * W, n);
+  trace_end(st, tr, 8ull * W, 1, 0, 0);
   st->stats[0] += 2;
   const uint32_t ntiles = (uint32_t)((n + tile - 1) / tile);
   for (uint32_t p = 0; p < plan.npass; ++p) {
-    const uint32_t ep = next_epoch(st);
+    uint32_t ep;
+    int rc = begin_launch(st, &ep);
+    if (rc) return rc;
     const Buf& in = st->buf[st->cur];
     const Buf& out = st->buf[st->cur ^ 1];
     tr = trace_begin(st, SS_TRACE_SORT_PASS);
@@ -356,7 +502,7 @@ int run_sort_w(ss_state* st, const SortPlan& plan) {
       k_sort_pass<W, 8><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, n,
                                                             plan.pass[p], st->digit_start + p * kRadix,
                                                             st->lb, st->meta, ep, xo(st));
-    trace_end(st, tr, 2 * n * entry_bytes(W), n);
+    trace_end(st, tr, 2 * entry_bytes(W), 1, 0, 0);
     st->cur ^= 1;
     st->stats[1]++;
   }
@@ -365,7 +511,10 @@ int run_sort_w(ss_state* st, const SortPlan& plan) {
   return check_launch(st);
 }
 
+// LSD sort of the current entries; needs the exact count.
 int run_sort(ss_state* st, const SortPlan& plan) {
+  int rc = ensure_n(st);
+  if (rc) return rc;
   switch (st->L.W) {
     case 1: return run_sort_w<1>(st, plan);
     case 2: return run_sort_w<2>(st, plan);
@@ -391,22 +540,23 @@ template <int W, int K, int ITEMS>
 void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
-  const uint32_t ntiles = (uint32_t)((st->n + kBlock * ITEMS - 1) / (kBlock * ITEMS));
+  const uint32_t ns = st->nslot;
+  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock * ITEMS - 1) / (kBlock * ITEMS));
   if (K == 1) {
     if (mode == MODE_GROUP)
       k_pair<W, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
-                                                                       st->n, st->cap, g, st->lb, st->meta, ep, xo(st));
+                                                                       ns, st->cap, g, st->lb, st->meta, ep, xo(st));
     else
       k_pair<W, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
-                                                                        st->n, st->cap, g, st->lb, st->meta, ep, xo(st));
+                                                                        ns, st->cap, g, st->lb, st->meta, ep, xo(st));
     return;
   }
   if (mode == MODE_GROUP)
     k_group<W, K, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
-                                                                         st->n, st->cap, g, st->lb, st->meta, ep, xo(st));
+                                                                         ns, st->cap, g, st->lb, st->meta, ep, xo(st));
   else
     k_group<W, K, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
-                                                                          st->n, st->cap, g, st->lb, st->meta, ep, xo(st));
+                                                                          ns, st->cap, g, st->lb, st->meta, ep, xo(st));
 }
 
 // Items per thread: several for one or two targets (bigger tiles, fewer
@@ -430,55 +580,33 @@ void launch_group_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep) {
   }
 }
 
-// Finish an emitting launch: read back, check errors, swap buffers.
-int finish_emit(ss_state* st, uint32_t ep, bool check_cap) {
-  int rc = readback(st);
-  if (rc) return rc;
-  const DevMeta* hm = st->hmeta;
-  if (hm->err & (kErrSpin | kErrGroup)) return hip_fail(st);
-  const uint64_t nout = hm->nnz_out[ep % kRing];
-  if (check_cap && ((hm->err & kErrCapacity) || nout > st->cap)) {
-    clear_err(st);
-    return SS_E_CAPACITY;
-  }
-  st->cur ^= 1;
-  st->n = nout;
-  st->peak = std::max(st->peak, nout);
-  take_masks(st, ep);
-  return SS_OK;
-}
-
-// Output bytes of an emitting launch are known only after it finished.
-void trace_add_output(ss_state* st, uint32_t cat, uint64_t nout) {
-  st->tr_bytes[cat] += nout * entry_bytes(st->L.W);
-}
-
 template <int W>
 void launch_filter_w(ss_state* st, const FilterOp& f, uint32_t ep) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
   constexpr int ITEMS = 4;
-  const uint32_t ntiles = (uint32_t)((st->n + kBlock * ITEMS - 1) / (kBlock * ITEMS));
-  k_filter<W, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->n, st->cap,
-                                                        f, st->lb, st->meta, ep, xo(st));
+  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock * ITEMS - 1) / (kBlock * ITEMS));
+  k_filter<W, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
+                                                        st->cap, f, st->lb, st->meta, ep, xo(st));
 }
 
+// Compaction (never grows the state); asynchronous.
 int run_filter(ss_state* st, const FilterOp& f) {
-  if (st->n == 0) return SS_OK;
-  const uint32_t ep = next_epoch(st);
-  const uint64_t n_in = st->n;
+  if (st->n_ub == 0) return SS_OK;
+  uint32_t ep;
+  int rc = begin_launch(st, &ep);
+  if (rc) return rc;
   const int tr = trace_begin(st, SS_TRACE_FILTER);
   switch (st->L.W) {
     case 1: launch_filter_w<1>(st, f, ep); break;
     case 2: launch_filter_w<2>(st, f, ep); break;
     default: launch_filter_w<4>(st, f, ep); break;
   }
-  trace_end(st, tr, n_in * entry_bytes(st->L.W), n_in);
-  int rc = check_launch(st);
+  trace_end(st, tr, entry_bytes(st->L.W), 1, ep, entry_bytes(st->L.W));
+  rc = check_launch(st);
   if (rc) return rc;
-  rc = finish_emit(st, ep, false);
-  if (rc == SS_OK && tr >= 0) trace_add_output(st, SS_TRACE_FILTER, st->n);
-  return rc;
+  after_emit(st, ep, st->n_ub, false, 0);
+  return SS_OK;
 }
 
 FilterOp base_filter(const ss_state* st, uint32_t inst) {
@@ -726,13 +854,13 @@ template <int W, int E>
 void launch_perm_fast(ss_state* st, const FastOp* f, uint32_t nfast, const PermOp* gops, uint32_t write_words,
                       bool amp, uint32_t ep) {
   const Buf& b = st->buf[st->cur];
-  const uint32_t grid = (uint32_t)((st->n + kBlock * E - 1) / (kBlock * E));
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock * E - 1) / (kBlock * E));
   if (amp)
-    k_perm_fast<W, E, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, f, nfast, gops, write_words,
-                                                             st->meta, ep);
+    k_perm_fast<W, E, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->nslot, f, nfast, gops,
+                                                             write_words, st->meta, ep);
   else
-    k_perm_fast<W, E, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, f, nfast, gops, write_words,
-                                                              st->meta, ep);
+    k_perm_fast<W, E, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->nslot, f, nfast, gops,
+                                                              write_words, st->meta, ep);
 }
 
 template <int W>
@@ -744,18 +872,41 @@ void launch_perm_w(ss_state* st, const void* dev, uint32_t nfast, const PermOp* 
     else launch_perm_fast<W, 4>(st, f, nfast, gops, write_words, amp, ep);
   } else {
     const Buf& b = st->buf[st->cur];
-    const uint32_t grid = (uint32_t)std::min<uint64_t>((st->n + kBlock - 1) / kBlock, 8192);
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((st->n_ub + kBlock - 1) / kBlock, 8192));
     if (amp)
-      k_perm<W, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, gops, nfast, write_words, st->meta, ep);
+      k_perm<W, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->nslot, gops, nfast, write_words,
+                                                       st->meta, ep);
     else
-      k_perm<W, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, gops, nfast, write_words, st->meta, ep);
+      k_perm<W, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->nslot, gops, nfast, write_words,
+                                                        st->meta, ep);
   }
+}
+
+// Copy `bytes` into the pinned staging ring and on to the device op ring (on
+// the stream); *dev gets the device address.  A full ring waits for the
+// stream (a synchronisation) before reuse.
+int ring_upload(ss_state* st, const void* src, uint64_t bytes, char** dev) {
+  const uint64_t need = align_up(std::max<uint64_t>(bytes, 1), kAlign);
+  if (need > kOpRingBytes) return SS_E_ARG;
+  if (st->ops_used + need > kOpRingBytes) {
+    const int rc = sync_state(st);
+    if (rc) return rc;
+  }
+  char* h = reinterpret_cast<char*>(st->hops) + st->ops_used;
+  char* d = reinterpret_cast<char*>(st->dev_ops) + st->ops_used;
+  if (bytes) {
+    std::memcpy(h, src, bytes);
+    if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st->stream) != hipSuccess) return hip_fail(st);
+  }
+  st->ops_used += need;
+  *dev = d;
+  return SS_OK;
 }
 
 // Launch the pending run of non-branching ops (one fused kernel per chunk).
 int flush_run(ss_state* st, std::vector<ss_op>& run) {
   if (run.empty()) return SS_OK;
-  if (st->n == 0) {
+  if (st->n_ub == 0) {
     run.clear();
     return SS_OK;
   }
@@ -780,21 +931,15 @@ int flush_run(ss_state* st, std::vector<ss_op>& run) {
       }
     }
     const uint64_t fbytes = align_up(fast.size() * sizeof(FastOp), kAlign);
-    const uint64_t bytes = fbytes + gen.size() * sizeof(PermOp);
-    if (st->ops_used + bytes > kOpRingBytes) {
-      // staging ring full: wait for the stream before reusing it
-      if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
-      st->stats[6]++;
-      st->ops_used = 0;
-      trace_flush(st);
-    }
-    char* h = reinterpret_cast<char*>(st->hops) + st->ops_used;
-    char* d = reinterpret_cast<char*>(st->dev_ops) + st->ops_used;
-    if (!fast.empty()) std::memcpy(h, fast.data(), fast.size() * sizeof(FastOp));
-    if (!gen.empty()) std::memcpy(h + fbytes, gen.data(), gen.size() * sizeof(PermOp));
-    if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st->stream) != hipSuccess) return hip_fail(st);
-    st->ops_used += align_up(bytes, kAlign);
-    const uint32_t ep = next_epoch(st);
+    std::vector<char> blob(fbytes + gen.size() * sizeof(PermOp));
+    if (!fast.empty()) std::memcpy(blob.data(), fast.data(), fast.size() * sizeof(FastOp));
+    if (!gen.empty()) std::memcpy(blob.data() + fbytes, gen.data(), gen.size() * sizeof(PermOp));
+    char* d = nullptr;
+    int rc = ring_upload(st, blob.data(), blob.size(), &d);
+    if (rc) return rc;
+    uint32_t ep;
+    rc = begin_launch(st, &ep);
+    if (rc) return rc;
     const int tr = trace_begin(st, SS_TRACE_PERM);
     const PermOp* gops = reinterpret_cast<const PermOp*>(d + fbytes);
     switch (W) {
@@ -802,12 +947,12 @@ int flush_run(ss_state* st, std::vector<ss_op>& run) {
       case 2: launch_perm_w<2>(st, d, chunk, gops, write_words, amp, ep); break;
       default: launch_perm_w<4>(st, d, chunk, gops, write_words, amp, ep); break;
     }
-    trace_end(st, tr, st->n * (8ull * W + 8ull * (uint64_t)__builtin_popcount(write_words) + (amp ? 32ull : 0ull)),
-              st->n * chunk);
-    int rc = check_launch(st);
+    trace_end(st, tr, 8ull * W + 8ull * (uint64_t)__builtin_popcount(write_words) + (amp ? 32ull : 0ull), chunk, 0,
+              0);
+    rc = check_launch(st);
     if (rc) return rc;
-    st->masks_stale = true;
-    st->mask_epoch = ep;
+    st->masks_valid = false;
+    st->mask_ep = ep;
     st->stats[5]++;
     i += chunk;
   }
@@ -816,7 +961,7 @@ int flush_run(ss_state* st, std::vector<ss_op>& run) {
 }
 
 // One branching op: chunks of at most kMaxGroupBits target qubits, ascending.
-int do_branching(ss_state* st, const ss_op& op) {
+int do_branching(ss_state* st, const ss_op& op, uint64_t op_index) {
   const RegInfo& d = st->L.regs[op.reg];
   std::vector<uint32_t> qs;
   for (uint32_t q = 0; q < d.width; ++q)
@@ -832,15 +977,22 @@ int do_branching(ss_state* st, const ss_op& op) {
   }
   // An op split over several launches cannot be rolled back once its first
   // part has run, so it is admitted only if the worst case fits.
-  if (qs.size() > (size_t)kMaxGroupBits &&
-      (qs.size() >= 40 || (st->n << qs.size()) > st->cap || ((st->n << qs.size()) >> qs.size()) != st->n))
-    return SS_E_CAPACITY;
+  if (qs.size() > (size_t)kMaxGroupBits) {
+    if (qs.size() >= 40) return SS_E_CAPACITY;
+    auto fits = [&](uint64_t n) { return (n << qs.size()) <= st->cap && ((n << qs.size()) >> qs.size()) == n; };
+    if (!fits(st->n_ub)) {
+      int rc = ensure_n(st);
+      if (rc) return rc;
+      if (!fits(st->n)) return SS_E_CAPACITY;
+    }
+  }
   for (size_t c0 = 0; c0 < qs.size(); c0 += kMaxGroupBits) {
-    if (st->n == 0) return SS_OK;
+    if (st->n_ub == 0) return SS_OK;
     const size_t c1 = std::min(qs.size(), c0 + kMaxGroupBits);
     const bool last = c1 == qs.size();
     GroupOp g{};
     g.k = (uint32_t)(c1 - c0);
+    g.upd = c0 == 0 ? 1u : 0u;
     std::vector<std::pair<uint32_t, uint32_t>> tl;
     for (size_t j = c0; j < c1; ++j) {
       const uint32_t bit = d.shift + qs[j];
@@ -878,8 +1030,11 @@ int do_branching(ss_state* st, const ss_op& op) {
         if (rc) return rc;
         mode = MODE_GROUP;
       }
+      if (st->n_ub == 0) return SS_OK;
     }
-    const uint32_t ep = next_epoch(st);
+    uint32_t ep;
+    int rc = begin_launch(st, &ep);
+    if (rc) return rc;
     const uint32_t cat = mode == MODE_GROUP ? SS_TRACE_GROUP : SS_TRACE_EXPAND;
     const int tr = trace_begin(st, cat);
     switch (st->L.W) {
@@ -887,19 +1042,11 @@ int do_branching(ss_state* st, const ss_op& op) {
       case 2: launch_group_w<2>(st, mode, g, ep); break;
       default: launch_group_w<4>(st, mode, g, ep); break;
     }
-    trace_end(st, tr, st->n * entry_bytes(st->L.W), st->n);
-    int rc = check_launch(st);
+    trace_end(st, tr, entry_bytes(st->L.W), 1, ep, entry_bytes(st->L.W));
+    rc = check_launch(st);
     if (rc) return rc;
     st->stats[mode == MODE_GROUP ? 3 : 4]++;
-    rc = finish_emit(st, ep, true);
-    if (rc == SS_OK && tr >= 0) trace_add_output(st, cat, st->n);
-    if (rc == SS_E_CAPACITY) {
-      // parents are intact in buf[cur] (possibly re-ordered by the sort)
-      st->grouped = (mode == MODE_GROUP);
-      for (int w = 0; w < kMaxW; ++w) st->gmask[w] = g.tmask[w];
-      return rc;
-    }
-    if (rc) return rc;
+    after_emit(st, ep, st->n_ub << g.k, true, op_index);
     st->grouped = true;
     for (int w = 0; w < kMaxW; ++w) st->gmask[w] = g.tmask[w];
   }
@@ -958,6 +1105,15 @@ int init_device(ss_state* st) {
   for (int i = 0; i < kXcds; ++i)
     for (int j = 0; j < i; ++j) rr = rr && ids[i] != ids[j];
   st->xcd_order = rr ? 1u : 0u;
+  // device meta is fresh: empty state in slot 0, no pending launches
+  st->epoch = 0;
+  st->nslot = 0;
+  set_known(st, 0);
+  st->masks_valid = false;
+  st->mask_ep = 0;
+  st->grouped = false;
+  st->emits.clear();
+  st->ops_used = 0;
   return SS_OK;
 }
 
@@ -968,37 +1124,70 @@ void launch_pack(ss_state* st, const uint64_t* values, const double2* amps, uint
   k_pack<W><<<(uint32_t)((n + 255) / 256), 256, 0, st->stream>>>(values, amps, n, kp<W>(b), b.amp, at, pd);
 }
 
+// Append n entries (register values, row-major, and amplitudes; host arrays)
+// at the current exact count, staged through the alternate buffer; the
+// instance field gets `inst`, or `inst` + row index with `row_inst`.
+int pack_entries(ss_state* st, const uint64_t* values, const double* amps, uint64_t n, uint32_t inst,
+                 bool row_inst) {
+  const uint32_t nr = (uint32_t)st->L.regs.size();
+  PackDesc pd{};
+  pd.nregs = nr;
+  pd.has_inst = st->L.has_inst ? (row_inst ? 2u : 1u) : 0u;
+  pd.iword = st->L.iword;
+  pd.ishift = st->L.ishift;
+  pd.inst = inst;
+  for (uint32_t r = 0; r < nr; ++r) {
+    pd.word[r] = st->L.regs[r].word;
+    pd.shift[r] = st->L.regs[r].shift;
+    pd.mask[r] = st->L.regs[r].mask;
+  }
+  const Buf& alt = st->buf[st->cur ^ 1];
+  char* stage = reinterpret_cast<char*>(alt.key[0]);
+  const uint64_t stage_bytes = st->cap * entry_bytes(st->L.W);
+  const uint64_t per = (uint64_t)nr * 8 + 16;
+  const uint64_t chunk = std::max<uint64_t>(1, stage_bytes / per - 1);
+  uint64_t done = 0;
+  while (done < n) {
+    const uint64_t c = std::min(chunk, n - done);
+    uint64_t* dv = reinterpret_cast<uint64_t*>(stage);
+    double2* da = reinterpret_cast<double2*>(stage + align_up(c * nr * 8, 16));
+    if (hipMemcpyAsync(dv, values + done * nr, c * nr * 8, hipMemcpyHostToDevice, st->stream) != hipSuccess ||
+        hipMemcpyAsync(da, amps + 2 * done, c * 16, hipMemcpyHostToDevice, st->stream) != hipSuccess)
+      return hip_fail(st);
+    PackDesc pc = pd;
+    pc.inst = inst + (row_inst ? done : 0);
+    switch (st->L.W) {
+      case 1: launch_pack<1>(st, dv, da, c, st->n + done, pc); break;
+      case 2: launch_pack<2>(st, dv, da, c, st->n + done, pc); break;
+      default: launch_pack<4>(st, dv, da, c, st->n + done, pc); break;
+    }
+    int rc = check_launch(st);
+    if (rc) return rc;
+    // the caller's arrays and the staging area are reused by the next chunk
+    if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
+    done += c;
+  }
+  set_known(st, st->n + n);
+  k_set_n<<<1, 64, 0, st->stream>>>(st->meta, st->nslot, st->n);
+  st->masks_valid = false;
+  st->mask_ep = 0;
+  st->grouped = false;
+  return check_launch(st);
+}
+
 // ---------------------------------------------------------------------------
 // Batched rounds (per-instance op lists)
 // ---------------------------------------------------------------------------
-// Upload `bytes` from `src` into the op ring; returns the device address.
-char* ring_upload(ss_state* st, const void* src, uint64_t bytes) {
-  const uint64_t need = align_up(std::max<uint64_t>(bytes, 1), kAlign);
-  if (st->ops_used + need > kOpRingBytes) {
-    if (hipStreamSynchronize(st->stream) != hipSuccess) return nullptr;
-    st->stats[6]++;
-    st->ops_used = 0;
-    trace_flush(st);
-  }
-  if (need > kOpRingBytes) return nullptr;
-  char* h = reinterpret_cast<char*>(st->hops) + st->ops_used;
-  char* d = reinterpret_cast<char*>(st->dev_ops) + st->ops_used;
-  if (bytes) std::memcpy(h, src, bytes);
-  if (bytes && hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st->stream) != hipSuccess) return nullptr;
-  st->ops_used += need;
-  return d;
-}
-
 template <int W>
 void launch_perm_batched_w(ss_state* st, const FastOp* f, const PermOp* g, const RunRange* runs, uint32_t ww,
                            bool amp, uint32_t ep) {
   const Buf& b = st->buf[st->cur];
-  const uint32_t grid = (uint32_t)((st->n + kBlock - 1) / kBlock);
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock - 1) / kBlock);
   if (amp)
-    k_perm_batched<W, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, f, g, runs, st->L.iword,
+    k_perm_batched<W, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->nslot, f, g, runs, st->L.iword,
                                                              st->L.ishift, st->L.imask, ww, st->meta, ep);
   else
-    k_perm_batched<W, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->n, f, g, runs, st->L.iword,
+    k_perm_batched<W, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->nslot, f, g, runs, st->L.iword,
                                                               st->L.ishift, st->L.imask, ww, st->meta, ep);
 }
 
@@ -1006,20 +1195,20 @@ template <int W>
 void launch_expand_batched_w(ss_state* st, const BatchOp* bops, uint32_t ep) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
-  const uint32_t ntiles = (uint32_t)((st->n + kBlock - 1) / kBlock);
-  k_expand_batched<W><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->n, st->cap,
-                                                         bops, st->L.iword, st->L.ishift, st->L.imask, st->lb,
-                                                         st->meta, ep, xo(st));
+  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock - 1) / kBlock);
+  k_expand_batched<W><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
+                                                         st->cap, bops, st->L.iword, st->L.ishift, st->L.imask,
+                                                         st->lb, st->meta, ep, xo(st));
 }
 
 template <int W>
 void launch_reduce_batched_w(ss_state* st, const BatchOp* bops, uint32_t ep) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
-  const uint32_t ntiles = (uint32_t)((st->n + kBlock - 1) / kBlock);
-  k_reduce_batched<W><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->n, st->cap,
-                                                         bops, st->L.iword, st->L.ishift, st->L.imask, st->lb,
-                                                         st->meta, ep, xo(st));
+  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock - 1) / kBlock);
+  k_reduce_batched<W><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
+                                                         st->cap, bops, st->L.iword, st->L.ishift, st->L.imask,
+                                                         st->lb, st->meta, ep, xo(st));
 }
 
 // Every instance i runs ops[off[i] .. off[i+1]).  Round r: one fused launch
@@ -1074,24 +1263,33 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
         }
         cur[i] = j + len;
       }
-      if (!fast.empty() && st->n > 0) {
-        char* dr = ring_upload(st, runs.data(), NI * sizeof(RunRange));
-        char* df = ring_upload(st, fast.data(), fast.size() * sizeof(FastOp));
-        char* dg = ring_upload(st, gen.data(), gen.size() * sizeof(PermOp));
-        if (!dr || !df || !dg) return hip_fail(st);
-        const uint32_t ep = next_epoch(st);
+      if (!fast.empty() && st->n_ub > 0) {
+        // one upload: run table, fast ops, generic ops (a full ring
+        // synchronises, which must not happen between parts of one launch)
+        const uint64_t o_f = align_up(NI * sizeof(RunRange), kAlign);
+        const uint64_t o_g = o_f + align_up(fast.size() * sizeof(FastOp), kAlign);
+        std::vector<char> blob(o_g + gen.size() * sizeof(PermOp));
+        std::memcpy(blob.data(), runs.data(), NI * sizeof(RunRange));
+        std::memcpy(blob.data() + o_f, fast.data(), fast.size() * sizeof(FastOp));
+        if (!gen.empty()) std::memcpy(blob.data() + o_g, gen.data(), gen.size() * sizeof(PermOp));
+        char* d = nullptr;
+        int rc = ring_upload(st, blob.data(), blob.size(), &d);
+        if (rc) return rc;
+        uint32_t ep;
+        rc = begin_launch(st, &ep);
+        if (rc) return rc;
         const int tr = trace_begin(st, SS_TRACE_PERM);
-        const FastOp* f = reinterpret_cast<const FastOp*>(df);
-        const PermOp* g = reinterpret_cast<const PermOp*>(dg);
-        const RunRange* r = reinterpret_cast<const RunRange*>(dr);
+        const FastOp* f = reinterpret_cast<const FastOp*>(d + o_f);
+        const PermOp* g = reinterpret_cast<const PermOp*>(d + o_g);
+        const RunRange* r = reinterpret_cast<const RunRange*>(d);
         if (W == 1) launch_perm_batched_w<1>(st, f, g, r, ww, amp, ep);
         else if (W == 2) launch_perm_batched_w<2>(st, f, g, r, ww, amp, ep);
         else launch_perm_batched_w<4>(st, f, g, r, ww, amp, ep);
-        trace_end(st, tr, st->n * (8ull * W + 8ull * (uint64_t)__builtin_popcount(ww) + (amp ? 32ull : 0ull)), st->n);
-        int rc = check_launch(st);
+        trace_end(st, tr, 8ull * W + 8ull * (uint64_t)__builtin_popcount(ww) + (amp ? 32ull : 0ull), 1, 0, 0);
+        rc = check_launch(st);
         if (rc) return rc;
-        st->masks_stale = true;
-        st->mask_epoch = ep;
+        st->masks_valid = false;
+        st->mask_ep = ep;
         st->stats[5]++;
         any_run = true;
       }
@@ -1143,29 +1341,28 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
       continue;
     }
     ++round;
-    if (st->n == 0) continue;
-    char* db = ring_upload(st, bops.data(), NI * sizeof(BatchOp));
-    if (!db) return hip_fail(st);
+    if (st->n_ub == 0) continue;
+    uint32_t kmax = 0;
+    for (uint32_t i = 0; i < NI; ++i) kmax = std::max(kmax, bops[i].k);
+    char* db = nullptr;
+    int rc = ring_upload(st, bops.data(), NI * sizeof(BatchOp), &db);
+    if (rc) return rc;
     const BatchOp* bo = reinterpret_cast<const BatchOp*>(db);
-    // expand
-    uint32_t ep = next_epoch(st);
+    // expand (capacity-checked; a failure rolls back to this round's input)
+    uint32_t ep;
+    rc = begin_launch(st, &ep);
+    if (rc) return rc;
     int tr = trace_begin(st, SS_TRACE_EXPAND);
     if (W == 1) launch_expand_batched_w<1>(st, bo, ep);
     else if (W == 2) launch_expand_batched_w<2>(st, bo, ep);
     else launch_expand_batched_w<4>(st, bo, ep);
-    trace_end(st, tr, st->n * entry_bytes(W), st->n);
-    int rc = check_launch(st);
+    trace_end(st, tr, entry_bytes(W), 1, ep, entry_bytes(W));
+    rc = check_launch(st);
     if (rc) return rc;
-    const uint64_t n_par = st->n;
-    rc = finish_emit(st, ep, true);
-    if (rc == SS_E_CAPACITY) {
-      res->failed_op = round;
-      return rc;
-    }
+    after_emit(st, ep, st->n_ub << kmax, true, round);
+    // sort candidates by (instance, key): the plan needs the key masks
+    rc = ensure_masks(st);
     if (rc) return rc;
-    if (tr >= 0) trace_add_output(st, SS_TRACE_EXPAND, st->n);
-    (void)n_par;
-    // sort candidates by (instance, key)
     uint64_t var[kMaxW], skip[kMaxW] = {0, 0, 0, 0};
     for (int w = 0; w < kMaxW; ++w) var[w] = st->orm[w] & ~st->andm[w];
     SortPlan plan;
@@ -1173,25 +1370,19 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
     rc = run_sort(st, plan);
     if (rc) return rc;
     // reduce by key + prune
-    ep = next_epoch(st);
+    rc = begin_launch(st, &ep);
+    if (rc) return rc;
     tr = trace_begin(st, SS_TRACE_FILTER);
     if (W == 1) launch_reduce_batched_w<1>(st, bo, ep);
     else if (W == 2) launch_reduce_batched_w<2>(st, bo, ep);
     else launch_reduce_batched_w<4>(st, bo, ep);
-    trace_end(st, tr, st->n * entry_bytes(W), st->n);
+    trace_end(st, tr, entry_bytes(W), 1, ep, entry_bytes(W));
     rc = check_launch(st);
     if (rc) return rc;
-    rc = finish_emit(st, ep, false);
-    if (rc) return rc;
-    if (tr >= 0) trace_add_output(st, SS_TRACE_FILTER, st->n);
+    after_emit(st, ep, st->n_ub, false, round);
   }
   st->grouped = false;
-  int rc = ensure_masks(st);
-  if (!rc && (st->hmeta->err & (kErrSpin | kErrGroup))) rc = hip_fail(st);
-  res->status = rc;
-  res->nnz = st->n;
-  res->peak = st->peak;
-  return rc;
+  return SS_OK;
 }
 
 }  // namespace
@@ -1258,13 +1449,11 @@ int ss_create_state(const ss_reg* regs, uint32_t nregs, uint32_t ninst, double e
   std::vector<uint64_t> vals((size_t)ninst * nregs, 0ull);
   std::vector<double> amps(2 * (size_t)ninst, 0.0);
   for (uint32_t i = 0; i < ninst; ++i) amps[2 * i] = 1.0;
-  st->n = 0;
-  for (uint32_t i = 0; i < ninst; ++i) {
-    rc = ss_set_entries(st, i, vals.data() + (size_t)i * nregs, amps.data() + 2 * i, 1);
-    if (rc) {
-      ss_destroy_state(st);
-      return rc;
-    }
+  rc = pack_entries(st, vals.data(), amps.data(), ninst, 0, true);
+  if (!rc) rc = sync_state(st);
+  if (rc) {
+    ss_destroy_state(st);
+    return rc;
   }
   *out = st;
   return SS_OK;
@@ -1273,7 +1462,7 @@ int ss_create_state(const ss_reg* regs, uint32_t nregs, uint32_t ninst, double e
 int ss_destroy_state(ss_state* st) {
   if (!st) return SS_E_STATE;
   (void)hipStreamSynchronize(st->stream);
-  trace_flush(st);
+  drop_trace(st);
   for (hipEvent_t e : st->ev_pool) (void)hipEventDestroy(e);
   if (st->hmeta) (void)hipHostFree(st->hmeta);
   if (st->hops) (void)hipHostFree(st->hops);
@@ -1339,61 +1528,24 @@ int ss_set_entries(ss_state* st, uint32_t inst, const uint64_t* values, const do
     FilterOp f = base_filter(st, inst);
     f.kind = FILTER_DROP_INST;
     rc = run_filter(st, f);
+    if (!rc) rc = sync_state(st);
     if (rc) return rc;
   } else {
-    st->n = 0;
-  }
-  if (st->n + n > st->cap) return SS_E_CAPACITY;
-  const uint32_t nr = (uint32_t)st->L.regs.size();
-  PackDesc pd{};
-  pd.nregs = nr;
-  pd.has_inst = st->L.has_inst ? 1u : 0u;
-  pd.iword = st->L.iword;
-  pd.ishift = st->L.ishift;
-  pd.inst = inst;
-  for (uint32_t r = 0; r < nr; ++r) {
-    pd.word[r] = st->L.regs[r].word;
-    pd.shift[r] = st->L.regs[r].shift;
-    pd.mask[r] = st->L.regs[r].mask;
-  }
-  // stage through the alternate buffer in chunks
-  const Buf& alt = st->buf[st->cur ^ 1];
-  char* stage = reinterpret_cast<char*>(alt.key[0]);
-  const uint64_t stage_bytes = st->cap * entry_bytes(st->L.W);
-  const uint64_t per = (uint64_t)nr * 8 + 16;
-  const uint64_t chunk = std::max<uint64_t>(1, stage_bytes / per - 1);
-  uint64_t done = 0;
-  while (done < n) {
-    const uint64_t c = std::min(chunk, n - done);
-    uint64_t* dv = reinterpret_cast<uint64_t*>(stage);
-    double2* da = reinterpret_cast<double2*>(stage + align_up(c * nr * 8, 16));
-    if (hipMemcpyAsync(dv, values + done * nr, c * nr * 8, hipMemcpyHostToDevice, st->stream) != hipSuccess ||
-        hipMemcpyAsync(da, amps + 2 * done, c * 16, hipMemcpyHostToDevice, st->stream) != hipSuccess)
-      return hip_fail(st);
-    switch (st->L.W) {
-      case 1: launch_pack<1>(st, dv, da, c, st->n + done, pd); break;
-      case 2: launch_pack<2>(st, dv, da, c, st->n + done, pd); break;
-      default: launch_pack<4>(st, dv, da, c, st->n + done, pd); break;
-    }
-    rc = check_launch(st);
+    rc = sync_state(st);
     if (rc) return rc;
-    if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
-    done += c;
+    set_known(st, 0);
   }
-  st->n += n;
-  st->peak = std::max(st->peak, st->n);
-  st->grouped = false;
-  // masks of the whole state: a no-op filter recomputes them
-  FilterOp f = base_filter(st, 0);
-  f.kind = FILTER_PRUNE;
-  f.has_inst = 1;
-  f.iword = 0;
-  f.ishift = 0;
-  f.imask = 0;
-  f.inst = 1;  // never matches: every entry passes unchanged
-  rc = run_filter(st, f);
+  if (st->n + n > st->cap) {
+    k_set_n<<<1, 64, 0, st->stream>>>(st->meta, st->nslot, st->n);
+    st->masks_valid = false;
+    st->mask_ep = 0;
+    st->grouped = false;
+    (void)check_launch(st);
+    return SS_E_CAPACITY;
+  }
+  rc = pack_entries(st, values, amps, n, inst, false);
   if (rc) return rc;
-  return SS_OK;
+  return sync_state(st);
 }
 
 int ss_apply_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst_offsets, ss_result* res) {
@@ -1411,24 +1563,36 @@ int ss_apply_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* 
       return rc;
     }
   }
+  auto finish = [&](int code, uint64_t op) {
+    // the status is final only after a synchronisation; a capacity failure
+    // found there names the op (batched: round) whose launch was rolled back
+    const int sc = st->poisoned ? SS_OK : sync_state(st);
+    if (sc == SS_E_CAPACITY) {
+      code = sc;
+      op = st->rb_op;
+    } else if (sc != SS_OK) {
+      code = sc;
+    }
+    res->status = code;
+    res->failed_op = code ? op : 0;
+    res->nnz = st->n;
+    res->peak = st->peak;
+    return code;
+  };
   if (inst_offsets) {
     rc = apply_batched(st, ops, nops, inst_offsets, res);
-    res->status = rc;
-    return rc;
+    if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
+    return finish(rc, 0);
   }
   std::vector<ss_op> run;
   for (uint64_t i = 0; i < nops; ++i) {
     const ss_op& op = ops[i];
-    st->stats[7] += st->n;
     if (is_branching(op.kind)) {
       rc = flush_run(st, run);
-      if (!rc) rc = do_branching(st, op);
+      if (!rc) rc = do_branching(st, op, i);
       if (rc) {
-        res->status = rc;
-        res->failed_op = i;
-        res->nnz = st->n;
-        res->peak = st->peak;
-        return rc;
+        if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
+        return finish(rc, i);
       }
     } else {
       if (st->grouped && !keeps_grouping(st, op, st->gmask)) st->grouped = false;
@@ -1436,12 +1600,8 @@ int ss_apply_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* 
     }
   }
   rc = flush_run(st, run);
-  if (!rc) rc = ensure_masks(st);
-  if (!rc && (st->hmeta->err & (kErrSpin | kErrGroup))) rc = hip_fail(st);
-  res->status = rc;
-  res->nnz = st->n;
-  res->peak = st->peak;
-  return rc;
+  if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
+  return finish(rc, nops);
 }
 
 int ss_prune(ss_state* st, double eps) {
@@ -1452,11 +1612,15 @@ int ss_prune(ss_state* st, double eps) {
   f.has_inst = 0;
   f.kind = FILTER_PRUNE;
   f.eps2 = eps * eps;
-  return run_filter(st, f);
+  rc = run_filter(st, f);
+  if (rc) return rc;
+  return sync_state(st);
 }
 
 int ss_nnz(ss_state* st, uint32_t inst, uint64_t* nnz, uint64_t* peak) {
   int rc = check_state(st);
+  if (rc) return rc;
+  rc = sync_state(st);
   if (rc) return rc;
   if (peak) *peak = st->peak;
   if (!nnz) return SS_OK;
@@ -1496,6 +1660,8 @@ int ss_export(ss_state* st, uint32_t inst, uint64_t* keys, double* amps, uint64_
   if (rc) return rc;
   if (inst >= st->ninst || !n_out || (cap && (!keys || !amps))) return SS_E_ARG;
   *n_out = 0;
+  rc = sync_state(st);
+  if (rc) return rc;
   if (st->n == 0) return SS_OK;
   rc = sort_canonical(st);
   if (rc) return rc;
@@ -1545,6 +1711,8 @@ int ss_measure(ss_state* st, uint32_t inst, uint32_t reg, double u, uint64_t* ou
   if (rc) return rc;
   if (inst >= st->ninst || reg >= st->L.regs.size() || !(u >= 0.0 && u < 1.0) || !outcome || !prob)
     return SS_E_ARG;
+  rc = sync_state(st);
+  if (rc) return rc;
   if (st->n == 0) return SS_E_ARG;
   rc = ensure_masks(st);
   if (rc) return rc;
@@ -1615,6 +1783,7 @@ int ss_measure(ss_state* st, uint32_t inst, uint32_t reg, double u, uint64_t* ou
   c.kind = FILTER_COLLAPSE;
   c.scale = std::sqrt(pv);
   rc = run_filter(st, c);
+  if (!rc) rc = sync_state(st);
   if (rc) return rc;
   st->grouped = false;
   *outcome = v;
@@ -1624,10 +1793,10 @@ int ss_measure(ss_state* st, uint32_t inst, uint32_t reg, double u, uint64_t* ou
 
 int ss_sync(ss_state* st, ss_result* res) {
   if (!st) return SS_E_STATE;
-  int rc = st->poisoned ? SS_E_STATE : readback(st);
-  if (!rc && (st->hmeta->err & (kErrSpin | kErrGroup))) rc = hip_fail(st);
+  const int rc = sync_state(st);
   if (res) {
     res->status = rc;
+    res->failed_op = rc == SS_E_CAPACITY ? st->rb_op : 0;
     res->nnz = st->n;
     res->peak = st->peak;
   }
@@ -1638,11 +1807,30 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes) {
   int rc = check_state(st);
   if (rc) return rc;
   if (!arena || ((uintptr_t)arena % kAlign)) return SS_E_ARG;
-  if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
-  ss_state old = *st;
+  rc = sync_state(st);
+  if (rc) return rc;
+  const uint64_t n = st->n, peak = st->peak, upd = st->stats[7];
+  const Buf src = st->buf[st->cur];
+  char* old_tab = st->tab_base;
+  const uint64_t old_used = st->tab_used;
+  struct Saved {
+    uint64_t cap;
+    Carve cv;
+    char* arena;
+    size_t arena_bytes;
+    DevMeta* meta;
+    uint64_t* digit_start;
+    PermOp* dev_ops;
+    uint64_t* uscr;
+    uint32_t* hist;
+    char* tab_base;
+    uint64_t* lb;
+    Buf b0, b1;
+  } old{st->cap, st->cv, st->arena, st->arena_bytes, st->meta, st->digit_start, st->dev_ops,
+        st->uscr, st->hist, st->tab_base, st->lb, st->buf[0], st->buf[1]};
   rc = setup_arena(st, static_cast<char*>(arena), arena_bytes);
-  if (rc || st->cap < old.n || st->table_bytes < old.tab_used) {
-    // restore the old carve
+  if (rc || st->cap < n || st->table_bytes < old_used) {
+    // keep the old carve
     st->cap = old.cap;
     st->cv = old.cv;
     st->arena = old.arena;
@@ -1654,28 +1842,30 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes) {
     st->hist = old.hist;
     st->tab_base = old.tab_base;
     st->lb = old.lb;
-    st->buf[0] = old.buf[0];
-    st->buf[1] = old.buf[1];
+    st->buf[0] = old.b0;
+    st->buf[1] = old.b1;
     return rc ? rc : SS_E_NOMEM;
   }
   st->cur = 0;
   const uint32_t W = st->L.W;
-  const Buf& src = old.buf[old.cur];
   for (uint32_t w = 0; w < W; ++w)
-    if (old.n && hipMemcpyAsync(st->buf[0].key[w], src.key[w], old.n * 8, hipMemcpyDeviceToDevice, st->stream) != hipSuccess)
+    if (n && hipMemcpyAsync(st->buf[0].key[w], src.key[w], n * 8, hipMemcpyDeviceToDevice, st->stream) != hipSuccess)
       return hip_fail(st);
-  if (old.n && hipMemcpyAsync(st->buf[0].amp, src.amp, old.n * 16, hipMemcpyDeviceToDevice, st->stream) != hipSuccess)
+  if (n && hipMemcpyAsync(st->buf[0].amp, src.amp, n * 16, hipMemcpyDeviceToDevice, st->stream) != hipSuccess)
     return hip_fail(st);
-  if (old.tab_used && hipMemcpyAsync(st->tab_base, old.tab_base, old.tab_used, hipMemcpyDeviceToDevice, st->stream) != hipSuccess)
+  if (old_used && hipMemcpyAsync(st->tab_base, old_tab, old_used, hipMemcpyDeviceToDevice, st->stream) != hipSuccess)
     return hip_fail(st);
-  for (auto& t : st->tables) t.dev = st->tab_base + (static_cast<char*>(t.dev) - old.tab_base);
+  for (auto& t : st->tables) t.dev = st->tab_base + (static_cast<char*>(t.dev) - old_tab);
   rc = init_device(st);
   if (rc) return rc;
-  if (hipMemcpyAsync(&st->meta->peak, &old.peak, 8, hipMemcpyHostToDevice, st->stream) != hipSuccess ||
-      hipStreamSynchronize(st->stream) != hipSuccess)
+  if (hipMemcpyAsync(&st->meta->peak, &peak, 8, hipMemcpyHostToDevice, st->stream) != hipSuccess ||
+      hipMemcpyAsync(&st->meta->upd, &upd, 8, hipMemcpyHostToDevice, st->stream) != hipSuccess)
     return hip_fail(st);
-  st->epoch = 0;
-  return SS_OK;
+  set_known(st, n);
+  k_set_n<<<1, 64, 0, st->stream>>>(st->meta, st->nslot, n);
+  rc = check_launch(st);
+  if (rc) return rc;
+  return sync_state(st);
 }
 
 int ss_set_option(ss_state* st, const char* key, int64_t value) {
@@ -1714,8 +1904,8 @@ int ss_trace_read(ss_state* st, uint32_t cat, uint64_t* launches, double* second
                   uint64_t* entries) {
   if (!st || cat >= SS_TRACE_NCAT) return SS_E_ARG;
   if (!st->pending.empty()) {
-    if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
-    trace_flush(st);
+    const int rc = sync_state(st);
+    if (rc) return rc;
   }
   if (launches) *launches = st->tr_cnt[cat];
   if (seconds) *seconds = st->tr_sec[cat];

@@ -14,7 +14,9 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxFields = 8;       // contiguous bit runs that make up one digit
 constexpr int kMaxPasses = 40;      // up to 256 key bits + 5 target bits, 8 bits per pass
 constexpr int kMaxGroupBits = 5;    // targets fused into one interference op (2^5 group)
-constexpr int kRing = 16;           // per-launch slots (tile counter, count, key masks)
+constexpr int kRing = 128;          // per-launch slots (tile counter, count, key masks)
+constexpr int kXcds = 8;            // XCDs of an MI355X
+constexpr int kXcdStride = 16;      // per-XCD counters 128 bytes apart
 
 // Lookback words: [epoch:24 | flag:2 | value:38].
 constexpr uint64_t kLbValueBits = 38;
@@ -29,25 +31,26 @@ constexpr uint32_t kEpochMask = (1u << 24) - 1;
 constexpr uint32_t kErrCapacity = 1u << 0;   // outputs would exceed the buffer capacity
 constexpr uint32_t kErrSpin = 1u << 1;       // a lookback wait exceeded its bound
 constexpr uint32_t kErrGroup = 1u << 2;      // two group members share a target value
-constexpr uint32_t kErrCollision = 1u << 3;  // reserved: duplicate key detected
+constexpr uint32_t kErrGrid = 1u << 3;       // a grid was sized below the entry count (host bug)
 
 // Device-side bookkeeping.  Every kernel launch that counts tiles, produces an
-// entry count or key masks owns ring slot (epoch % kRing); the first
-// workgroup of launch e clears slot (e + kRing/2) % kRing for a later launch.
-constexpr int kXcds = 8;            // XCDs of an MI355X; workgroup i runs on XCD i % 8
-constexpr int kXcdStride = 16;      // counters 128 bytes apart
-
+// entry count or key masks owns ring slot (epoch % kRing); workgroup 0 of
+// launch e clears slot (e + kRing/2) % kRing for a later launch.  The host
+// reads back the leading status part (up to `dscratch`) when it synchronises.
 struct DevMeta {
-  unsigned long long counters[kRing];        // dynamic tile ids (one ticket per launch)
-  unsigned long long xcd_ctr[kRing][kXcds * kXcdStride];  // per-XCD tickets
+  unsigned long long nring[2];               // entry count: launches read one slot, emitters write the other
+  unsigned long long peak;                   // running maximum of nnz
+  unsigned int err;                          // kErr* bits, sticky until the host clears them
+  unsigned int err_epoch;                    // epoch of the launch that raised the first error
+  unsigned long long upd;                    // entries updated: sum over ops of the input count
   unsigned long long nnz_out[kRing];         // entry count written by an emitting kernel
   unsigned long long or_mask[kRing][kMaxW];  // OR of the produced keys, per word
   unsigned long long and_mask[kRing][kMaxW]; // AND of the produced keys, per word
-  unsigned long long peak;                   // running maximum of nnz
-  unsigned int err;                          // kErr* bits, sticky until the host clears them
-  unsigned int pad;
+  // device-only part
   double dscratch[16];
   unsigned long long uscratch[16];
+  unsigned long long counters[kRing];        // dynamic tile ids (one ticket per launch)
+  unsigned long long xcd_ctr[kRing][kXcds * kXcdStride];  // per-XCD tickets
 };
 
 // A run of non-branching ops is executed from an array of these (uniform per op).
@@ -116,6 +119,7 @@ struct FastOp {
 struct GroupOp {
   uint32_t k;                   // number of target qubits (1..kMaxGroupBits); 0 = plain filter
   uint32_t has_ctl;
+  uint32_t upd;                 // 1: add the input count to the update counter
   uint32_t tword[kMaxGroupBits];  // target j: key word and bit, ascending qubit order
   uint32_t tbit[kMaxGroupBits];
   uint64_t tmask[kMaxW];        // all target bits per word

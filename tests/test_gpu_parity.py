@@ -180,6 +180,44 @@ def test_capacity_error_rolls_back(abi):
     assert len(k) == 1 and a[0] == 1.0
 
 
+def test_capacity_failure_mid_stream_then_resume(abi):
+    """A capacity failure inside a run of launches that the host queued
+    without waiting: the launches after it change nothing, the state returns
+    to the failing op's input, and after moving to a larger arena the rest of
+    the ops give the oracle's result for the whole list."""
+    regs = [("a", 8), ("b", 8)]
+    ops = wl.ops_array([
+        wl.make_op("H", 0, qmask=0xFF),                  # 256 entries (two launches)
+        wl.make_op("ADD", 1, reg2=0),                    # b = a
+        wl.make_op("RY", 1, qmask=0x0F, theta=0.7),      # 16 children each: 4096 > capacity
+        wl.make_op("X", 0, qmask=1),
+        wl.make_op("RY", 1, qmask=0x0F, theta=-0.7),     # same targets: no wait before it
+        wl.make_op("XORC", 1, imm=0x35),
+        wl.make_op("H", 0, qmask=0x03),
+    ])
+    c = wl.Circuit(name="cap-mid", regs=regs, ops=ops, eps=1e-14)
+    print("[case] capacity mid-stream", flush=True)
+    st = abi.State(regs, eps=c.eps, cap_entries=1024, table_bytes=0)
+    cap = st.capacity
+    assert 1024 <= cap < 4096
+    res = st.apply(ops, raise_on_error=False)
+    assert res.status == abi.SS_E_CAPACITY and res.failed_op == 2
+    gk, ga = st.export()
+    ora, _, _ = run_circuit(c, ops=ops[:2])
+    ok, _, oa = ora.export()
+    s = compare(gk, ga, ok, oa, c.eps)
+    assert s["n_gpu"] == 256 and res.nnz == 256
+    assert st.peak() == 256
+    st.rebind(1 << 14)
+    res = st.apply(ops[2:], raise_on_error=False)
+    assert res.status == 0, abi.strerror(res.status)
+    gk, ga = st.export()
+    ora, _, _ = run_circuit(c)
+    ok, _, oa = ora.export()
+    compare(gk, ga, ok, oa, c.eps)
+    st.close()
+
+
 def test_deterministic_reruns(abi):
     c = wl.c1_circuit(9)
     k1, a1 = _gpu(abi, c).export()
