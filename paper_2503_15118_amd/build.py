@@ -19,6 +19,11 @@ FLAGS = [
     "-ffp-contract=off",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # Branches on wave-uniform values (the op interpreter's dispatch) stay
+    # plain scalar branches.  Structurizing them makes every case region read
+    # the dispatch's incoming key registers, which then interfere with the
+    # merged results and cost a copy of every key register per op.
+    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

@@ -178,70 +178,70 @@ __device__ __forceinline__ void fast_step(uint32_t (&h)[E][4], double2 (&a)[E], 
     case F_XC1 + 13: SQ_E h[j][3] ^= (((h[j][1] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
     case F_XC1 + 14: SQ_E h[j][3] ^= (((h[j][2] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
     case F_XC1 + 15: SQ_E h[j][3] ^= (((h[j][3] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC2 + 0: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 1: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 2: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 3: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 4: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 5: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 6: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 7: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 8: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 9: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 10: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 11: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 12: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 13: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 14: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 15: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 16: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 17: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 18: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 19: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 20: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 21: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 22: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 23: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 24: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 25: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 26: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 27: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 28: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 29: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 30: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 31: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 32: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 33: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 34: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 35: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 36: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 37: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 38: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 39: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 40: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 41: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 42: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 43: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 44: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 45: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 46: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 47: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 48: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 49: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 50: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 51: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 52: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 53: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 54: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 55: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 56: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 57: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 58: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 59: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 60: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 61: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 62: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 63: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) && (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 0: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 1: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 2: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 3: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 4: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 5: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 6: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 7: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 8: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 9: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 10: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 11: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 12: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 13: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 14: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 15: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 16: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 17: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 18: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 19: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 20: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 21: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 22: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 23: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 24: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 25: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 26: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 27: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 28: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 29: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 30: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 31: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 32: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 33: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 34: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 35: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 36: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 37: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 38: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 39: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 40: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 41: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 42: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 43: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 44: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 45: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 46: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 47: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 48: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 49: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 50: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 51: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 52: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 53: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 54: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 55: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 56: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 57: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 58: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 59: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 60: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 61: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 62: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
+    case F_XC2 + 63: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
     case F_ADDA + 0: SQ_E h[j][0] += h[j][0]; break;
     case F_ADDA + 1: SQ_E h[j][0] += h[j][1]; break;
     case F_ADDA + 2: SQ_E h[j][0] += h[j][2]; break;
@@ -413,7 +413,19 @@ __global__ __launch_bounds__(kBlock) void k_perm_fast(KeyPtrs<W> keys, double2* 
       h[j][0] = h[j][1] = 0u;
     }
   }
-  for (uint32_t o = 0; o < nops; ++o) fast_step<W, E, AMP>(h, a, ops[o], gops);
+  // Op records are staged through LDS a chunk at a time: every wave of the
+  // workgroup reads each record at the same moment, and from global memory
+  // each such read would wait for one cache miss per op.
+  __shared__ uint4 s_ops[kOpChunk * (sizeof(FastOp) / 16)];
+  for (uint32_t c0 = 0; c0 < nops; c0 += kOpChunk) {
+    const uint32_t cn = nops - c0 < (uint32_t)kOpChunk ? nops - c0 : (uint32_t)kOpChunk;
+    __syncthreads();
+    const uint4* src = reinterpret_cast<const uint4*>(ops + c0);
+    for (uint32_t q = threadIdx.x; q < cn * (uint32_t)(sizeof(FastOp) / 16); q += kBlock) s_ops[q] = src[q];
+    __syncthreads();
+    const FastOp* lops = reinterpret_cast<const FastOp*>(s_ops);
+    for (uint32_t o = 0; o < cn; ++o) fast_step<W, E, AMP>(h, a, lops[o], gops);
+  }
   uint64_t orv[W], andv[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) {

@@ -15,6 +15,7 @@ constexpr int kMaxFields = 8;       // contiguous bit runs that make up one digi
 constexpr int kMaxPasses = 40;      // up to 256 key bits + 5 target bits, 8 bits per pass
 constexpr int kMaxGroupBits = 5;    // targets fused into one interference op (2^5 group)
 constexpr int kRing = 128;          // per-launch slots (tile counter, count, key masks)
+constexpr int kOpChunk = 128;       // op records staged in LDS at a time by the interpreter
 constexpr int kXcds = 8;            // XCDs of an MI355X
 constexpr int kXcdStride = 16;      // per-XCD counters 128 bytes apart
 
@@ -104,7 +105,7 @@ enum FastBase : uint32_t {
   F_NCODES = 209
 };
 
-struct FastOp {
+struct alignas(64) FastOp {       // 64 bytes: four 16-byte LDS words
   uint32_t code;
   uint32_t dsh, dm;             // dst shift within its half, width mask
   uint32_t ssh, sm;             // src shift within its half, width mask
