@@ -32,7 +32,7 @@ def counter_traffic(kernel_label):
     or None when the kernel sources changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "c2_hbm_counters.txt")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or kernel_label is None:
         return None
     kv = {}
     for line in open(path):
@@ -42,9 +42,9 @@ def counter_traffic(kernel_label):
     src = os.path.join(ROOT, "paper_2503_15118_amd", "csrc")
     sha = hashlib.sha256(open(os.path.join(src, "kernels.hip"), "rb").read()
                          + open(os.path.join(src, "kernels_common.hpp"), "rb").read()).hexdigest()[:16]
-    if kv.get("sources_sha") != sha or kernel_label not in kv.get("traffic_kernel", ""):
+    if kv.get("sources_sha") != sha or ("traffic " + kernel_label) not in kv:
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return float(kv["traffic " + kernel_label])
 
 
 def cpu_baseline(circ, nops_sample):
@@ -265,7 +265,11 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     d = tr[dom]
     achieved = d["bytes"] / d["seconds"] / 1e9
-    traffic = counter_traffic("k_perm_fast") if dom == "perm" else None
+    # the kernel behind each category at this configuration (W = 2 keys)
+    label = {"perm": "k_perm_fast<2, %d, false>" % args.perm_entries,
+             "group": "k_pair<2, 0, %d>" % args.group_items if args.group_items in (2, 4) else None,
+             "expand": "k_pair<2, 1, %d>" % args.group_items if args.group_items in (2, 4) else None}.get(dom)
+    traffic = counter_traffic(label)
     gpu_kernel_ms = sum(k["ms_per_step"] for k in kernels.values())
 
     out = {
@@ -297,6 +301,7 @@ def main():
         "roofline": {
             "bound": "hbm",
             "kernel": dom,
+            "kernel_name": label,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
