@@ -860,6 +860,9 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
   __shared__ uint64_t s_lb[12];
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
+  // group mode: the tile's keys (W words) and amplitudes plus one entry on
+  // each side, for the partner test
+  __shared__ uint64_t s_stage[MODE == MODE_GROUP ? (W + 2) * (TILE + 2) : 1];
   uint64_t n;
   if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
   if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) meta->upd += n;
@@ -868,19 +871,52 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
   if (tile_out_of_range(tile, ntiles, &meta->err)) return;
   const uint32_t tw = op.tword[0], tb = op.tbit[0];
   uint64_t key[ITEMS][W];
+  double2 amp[ITEMS];
   double2 out[ITEMS][2];
   uint32_t keepm[ITEMS], cnt[ITEMS];
+  const uint64_t e0 = (uint64_t)tile * TILE;
+  // every load of the tile is issued before any is used
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
-    const uint64_t e = (uint64_t)tile * TILE + (uint64_t)it * kBlock + threadIdx.x;
-    keepm[it] = 0;
-    out[it][0] = out[it][1] = make_double2(0.0, 0.0);
+    const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
+    amp[it] = make_double2(0.0, 0.0);
 #pragma unroll
     for (int w = 0; w < W; ++w) key[it][w] = 0;
     if (e < n) {
 #pragma unroll
       for (int w = 0; w < W; ++w) key[it][w] = in_keys.w[w][e];
-      const double2 a = in_amp[e];
+      amp[it] = in_amp[e];
+    }
+  }
+  if (MODE == MODE_GROUP) {
+    // Neighbours come from LDS: slot 1 + i holds tile entry i, slot 0 the
+    // entry before the tile and slot TILE + 1 the one after (when present).
+    uint64_t* s_key = s_stage;
+    double2* s_amp = reinterpret_cast<double2*>(s_stage + W * (TILE + 2));
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const uint32_t l = 1 + it * kBlock + threadIdx.x;
+#pragma unroll
+      for (int w = 0; w < W; ++w) s_key[w * (TILE + 2) + l] = key[it][w];
+      s_amp[l] = amp[it];
+    }
+    if (threadIdx.x < 2) {
+      const uint64_t e = threadIdx.x == 0 ? e0 - 1 : e0 + TILE;
+      const uint32_t l = threadIdx.x == 0 ? 0 : TILE + 1;
+      const bool ok = threadIdx.x == 0 ? e0 > 0 : e0 + TILE < n;
+#pragma unroll
+      for (int w = 0; w < W; ++w) s_key[w * (TILE + 2) + l] = ok ? in_keys.w[w][e] : 0ull;
+      s_amp[l] = ok ? in_amp[e] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
+    keepm[it] = 0;
+    out[it][0] = out[it][1] = make_double2(0.0, 0.0);
+    if (e < n) {
+      const double2 a = amp[it];
       const uint32_t b = (uint32_t)((sel_word<W>(key[it], tw) >> tb) & 1ull);
       const bool ctl = !op.has_ctl || controls_hold<W>(key[it], op.cmask, op.cval);
       if (!ctl) {
@@ -894,26 +930,19 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
         if (MODE == MODE_GROUP) {
           // the partner is a neighbour on either side: grouped order keeps the
           // two members adjacent but not necessarily bit 0 first
-          uint64_t c = 0;
-          if (e > 0) {
-            uint64_t pk[W];
+          const uint64_t* s_key = s_stage;
+          const double2* s_amp = reinterpret_cast<const double2*>(s_stage + W * (TILE + 2));
+          const uint32_t l = 1 + it * kBlock + threadIdx.x;
+          uint64_t pk[W], nk[W];
 #pragma unroll
-            for (int w = 0; w < W; ++w) pk[w] = in_keys.w[w][e - 1];
-            if (same_idle<W>(key[it], pk, op.tmask)) {
-              has_p = true;
-              c = e - 1;
-            }
+          for (int w = 0; w < W; ++w) {
+            pk[w] = s_key[w * (TILE + 2) + l - 1];
+            nk[w] = s_key[w * (TILE + 2) + l + 1];
           }
-          if (!has_p && e + 1 < n) {
-            uint64_t pk[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) pk[w] = in_keys.w[w][e + 1];
-            if (same_idle<W>(key[it], pk, op.tmask)) {
-              has_p = true;
-              c = e + 1;
-            }
-          }
-          if (has_p) ap = in_amp[c];
+          const bool prev_p = e > 0 && same_idle<W>(key[it], pk, op.tmask);
+          const bool next_p = !prev_p && e + 1 < n && same_idle<W>(key[it], nk, op.tmask);
+          has_p = prev_p || next_p;
+          if (has_p) ap = s_amp[prev_p ? l - 1 : l + 1];
         }
         const double2 a0 = b == 0 ? a : ap;
         const double2 a1 = b == 0 ? ap : a;
@@ -1161,55 +1190,73 @@ __global__ __launch_bounds__(kBlock) void k_perm_batched(KeyPtrs<W> keys, double
 // stage in ascending qubit order), skipping children reached through an exact
 // 0.0 element; where the controls fail, or the instance has no branching op
 // this round, the parent is copied.  Output offsets come from a look-back
-// prefix of the per-parent child counts.
-template <int W>
+// prefix of the per-parent child counts.  ITEMS parents per thread, all loads
+// of the tile issued before any is used.
+template <int W, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                            KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
                                                            uint32_t ns, uint64_t cap, const BatchOp* __restrict__ bops,
                                                            uint32_t iword, uint32_t ishift, uint64_t imask,
                                                            uint64_t* lb, DevMeta* meta, uint32_t epoch, uint32_t xo) {
-  __shared__ uint32_t s_wtot[1][kBlock / 64];
+  constexpr uint32_t TILE = kBlock * ITEMS;
+  __shared__ uint32_t s_wtot[ITEMS][kBlock / 64];
   __shared__ uint64_t s_off;
   __shared__ uint64_t s_lb[12];
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
   uint64_t n;
-  if (!emit_begin(meta, ns, epoch, kBlock, &n)) return;
+  if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
-  const uint64_t ntiles = (n + kBlock - 1) / kBlock;
+  const uint64_t ntiles = (n + TILE - 1) / TILE;
   if (tile_out_of_range(tile, ntiles, &meta->err)) return;
-  const uint64_t e = (uint64_t)tile * kBlock + threadIdx.x;
-  uint64_t key[W];
-  double2 a = make_double2(0.0, 0.0);
-  uint32_t k = 0, b = 0, cnt = 0;
-  bool copy = true;
-  const BatchOp* op = nullptr;
+  const uint64_t e0 = (uint64_t)tile * TILE;
+  uint64_t key[ITEMS][W];
+  double2 a[ITEMS];
 #pragma unroll
-  for (int w = 0; w < W; ++w) key[w] = 0;
-  if (e < n) {
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
+    a[it] = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int w = 0; w < W; ++w) key[w] = in_keys.w[w][e];
-    a = in_amp[e];
-    op = &bops[inst_of<W>(key, iword, ishift, imask)];
-    k = op->k;
-    copy = k == 0 || (op->has_ctl && !controls_hold<W>(key, op->cmask, op->cval));
-    if (copy) {
-      cnt = 1;
-    } else {
-      for (uint32_t j = 0; j < k; ++j) b |= (uint32_t)((sel_word<W>(key, op->tword[j]) >> op->tbit[j]) & 1ull) << j;
-      // children reachable through nonzero elements: product over stages of
-      // the number of nonzero entries in column b_j
-      cnt = 1;
-      for (uint32_t j = 0; j < k; ++j) {
-        const uint32_t bj = (b >> j) & 1u;
-        const double e0 = bj ? op->m[0][1] : op->m[0][0];
-        const double e1 = bj ? op->m[1][1] : op->m[1][0];
-        cnt *= (uint32_t)(e0 != 0.0) + (uint32_t)(e1 != 0.0);
+    for (int w = 0; w < W; ++w) key[it][w] = 0;
+    if (e < n) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) key[it][w] = in_keys.w[w][e];
+      a[it] = in_amp[e];
+    }
+  }
+  uint32_t k[ITEMS], b[ITEMS], cnt[ITEMS], inst[ITEMS];
+  bool copy[ITEMS];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
+    k[it] = 0;
+    b[it] = 0;
+    cnt[it] = 0;
+    copy[it] = true;
+    inst[it] = inst_of<W>(key[it], iword, ishift, imask);
+    if (e < n) {
+      const BatchOp& op = bops[inst[it]];
+      k[it] = op.k;
+      copy[it] = k[it] == 0 || (op.has_ctl && !controls_hold<W>(key[it], op.cmask, op.cval));
+      if (copy[it]) {
+        cnt[it] = 1;
+      } else {
+        for (uint32_t j = 0; j < k[it]; ++j)
+          b[it] |= (uint32_t)((sel_word<W>(key[it], op.tword[j]) >> op.tbit[j]) & 1ull) << j;
+        // children reachable through nonzero elements: product over stages of
+        // the number of nonzero entries in column b_j
+        cnt[it] = 1;
+        for (uint32_t j = 0; j < k[it]; ++j) {
+          const uint32_t bj = (b[it] >> j) & 1u;
+          const double c0 = bj ? op.m[0][1] : op.m[0][0];
+          const double c1 = bj ? op.m[1][1] : op.m[1][0];
+          cnt[it] *= (uint32_t)(c0 != 0.0) + (uint32_t)(c1 != 0.0);
+        }
       }
     }
   }
-  uint32_t cnta[1] = {cnt}, offa[1];
-  const uint64_t tile_total = tile_offsets<1>(cnta, offa, s_wtot);
+  uint32_t off[ITEMS];
+  const uint64_t tile_total = tile_offsets<ITEMS>(cnt, off, s_wtot);
   {
     const uint64_t ex = lookback_block(lb, tile, tile_total, epoch, &meta->err, s_lb);
     if (threadIdx.x == 0) {
@@ -1228,26 +1275,30 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
     orv[w] = 0;
     andv[w] = ~0ull;
   }
-  uint64_t p = s_off + offa[0];
-  if (e < n) {
-    const uint32_t nchild = copy ? 1u : (1u << k);
-    for (uint32_t s = 0; s < nchild; ++s) {
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
+    if (e >= n) continue;
+    uint64_t p = s_off + off[it];
+    const BatchOp& op = bops[inst[it]];
+    const uint32_t nchild = copy[it] ? 1u : (1u << k[it]);
+    for (uint32_t sv = 0; sv < nchild; ++sv) {
       uint64_t ok[W];
 #pragma unroll
-      for (int w = 0; w < W; ++w) ok[w] = key[w];
-      double2 v = a;
+      for (int w = 0; w < W; ++w) ok[w] = key[it][w];
+      double2 v = a[it];
       bool exists = true;
-      if (!copy) {
-        for (uint32_t j = 0; j < k; ++j) {
-          const uint32_t sj = (s >> j) & 1u, bj = (b >> j) & 1u;
-          const double c = sj ? (bj ? op->m[1][1] : op->m[1][0]) : (bj ? op->m[0][1] : op->m[0][0]);
+      if (!copy[it]) {
+        for (uint32_t j = 0; j < k[it]; ++j) {
+          const uint32_t sj = (sv >> j) & 1u, bj = (b[it] >> j) & 1u;
+          const double c = sj ? (bj ? op.m[1][1] : op.m[1][0]) : (bj ? op.m[0][1] : op.m[0][0]);
           if (c == 0.0) exists = false;
           v.x = c * v.x;
           v.y = c * v.y;
-          const uint64_t bit = 1ull << op->tbit[j];
+          const uint64_t bit = 1ull << op.tbit[j];
 #pragma unroll
           for (int w = 0; w < W; ++w)
-            if ((uint32_t)w == op->tword[j]) ok[w] = sj ? (ok[w] | bit) : (ok[w] & ~bit);
+            if ((uint32_t)w == op.tword[j]) ok[w] = sj ? (ok[w] | bit) : (ok[w] & ~bit);
         }
       }
       if (!exists) continue;
@@ -1269,57 +1320,80 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
 
 // Reduce-by-key over sorted candidates: the first entry of each run of equal
 // keys sums the run left to right; instances that branched this round drop
-// sums with |a|^2 < eps^2 or a == 0.  One output per run, compacted.
-template <int W>
+// sums with |a|^2 < eps^2 or a == 0.  One output per run, compacted.  A run
+// has at most 2^5 members (one branching op of up to five targets per
+// instance and round), so the tile is staged in LDS with the entry before it
+// and the kRunHalo entries after it.
+constexpr uint32_t kRunHalo = 64;
+
+template <int W, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                            KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
                                                            uint32_t ns, uint64_t cap, const BatchOp* __restrict__ bops,
                                                            uint32_t iword, uint32_t ishift, uint64_t imask,
                                                            uint64_t* lb, DevMeta* meta, uint32_t epoch, uint32_t xo) {
-  __shared__ uint32_t s_wtot[1][kBlock / 64];
+  constexpr uint32_t TILE = kBlock * ITEMS;
+  constexpr uint32_t S = TILE + 1 + kRunHalo;   // staged slots: [e0 - 1, e0 + TILE + kRunHalo)
+  __shared__ uint32_t s_wtot[ITEMS][kBlock / 64];
   __shared__ uint64_t s_off;
   __shared__ uint64_t s_lb[12];
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
+  __shared__ uint64_t s_key[W * S];
+  __shared__ double2 s_amp[S];
   uint64_t n;
-  if (!emit_begin(meta, ns, epoch, kBlock, &n)) return;
+  if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
-  const uint64_t ntiles = (n + kBlock - 1) / kBlock;
+  const uint64_t ntiles = (n + TILE - 1) / TILE;
   if (tile_out_of_range(tile, ntiles, &meta->err)) return;
-  const uint64_t e = (uint64_t)tile * kBlock + threadIdx.x;
-  uint64_t key[W];
-  double2 sum = make_double2(0.0, 0.0);
-  bool keep = false;
+  const uint64_t e0 = (uint64_t)tile * TILE;
+  // stage slot l = entry e0 - 1 + l (zero key, zero amplitude past n)
+  for (uint32_t l = threadIdx.x; l < S; l += kBlock) {
+    const uint64_t e = e0 + l - 1;
+    const bool ok = (l > 0 || e0 > 0) && e < n;
 #pragma unroll
-  for (int w = 0; w < W; ++w) key[w] = 0;
-  if (e < n) {
+    for (int w = 0; w < W; ++w) s_key[w * S + l] = ok ? in_keys.w[w][e] : 0ull;
+    s_amp[l] = ok ? in_amp[e] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  uint64_t key[ITEMS][W];
+  double2 sum[ITEMS];
+  uint32_t cnt[ITEMS];
 #pragma unroll
-    for (int w = 0; w < W; ++w) key[w] = in_keys.w[w][e];
-    bool head = true;
-    if (e > 0) {
-      bool eq = true;
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint32_t l = 1 + it * kBlock + threadIdx.x;
+    const uint64_t e = e0 + l - 1;
+    sum[it] = make_double2(0.0, 0.0);
+    cnt[it] = 0;
 #pragma unroll
-      for (int w = 0; w < W; ++w) eq = eq && in_keys.w[w][e - 1] == key[w];
-      head = !eq;
-    }
-    if (head) {
-      sum = in_amp[e];
-      uint64_t j = e + 1;
-      for (uint32_t m = 1; j < n && m < 64; ++m, ++j) {
+    for (int w = 0; w < W; ++w) key[it][w] = s_key[w * S + l];
+    if (e < n) {
+      bool head = true;
+      if (e > 0) {
         bool eq = true;
 #pragma unroll
-        for (int w = 0; w < W; ++w) eq = eq && in_keys.w[w][j] == key[w];
-        if (!eq) break;
-        const double2 x = in_amp[j];
-        sum.x = sum.x + x.x;
-        sum.y = sum.y + x.y;
+        for (int w = 0; w < W; ++w) eq = eq && s_key[w * S + l - 1] == key[it][w];
+        head = !eq;
       }
-      const BatchOp* op = &bops[inst_of<W>(key, iword, ishift, imask)];
-      keep = op->prune ? keep_amp(sum.x, sum.y, op->eps2) : true;
+      if (head) {
+        double2 acc = s_amp[l];
+        for (uint32_t m = 1; m <= kRunHalo - 1 && e + m < n; ++m) {
+          bool eq = true;
+#pragma unroll
+          for (int w = 0; w < W; ++w) eq = eq && s_key[w * S + l + m] == key[it][w];
+          if (!eq) break;
+          const double2 x = s_amp[l + m];
+          acc.x = acc.x + x.x;
+          acc.y = acc.y + x.y;
+        }
+        sum[it] = acc;
+        const BatchOp& op = bops[inst_of<W>(key[it], iword, ishift, imask)];
+        cnt[it] = (op.prune ? keep_amp(acc.x, acc.y, op.eps2) : true) ? 1u : 0u;
+      }
     }
   }
-  uint32_t cnta[1] = {keep ? 1u : 0u}, offa[1];
-  const uint64_t tile_total = tile_offsets<1>(cnta, offa, s_wtot);
+  uint32_t off[ITEMS];
+  const uint64_t tile_total = tile_offsets<ITEMS>(cnt, off, s_wtot);
   {
     const uint64_t ex = lookback_block(lb, tile, tile_total, epoch, &meta->err, s_lb);
     if (threadIdx.x == 0) {
@@ -1335,15 +1409,22 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
   uint64_t orv[W], andv[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    orv[w] = keep ? key[w] : 0ull;
-    andv[w] = keep ? key[w] : ~0ull;
+    orv[w] = 0;
+    andv[w] = ~0ull;
   }
-  if (keep) {
-    const uint64_t p = s_off + offa[0];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    if (!cnt[it]) continue;
+    const uint64_t p = s_off + off[it];
     if (p < cap) {
 #pragma unroll
-      for (int w = 0; w < W; ++w) out_keys.w[w][p] = key[w];
-      out_amp[p] = sum;
+      for (int w = 0; w < W; ++w) out_keys.w[w][p] = key[it][w];
+      out_amp[p] = sum[it];
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      orv[w] |= key[it][w];
+      andv[w] &= key[it][w];
     }
   }
   publish_masks<W>(meta, epoch, orv, andv, s_red);

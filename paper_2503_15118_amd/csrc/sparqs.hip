@@ -1191,12 +1191,15 @@ void launch_perm_batched_w(ss_state* st, const FastOp* f, const PermOp* g, const
                                                               st->L.ishift, st->L.imask, ww, st->meta, ep);
 }
 
+constexpr int kBatchItems = 4;   // entries per thread in the batched expand / reduce kernels
+
 template <int W>
 void launch_expand_batched_w(ss_state* st, const BatchOp* bops, uint32_t ep) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
-  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock - 1) / kBlock);
-  k_expand_batched<W><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
+  constexpr uint64_t T = (uint64_t)kBlock * kBatchItems;
+  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + T - 1) / T);
+  k_expand_batched<W, kBatchItems><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
                                                          st->cap, bops, st->L.iword, st->L.ishift, st->L.imask,
                                                          st->lb, st->meta, ep, xo(st));
 }
@@ -1205,8 +1208,9 @@ template <int W>
 void launch_reduce_batched_w(ss_state* st, const BatchOp* bops, uint32_t ep) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
-  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock - 1) / kBlock);
-  k_reduce_batched<W><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
+  constexpr uint64_t T = (uint64_t)kBlock * kBatchItems;
+  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + T - 1) / T);
+  k_reduce_batched<W, kBatchItems><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
                                                          st->cap, bops, st->L.iword, st->L.ishift, st->L.imask,
                                                          st->lb, st->meta, ep, xo(st));
 }
