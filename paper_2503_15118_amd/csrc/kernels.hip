@@ -464,20 +464,45 @@ __device__ __forceinline__ uint32_t digit_of(const uint64_t (&k)[W], const PassD
   return d;
 }
 
-// Per-workgroup digit histograms of every pass in one read of the keys.
+// Per-workgroup digit histograms of every pass in one read of the keys.  Each
+// workgroup takes a contiguous chunk, four entries per thread per step with the
+// loads issued together.  Keys are often nearly sorted, so a wave whose lanes
+// all carry the same digit adds its count with one LDS atomic.
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_sort_hist(KeyPtrs<W> keys, uint64_t n, SortPlan plan,
                                                       uint32_t* __restrict__ partial) {
+  constexpr int U = 4;
   extern __shared__ uint32_t s_h[];  // npass * 256
   const uint32_t np = plan.npass;
   for (uint32_t i = threadIdx.x; i < np * kRadix; i += kBlock) s_h[i] = 0;
   __syncthreads();
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-    uint64_t k[W];
+  const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+  const uint64_t hi = lo + chunk < n ? lo + chunk : n;
+  for (uint64_t base = lo; base < hi; base += (uint64_t)kBlock * U) {
+    uint64_t k[U][W];
+    bool valid[U];
 #pragma unroll
-    for (int w = 0; w < W; ++w) k[w] = keys.w[w][i];
-    for (uint32_t p = 0; p < np; ++p) atomicAdd(&s_h[p * kRadix + digit_of<W>(k, plan.pass[p])], 1u);
+    for (int u = 0; u < U; ++u) {
+      const uint64_t i = base + (uint64_t)u * kBlock + threadIdx.x;
+      valid[u] = i < hi;
+#pragma unroll
+      for (int w = 0; w < W; ++w) k[u][w] = valid[u] ? keys.w[w][i] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t active = __ballot(valid[u]);
+      if (!valid[u]) continue;
+      for (uint32_t p = 0; p < np; ++p) {
+        const uint32_t d = digit_of<W>(k[u], plan.pass[p]);
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        if (__ballot(d == d0) == active) {
+          if (lane_id() == (uint32_t)__builtin_ctzll(active)) atomicAdd(&s_h[p * kRadix + d0], (uint32_t)__popcll(active));
+        } else {
+          atomicAdd(&s_h[p * kRadix + d], 1u);
+        }
+      }
+    }
   }
   __syncthreads();
   uint32_t* out = partial + (uint64_t)blockIdx.x * np * kRadix;
@@ -525,18 +550,18 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(KeyPtrs<W> in_keys, const 
 
   uint64_t k[ITEMS][W];
   uint32_t dig[ITEMS], rank[ITEMS];
+  // all key loads first (the digit extraction loops would otherwise make
+  // each load wait for the previous item)
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
-    if (le < tile_n) {
 #pragma unroll
-      for (int w = 0; w < W; ++w) k[i][w] = in_keys.w[w][base + le];
-      dig[i] = digit_of<W>(k[i], pd);
-    } else {
+    for (int w = 0; w < W; ++w) k[i][w] = le < tile_n ? in_keys.w[w][base + le] : 0ull;
+  }
 #pragma unroll
-      for (int w = 0; w < W; ++w) k[i][w] = 0;
-      dig[i] = 0;
-    }
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
+    dig[i] = le < tile_n ? digit_of<W>(k[i], pd) : 0u;
   }
   // stable rank within the wave's chunk: ballot-match on the digit bits
 #pragma unroll
@@ -598,15 +623,18 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(KeyPtrs<W> in_keys, const 
     }
     __syncthreads();
   }
+  double2 av[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
+    av[i] = le < tile_n ? in_amp[base + le] : make_double2(0.0, 0.0);
+  }
   double im_part[ITEMS];
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
-    if (le < tile_n) {
-      const double2 a = in_amp[base + le];
-      s_stage[pos[i]] = __double_as_longlong(a.x);
-      im_part[i] = a.y;
-    }
+    if (le < tile_n) s_stage[pos[i]] = __double_as_longlong(av[i].x);
+    im_part[i] = av[i].y;
   }
   __syncthreads();
   double* out_d = reinterpret_cast<double*>(out_amp);

@@ -30,7 +30,7 @@ constexpr uint64_t kAlign = 256;
 constexpr uint32_t kMaxOpsPerCall = 16384;  // device op ring, in PermOp records
 constexpr uint64_t kOpRingBytes = (uint64_t)kMaxOpsPerCall * sizeof(PermOp);
 constexpr uint32_t kRunChunk = 4096;        // ops per fused launch
-constexpr uint32_t kHistBlocksMax = 256;
+constexpr uint32_t kHistBlocksMax = 1024;
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -114,7 +114,7 @@ Carve carve(uint32_t W, uint32_t ninst, uint64_t cap, uint64_t table_bytes) {
   off = align_up(off + (uint64_t)kMaxOpsPerCall * sizeof(PermOp), kAlign);
   c.uscr = off;
   off = align_up(off + (uint64_t)(ninst + 64) * 8, kAlign);
-  c.hist_blocks = std::min<uint64_t>(kHistBlocksMax, std::max<uint64_t>(1, cap / 16384));
+  c.hist_blocks = std::min<uint64_t>(kHistBlocksMax, std::max<uint64_t>(1, cap / 8192));
   c.hist = off;
   off = align_up(off + c.hist_blocks * kMaxPasses * kRadix * 4, kAlign);
   c.tables = off;
@@ -479,7 +479,7 @@ int run_sort_w(ss_state* st, const SortPlan& plan) {
   if (plan.npass == 0 || n <= 1) return SS_OK;
   const int items = (W == 4) ? 8 : st->sort_items;
   const uint64_t tile = (uint64_t)kBlock * items;
-  const uint32_t nb = (uint32_t)std::min<uint64_t>(st->cv.hist_blocks, (n + 2047) / 2048);
+  const uint32_t nb = (uint32_t)std::min<uint64_t>(st->cv.hist_blocks, (n + 8191) / 8192);
   int tr = trace_begin(st, SS_TRACE_SORT_HIST);
   k_sort_hist<W><<<nb, kBlock, plan.npass * kRadix * 4, st->stream>>>(kp<W>(st->buf[st->cur]), n, plan,
                                                                        st->hist);
