@@ -1213,6 +1213,8 @@ __global__ __launch_bounds__(kBlock) void k_perm_batched(KeyPtrs<W> keys, double
   publish_masks<W>(meta, epoch, orv, andv, s_red);
 }
 
+constexpr int kOpStage = 16;   // op records of one tile's instances staged in LDS
+
 // Branch expansion: every parent emits the children of its instance's op
 // (target bits set to s, amplitude multiplied by the matrix elements stage by
 // stage in ascending qubit order), skipping children reached through an exact
@@ -1232,6 +1234,8 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
   __shared__ uint64_t s_lb[12];
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_irange[2];
+  __shared__ BatchOp s_bop[kOpStage];
   uint64_t n;
   if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
@@ -1254,6 +1258,31 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
   }
   uint32_t k[ITEMS], b[ITEMS], cnt[ITEMS], inst[ITEMS];
   bool copy[ITEMS];
+  // Entries are ordered by instance, so a tile usually spans few instances:
+  // their op records are staged in LDS (the first and the last entry of the
+  // tile bound the range); an instance outside the staged range reads its
+  // record from global memory.
+  const uint64_t e_last = (e0 + TILE < n ? e0 + TILE : n) - 1;
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    inst[it] = inst_of<W>(key[it], iword, ishift, imask);
+    const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
+    if (e == e0) s_irange[0] = inst[it];
+    if (e == e_last) s_irange[1] = inst[it];
+  }
+  __syncthreads();
+  const uint32_t i0 = s_irange[0], i1 = s_irange[1];
+  const bool staged = i1 >= i0 && i1 - i0 < (uint32_t)kOpStage;
+  if (staged) {
+    constexpr uint32_t Q = sizeof(BatchOp) / 16;
+    const uint4* src = reinterpret_cast<const uint4*>(bops + i0);
+    uint4* dst = reinterpret_cast<uint4*>(s_bop);
+    for (uint32_t q = threadIdx.x; q < (i1 - i0 + 1) * Q; q += kBlock) dst[q] = src[q];
+  }
+  __syncthreads();
+  auto op_of = [&](uint32_t i) -> const BatchOp& {
+    return (staged && i >= i0 && i <= i1) ? s_bop[i - i0] : bops[i];
+  };
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
@@ -1261,9 +1290,8 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
     b[it] = 0;
     cnt[it] = 0;
     copy[it] = true;
-    inst[it] = inst_of<W>(key[it], iword, ishift, imask);
     if (e < n) {
-      const BatchOp& op = bops[inst[it]];
+      const BatchOp& op = op_of(inst[it]);
       k[it] = op.k;
       copy[it] = k[it] == 0 || (op.has_ctl && !controls_hold<W>(key[it], op.cmask, op.cval));
       if (copy[it]) {
@@ -1308,7 +1336,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
     const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
     if (e >= n) continue;
     uint64_t p = s_off + off[it];
-    const BatchOp& op = bops[inst[it]];
+    const BatchOp& op = op_of(inst[it]);
     const uint32_t nchild = copy[it] ? 1u : (1u << k[it]);
     for (uint32_t sv = 0; sv < nchild; ++sv) {
       uint64_t ok[W];
@@ -1375,13 +1403,28 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
   const uint64_t ntiles = (n + TILE - 1) / TILE;
   if (tile_out_of_range(tile, ntiles, &meta->err)) return;
   const uint64_t e0 = (uint64_t)tile * TILE;
-  // stage slot l = entry e0 - 1 + l (zero key, zero amplitude past n)
-  for (uint32_t l = threadIdx.x; l < S; l += kBlock) {
-    const uint64_t e = e0 + l - 1;
-    const bool ok = (l > 0 || e0 > 0) && e < n;
+  // stage slot l = entry e0 - 1 + l (zero key, zero amplitude past n); all
+  // loads first, then the LDS stores
+  constexpr uint32_t R = (S + kBlock - 1) / kBlock;
+  uint64_t sk[R][W];
+  double2 sa[R];
 #pragma unroll
-    for (int w = 0; w < W; ++w) s_key[w * S + l] = ok ? in_keys.w[w][e] : 0ull;
-    s_amp[l] = ok ? in_amp[e] : make_double2(0.0, 0.0);
+  for (uint32_t r = 0; r < R; ++r) {
+    const uint32_t l = r * kBlock + threadIdx.x;
+    const uint64_t e = e0 + l - 1;
+    const bool ok = l < S && (l > 0 || e0 > 0) && e < n;
+#pragma unroll
+    for (int w = 0; w < W; ++w) sk[r][w] = ok ? in_keys.w[w][e] : 0ull;
+    sa[r] = ok ? in_amp[e] : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
+    const uint32_t l = r * kBlock + threadIdx.x;
+    if (l < S) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) s_key[w * S + l] = sk[r][w];
+      s_amp[l] = sa[r];
+    }
   }
   __syncthreads();
   uint64_t key[ITEMS][W];
