@@ -123,6 +123,184 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def _kernel_table(tr, steps=1):
+    return {k: {"launches": v["launches"] / steps, "avg_us": 1e6 * v["seconds"] / v["launches"],
+                "ms_per_step": 1e3 * v["seconds"] / steps,
+                "GBps": v["bytes"] / v["seconds"] / 1e9 if v["seconds"] else None}
+            for k, v in tr.items() if v["launches"]}
+
+
+def bench_c1(args):
+    """Small circuits (20-bit keys, nnz <= 2^14, 300 ops): the latency-bound
+    end.  Per seed: 2 warm-up runs, then the median of 10 timed runs."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2503_15118_amd import _abi
+
+    seeds = list(range(args.c1_seeds))
+    med, ents = [], []
+    st = None
+    for seed in seeds:
+        c = wl.c1_circuit(seed)
+        ops = _abi.to_ss_ops(c.ops)
+        if st is None:
+            st = _abi.State(c.regs, eps=c.eps, cap_entries=1 << 15, table_bytes=0)
+        zero = np.zeros((1, len(c.regs)), dtype=np.uint64)
+        one = np.array([1.0 + 0j])
+        times = []
+        for r in range(12):
+            st.set_entries(0, zero, one)
+            e0 = st.stats()["entries_updated"]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st.apply(ops)
+            torch.cuda.synchronize()
+            if r >= 2:
+                times.append(time.perf_counter() - t0)
+        ents.append(st.stats()["entries_updated"] - e0)
+        med.append(float(np.median(times)))
+    out = {"workload": f"C1-form circuits (a:7, b:7, anc:6; 300 ops; nnz <= 2^14), seeds 0..{len(seeds) - 1}",
+           "median_us_per_circuit": 1e6 * float(np.median(med)),
+           "max_us_per_circuit": 1e6 * float(np.max(med)),
+           "entries_per_s": float(np.sum(ents) / np.sum(med))}
+    if not args.no_cpu_baseline:
+        from oracle.oracle import OracleState
+        osec, oent = 0.0, 0
+        for seed in seeds[:2]:
+            c = wl.c1_circuit(seed)
+            o = OracleState(c.regs, c.eps)
+            sec, ent = o.apply(c.ops)
+            osec += sec
+            oent += ent
+        out["cpu_baseline"] = {"value": oent / osec, "unit": "entries/s", "cores": 1, "kind": "oracle",
+                               "sample": f"seeds 0..1 whole circuits ({oent} entry updates in {osec:.2f} s)"}
+        out["gpu_vs_oracle"] = out["entries_per_s"] / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+
+
+def bench_c4(args):
+    """The linear-solver walk: 64 right-hand sides as instances of one state
+    (52-bit key), each step QRAM load, 16 controlled Ry, unload, reflection."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2503_15118_amd import _abi
+
+    circ = wl.c4_batch(args.seed, nrhs=args.nrhs, steps=args.c4_steps)
+    c0 = circ[0]
+    ops = _abi.to_ss_ops(c0.ops)
+    st = _abi.State(c0.regs, ninst=len(circ), eps=c0.eps, cap_entries=1 << 22, table_bytes=1 << 16)
+    st.load_qram(c0.tables[0])
+
+    def reset():
+        for i, c in enumerate(circ):
+            st.set_entries(i, c.init_values, c.init_amps)
+
+    reset()
+    st.apply(ops)   # warm-up
+    times = []
+    st.set_option("trace", 1)
+    st.set_option("trace_reset", 1)
+    ent = 0
+    for _ in range(args.c4_trials):
+        reset()
+        e0 = st.stats()["entries_updated"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.apply(ops)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        ent = st.stats()["entries_updated"] - e0
+    tr = st.trace()
+    kernels = _kernel_table(tr, args.c4_trials)
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    out = {"workload": f"QRAM linear-solver walk: {len(circ)} right-hand sides (N=1024, 8 nnz/row), "
+                       f"{args.c4_steps} steps, 52-bit key; seed {args.seed}",
+           "ms_per_batch": 1e3 * float(np.median(times)), "entries_per_batch": int(ent),
+           "entries_per_s": ent / float(np.median(times)), "nnz_final": st.nnz(),
+           "kernels": kernels, "dominant": dom,
+           "dominant_frac_of_8TBps": kernels[dom]["GBps"] / HBM_PEAK_GBS if kernels[dom]["GBps"] else None}
+    print(json.dumps(out), flush=True)
+
+
+def bench_m6(args):
+    """Roofline sweep: one op per launch on n random distinct keys, per op kind
+    and size, timed with HIP events; algorithmic bytes per launch / time."""
+    import numpy as np
+    import workloads as wl
+    from paper_2503_15118_amd import _abi
+
+    rng = np.random.default_rng(args.seed)
+    # a 1-qubit register that no key sets is the branching target
+    layouts = {1: [("a", 20), ("b", 20), ("t", 1)], 2: [("a", 32), ("b", 32), ("c", 32), ("t", 1)]}
+    rows = []
+
+    def trace_rows(st, W, lg, kind, cats):
+        tr = st.trace()
+        for cat in cats:
+            r = tr[cat]
+            if r["launches"]:
+                gbps = r["bytes"] / r["seconds"] / 1e9
+                rows.append({"W": W, "log2_n": lg, "kind": kind if len(cats) == 1 else cat,
+                             "launches": r["launches"], "avg_us": 1e6 * r["seconds"] / r["launches"],
+                             "GBps": gbps, "frac_of_8TBps": gbps / HBM_PEAK_GBS})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+
+    def run(st, ops, reps=3, grouping_first=None):
+        st.set_option("trace", 1)
+        st.set_option("trace_reset", 1)
+        for _ in range(reps):
+            for i, o in enumerate(ops):
+                if grouping_first is not None and i == 0:
+                    st.set_option("grouping", grouping_first)
+                st.apply(_abi.to_ss_ops(wl.ops_array([o])))
+                st.set_option("grouping", 1)
+        st.set_option("trace", 0)
+
+    for W, regs in layouts.items():
+        for lg in range(args.m6_min_log2, args.m6_max_log2 + 1, 3):
+            n = 1 << lg
+            w0, w1 = regs[0][1], regs[1][1]
+            tb = (1 << 22) + 4096 if W == 1 else 4096
+            st = _abi.State(regs, eps=1e-14, cap_entries=2 * n, table_bytes=tb)
+            if W == 1:
+                st.load_qram(wl.Table(values=rng.integers(0, 2 ** w1, size=2 ** w0, dtype=np.uint64),
+                                      addr_bits=w0, word_bits=w1))
+            hi = np.uint64(2 ** (w0 + w1) - 1) if w0 + w1 < 64 else np.uint64(2 ** 64 - 1)
+            v = np.unique(rng.integers(0, hi, size=int(n * 1.1) + 16, dtype=np.uint64, endpoint=False))[:n]
+            rng.shuffle(v)
+            vals = np.zeros((len(v), len(regs)), dtype=np.uint64)
+            vals[:, 0] = v & np.uint64((1 << w0) - 1)
+            vals[:, 1] = v >> np.uint64(w0)
+            amps = (rng.standard_normal(len(v)) + 1j * rng.standard_normal(len(v))) / np.sqrt(2 * len(v))
+            st.set_entries(0, vals, amps)
+            t = len(regs) - 1
+            perm = [("X", wl.make_op("X", 0, qmask=1)),
+                    ("ADD", wl.make_op("ADD", 1, reg2=0)),
+                    ("MULC", wl.make_op("MULC", 0, imm=(0x9E3779B1 & ((1 << w0) - 1)) | 1)),
+                    ("phase", wl.make_op("REFLECT0", 1))]
+            if W == 1:
+                perm.append(("QRAM", wl.make_op("QRAM_LOAD", 1, reg2=0, table=0)))
+            for name, op in perm:
+                run(st, [op], reps=1)              # warm-up
+                run(st, [op])
+                trace_rows(st, W, lg, name, ["perm"])
+            h = wl.make_op("H", t, qmask=1)
+            # H on t twice: an expansion (every key gets both children), then the
+            # grouped merge of the adjacent pairs back to n entries
+            run(st, [h, h], reps=1, grouping_first=0)
+            run(st, [h, h], grouping_first=0)
+            trace_rows(st, W, lg, "H", ["expand", "group"])
+            # sort + merge on 2n entries where every idle key appears twice
+            run(st, [h], reps=1)
+            run(st, [h], reps=1, grouping_first=0)
+            trace_rows(st, W, lg + 1, "sort", ["sort_hist", "sort_pass", "group"])
+            st.close()
+    print(json.dumps({"workload": "roofline sweep: one op per launch on random distinct keys "
+                                  "(W=1: a:20 b:20 t:1; W=2: a,b,c:32 t:1)", "rows": rows}), flush=True)
+
+
 def bench_serving(args):
     """Serving: a Poisson request stream mixing the four workload forms, served
     with footprint admission and continuous batching, against the same trace
@@ -182,7 +360,12 @@ def main():
     ap.add_argument("--tile-order", type=int, default=1)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 64 MiB device copy first (reference for HBM counters)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "m6"])
+    ap.add_argument("--c1-seeds", type=int, default=32)
+    ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--c4-trials", type=int, default=3)
+    ap.add_argument("--m6-min-log2", type=int, default=16)
+    ap.add_argument("--m6-max-log2", type=int, default=25)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--duration", type=float, default=2.0)
     ap.add_argument("--serve-hi-bits", type=float, default=24.0)
@@ -197,8 +380,17 @@ def main():
               "sharding is a design note, not an implemented path", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "c1":
+        bench_c1(args)
+        return
     if args.workload == "c3":
         bench_batched(args)
+        return
+    if args.workload == "c4":
+        bench_c4(args)
+        return
+    if args.workload == "m6":
+        bench_m6(args)
         return
     if args.workload == "c5":
         bench_serving(args)

@@ -53,6 +53,11 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950)")
+    # The library shares the HIP runtime, the device memory and the streams of
+    # PyTorch.  PyTorch ships its own HIP runtime under the same soname, so it
+    # is loaded first: the library then binds to that copy instead of bringing
+    # in a second runtime that PyTorch would pick up in turn.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, u32, u64, f64, i32, i64 = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double,
                                    ctypes.c_int, ctypes.c_int64)

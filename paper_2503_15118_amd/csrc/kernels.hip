@@ -517,7 +517,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_scan(const uint32_t* __restrict
   __shared__ uint64_t s_tmp[4];
   const uint32_t p = blockIdx.x, d = threadIdx.x;
   uint64_t c = 0;
-  for (uint32_t b = 0; b < nblk; ++b) c += partial[((uint64_t)b * np + p) * kRadix + d];
+  uint32_t b = 0;
+  for (; b + 8 <= nblk; b += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = partial[((uint64_t)(b + u) * np + p) * kRadix + d];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c += v[u];
+  }
+  for (; b < nblk; ++b) c += partial[((uint64_t)b * np + p) * kRadix + d];
   uint64_t tot;
   const uint64_t ex = block_excl_scan<uint64_t>(c, s_tmp, tot);
   digit_start[p * kRadix + d] = ex;

@@ -103,6 +103,10 @@ struct Carve {
   uint64_t lb_words, hist_blocks;
 };
 
+// Radix passes a sort of W-word keys can need: every key bit plus the
+// targets of one interference op, 8 bits per pass.
+uint64_t max_passes(uint32_t W) { return (64ull * W + kMaxGroupBits + kRadixBits - 1) / kRadixBits; }
+
 Carve carve(uint32_t W, uint32_t ninst, uint64_t cap, uint64_t table_bytes) {
   Carve c{};
   uint64_t off = 0;
@@ -114,9 +118,9 @@ Carve carve(uint32_t W, uint32_t ninst, uint64_t cap, uint64_t table_bytes) {
   off = align_up(off + (uint64_t)kMaxOpsPerCall * sizeof(PermOp), kAlign);
   c.uscr = off;
   off = align_up(off + (uint64_t)(ninst + 64) * 8, kAlign);
-  c.hist_blocks = std::min<uint64_t>(kHistBlocksMax, std::max<uint64_t>(1, cap / 8192));
+  c.hist_blocks = std::min<uint64_t>(kHistBlocksMax, std::max<uint64_t>(1, cap / 4096));
   c.hist = off;
-  off = align_up(off + c.hist_blocks * kMaxPasses * kRadix * 4, kAlign);
+  off = align_up(off + c.hist_blocks * max_passes(W) * kRadix * 4, kAlign);
   c.tables = off;
   off = align_up(off + table_bytes, kAlign);
   // look-back words: sort tiles (>= 2048 entries) x 256 digits, emit tiles (256 entries)
@@ -477,9 +481,10 @@ template <int W>
 int run_sort_w(ss_state* st, const SortPlan& plan) {
   const uint64_t n = st->n;
   if (plan.npass == 0 || n <= 1) return SS_OK;
+  if (plan.npass > max_passes(W)) return hip_fail(st);  // the histogram area is sized for this
   const int items = (W == 4) ? 8 : st->sort_items;
   const uint64_t tile = (uint64_t)kBlock * items;
-  const uint32_t nb = (uint32_t)std::min<uint64_t>(st->cv.hist_blocks, (n + 8191) / 8192);
+  const uint32_t nb = (uint32_t)std::min<uint64_t>(st->cv.hist_blocks, (n + 4095) / 4096);
   int tr = trace_begin(st, SS_TRACE_SORT_HIST);
   k_sort_hist<W><<<nb, kBlock, plan.npass * kRadix * 4, st->stream>>>(kp<W>(st->buf[st->cur]), n, plan,
                                                                        st->hist);

@@ -30,11 +30,12 @@ def test_strerror_and_footprint():
     c1 = [("a", 7), ("b", 7), ("anc", 6)]
     small = _abi.required_bytes(c1, 1, 1 << 14)
     big = _abi.required_bytes(c1, 1, 1 << 20)
-    # two 24-byte buffers per entry dominate (W = 1)
-    assert 48 * (1 << 20) < big - small < 52 * (1 << 20)
+    # two 24-byte buffers per entry dominate (W = 1); look-back words and the
+    # per-workgroup sort histograms add a few bytes per entry
+    assert 48 * (1 << 20) < big - small < 53 * (1 << 20)
     c2 = [("a", 32), ("b", 32), ("c", 32), ("flag", 1)]
     b2 = _abi.required_bytes(c2, 1, 1 << 20) - _abi.required_bytes(c2, 1, 1 << 14)
-    assert 64 * ((1 << 20) - (1 << 14)) < b2 < 68 * (1 << 20)
+    assert 64 * ((1 << 20) - (1 << 14)) < b2 < 70 * (1 << 20)
 
 
 def test_layout_rejections():
