@@ -122,70 +122,18 @@ __device__ uint64_t lookback_single(uint64_t* lb, uint32_t tile, uint64_t agg, u
   return excl;
 }
 
-// Decoupled look-back for one running total per tile, executed by all 256
-// threads: each step reads the flags of 256 predecessors at once, so when
-// many tiles start together (only a few carry an inclusive total yet) the
-// walk back reaches one in few round trips.  `s` holds 12 LDS words.
+// Exclusive prefix of a tile's count for a whole workgroup: wave 0 runs the
+// look-back (64 predecessor words per round trip), the others wait at the
+// barrier.  A block-wide 256-word window was measured slower: four barriers
+// per round cost more than the round trips it saves.
 __device__ uint64_t lookback_block(uint64_t* lb, uint32_t tile, uint64_t agg, uint32_t epoch,
                                    unsigned int* err, uint64_t* s) {
-  const uint64_t ep = (uint64_t)(epoch & kEpochMask) << kLbEpochShift;
-  const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-  if (tile == 0) {
-    if (tid == 0) st_agent(&lb[0], ep | kLbInc | agg);
-    return 0;
+  if ((threadIdx.x >> 6) == 0) {
+    const uint64_t excl = lookback_single(lb, tile, agg, epoch, err);
+    if (threadIdx.x == 0) s[0] = excl;
   }
-  if (tid == 0) st_agent(&lb[tile], ep | kLbAgg | agg);
-  uint64_t excl = 0;
-  int64_t top = (int64_t)tile - 1;
-  uint32_t spins = 0;
-  while (true) {
-    const int64_t idx = top - (int64_t)tid;
-    const uint64_t v = idx >= 0 ? ld_agent(&lb[idx]) : (ep | kLbInc);
-    const bool rd = lb_ready(v, epoch);
-    const uint64_t rdy = __ballot(rd);
-    const uint64_t inc = __ballot(rd && (v & kLbInc));
-    // per wave: first not-ready lane and first inclusive lane (64 = none)
-    const uint32_t fnr = (~rdy) ? (uint32_t)__builtin_ctzll(~rdy) : 64u;
-    const uint32_t finc = inc ? (uint32_t)__builtin_ctzll(inc) : 64u;
-    if (lane == 0) {
-      s[wave] = fnr == 64u ? 256u : wave * 64u + fnr;
-      s[4 + wave] = finc == 64u ? 256u : wave * 64u + finc;
-    }
-    __syncthreads();
-    uint32_t first_nr = 256u, first_inc = 256u;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      first_nr = min(first_nr, (uint32_t)s[w]);
-      first_inc = min(first_inc, (uint32_t)s[4 + w]);
-    }
-    const bool done = first_inc < first_nr;
-    const bool step = !done && first_nr == 256u;
-    uint64_t part = 0;
-    if (done) part = tid <= first_inc ? (v & kLbValueMask) : 0ull;
-    else if (step) part = v & kLbValueMask;
-    part = wave_sum<uint64_t>(part);
-    __syncthreads();
-    if (lane == 0) s[8 + wave] = part;
-    __syncthreads();
-    const uint64_t sum = s[8] + s[9] + s[10] + s[11];
-    __syncthreads();
-    if (done) {
-      excl += sum;
-      break;
-    }
-    if (step) {
-      excl += sum;
-      top -= 256;
-      continue;
-    }
-    if (++spins > kSpinLimit) {
-      if (tid == 0) atomicOr(err, kErrSpin);
-      break;
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
-  if (tid == 0) st_agent(&lb[tile], ep | kLbInc | (excl + agg));
-  return excl;
+  __syncthreads();
+  return s[0];
 }
 
 // Per-digit look-back: thread `d` of the workgroup walks its own chain,
