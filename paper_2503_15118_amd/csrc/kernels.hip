@@ -885,32 +885,17 @@ __global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const doub
 // stay adjacent, in target-value order, and every child is computed with the
 // same expression as in k_group (m[r][0] * a0 + m[r][1] * a1, absent = 0).
 // ---------------------------------------------------------------------------
+// The children of the ITEMS entries e0 + it * kBlock + threadIdx.x of one
+// tile: keep mask (bit r: child with target value r) and amplitudes.  Every
+// thread of the workgroup calls it (group mode stages the tile in LDS).
 template <int W, int MODE, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
-                                                 KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
-                                                 uint32_t ns, uint64_t cap, GroupOp op, uint64_t* lb,
-                                                 DevMeta* meta, uint32_t epoch, uint32_t xo) {
+__device__ __forceinline__ void pair_tile(const KeyPtrs<W>& in_keys, const double2* __restrict__ in_amp,
+                                          uint64_t n, uint64_t e0, const GroupOp& op, uint64_t* s_stage,
+                                          uint64_t (&key)[ITEMS][W], double2 (&out)[ITEMS][2],
+                                          uint32_t (&keepm)[ITEMS]) {
   constexpr uint32_t TILE = kBlock * ITEMS;
-  __shared__ uint32_t s_wtot[ITEMS][kBlock / 64];
-  __shared__ uint64_t s_off;
-  __shared__ uint64_t s_lb[12];
-  __shared__ uint64_t s_red[2 * kMaxW * 4];
-  __shared__ uint32_t s_tile;
-  // group mode: the tile's keys (W words) and amplitudes plus one entry on
-  // each side, for the partner test
-  __shared__ uint64_t s_stage[MODE == MODE_GROUP ? (W + 2) * (TILE + 2) : 1];
-  uint64_t n;
-  if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
-  if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) meta->upd += n;
-  const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
-  const uint64_t ntiles = (n + TILE - 1) / TILE;
-  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
   const uint32_t tw = op.tword[0], tb = op.tbit[0];
-  uint64_t key[ITEMS][W];
   double2 amp[ITEMS];
-  double2 out[ITEMS][2];
-  uint32_t keepm[ITEMS], cnt[ITEMS];
-  const uint64_t e0 = (uint64_t)tile * TILE;
   // every load of the tile is issued before any is used
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
@@ -996,33 +981,21 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
         }
       }
     }
-    cnt[it] = (uint32_t)__popc(keepm[it]);
   }
-  uint32_t off[ITEMS];
-  const uint64_t tile_total = tile_offsets<ITEMS>(cnt, off, s_wtot);
-  {
-    const uint64_t ex = lookback_block(lb, tile, tile_total, epoch, &meta->err, s_lb);
-    if (threadIdx.x == 0) {
-      s_off = ex;
-      if (tile == ntiles - 1) {
-        meta->nnz_out[epoch % kRing] = ex + tile_total;
-        meta->nring[(ns & 1) ^ 1] = ex + tile_total;
-        if (ex + tile_total > cap) raise_error(meta, kErrCapacity, epoch);
-        else atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
-      }
-    }
-  }
-  __syncthreads();
-  uint64_t orv[W], andv[W];
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    orv[w] = 0;
-    andv[w] = ~0ull;
-  }
-  const uint64_t tbit = 1ull << tb;
+}
+
+// Write the kept children of one tile: the child of item `it` with target
+// value r goes to pos[it] + (its rank among the item's kept children).
+template <int W, int ITEMS>
+__device__ __forceinline__ void pair_write(KeyPtrs<W>& out_keys, double2* __restrict__ out_amp, uint64_t cap,
+                                           const GroupOp& op, const uint64_t (&key)[ITEMS][W],
+                                           const double2 (&out)[ITEMS][2], const uint32_t (&keepm)[ITEMS],
+                                           const uint64_t (&pos)[ITEMS], uint64_t (&orv)[W], uint64_t (&andv)[W]) {
+  const uint32_t tw = op.tword[0];
+  const uint64_t tbit = 1ull << op.tbit[0];
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
-    uint64_t p = s_off + off[it];
+    uint64_t p = pos[it];
 #pragma unroll
     for (uint32_t r = 0; r < 2; ++r) {
       if (!((keepm[it] >> r) & 1u)) continue;
@@ -1045,6 +1018,126 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
       ++p;
     }
   }
+}
+
+// Speculative placement without look-back: when every entry of the op has
+// exactly `f` kept children (f = 1: full pairs or pass-through in group mode;
+// f = 2: both children in expand mode) the compacted position of entry e's
+// children is f * e.  A tile that finds an entry with another count (or an
+// output past the capacity) writes nothing and flags the launch; k_pair then
+// compacts the whole op.  Tile = workgroup, no tickets.
+template <int W, int MODE, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_pair_spec(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
+                                                      KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
+                                                      uint32_t ns, uint64_t cap, GroupOp op, uint32_t f,
+                                                      DevMeta* meta, uint32_t epoch) {
+  constexpr uint32_t TILE = kBlock * ITEMS;
+  __shared__ uint64_t s_red[2 * kMaxW * 4];
+  __shared__ uint64_t s_stage[MODE == MODE_GROUP ? (W + 2) * (TILE + 2) : 1];
+  if (launch_prologue(meta, epoch)) return;
+  const uint64_t n = meta->nring[ns & 1];
+  const uint64_t e0 = (uint64_t)blockIdx.x * TILE;
+  if (e0 >= n) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (uint64_t)gridDim.x * TILE < n) raise_error(meta, kErrGrid, epoch);
+  if (f * n > cap) {
+    if (threadIdx.x == 0) meta->spec_irr[epoch % kRing] = 1u;
+    return;
+  }
+  uint64_t key[ITEMS][W];
+  double2 out[ITEMS][2];
+  uint32_t keepm[ITEMS];
+  pair_tile<W, MODE, ITEMS>(in_keys, in_amp, n, e0, op, s_stage, key, out, keepm);
+  bool reg = true;
+  uint64_t pos[ITEMS];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
+    if (e < n && (uint32_t)__popc(keepm[it]) != f) reg = false;
+    pos[it] = f * e;
+  }
+  if (!__syncthreads_and(reg)) {
+    if (threadIdx.x == 0) atomicOr(&meta->spec_irr[epoch % kRing], 1u);
+    return;
+  }
+  uint64_t orv[W], andv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    orv[w] = 0;
+    andv[w] = ~0ull;
+  }
+  pair_write<W, ITEMS>(out_keys, out_amp, cap, op, key, out, keepm, pos, orv, andv);
+  publish_masks<W>(meta, epoch, orv, andv, s_red);
+}
+
+// The compacting launch.  With spec_ep != 0 it follows k_pair_spec (launch
+// spec_ep): when that launch met no irregular tile, its outputs stand and
+// workgroup 0 only records the count f * n, the peak and the key masks.
+template <int W, int MODE, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
+                                                 KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
+                                                 uint32_t ns, uint64_t cap, GroupOp op, uint64_t* lb,
+                                                 DevMeta* meta, uint32_t epoch, uint32_t xo, uint32_t spec_ep,
+                                                 uint32_t f) {
+  constexpr uint32_t TILE = kBlock * ITEMS;
+  __shared__ uint32_t s_wtot[ITEMS][kBlock / 64];
+  __shared__ uint64_t s_off;
+  __shared__ uint64_t s_lb[12];
+  __shared__ uint64_t s_red[2 * kMaxW * 4];
+  __shared__ uint32_t s_tile;
+  // group mode: the tile's keys (W words) and amplitudes plus one entry on
+  // each side, for the partner test
+  __shared__ uint64_t s_stage[MODE == MODE_GROUP ? (W + 2) * (TILE + 2) : 1];
+  uint64_t n;
+  if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
+  if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) meta->upd += n;
+  if (spec_ep != 0 && *reinterpret_cast<volatile unsigned int*>(&meta->spec_irr[spec_ep % kRing]) == 0u) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      const uint64_t m = f * n;
+      meta->nnz_out[epoch % kRing] = m;
+      meta->nring[(ns & 1) ^ 1] = m;
+      atomicMax(&meta->peak, (unsigned long long)m);
+      for (int w = 0; w < kMaxW; ++w) {
+        meta->or_mask[epoch % kRing][w] = meta->or_mask[spec_ep % kRing][w];
+        meta->and_mask[epoch % kRing][w] = meta->and_mask[spec_ep % kRing][w];
+      }
+    }
+    return;
+  }
+  const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
+  const uint64_t ntiles = (n + TILE - 1) / TILE;
+  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
+  const uint64_t e0 = (uint64_t)tile * TILE;
+  uint64_t key[ITEMS][W];
+  double2 out[ITEMS][2];
+  uint32_t keepm[ITEMS], cnt[ITEMS];
+  pair_tile<W, MODE, ITEMS>(in_keys, in_amp, n, e0, op, s_stage, key, out, keepm);
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) cnt[it] = (uint32_t)__popc(keepm[it]);
+  uint32_t off[ITEMS];
+  const uint64_t tile_total = tile_offsets<ITEMS>(cnt, off, s_wtot);
+  {
+    const uint64_t ex = lookback_block(lb, tile, tile_total, epoch, &meta->err, s_lb);
+    if (threadIdx.x == 0) {
+      s_off = ex;
+      if (tile == ntiles - 1) {
+        meta->nnz_out[epoch % kRing] = ex + tile_total;
+        meta->nring[(ns & 1) ^ 1] = ex + tile_total;
+        if (ex + tile_total > cap) raise_error(meta, kErrCapacity, epoch);
+        else atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
+      }
+    }
+  }
+  __syncthreads();
+  uint64_t orv[W], andv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    orv[w] = 0;
+    andv[w] = ~0ull;
+  }
+  uint64_t pos[ITEMS];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) pos[it] = s_off + off[it];
+  pair_write<W, ITEMS>(out_keys, out_amp, cap, op, key, out, keepm, pos, orv, andv);
   publish_masks<W>(meta, epoch, orv, andv, s_red);
 }
 
@@ -1521,6 +1614,7 @@ __global__ void k_ring_init(DevMeta* meta) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     for (int r = 0; r < kRing; ++r) {
       meta->counters[r] = 0;
+      meta->spec_irr[r] = 0;
       for (int x = 0; x < kXcds; ++x) meta->xcd_ctr[r][x * kXcdStride] = 0;
       meta->nnz_out[r] = 0;
       for (int w = 0; w < kMaxW; ++w) {
@@ -1581,6 +1675,7 @@ __global__ void k_meta_init(DevMeta* meta) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     for (int r = 0; r < kRing; ++r) {
       meta->counters[r] = 0;
+      meta->spec_irr[r] = 0;
       for (int x = 0; x < kXcds; ++x) meta->xcd_ctr[r][x * kXcdStride] = 0;
       meta->nnz_out[r] = 0;
       for (int w = 0; w < kMaxW; ++w) {

@@ -225,6 +225,7 @@ __device__ __forceinline__ bool launch_prologue(DevMeta* meta, uint32_t epoch) {
     if (blockIdx.x == 0) {
       const uint32_t r = (epoch + kRing / 2) % kRing;
       meta->counters[r] = 0;
+      meta->spec_irr[r] = 0;
       for (int x = 0; x < kXcds; ++x) meta->xcd_ctr[r][x * kXcdStride] = 0;
       meta->nnz_out[r] = 0;
       for (int w = 0; w < kMaxW; ++w) {

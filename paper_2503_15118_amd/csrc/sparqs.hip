@@ -194,6 +194,11 @@ struct ss_state {
   int grouping = 1;
   int group_items = 4;
   int perm_entries = 8;
+  // option: a one-target expansion on at least this many entries (upper
+  // bound) first tries the fixed-fan-out placement; 0 never.  Below a few
+  // million entries the look-back chain is short and the extra launch costs
+  // more than it saves.
+  uint64_t speculate = 1ull << 23;
   uint32_t xcd_order = 0;        // 1 when workgroups spread round-robin over 8 XCDs
   int tile_order_opt = 1;        // option: 1 use XCD tickets when possible, 0 one counter
   uint64_t stats[8]{};
@@ -542,18 +547,29 @@ int sort_canonical(ss_state* st) {
 // emitting kernels (group / expand / filter): read buf[cur], write buf[cur^1]
 // ---------------------------------------------------------------------------
 template <int W, int K, int ITEMS>
-void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep) {
+void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
   const uint32_t ns = st->nslot;
   const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock * ITEMS - 1) / (kBlock * ITEMS));
   if (K == 1) {
-    if (mode == MODE_GROUP)
+    // one child per entry in group mode, two in expand mode
+    const uint32_t f = mode == MODE_GROUP ? 1u : 2u;
+    if (mode == MODE_GROUP) {
+      if (ep_spec)
+        k_pair_spec<W, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
+                                                                             ns, st->cap, g, f, st->meta, ep_spec);
       k_pair<W, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
-                                                                       ns, st->cap, g, st->lb, st->meta, ep, xo(st));
-    else
+                                                                       ns, st->cap, g, st->lb, st->meta, ep, xo(st),
+                                                                       ep_spec, f);
+    } else {
+      if (ep_spec)
+        k_pair_spec<W, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
+                                                                              ns, st->cap, g, f, st->meta, ep_spec);
       k_pair<W, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
-                                                                        ns, st->cap, g, st->lb, st->meta, ep, xo(st));
+                                                                        ns, st->cap, g, st->lb, st->meta, ep, xo(st),
+                                                                        ep_spec, f);
+    }
     return;
   }
   if (mode == MODE_GROUP)
@@ -567,21 +583,23 @@ void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep) {
 // Items per thread: several for one or two targets (bigger tiles, fewer
 // tile-id atomics), one for 8..32-member groups (register budget).
 template <int W, int K>
-void launch_group_wk(ss_state* st, int mode, const GroupOp& g, uint32_t ep) {
+void launch_group_wk(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec) {
   const int items = K <= 2 ? st->group_items : 1;
-  if (K <= 2 && items >= 4) launch_group_wki<W, K, (K <= 2 ? 4 : 1)>(st, mode, g, ep);
-  else if (K <= 2 && items == 2) launch_group_wki<W, K, (K <= 2 ? 2 : 1)>(st, mode, g, ep);
-  else launch_group_wki<W, K, 1>(st, mode, g, ep);
+  if (K <= 2 && items >= 4) launch_group_wki<W, K, (K <= 2 ? 4 : 1)>(st, mode, g, ep, ep_spec);
+  else if (K <= 2 && items == 2) launch_group_wki<W, K, (K <= 2 ? 2 : 1)>(st, mode, g, ep, ep_spec);
+  else launch_group_wki<W, K, 1>(st, mode, g, ep, ep_spec);
 }
 
+// ep_spec != 0 (one target only): a speculative fixed-fan-out launch of that
+// epoch runs first.
 template <int W>
-void launch_group_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep) {
+void launch_group_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec) {
   switch (g.k) {
-    case 1: launch_group_wk<W, 1>(st, mode, g, ep); break;
-    case 2: launch_group_wk<W, 2>(st, mode, g, ep); break;
-    case 3: launch_group_wk<W, 3>(st, mode, g, ep); break;
-    case 4: launch_group_wk<W, 4>(st, mode, g, ep); break;
-    default: launch_group_wk<W, 5>(st, mode, g, ep); break;
+    case 1: launch_group_wk<W, 1>(st, mode, g, ep, ep_spec); break;
+    case 2: launch_group_wk<W, 2>(st, mode, g, ep, 0); break;
+    case 3: launch_group_wk<W, 3>(st, mode, g, ep, 0); break;
+    case 4: launch_group_wk<W, 4>(st, mode, g, ep, 0); break;
+    default: launch_group_wk<W, 5>(st, mode, g, ep, 0); break;
   }
 }
 
@@ -1037,15 +1055,22 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index) {
       }
       if (st->n_ub == 0) return SS_OK;
     }
-    uint32_t ep;
-    int rc = begin_launch(st, &ep);
+    // one-target expansion: try the fixed two-children placement first (no
+    // look-back); the compacting launch after it finishes the op either way.
+    // Not in group mode: a merge (destructive interference) leaves members
+    // without a child, and the speculative launch would be wasted.
+    uint32_t ep_spec = 0, ep;
+    int rc = SS_OK;
+    if (g.k == 1 && mode == MODE_EXPAND && st->speculate && st->n_ub >= st->speculate)
+      rc = begin_launch(st, &ep_spec);
+    if (!rc) rc = begin_launch(st, &ep);
     if (rc) return rc;
     const uint32_t cat = mode == MODE_GROUP ? SS_TRACE_GROUP : SS_TRACE_EXPAND;
     const int tr = trace_begin(st, cat);
     switch (st->L.W) {
-      case 1: launch_group_w<1>(st, mode, g, ep); break;
-      case 2: launch_group_w<2>(st, mode, g, ep); break;
-      default: launch_group_w<4>(st, mode, g, ep); break;
+      case 1: launch_group_w<1>(st, mode, g, ep, ep_spec); break;
+      case 2: launch_group_w<2>(st, mode, g, ep, ep_spec); break;
+      default: launch_group_w<4>(st, mode, g, ep, ep_spec); break;
     }
     trace_end(st, tr, entry_bytes(st->L.W), 1, ep, entry_bytes(st->L.W));
     rc = check_launch(st);
@@ -1896,6 +1921,9 @@ int ss_set_option(ss_state* st, const char* key, int64_t value) {
     st->group_items = (int)value;
   } else if (k == "grouping") {
     st->grouping = value ? 1 : 0;
+  } else if (k == "speculate") {
+    if (value < 0) return SS_E_ARG;
+    st->speculate = (uint64_t)value;
   } else if (k == "trace") {
     st->trace = value != 0;
   } else if (k == "trace_reset") {

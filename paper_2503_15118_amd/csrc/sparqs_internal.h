@@ -51,6 +51,7 @@ struct DevMeta {
   double dscratch[16];
   unsigned long long uscratch[16];
   unsigned long long counters[kRing];        // dynamic tile ids (one ticket per launch)
+  unsigned int spec_irr[kRing];              // a speculative fixed-fan-out launch met an irregular tile
   unsigned long long xcd_ctr[kRing][kXcds * kXcdStride];  // per-XCD tickets
 };
 

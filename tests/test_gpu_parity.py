@@ -218,6 +218,28 @@ def test_capacity_failure_mid_stream_then_resume(abi):
     st.close()
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_speculative_placement_is_exact(abi, seed):
+    """One-target interference ops first try the fixed-fan-out placement; on
+    circuits with controls (some entries pass through, some pairs are
+    incomplete) and on the arithmetic-heavy form (full pairs) the result must
+    equal, bit for bit and in the same order, the compacting path alone."""
+    for c in (wl.c1_circuit(seed), wl.c2_circuit(seed, nops=60, n_ry=6, h_qubits=10),
+              wl.random_small_circuit(seed, nops=80, with_init=True)):
+        print(f"[case] {c.name} speculation on/off", flush=True)
+        outs = []
+        for spec in (1, 0):            # 1: speculate at any size
+            st = _gpu(abi, c, opts={"speculate": spec})
+            outs.append(st.export())
+            st.close()
+        (k1, a1), (k0, a0) = outs
+        assert np.array_equal(k1, k0)
+        assert np.array_equal(a1.view(np.uint64), a0.view(np.uint64))
+        ora, _, _ = run_circuit(c)
+        ok, _, oa = ora.export()
+        compare(k1, a1, ok, oa, c.eps)
+
+
 def test_deterministic_reruns(abi):
     c = wl.c1_circuit(9)
     k1, a1 = _gpu(abi, c).export()
