@@ -361,6 +361,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep --group-items/--sort-items/--perm-entries instead of autotuning them")
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache (default: per-user cache)")
+    ap.add_argument("--graph-steps", type=int, default=None,
+                    help="also time this many steps replayed from a captured HIP graph (default: --steps; 0: off)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 64 MiB device copy first (reference for HBM counters)")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "m6"])
@@ -466,6 +468,31 @@ def main():
 
     elapsed = t1 - t0
     value = entries_per_step * args.steps / elapsed
+
+    # the same step with the circuit replayed from a captured HIP graph: one
+    # host wait per replay instead of the planner's read-backs
+    graph = None
+    gsteps = args.steps if args.graph_steps is None else args.graph_steps
+    if gsteps > 0:
+        st.set_entries(0, zero, one)
+        g = st.capture(ops)
+        for _ in range(args.warmup):
+            st.set_entries(0, zero, one)
+            g.launch()
+        s0 = st.stats()["entries_updated"]
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(gsteps):
+            st.set_entries(0, zero, one)
+            g.launch()
+        torch.cuda.synchronize()
+        g1 = time.perf_counter()
+        gent = (st.stats()["entries_updated"] - s0) / gsteps
+        assert gent == entries_per_step, (gent, entries_per_step)
+        assert st.nnz() == nnz_final
+        graph = {"steps": gsteps, "ms_per_step": 1e3 * (g1 - g0) / gsteps,
+                 "value": gent * gsteps / (g1 - g0)}
+        g.close()
     kernels = {}
     for name, r in tr.items():
         if r["launches"] == 0:
@@ -527,6 +554,7 @@ def main():
         "gpu_kernel_ms_per_step": gpu_kernel_ms,
         "host_syncs_per_step": syncs,
         "kernels": kernels,
+        "graph_replay": graph,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(circ, args.cpu_ops)

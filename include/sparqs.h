@@ -53,7 +53,8 @@ enum ss_status {
   SS_E_CAPACITY = -4,     /* an op would exceed the arena's entry capacity (state rolled back) */
   SS_E_NOMEM = -5,        /* arena too small at creation */
   SS_E_HIP = -6,          /* HIP runtime or kernel-side failure; the state is poisoned */
-  SS_E_STATE = -7         /* use of a poisoned or null state */
+  SS_E_STATE = -7,        /* use of a poisoned or null state */
+  SS_E_PLAN = -8          /* a graph replay met a state its captured plan does not fit (rolled back) */
 };
 
 enum ss_kind {
@@ -171,6 +172,51 @@ int ss_export(ss_state* st, uint32_t inst, uint64_t* keys, double* amps, uint64_
 
 /* Wait for the stream and report kernel-side errors. */
 int ss_sync(ss_state* st, ss_result* res);
+
+/* Captured op lists (HIP graphs).
+ *
+ * The planner's choices for an op list (sort or not, which key bits a sort
+ * covers, grid sizes) depend on entry counts and key masks that it reads back
+ * from the device between launches.  ss_graph_capture applies the ops to the
+ * state exactly as ss_apply_ops does (same arguments, same result, same
+ * errors), recording each read-back, and then builds a HIP graph of the same
+ * launch sequence, with the recorded values in place of the read-backs.  The
+ * graph holds every kernel and op-record copy of the list; a replay has no
+ * host synchronisation until its end.
+ *
+ * A replay is valid for a state on which the planner would make the same
+ * choices.  At every point where the capture read back, the graph checks on
+ * the device that the entry count equals the recorded one and that no key
+ * bit varies that did not vary then; the first failed check makes every later
+ * launch of the replay a no-op.  So a replay gives the result of
+ * ss_apply_ops on the same ops, or SS_E_PLAN.
+ *
+ * Typical use: a circuit applied again and again to states of one shape (a
+ * reset followed by the same ops, a repeated walk step).  Graphs belong to
+ * their state: destroy them before the state (a graph of a destroyed state,
+ * or of a state moved by ss_rebind_arena, is refused with SS_E_STATE /
+ * SS_E_ARG).  Option changes after a capture do not affect the graph. */
+typedef struct ss_graph ss_graph;
+
+/* Apply `nops` ops (as ss_apply_ops) and capture them.  On success *out gets
+ * the graph; on any error no graph is made, *out is NULL and the status and
+ * state are those of ss_apply_ops.  SS_E_HIP here from the capture itself
+ * (graph instantiation) leaves the state usable.  Blocking. */
+int ss_graph_capture(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst_offsets,
+                     ss_result* res, ss_graph** out);
+
+/* Replay a captured op list on its state.  Blocking, like ss_apply_ops.
+ * SS_E_PLAN: the state did not fit the plan; when found before the first
+ * launch (entry count differs from the capture's input) nothing ran and
+ * res->failed_op = 0; otherwise the state holds the result of ops
+ * [0, res->failed_op) (batched lists: rounds) and the caller may continue with
+ * ss_apply_ops from there.  A divergence inside an op split over several
+ * launches (H on more than 5 qubits) leaves nothing to return to: the state is
+ * then poisoned.  SS_E_CAPACITY as for ss_apply_ops. */
+int ss_graph_launch(ss_graph* g, ss_result* res);
+
+/* Free the graph (host objects and its pinned op records). */
+int ss_graph_destroy(ss_graph* g);
 
 /* Move the state into another (larger) arena; the old one may be freed after
  * the call returns.  Blocking. */

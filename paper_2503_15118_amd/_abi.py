@@ -18,8 +18,8 @@ import workloads as wl
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsparqs.so")
 
-SS_OK, SS_E_ARG, SS_E_NOT_UNITARY, SS_E_QRAM, SS_E_CAPACITY, SS_E_NOMEM, SS_E_HIP, SS_E_STATE = \
-    0, -1, -2, -3, -4, -5, -6, -7
+SS_OK, SS_E_ARG, SS_E_NOT_UNITARY, SS_E_QRAM, SS_E_CAPACITY, SS_E_NOMEM, SS_E_HIP, SS_E_STATE, SS_E_PLAN = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
 
 # enum ss_kind of include/sparqs.h
 SS_KIND = {"X": 0, "H": 1, "RY": 2, "ADD": 3, "SUB": 4, "MULC": 5, "XOR": 6, "XORC": 7,
@@ -82,6 +82,9 @@ def _load():
         "ss_stats": [vp, P(u64)],
         "ss_trace_read": [vp, u32, P(u64), P(f64), P(u64), P(u64)],
         "ss_device_error": [vp, P(u32)],
+        "ss_graph_capture": [vp, vp, u64, P(u64), P(_Result), P(vp)],
+        "ss_graph_launch": [vp, P(_Result)],
+        "ss_graph_destroy": [vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -97,7 +100,8 @@ lib = _load()
 EXPORTED = ("ss_required_bytes", "ss_create_state", "ss_destroy_state", "ss_capacity", "ss_layout",
             "ss_key_words", "ss_load_qram", "ss_set_entries", "ss_apply_ops", "ss_prune", "ss_measure",
             "ss_nnz", "ss_export", "ss_sync", "ss_rebind_arena", "ss_set_option", "ss_stats",
-            "ss_trace_read", "ss_device_error", "ss_strerror")
+            "ss_trace_read", "ss_device_error", "ss_strerror", "ss_graph_capture", "ss_graph_launch",
+            "ss_graph_destroy")
 
 TRACE_CATS = ("perm", "sort_hist", "sort_pass", "group", "expand", "filter")
 
@@ -278,6 +282,26 @@ class State:
         m = min(int(got.value), n)
         return keys[:m], amps[:m]
 
+    def capture(self, ops: np.ndarray, inst_offsets=None, raise_on_error: bool = True) -> "Graph":
+        """Apply ops (as ``apply``) and capture them into a replayable HIP graph."""
+        rec = np.ascontiguousarray(ops if ops.dtype == SS_OP else to_ss_ops(ops))
+        res = _Result()
+        offp = None
+        if inst_offsets is not None:
+            off = np.ascontiguousarray(inst_offsets, dtype=np.uint64)
+            if len(off) != self.ninst + 1:
+                raise ValueError("inst_offsets needs ninst + 1 entries")
+            offp = _p(off, ctypes.c_uint64)
+        g = ctypes.c_void_p(0)
+        rc = lib.ss_graph_capture(self.h, ctypes.c_void_p(rec.ctypes.data), len(rec), offp, ctypes.byref(res),
+                                  ctypes.byref(g))
+        res.status = rc
+        if rc != SS_OK:
+            if raise_on_error:
+                raise SSError(rc, f"ss_graph_capture (op {res.failed_op})")
+            return Graph(None, self, res)
+        return Graph(g, self, res)
+
     def sync(self) -> _Result:
         res = _Result()
         _check(lib.ss_sync(self.h, ctypes.byref(res)), "ss_sync")
@@ -304,6 +328,36 @@ class State:
         names = ("kernels", "sort_passes", "sorts", "group_launches", "expand_launches", "perm_runs",
                  "host_syncs", "entries_updated")
         return {k: int(v) for k, v in zip(names, a)}
+
+
+class Graph:
+    """A captured op list of one State (``State.capture``); ``launch`` replays it."""
+
+    def __init__(self, handle, state: "State", result: _Result):
+        self.h = handle
+        self.state = state          # keeps the state (and its arena) alive
+        self.result = result        # status of the applying capture call
+
+    def launch(self, raise_on_error: bool = True) -> _Result:
+        res = _Result()
+        if not self.h:
+            raise SSError(SS_E_ARG, "ss_graph_launch (no graph)")
+        rc = lib.ss_graph_launch(self.h, ctypes.byref(res))
+        res.status = rc
+        if rc != SS_OK and raise_on_error:
+            raise SSError(rc, f"ss_graph_launch (op {res.failed_op})")
+        return res
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.ss_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def state_for_circuit(c: "wl.Circuit", cap_entries: Optional[int] = None, ninst: int = 1, **kw) -> State:

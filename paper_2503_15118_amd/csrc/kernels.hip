@@ -1611,18 +1611,49 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
 }
 
 __global__ void k_ring_init(DevMeta* meta) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    for (int r = 0; r < kRing; ++r) {
-      meta->counters[r] = 0;
-      meta->spec_irr[r] = 0;
-      for (int x = 0; x < kXcds; ++x) meta->xcd_ctr[r][x * kXcdStride] = 0;
-      meta->nnz_out[r] = 0;
-      for (int w = 0; w < kMaxW; ++w) {
-        meta->or_mask[r][w] = 0;
-        meta->and_mask[r][w] = ~0ull;
-      }
+  if (blockIdx.x != 0) return;
+  for (int r = threadIdx.x; r < kRing; r += blockDim.x) {
+    meta->counters[r] = 0;
+    meta->spec_irr[r] = 0;
+    for (int x = 0; x < kXcds; ++x) meta->xcd_ctr[r][x * kXcdStride] = 0;
+    meta->nnz_out[r] = 0;
+    for (int w = 0; w < kMaxW; ++w) {
+      meta->or_mask[r][w] = 0;
+      meta->and_mask[r][w] = ~0ull;
     }
   }
+}
+
+// Check point of a replayed graph: the entry count in slot `ns` must equal the
+// count the plan was made for, and (mask_slot >= 0) the key bits that vary
+// over the entries, per the OR / AND masks in that ring slot, must lie inside
+// `allowed`.  Otherwise raise kErrPlan tagged `epoch`; every later launch then
+// changes nothing.  An earlier error takes precedence.
+__global__ void k_plan_guard(DevMeta* meta, uint32_t ns, uint64_t n_expect, int mask_slot, PlanVar allowed,
+                             uint32_t epoch) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (*reinterpret_cast<volatile unsigned int*>(&meta->err) != 0u) return;
+  bool bad = meta->nring[ns & 1] != n_expect;
+  if (mask_slot >= 0)
+    for (int w = 0; w < kMaxW; ++w)
+      bad = bad || ((meta->or_mask[mask_slot][w] & ~meta->and_mask[mask_slot][w]) & ~allowed.var[w]) != 0ull;
+  if (bad) raise_error(meta, kErrPlan, epoch);
+}
+
+// Copy the entries of slot `ns` (count read on the device) to the other
+// buffer and count slot.  Does nothing after an error.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_copy_state(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
+                                                       KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
+                                                       uint32_t ns, DevMeta* meta) {
+  if (*reinterpret_cast<volatile unsigned int*>(&meta->err) != 0u) return;
+  const uint64_t n = meta->nring[ns & 1];
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) out_keys.w[w][i] = in_keys.w[w][i];
+    out_amp[i] = in_amp[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) meta->nring[(ns & 1) ^ 1] = n;
 }
 
 // XCD of each of the first gridDim.x workgroups (checks the round-robin spread).

@@ -183,6 +183,33 @@ struct ss_state {
     uint64_t op;
   };
   std::vector<EmitLog> emits;
+  // Graph capture (ss_graph_capture).  The planner runs the op list once for
+  // real while recording every read-back of the status block, then once more
+  // under stream capture, where each synchronisation takes the recorded
+  // read-back instead and enqueues a check kernel: a replay must meet the same
+  // entry count there and no key bit varying that did not vary then.
+  enum { G_EAGER = 0, G_RECORD = 1, G_CAPTURE = 2 };
+  int gmode = G_EAGER;
+  std::vector<std::vector<char>> snaps;
+  size_t snap_pos = 0;
+  uint64_t rec_bytes = 0;         // op-record bytes the recording run uploaded
+  char* cap_hops = nullptr;       // graph-owned pinned op records (capture)
+  uint64_t cap_used = 0, cap_size = 0;
+  bool final_sync = false;        // the synchronisation that ends a call: no check
+  // last consistent point (buffer, count slot, op or round index) and the
+  // buffer swaps since: a check can roll back to it while at most one swap
+  // (one emitting launch) has happened, i.e. its buffer is still intact
+  struct PlanMark {
+    uint32_t ep;
+    int cur;
+    uint32_t nslot;
+    uint64_t op;
+    bool valid;
+  };
+  PlanMark mark{};
+  uint32_t flips = 0;
+  std::vector<PlanMark> plan_log;  // check points of a replay, for rollback
+  std::vector<ss_graph*> graphs;   // live graphs built on this state
   bool rolled_back = false;       // the last synchronisation rolled back a launch
   uint64_t rb_op = 0;             // ... whose op index (batched: round) this is
   uint32_t dev_err = 0;           // kernel-side error bits seen at the last read-back
@@ -335,23 +362,78 @@ void set_known(ss_state* st, uint64_t n) {
 // ran out of capacity made every later launch a no-op; the state returns to
 // that launch's input (buffer and count), and SS_E_CAPACITY is returned with
 // rolled_back / rb_op set.  Any other kernel-side error poisons the state.
+void set_mark(ss_state* st, uint64_t op, bool valid = true) {
+  st->mark = {0u, st->cur, st->nslot, op, valid};
+  st->flips = 0;
+}
+
+void roll_back(ss_state* st, int cur, uint32_t nslot, uint64_t op) {
+  st->cur = cur;
+  st->nslot = nslot;
+  st->rb_op = op;
+  st->rolled_back = true;
+  set_known(st, st->hmeta->nring[nslot]);
+  st->masks_valid = false;
+  st->mask_ep = 0;
+  st->grouped = false;
+  st->emits.clear();
+  st->plan_log.clear();
+}
+
+// Synchronise: wait for the stream, copy the status part of the device meta
+// block to pinned memory and bring the host view up to date.  A launch that
+// ran out of capacity made every later launch a no-op; the state returns to
+// that launch's input (buffer and count), and SS_E_CAPACITY is returned with
+// rolled_back / rb_op set.  A failed check of a replayed graph returns
+// SS_E_PLAN the same way (rolled back to the op where the plan diverged).  Any
+// other kernel-side error poisons the state.
 int sync_state(ss_state* st) {
   st->rolled_back = false;
   if (st->poisoned) return SS_E_STATE;
-  if (hipMemcpyAsync(st->hmeta, st->meta, offsetof(DevMeta, dscratch), hipMemcpyDeviceToHost, st->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(st->stream) != hipSuccess)
-    return hip_fail(st);
-  st->stats[6]++;
+  constexpr size_t kStatus = offsetof(DevMeta, dscratch);
+  if (st->gmode == ss_state::G_CAPTURE) {
+    // the read-back the recording run made at this point
+    if (st->snap_pos >= st->snaps.size()) return hip_fail(st);
+    std::memcpy(st->hmeta, st->snaps[st->snap_pos++].data(), kStatus);
+  } else {
+    if (hipMemcpyAsync(st->hmeta, st->meta, kStatus, hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
+        hipStreamSynchronize(st->stream) != hipSuccess)
+      return hip_fail(st);
+    st->stats[6]++;
+    if (st->gmode == ss_state::G_RECORD) {
+      const char* p = reinterpret_cast<const char*>(st->hmeta);
+      st->snaps.emplace_back(p, p + kStatus);
+    }
+  }
   st->ops_used = 0;
   const DevMeta* hm = st->hmeta;
   st->dev_err |= hm->err;
   trace_flush(st);
   st->peak = hm->peak;
   st->stats[7] = hm->upd;
-  if (hm->err & ~kErrCapacity) {
+  if (hm->err & ~(kErrCapacity | kErrPlan)) {
     st->emits.clear();
+    st->plan_log.clear();
     return hip_fail(st);
+  }
+  if (hm->err & kErrPlan) {
+    const ss_state::PlanMark* e = nullptr;
+    for (const auto& x : st->plan_log)
+      if (x.ep == hm->err_epoch) {
+        e = &x;
+        break;
+      }
+    if (!e || !e->valid) {
+      // diverged inside an op split over several launches: nothing to return to
+      st->emits.clear();
+      st->plan_log.clear();
+      st->poisoned = true;
+      return SS_E_PLAN;
+    }
+    roll_back(st, e->cur, e->nslot, e->op);
+    k_clear_err<<<1, 64, 0, st->stream>>>(st->meta);
+    if (check_launch(st)) return SS_E_HIP;
+    return SS_E_PLAN;
   }
   if (hm->err & kErrCapacity) {
     const ss_state::EmitLog* e = nullptr;
@@ -359,24 +441,34 @@ int sync_state(ss_state* st) {
       if (x.ep == hm->err_epoch) e = &x;
     if (!e) {
       st->emits.clear();
+      st->plan_log.clear();
       return hip_fail(st);
     }
-    st->cur = e->cur;
-    st->nslot = e->nslot;
-    st->rb_op = e->op;
-    st->rolled_back = true;
-    set_known(st, hm->nring[e->nslot]);
-    st->masks_valid = false;
-    st->mask_ep = 0;
-    st->grouped = false;
-    st->emits.clear();
+    roll_back(st, e->cur, e->nslot, e->op);
     k_clear_err<<<1, 64, 0, st->stream>>>(st->meta);
     if (check_launch(st)) return SS_E_HIP;
     return SS_E_CAPACITY;
   }
-  st->emits.clear();
+  if (st->gmode != ss_state::G_CAPTURE) {
+    // (a capture keeps the logs: a replay needs all of them at its one read-back)
+    st->emits.clear();
+    st->plan_log.clear();
+  }
   set_known(st, hm->nring[st->nslot]);
-  if (!st->masks_valid && st->mask_ep && st->epoch - st->mask_ep < (uint32_t)kRing / 2) take_masks(st, st->mask_ep);
+  bool took = false;
+  if (!st->masks_valid && st->mask_ep && st->epoch - st->mask_ep < (uint32_t)kRing / 2) {
+    take_masks(st, st->mask_ep);
+    took = true;
+  }
+  if (st->gmode == ss_state::G_CAPTURE && !st->final_sync) {
+    PlanVar v{};
+    for (int w = 0; w < kMaxW; ++w) v.var[w] = st->orm[w] & ~st->andm[w];
+    k_plan_guard<<<1, 64, 0, st->stream>>>(st->meta, st->nslot, st->n, took ? (int)(st->mask_ep % kRing) : -1, v,
+                                           st->epoch);
+    st->stats[0]++;
+    st->plan_log.push_back({st->epoch, st->mark.cur, st->mark.nslot, st->mark.op, st->mark.valid && st->flips <= 1});
+    if (check_launch(st)) return SS_E_HIP;
+  }
   if (st->epoch >= kEpochMask - 4096) {
     // the 24-bit look-back tag is about to wrap: start over with clean words
     k_fill_u64<<<1024, 256, 0, st->stream>>>(st->lb, st->cv.lb_words, 0ull);
@@ -414,6 +506,7 @@ int begin_launch(ss_state* st, uint32_t* ep) {
 void after_emit(ss_state* st, uint32_t ep, uint64_t bound, bool logged, uint64_t op) {
   if (logged) st->emits.push_back({ep, st->cur, st->nslot, op});
   st->cur ^= 1;
+  st->flips++;
   st->nslot ^= 1;
   st->n_known = false;
   st->n_ub = std::min(st->cap, bound);
@@ -514,6 +607,7 @@ int run_sort_w(ss_state* st, const SortPlan& plan) {
                                                             st->lb, st->meta, ep, xo(st));
     trace_end(st, tr, 2 * entry_bytes(W), 1, 0, 0);
     st->cur ^= 1;
+    st->flips++;
     st->stats[1]++;
   }
   st->stats[2]++;
@@ -917,6 +1011,14 @@ int ring_upload(ss_state* st, const void* src, uint64_t bytes, char** dev) {
   }
   char* h = reinterpret_cast<char*>(st->hops) + st->ops_used;
   char* d = reinterpret_cast<char*>(st->dev_ops) + st->ops_used;
+  if (st->gmode == ss_state::G_CAPTURE) {
+    // a graph copies from records it owns (the staging ring is reused)
+    if (st->cap_used + need > st->cap_size) return hip_fail(st);
+    h = st->cap_hops + st->cap_used;
+    st->cap_used += need;
+  } else if (st->gmode == ss_state::G_RECORD) {
+    st->rec_bytes += need;
+  }
   if (bytes) {
     std::memcpy(h, src, bytes);
     if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st->stream) != hipSuccess) return hip_fail(st);
@@ -927,7 +1029,7 @@ int ring_upload(ss_state* st, const void* src, uint64_t bytes, char** dev) {
 }
 
 // Launch the pending run of non-branching ops (one fused kernel per chunk).
-int flush_run(ss_state* st, std::vector<ss_op>& run) {
+int flush_run(ss_state* st, std::vector<ss_op>& run, uint64_t run_start) {
   if (run.empty()) return SS_OK;
   if (st->n_ub == 0) {
     run.clear();
@@ -957,6 +1059,7 @@ int flush_run(ss_state* st, std::vector<ss_op>& run) {
     std::vector<char> blob(fbytes + gen.size() * sizeof(PermOp));
     if (!fast.empty()) std::memcpy(blob.data(), fast.data(), fast.size() * sizeof(FastOp));
     if (!gen.empty()) std::memcpy(blob.data() + fbytes, gen.data(), gen.size() * sizeof(PermOp));
+    set_mark(st, run_start + i);
     char* d = nullptr;
     int rc = ring_upload(st, blob.data(), blob.size(), &d);
     if (rc) return rc;
@@ -985,6 +1088,7 @@ int flush_run(ss_state* st, std::vector<ss_op>& run) {
 
 // One branching op: chunks of at most kMaxGroupBits target qubits, ascending.
 int do_branching(ss_state* st, const ss_op& op, uint64_t op_index) {
+  set_mark(st, op_index);
   const RegInfo& d = st->L.regs[op.reg];
   std::vector<uint32_t> qs;
   for (uint32_t q = 0; q < d.width; ++q)
@@ -1261,6 +1365,8 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
   uint64_t round = 0;
   std::vector<RunRange> runs(NI);
   std::vector<BatchOp> bops(NI);
+  // a replay's check can return only to a round's input (after its runs)
+  set_mark(st, 0, false);
   while (true) {
     // --- non-branching runs -------------------------------------------------
     bool any_run = false;
@@ -1393,6 +1499,7 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
     trace_end(st, tr, entry_bytes(W), 1, ep, entry_bytes(W));
     rc = check_launch(st);
     if (rc) return rc;
+    set_mark(st, round);
     after_emit(st, ep, st->n_ub << kmax, true, round);
     // sort candidates by (instance, key): the plan needs the key masks
     rc = ensure_masks(st);
@@ -1414,9 +1521,189 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
     rc = check_launch(st);
     if (rc) return rc;
     after_emit(st, ep, st->n_ub, false, round);
+    set_mark(st, round + 1, false);
   }
   st->grouped = false;
   return SS_OK;
+}
+
+int validate_ops(ss_state* st, const ss_op* ops, uint64_t nops, ss_result* res) {
+  if (nops && !ops) return SS_E_ARG;
+  for (uint64_t i = 0; i < nops; ++i) {
+    const int rc = validate_op(st, ops[i]);
+    if (rc) {
+      res->status = rc;
+      res->failed_op = i;
+      return rc;
+    }
+  }
+  return SS_OK;
+}
+
+// Plan and launch a validated op list; ends with a synchronisation, whose
+// status is the call's.
+int plan_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst_offsets, ss_result* res) {
+  auto finish = [&](int code, uint64_t op) {
+    // the status is final only after a synchronisation; a capacity failure
+    // found there names the op (batched: round) whose launch was rolled back
+    st->final_sync = true;
+    const int sc = st->poisoned ? SS_OK : sync_state(st);
+    st->final_sync = false;
+    if (sc == SS_E_CAPACITY) {
+      code = sc;
+      op = st->rb_op;
+    } else if (sc != SS_OK) {
+      code = sc;
+    }
+    res->status = code;
+    res->failed_op = code ? op : 0;
+    res->nnz = st->n;
+    res->peak = st->peak;
+    return code;
+  };
+  int rc;
+  if (inst_offsets) {
+    rc = apply_batched(st, ops, nops, inst_offsets, res);
+    if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
+    return finish(rc, 0);
+  }
+  set_mark(st, 0);
+  std::vector<ss_op> run;
+  uint64_t run_start = 0;
+  for (uint64_t i = 0; i < nops; ++i) {
+    const ss_op& op = ops[i];
+    if (is_branching(op.kind)) {
+      rc = flush_run(st, run, run_start);
+      if (!rc) rc = do_branching(st, op, i);
+      if (rc) {
+        if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
+        return finish(rc, i);
+      }
+    } else {
+      if (st->grouped && !keeps_grouping(st, op, st->gmask)) st->grouped = false;
+      if (run.empty()) run_start = i;
+      run.push_back(op);
+    }
+  }
+  rc = flush_run(st, run, run_start);
+  if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
+  set_mark(st, nops);
+  return finish(rc, nops);
+}
+
+// Host planner state saved around a capture (which must plan from the same
+// starting point as the recording run and leave the state as that run did).
+struct PlanSnap {
+  int cur;
+  uint32_t nslot;
+  uint64_t n, n_ub, peak;
+  bool n_known, masks_valid, grouped, poisoned;
+  uint32_t n_src_ep, mask_ep, epoch, ops_used, dev_err;
+  uint64_t orm[kMaxW], andm[kMaxW], gmask[kMaxW];
+  uint64_t stats[8];
+};
+
+PlanSnap save_plan(const ss_state* st) {
+  PlanSnap p{};
+  p.cur = st->cur;
+  p.nslot = st->nslot;
+  p.n = st->n;
+  p.n_ub = st->n_ub;
+  p.peak = st->peak;
+  p.n_known = st->n_known;
+  p.masks_valid = st->masks_valid;
+  p.grouped = st->grouped;
+  p.poisoned = st->poisoned;
+  p.n_src_ep = st->n_src_ep;
+  p.mask_ep = st->mask_ep;
+  p.epoch = st->epoch;
+  p.ops_used = st->ops_used;
+  p.dev_err = st->dev_err;
+  for (int w = 0; w < kMaxW; ++w) {
+    p.orm[w] = st->orm[w];
+    p.andm[w] = st->andm[w];
+    p.gmask[w] = st->gmask[w];
+  }
+  for (int i = 0; i < 8; ++i) p.stats[i] = st->stats[i];
+  return p;
+}
+
+void restore_plan(ss_state* st, const PlanSnap& p) {
+  st->cur = p.cur;
+  st->nslot = p.nslot;
+  st->n = p.n;
+  st->n_ub = p.n_ub;
+  st->peak = p.peak;
+  st->n_known = p.n_known;
+  st->masks_valid = p.masks_valid;
+  st->grouped = p.grouped;
+  st->poisoned = p.poisoned;
+  st->n_src_ep = p.n_src_ep;
+  st->mask_ep = p.mask_ep;
+  st->epoch = p.epoch;
+  st->ops_used = p.ops_used;
+  st->dev_err = p.dev_err;
+  for (int w = 0; w < kMaxW; ++w) {
+    st->orm[w] = p.orm[w];
+    st->andm[w] = p.andm[w];
+    st->gmask[w] = p.gmask[w];
+  }
+  for (int i = 0; i < 8; ++i) st->stats[i] = p.stats[i];
+}
+
+// Move the entries to the other buffer and count slot (count read on the
+// device).  Asynchronous.
+template <int W>
+void launch_copy_w(ss_state* st) {
+  const Buf& in = st->buf[st->cur];
+  const Buf& out = st->buf[st->cur ^ 1];
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((st->n_ub + kBlock - 1) / kBlock, 4096));
+  k_copy_state<W><<<grid, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot, st->meta);
+}
+
+int launch_copy(ss_state* st) {
+  switch (st->L.W) {
+    case 1: launch_copy_w<1>(st); break;
+    case 2: launch_copy_w<2>(st); break;
+    default: launch_copy_w<4>(st); break;
+  }
+  st->cur ^= 1;
+  st->nslot ^= 1;
+  st->stats[0]++;
+  return check_launch(st);
+}
+
+}  // namespace
+
+// A captured op list: the instantiated graph, the pinned op records its copy
+// nodes read, where its plan starts and ends, and the rollback points of its
+// launches and checks.
+struct ss_graph {
+  ss_state* st = nullptr;
+  char* arena = nullptr;
+  uint64_t cap = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  char* hops = nullptr;
+  int cur0 = 0;
+  uint32_t nslot0 = 0;
+  uint64_t n0 = 0;              // entry count the plan starts from
+  uint64_t n_end = 0;           // ... and ends with
+  bool grouped_end = false;
+  uint64_t gmask_end[kMaxW]{};
+  uint32_t epoch_end = 0;
+  uint64_t kernels = 0;
+  std::vector<ss_state::EmitLog> emits;
+  std::vector<ss_state::PlanMark> plan_log;
+};
+
+namespace {
+
+void graph_free(ss_graph* g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->hops) (void)hipHostFree(g->hops);
+  delete g;
 }
 
 }  // namespace
@@ -1433,6 +1720,7 @@ const char* ss_strerror(int code) {
     case SS_E_NOMEM: return "arena too small";
     case SS_E_HIP: return "HIP runtime or kernel failure";
     case SS_E_STATE: return "state is null or poisoned";
+    case SS_E_PLAN: return "state does not fit the captured plan (rolled back)";
     default: return "unknown error";
   }
 }
@@ -1495,6 +1783,7 @@ int ss_create_state(const ss_reg* regs, uint32_t nregs, uint32_t ninst, double e
 
 int ss_destroy_state(ss_state* st) {
   if (!st) return SS_E_STATE;
+  for (ss_graph* g : st->graphs) g->st = nullptr;
   (void)hipStreamSynchronize(st->stream);
   drop_trace(st);
   for (hipEvent_t e : st->ev_pool) (void)hipEventDestroy(e);
@@ -1588,54 +1877,9 @@ int ss_apply_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* 
   ss_result local{};
   if (!res) res = &local;
   *res = ss_result{};
-  if (nops && !ops) return SS_E_ARG;
-  for (uint64_t i = 0; i < nops; ++i) {
-    rc = validate_op(st, ops[i]);
-    if (rc) {
-      res->status = rc;
-      res->failed_op = i;
-      return rc;
-    }
-  }
-  auto finish = [&](int code, uint64_t op) {
-    // the status is final only after a synchronisation; a capacity failure
-    // found there names the op (batched: round) whose launch was rolled back
-    const int sc = st->poisoned ? SS_OK : sync_state(st);
-    if (sc == SS_E_CAPACITY) {
-      code = sc;
-      op = st->rb_op;
-    } else if (sc != SS_OK) {
-      code = sc;
-    }
-    res->status = code;
-    res->failed_op = code ? op : 0;
-    res->nnz = st->n;
-    res->peak = st->peak;
-    return code;
-  };
-  if (inst_offsets) {
-    rc = apply_batched(st, ops, nops, inst_offsets, res);
-    if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
-    return finish(rc, 0);
-  }
-  std::vector<ss_op> run;
-  for (uint64_t i = 0; i < nops; ++i) {
-    const ss_op& op = ops[i];
-    if (is_branching(op.kind)) {
-      rc = flush_run(st, run);
-      if (!rc) rc = do_branching(st, op, i);
-      if (rc) {
-        if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
-        return finish(rc, i);
-      }
-    } else {
-      if (st->grouped && !keeps_grouping(st, op, st->gmask)) st->grouped = false;
-      run.push_back(op);
-    }
-  }
-  rc = flush_run(st, run);
-  if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
-  return finish(rc, nops);
+  rc = validate_ops(st, ops, nops, res);
+  if (rc) return rc;
+  return plan_ops(st, ops, nops, inst_offsets, res);
 }
 
 int ss_prune(ss_state* st, double eps) {
@@ -1830,7 +2074,7 @@ int ss_sync(ss_state* st, ss_result* res) {
   const int rc = sync_state(st);
   if (res) {
     res->status = rc;
-    res->failed_op = rc == SS_E_CAPACITY ? st->rb_op : 0;
+    res->failed_op = (rc == SS_E_CAPACITY || rc == SS_E_PLAN) ? st->rb_op : 0;
     res->nnz = st->n;
     res->peak = st->peak;
   }
@@ -1900,6 +2144,191 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes) {
   rc = check_launch(st);
   if (rc) return rc;
   return sync_state(st);
+}
+
+int ss_graph_capture(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst_offsets,
+                     ss_result* res, ss_graph** out) {
+  if (!out) return SS_E_ARG;
+  *out = nullptr;
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (st->gmode != ss_state::G_EAGER) return SS_E_STATE;
+  ss_result local{};
+  if (!res) res = &local;
+  *res = ss_result{};
+  rc = validate_ops(st, ops, nops, res);
+  if (rc) return rc;
+  // A clean start, as every replay's prologue makes it: exact count, nothing
+  // pending, fresh look-back words and ring, epoch 1 (the tag of checks made
+  // before the first launch), no masks or grouping carried over.
+  rc = sync_state(st);
+  if (rc) {
+    res->status = rc;
+    return rc;
+  }
+  k_fill_u64<<<1024, 256, 0, st->stream>>>(st->lb, st->cv.lb_words, 0ull);
+  k_ring_init<<<1, 64, 0, st->stream>>>(st->meta);
+  st->stats[0] += 2;
+  if (check_launch(st)) return SS_E_HIP;
+  st->epoch = 1;
+  st->mask_ep = 0;
+  st->masks_valid = false;
+  st->grouped = false;
+  const PlanSnap p0 = save_plan(st);
+  const bool trace = st->trace;
+  st->trace = false;
+  // 1. the real application, recording every read-back
+  st->gmode = ss_state::G_RECORD;
+  st->snaps.clear();
+  st->rec_bytes = 0;
+  rc = plan_ops(st, ops, nops, inst_offsets, res);
+  st->gmode = ss_state::G_EAGER;
+  if (rc) {
+    st->trace = trace;
+    st->snaps.clear();
+    return rc;
+  }
+  const PlanSnap p1 = save_plan(st);
+  // 2. the same plan under stream capture on a private stream (nothing runs)
+  ss_graph* g = new ss_graph();
+  g->st = st;
+  g->arena = st->arena;
+  g->cap = st->cap;
+  g->cur0 = p0.cur;
+  g->nslot0 = p0.nslot;
+  g->n0 = p0.n;
+  const uint64_t rec = std::max<uint64_t>(st->rec_bytes, kAlign);
+  hipStream_t cs = nullptr;
+  int crc = SS_OK;
+  if (hipHostMalloc(reinterpret_cast<void**>(&g->hops), rec, hipHostMallocDefault) != hipSuccess ||
+      hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    crc = SS_E_HIP;
+  if (!crc) {
+    hipStream_t real = st->stream;
+    restore_plan(st, p0);
+    st->stream = cs;
+    st->gmode = ss_state::G_CAPTURE;
+    st->snap_pos = 0;
+    st->cap_hops = g->hops;
+    st->cap_used = 0;
+    st->cap_size = rec;
+    st->emits.clear();
+    st->plan_log.clear();
+    const uint64_t k0 = st->stats[0];
+    (void)hipGetLastError();
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      crc = SS_E_HIP;
+    } else {
+      // prologue: fresh look-back words and ring, then the input check
+      k_fill_u64<<<1024, 256, 0, cs>>>(st->lb, st->cv.lb_words, 0ull);
+      k_ring_init<<<1, 64, 0, cs>>>(st->meta);
+      k_plan_guard<<<1, 64, 0, cs>>>(st->meta, st->nslot, st->n, -1, PlanVar{}, st->epoch);
+      st->plan_log.push_back({st->epoch, st->cur, st->nslot, 0, true});
+      st->stats[0] += 3;
+      ss_result cres{};
+      int prc = check_launch(st);
+      if (!prc) prc = plan_ops(st, ops, nops, inst_offsets, &cres);
+      if (!prc && (st->poisoned || st->snap_pos != st->snaps.size())) prc = SS_E_HIP;
+      // end in the buffer it began in, so that replays chain
+      if (!prc && (st->cur != g->cur0 || st->nslot != g->nslot0)) prc = launch_copy(st);
+      if (!prc) {
+        // epilogue: a clean ring for the launches that follow the replay
+        k_ring_init<<<1, 64, 0, cs>>>(st->meta);
+        st->stats[0]++;
+        prc = check_launch(st);
+      }
+      g->n_end = st->n;
+      g->grouped_end = st->grouped;
+      for (int w = 0; w < kMaxW; ++w) g->gmask_end[w] = st->gmask[w];
+      g->epoch_end = st->epoch;
+      g->emits = st->emits;
+      g->plan_log = st->plan_log;
+      g->kernels = st->stats[0] - k0;
+      hipGraph_t graph = nullptr;
+      if (hipStreamEndCapture(cs, &graph) != hipSuccess && !prc) prc = SS_E_HIP;
+      g->graph = graph;
+      crc = prc;
+    }
+    (void)hipGetLastError();
+    st->stream = real;
+    st->gmode = ss_state::G_EAGER;
+    st->cap_hops = nullptr;
+    st->cap_used = st->cap_size = 0;
+    restore_plan(st, p1);   // the capture ran nothing on the device
+    st->emits.clear();
+    st->plan_log.clear();
+  }
+  st->snaps.clear();
+  st->trace = trace;
+  if (cs) (void)hipStreamDestroy(cs);
+  if (!crc && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) crc = SS_E_HIP;
+  (void)hipGetLastError();
+  if (crc) {
+    graph_free(g);
+    return crc;
+  }
+  st->graphs.push_back(g);
+  *out = g;
+  return SS_OK;
+}
+
+int ss_graph_launch(ss_graph* g, ss_result* res) {
+  if (!g) return SS_E_ARG;
+  ss_result local{};
+  if (!res) res = &local;
+  *res = ss_result{};
+  ss_state* st = g->st;
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (st->gmode != ss_state::G_EAGER) return SS_E_STATE;
+  if (st->arena != g->arena || st->cap != g->cap) return SS_E_ARG;
+  if (!st->n_known || !st->emits.empty() || !st->plan_log.empty() || !st->pending.empty()) {
+    rc = sync_state(st);
+    if (rc) {
+      res->status = rc;
+      return rc;
+    }
+  }
+  res->nnz = st->n;
+  res->peak = st->peak;
+  if (st->n != g->n0) {
+    res->status = SS_E_PLAN;
+    return SS_E_PLAN;
+  }
+  if (st->cur != g->cur0 || st->nslot != g->nslot0) {
+    rc = launch_copy(st);
+    if (rc) return rc;
+  }
+  if (hipGraphLaunch(g->exec, st->stream) != hipSuccess) return hip_fail(st);
+  st->stats[0] += g->kernels;
+  st->emits = g->emits;
+  st->plan_log = g->plan_log;
+  st->cur = g->cur0;
+  st->nslot = g->nslot0;
+  st->n_known = false;
+  st->n_ub = g->n_end;
+  st->n_src_ep = 0;
+  st->masks_valid = false;
+  st->mask_ep = 0;
+  st->grouped = g->grouped_end;
+  for (int w = 0; w < kMaxW; ++w) st->gmask[w] = g->gmask_end[w];
+  st->epoch = std::max(st->epoch, g->epoch_end);
+  rc = sync_state(st);
+  res->status = rc;
+  res->failed_op = (rc == SS_E_CAPACITY || rc == SS_E_PLAN) ? st->rb_op : 0;
+  res->nnz = st->n;
+  res->peak = st->peak;
+  return rc;
+}
+
+int ss_graph_destroy(ss_graph* g) {
+  if (!g) return SS_E_ARG;
+  if (g->st) {
+    auto& v = g->st->graphs;
+    v.erase(std::remove(v.begin(), v.end(), g), v.end());
+  }
+  graph_free(g);
+  return SS_OK;
 }
 
 int ss_set_option(ss_state* st, const char* key, int64_t value) {

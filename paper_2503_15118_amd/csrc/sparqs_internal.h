@@ -33,6 +33,7 @@ constexpr uint32_t kErrCapacity = 1u << 0;   // outputs would exceed the buffer 
 constexpr uint32_t kErrSpin = 1u << 1;       // a lookback wait exceeded its bound
 constexpr uint32_t kErrGroup = 1u << 2;      // two group members share a target value
 constexpr uint32_t kErrGrid = 1u << 3;       // a grid was sized below the entry count (host bug)
+constexpr uint32_t kErrPlan = 1u << 4;       // a graph replay met a count or key mask its plan did not
 
 // Device-side bookkeeping.  Every kernel launch that counts tiles, produces an
 // entry count or key masks owns ring slot (epoch % kRing); workgroup 0 of
@@ -129,6 +130,11 @@ struct GroupOp {
   uint64_t cval[kMaxW];
   double m[2][2];               // real matrix, m[out][in]
   double eps2;                  // prune below this |a|^2 (strict)
+};
+
+// Key bits a captured plan allows to vary at one of its check points.
+struct PlanVar {
+  uint64_t var[kMaxW];
 };
 
 // Per-instance tables of a batched round (instances with their own op lists).
