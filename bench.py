@@ -47,6 +47,12 @@ def counter_traffic(kernel_label):
     return float(kv["traffic " + kernel_label])
 
 
+def set_opts(st, opts):
+    for kv in opts:
+        k, v = kv.split("=", 1)
+        st.set_option(k, int(v))
+
+
 def cpu_baseline(circ, nops_sample):
     """The oracle (std::map, one core) on a bounded sample of the same circuit:
     the H prelude and the first `nops_sample` ops after it."""
@@ -192,6 +198,7 @@ def bench_c4(args):
     ops = _abi.to_ss_ops(c0.ops)
     st = _abi.State(c0.regs, ninst=len(circ), eps=c0.eps, cap_entries=1 << 22, table_bytes=1 << 16)
     st.load_qram(c0.tables[0])
+    set_opts(st, args.opt)
 
     def reset():
         for i, c in enumerate(circ):
@@ -358,6 +365,8 @@ def main():
     ap.add_argument("--sort-items", type=int, default=16)
     ap.add_argument("--perm-entries", type=int, default=8)
     ap.add_argument("--tile-order", type=int, default=1)
+    ap.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
+                    help="extra ss_set_option on the state (c2, c4)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep --group-items/--sort-items/--perm-entries instead of autotuning them")
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache (default: per-user cache)")
@@ -422,6 +431,7 @@ def main():
     st.set_option("sort_items", args.sort_items)
     st.set_option("perm_entries", args.perm_entries)
     st.set_option("tile_order", args.tile_order)
+    set_opts(st, args.opt)
     zero = np.zeros((1, len(circ.regs)), dtype=np.uint64)
     one = np.array([1.0 + 0j])
 

@@ -170,6 +170,13 @@ struct ss_state {
   // key masks: OR / AND over all keys, per word
   uint64_t orm[kMaxW]{}, andm[kMaxW]{};
   bool masks_valid = false;       // orm/andm describe the current entries
+  // A superset of the varying key bits kept on the host without read-backs:
+  // a key bit clear in sorm is 0 in every entry, one set in sandm is 1 in
+  // every entry.  Updated per op from what the op can write; exact whenever
+  // exact masks are read back.  It decides expansions (target bits provably
+  // constant) without a synchronisation; sorts still use exact masks.
+  uint64_t sorm[kMaxW]{}, sandm[kMaxW]{};
+  bool sup_valid = false;
   uint32_t mask_ep = 0;           // launch whose ring slot holds them (0: none, recompute)
   uint32_t epoch = 0;
   bool grouped = false;
@@ -226,6 +233,7 @@ struct ss_state {
   // million entries the look-back chain is short and the extra launch costs
   // more than it saves.
   uint64_t speculate = 1ull << 23;
+  uint64_t spec_group = 0;       // the same for one-target ops on grouped entries (0: never)
   uint32_t xcd_order = 0;        // 1 when workgroups spread round-robin over 8 XCDs
   int tile_order_opt = 1;        // option: 1 use XCD tickets when possible, 0 one counter
   uint64_t stats[8]{};
@@ -344,10 +352,43 @@ void drop_trace(ss_state* st) {
 void take_masks(ss_state* st, uint32_t ep) {
   const uint32_t r = ep % kRing;
   for (int w = 0; w < kMaxW; ++w) {
-    st->orm[w] = st->hmeta->or_mask[r][w];
-    st->andm[w] = st->hmeta->and_mask[r][w];
+    st->orm[w] = st->sorm[w] = st->hmeta->or_mask[r][w];
+    st->andm[w] = st->sandm[w] = st->hmeta->and_mask[r][w];
   }
   st->masks_valid = true;
+  st->sup_valid = true;
+}
+
+// The superset after an op that may set `bits` of `word` to anything.
+void sup_vary(ss_state* st, uint32_t word, uint64_t bits) {
+  st->sorm[word] |= bits;
+  st->sandm[word] &= ~bits;
+}
+
+// ... after an op that flips `bits` of `word` in every entry.
+void sup_flip(ss_state* st, uint32_t word, uint64_t bits) {
+  const uint64_t o = st->sorm[word], a = st->sandm[word];
+  st->sorm[word] = (o & ~bits) | (~a & bits);
+  st->sandm[word] = (a & ~bits) | (~o & bits);
+}
+
+// ... after a non-branching op.
+void sup_op(ss_state* st, const ss_op& op) {
+  const RegInfo& d = st->L.regs[op.reg];
+  switch (op.kind) {
+    case SS_REFLECT0:
+      break;
+    case SS_X:
+    case SS_XORC: {
+      const uint64_t bits = ((op.kind == SS_X ? op.qmask : op.imm) & d.mask) << d.shift;
+      if (op.nctl == 0) sup_flip(st, d.word, bits);
+      else sup_vary(st, d.word, bits);
+      break;
+    }
+    default:
+      sup_vary(st, d.word, d.mask << d.shift);
+      break;
+  }
 }
 
 void set_known(ss_state* st, uint64_t n) {
@@ -374,6 +415,7 @@ void roll_back(ss_state* st, int cur, uint32_t nslot, uint64_t op) {
   st->rolled_back = true;
   set_known(st, st->hmeta->nring[nslot]);
   st->masks_valid = false;
+  st->sup_valid = false;
   st->mask_ep = 0;
   st->grouped = false;
   st->emits.clear();
@@ -1137,8 +1179,13 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index) {
     int mode;
     bool same = st->grouped && st->grouping;
     for (int w = 0; w < kMaxW && same; ++w) same = st->gmask[w] == g.tmask[w];
+    bool sup_const = !st->masks_valid && st->sup_valid;
+    for (int w = 0; w < kMaxW && sup_const; ++w) sup_const = ((st->sorm[w] & ~st->sandm[w]) & g.tmask[w]) == 0;
     if (same) {
       mode = MODE_GROUP;
+    } else if (sup_const) {
+      // no target bit can vary: every group has one member
+      mode = MODE_EXPAND;
     } else {
       int rc = ensure_masks(st);
       if (rc) return rc;
@@ -1165,7 +1212,8 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index) {
     // without a child, and the speculative launch would be wasted.
     uint32_t ep_spec = 0, ep;
     int rc = SS_OK;
-    if (g.k == 1 && mode == MODE_EXPAND && st->speculate && st->n_ub >= st->speculate)
+    if (g.k == 1 && ((mode == MODE_EXPAND && st->speculate && st->n_ub >= st->speculate) ||
+                     (mode == MODE_GROUP && st->spec_group && st->n_ub >= st->spec_group)))
       rc = begin_launch(st, &ep_spec);
     if (!rc) rc = begin_launch(st, &ep);
     if (rc) return rc;
@@ -1181,6 +1229,7 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index) {
     if (rc) return rc;
     st->stats[mode == MODE_GROUP ? 3 : 4]++;
     after_emit(st, ep, st->n_ub << g.k, true, op_index);
+    for (int w = 0; w < kMaxW; ++w) sup_vary(st, (uint32_t)w, g.tmask[w]);
     st->grouped = true;
     for (int w = 0; w < kMaxW; ++w) st->gmask[w] = g.tmask[w];
   }
@@ -1275,6 +1324,32 @@ int pack_entries(ss_state* st, const uint64_t* values, const double* amps, uint6
     pd.shift[r] = st->L.regs[r].shift;
     pd.mask[r] = st->L.regs[r].mask;
   }
+  // superset masks: the imported keys' exact OR / AND, joined with those of
+  // the entries kept
+  {
+    uint64_t o[kMaxW] = {0, 0, 0, 0}, a[kMaxW] = {~0ull, ~0ull, ~0ull, ~0ull};
+    for (uint64_t i = 0; i < n; ++i) {
+      uint64_t k[kMaxW] = {0, 0, 0, 0};
+      for (uint32_t r = 0; r < nr; ++r) k[pd.word[r]] |= (values[i * nr + r] & pd.mask[r]) << pd.shift[r];
+      if (pd.has_inst) k[pd.iword] |= (pd.has_inst == 2 ? inst + i : (uint64_t)inst) << pd.ishift;
+      for (int w = 0; w < kMaxW; ++w) {
+        o[w] |= k[w];
+        a[w] &= k[w];
+      }
+    }
+    if (st->n == 0) {
+      for (int w = 0; w < kMaxW; ++w) {
+        st->sorm[w] = o[w];
+        st->sandm[w] = a[w];
+      }
+      st->sup_valid = true;
+    } else if (st->sup_valid) {
+      for (int w = 0; w < kMaxW; ++w) {
+        st->sorm[w] |= o[w];
+        st->sandm[w] &= a[w];
+      }
+    }
+  }
   const Buf& alt = st->buf[st->cur ^ 1];
   char* stage = reinterpret_cast<char*>(alt.key[0]);
   const uint64_t stage_bytes = st->cap * entry_bytes(st->L.W);
@@ -1299,6 +1374,7 @@ int pack_entries(ss_state* st, const uint64_t* values, const double* amps, uint6
     if (rc) return rc;
     // the caller's arrays and the staging area are reused by the next chunk
     if (hipStreamSynchronize(st->stream) != hipSuccess) return hip_fail(st);
+    st->stats[6]++;
     done += c;
   }
   set_known(st, st->n + n);
@@ -1367,6 +1443,7 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
   std::vector<BatchOp> bops(NI);
   // a replay's check can return only to a round's input (after its runs)
   set_mark(st, 0, false);
+  st->sup_valid = false;
   while (true) {
     // --- non-branching runs -------------------------------------------------
     bool any_run = false;
@@ -1583,6 +1660,7 @@ int plan_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst
       if (st->grouped && !keeps_grouping(st, op, st->gmask)) st->grouped = false;
       if (run.empty()) run_start = i;
       run.push_back(op);
+      sup_op(st, op);
     }
   }
   rc = flush_run(st, run, run_start);
@@ -1597,9 +1675,9 @@ struct PlanSnap {
   int cur;
   uint32_t nslot;
   uint64_t n, n_ub, peak;
-  bool n_known, masks_valid, grouped, poisoned;
+  bool n_known, masks_valid, grouped, poisoned, sup_valid;
   uint32_t n_src_ep, mask_ep, epoch, ops_used, dev_err;
-  uint64_t orm[kMaxW], andm[kMaxW], gmask[kMaxW];
+  uint64_t orm[kMaxW], andm[kMaxW], gmask[kMaxW], sorm[kMaxW], sandm[kMaxW];
   uint64_t stats[8];
 };
 
@@ -1614,6 +1692,7 @@ PlanSnap save_plan(const ss_state* st) {
   p.masks_valid = st->masks_valid;
   p.grouped = st->grouped;
   p.poisoned = st->poisoned;
+  p.sup_valid = st->sup_valid;
   p.n_src_ep = st->n_src_ep;
   p.mask_ep = st->mask_ep;
   p.epoch = st->epoch;
@@ -1623,6 +1702,8 @@ PlanSnap save_plan(const ss_state* st) {
     p.orm[w] = st->orm[w];
     p.andm[w] = st->andm[w];
     p.gmask[w] = st->gmask[w];
+    p.sorm[w] = st->sorm[w];
+    p.sandm[w] = st->sandm[w];
   }
   for (int i = 0; i < 8; ++i) p.stats[i] = st->stats[i];
   return p;
@@ -1638,6 +1719,7 @@ void restore_plan(ss_state* st, const PlanSnap& p) {
   st->masks_valid = p.masks_valid;
   st->grouped = p.grouped;
   st->poisoned = p.poisoned;
+  st->sup_valid = p.sup_valid;
   st->n_src_ep = p.n_src_ep;
   st->mask_ep = p.mask_ep;
   st->epoch = p.epoch;
@@ -1647,6 +1729,8 @@ void restore_plan(ss_state* st, const PlanSnap& p) {
     st->orm[w] = p.orm[w];
     st->andm[w] = p.andm[w];
     st->gmask[w] = p.gmask[w];
+    st->sorm[w] = p.sorm[w];
+    st->sandm[w] = p.sandm[w];
   }
   for (int i = 0; i < 8; ++i) st->stats[i] = p.stats[i];
 }
@@ -1854,8 +1938,11 @@ int ss_set_entries(ss_state* st, uint32_t inst, const uint64_t* values, const do
     if (!rc) rc = sync_state(st);
     if (rc) return rc;
   } else {
-    rc = sync_state(st);
-    if (rc) return rc;
+    // every call ends synchronised; wait only if something is still pending
+    if (!st->n_known || !st->emits.empty() || !st->plan_log.empty() || !st->pending.empty()) {
+      rc = sync_state(st);
+      if (rc) return rc;
+    }
     set_known(st, 0);
   }
   if (st->n + n > st->cap) {
@@ -1866,9 +1953,8 @@ int ss_set_entries(ss_state* st, uint32_t inst, const uint64_t* values, const do
     (void)check_launch(st);
     return SS_E_CAPACITY;
   }
-  rc = pack_entries(st, values, amps, n, inst, false);
-  if (rc) return rc;
-  return sync_state(st);
+  // (pack_entries waits for its copies: the caller's arrays are free on return)
+  return pack_entries(st, values, amps, n, inst, false);
 }
 
 int ss_apply_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst_offsets, ss_result* res) {
@@ -2173,6 +2259,7 @@ int ss_graph_capture(ss_state* st, const ss_op* ops, uint64_t nops, const uint64
   st->epoch = 1;
   st->mask_ep = 0;
   st->masks_valid = false;
+  st->sup_valid = false;
   st->grouped = false;
   const PlanSnap p0 = save_plan(st);
   const bool trace = st->trace;
@@ -2309,6 +2396,7 @@ int ss_graph_launch(ss_graph* g, ss_result* res) {
   st->n_ub = g->n_end;
   st->n_src_ep = 0;
   st->masks_valid = false;
+  st->sup_valid = false;
   st->mask_ep = 0;
   st->grouped = g->grouped_end;
   for (int w = 0; w < kMaxW; ++w) st->gmask[w] = g->gmask_end[w];
@@ -2353,6 +2441,9 @@ int ss_set_option(ss_state* st, const char* key, int64_t value) {
   } else if (k == "speculate") {
     if (value < 0) return SS_E_ARG;
     st->speculate = (uint64_t)value;
+  } else if (k == "speculate_group") {
+    if (value < 0) return SS_E_ARG;
+    st->spec_group = (uint64_t)value;
   } else if (k == "trace") {
     st->trace = value != 0;
   } else if (k == "trace_reset") {

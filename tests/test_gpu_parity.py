@@ -228,13 +228,16 @@ def test_speculative_placement_is_exact(abi, seed):
               wl.random_small_circuit(seed, nops=80, with_init=True)):
         print(f"[case] {c.name} speculation on/off", flush=True)
         outs = []
-        for spec in (1, 0):            # 1: speculate at any size
-            st = _gpu(abi, c, opts={"speculate": spec})
+        # 1: speculate at any size (expansions; grouped entries too)
+        for opts in ({"speculate": 1, "speculate_group": 1}, {"speculate": 1}, {"speculate": 0}):
+            st = _gpu(abi, c, opts=opts)
             outs.append(st.export())
             st.close()
-        (k1, a1), (k0, a0) = outs
-        assert np.array_equal(k1, k0)
-        assert np.array_equal(a1.view(np.uint64), a0.view(np.uint64))
+        k0, a0 = outs[-1]
+        for k1, a1 in outs[:-1]:
+            assert np.array_equal(k1, k0)
+            assert np.array_equal(a1.view(np.uint64), a0.view(np.uint64))
+        k1, a1 = outs[0]
         ora, _, _ = run_circuit(c)
         ok, _, oa = ora.export()
         compare(k1, a1, ok, oa, c.eps)
@@ -356,3 +359,33 @@ def test_batched_mixed_kinds(abi):
         ora, _, _ = run_circuit(c)
         ok, _, oa = ora.export()
         compare(gk, ga, ok, oa, c.eps)
+
+
+def test_host_superset_decisions(abi):
+    """Expansions decided from the host's superset of varying key bits (no
+    read-back): constant flips, controlled flips, arithmetic and imported
+    superpositions must lead to the same state as the oracle."""
+    mk = wl.make_op
+    ops = wl.ops_array([
+        mk("X", 0, qmask=1),                       # flip: q0 constant 1
+        mk("H", 0, qmask=2),                       # q1 constant -> expansion
+        mk("XORC", 0, imm=4),                      # flip q2
+        mk("H", 0, qmask=4),                       # still constant -> expansion
+        mk("X", 0, qmask=8, ctls=[(0, 1, 1)]),     # q3 varies now
+        mk("H", 0, qmask=8),                       # needs the exact masks (grouped)
+        mk("ADD", 1, reg2=0),                      # b += a: b varies
+        mk("H", 1, qmask=1),
+        mk("X", 1, qmask=2, ctls=[(0, 0, 0)]),     # control never true: q1 of b stays 0
+        mk("H", 1, qmask=2),                       # superset says varying, exact says constant
+        mk("H", 0, qmask=2),                       # q1 of a varies: group
+        mk("RY", 2, qmask=1, theta=0.7),
+    ])
+    c = wl.Circuit(regs=[("a", 4), ("b", 3), ("f", 1)], ops=ops, name="superset")
+    _check(abi, c)
+    # imported superposition: the import's own masks say which bits vary
+    vals = np.array([[0, 0, 0], [2, 0, 0], [2, 5, 0]], dtype=np.uint64)
+    amps = np.array([0.6, 0.0 + 0.64j, 0.48], dtype=np.complex128)
+    c2 = wl.Circuit(regs=[("a", 4), ("b", 3), ("f", 1)], ops=wl.ops_array([
+        mk("H", 0, qmask=2), mk("H", 0, qmask=1), mk("H", 1, qmask=4), mk("H", 1, qmask=1),
+        mk("RY", 2, qmask=1, theta=1.1)]), init_values=vals, init_amps=amps, name="superset-import")
+    _check(abi, c2)
