@@ -30,6 +30,7 @@ constexpr uint64_t kAlign = 256;
 constexpr uint32_t kMaxOpsPerCall = 16384;  // device op ring, in PermOp records
 constexpr uint64_t kOpRingBytes = (uint64_t)kMaxOpsPerCall * sizeof(PermOp);
 constexpr uint32_t kRunChunk = 4096;        // ops per fused launch
+constexpr uint64_t kUploadOps = 256;        // non-branching ops whose records one copy uploads
 constexpr uint32_t kHistBlocksMax = 1024;
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
@@ -1070,25 +1071,52 @@ int ring_upload(ss_state* st, const void* src, uint64_t bytes, char** dev) {
   return SS_OK;
 }
 
-// Launch the pending run of non-branching ops (one fused kernel per chunk).
-int flush_run(ss_state* st, std::vector<ss_op>& run, uint64_t run_start) {
-  if (run.empty()) return SS_OK;
-  if (st->n_ub == 0) {
-    run.clear();
-    return SS_OK;
+// One fused launch of non-branching ops: its op range, and once uploaded the
+// device address of its records (FastOps for W <= 2, then generic records).
+struct RunChunk {
+  uint64_t first;
+  uint32_t len;
+  uint32_t write_words;
+  bool amp;
+  uint64_t fbytes;
+  char* dev;
+};
+
+// Op ranges of the launches of a call: the runs of non-branching ops, at
+// most kRunChunk ops per launch.
+void plan_runs(const ss_op* ops, uint64_t nops, std::vector<RunChunk>& chunks) {
+  uint64_t i = 0;
+  while (i < nops) {
+    if (is_branching(ops[i].kind)) {
+      ++i;
+      continue;
+    }
+    uint64_t j = i;
+    while (j < nops && !is_branching(ops[j].kind) && j - i < kRunChunk) ++j;
+    RunChunk c{};
+    c.first = i;
+    c.len = (uint32_t)(j - i);
+    chunks.push_back(c);
+    i = j;
   }
+}
+
+// Encode chunks [a, b) into one blob and upload it with one copy.  Encoding
+// depends on the register layout only.
+int upload_chunks(ss_state* st, const ss_op* ops, std::vector<RunChunk>& chunks, size_t a, size_t b) {
   const uint32_t W = st->L.W;
-  size_t i = 0;
-  while (i < run.size()) {
-    const uint32_t chunk = (uint32_t)std::min<size_t>(run.size() - i, kRunChunk);
+  std::vector<char> blob;
+  std::vector<uint64_t> off(b - a);
+  for (size_t k = a; k < b; ++k) {
+    RunChunk& c = chunks[k];
     std::vector<FastOp> fast;
     std::vector<PermOp> gen;
-    uint32_t write_words = 0;
-    bool amp = false;
-    for (uint32_t j = 0; j < chunk; ++j) {
-      const ss_op& op = run[i + j];
-      if (op.kind == SS_REFLECT0) amp = true;
-      else write_words |= 1u << st->L.regs[op.reg].word;
+    c.write_words = 0;
+    c.amp = false;
+    for (uint64_t q = c.first; q < c.first + c.len; ++q) {
+      const ss_op& op = ops[q];
+      if (op.kind == SS_REFLECT0) c.amp = true;
+      else c.write_words |= 1u << st->L.regs[op.reg].word;
       if (W <= 2) {
         FastOp f = encode_fast(st, op, (uint32_t)gen.size());
         if (f.code == F_GEN) gen.push_back(to_perm(st, op));
@@ -1097,34 +1125,40 @@ int flush_run(ss_state* st, std::vector<ss_op>& run, uint64_t run_start) {
         gen.push_back(to_perm(st, op));
       }
     }
-    const uint64_t fbytes = align_up(fast.size() * sizeof(FastOp), kAlign);
-    std::vector<char> blob(fbytes + gen.size() * sizeof(PermOp));
-    if (!fast.empty()) std::memcpy(blob.data(), fast.data(), fast.size() * sizeof(FastOp));
-    if (!gen.empty()) std::memcpy(blob.data() + fbytes, gen.data(), gen.size() * sizeof(PermOp));
-    set_mark(st, run_start + i);
-    char* d = nullptr;
-    int rc = ring_upload(st, blob.data(), blob.size(), &d);
-    if (rc) return rc;
-    uint32_t ep;
-    rc = begin_launch(st, &ep);
-    if (rc) return rc;
-    const int tr = trace_begin(st, SS_TRACE_PERM);
-    const PermOp* gops = reinterpret_cast<const PermOp*>(d + fbytes);
-    switch (W) {
-      case 1: launch_perm_w<1>(st, d, chunk, gops, write_words, amp, ep); break;
-      case 2: launch_perm_w<2>(st, d, chunk, gops, write_words, amp, ep); break;
-      default: launch_perm_w<4>(st, d, chunk, gops, write_words, amp, ep); break;
-    }
-    trace_end(st, tr, 8ull * W + 8ull * (uint64_t)__builtin_popcount(write_words) + (amp ? 32ull : 0ull), chunk, 0,
-              0);
-    rc = check_launch(st);
-    if (rc) return rc;
-    st->masks_valid = false;
-    st->mask_ep = ep;
-    st->stats[5]++;
-    i += chunk;
+    c.fbytes = align_up(fast.size() * sizeof(FastOp), kAlign);
+    const uint64_t bytes = c.fbytes + gen.size() * sizeof(PermOp);
+    off[k - a] = blob.size();
+    blob.resize(off[k - a] + align_up(std::max<uint64_t>(bytes, 1), kAlign));
+    if (!fast.empty()) std::memcpy(blob.data() + off[k - a], fast.data(), fast.size() * sizeof(FastOp));
+    if (!gen.empty()) std::memcpy(blob.data() + off[k - a] + c.fbytes, gen.data(), gen.size() * sizeof(PermOp));
   }
-  run.clear();
+  char* d = nullptr;
+  const int rc = ring_upload(st, blob.data(), blob.size(), &d);
+  if (rc) return rc;
+  for (size_t k = a; k < b; ++k) chunks[k].dev = d + off[k - a];
+  return SS_OK;
+}
+
+// Launch one uploaded chunk.
+int launch_chunk(ss_state* st, const RunChunk& c) {
+  const uint32_t W = st->L.W;
+  uint32_t ep;
+  int rc = begin_launch(st, &ep);
+  if (rc) return rc;
+  const int tr = trace_begin(st, SS_TRACE_PERM);
+  const PermOp* gops = reinterpret_cast<const PermOp*>(c.dev + c.fbytes);
+  switch (W) {
+    case 1: launch_perm_w<1>(st, c.dev, c.len, gops, c.write_words, c.amp, ep); break;
+    case 2: launch_perm_w<2>(st, c.dev, c.len, gops, c.write_words, c.amp, ep); break;
+    default: launch_perm_w<4>(st, c.dev, c.len, gops, c.write_words, c.amp, ep); break;
+  }
+  trace_end(st, tr, 8ull * W + 8ull * (uint64_t)__builtin_popcount(c.write_words) + (c.amp ? 32ull : 0ull), c.len,
+            0, 0);
+  rc = check_launch(st);
+  if (rc) return rc;
+  st->masks_valid = false;
+  st->mask_ep = ep;
+  st->stats[5]++;
   return SS_OK;
 }
 
@@ -1645,12 +1679,39 @@ int plan_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst
     return finish(rc, 0);
   }
   set_mark(st, 0);
-  std::vector<ss_op> run;
-  uint64_t run_start = 0;
+  std::vector<RunChunk> chunks;
+  plan_runs(ops, nops, chunks);
+  size_t ci = 0, up = 0;
+  // launch the chunks of ops before `upto`; records are encoded and uploaded
+  // a group of chunks (>= kUploadOps ops) at a time, so that the host encodes
+  // while the device runs earlier launches and one copy serves several runs
+  auto flush = [&](uint64_t upto) -> int {
+    for (; ci < chunks.size() && chunks[ci].first < upto; ++ci) {
+      if (st->n_ub == 0) continue;
+      set_mark(st, chunks[ci].first);
+      if (ci >= up) {
+        size_t b = ci;
+        uint64_t nops_group = 0, bytes = 0;
+        while (b < chunks.size() && (b == ci || nops_group < kUploadOps)) {
+          const uint64_t cb = (uint64_t)chunks[b].len * (sizeof(FastOp) + sizeof(PermOp)) + 2 * kAlign;
+          if (b > ci && bytes + cb > kOpRingBytes / 2) break;
+          nops_group += chunks[b].len;
+          bytes += cb;
+          ++b;
+        }
+        const int r = upload_chunks(st, ops, chunks, ci, b);
+        if (r) return r;
+        up = b;
+      }
+      const int r = launch_chunk(st, chunks[ci]);
+      if (r) return r;
+    }
+    return SS_OK;
+  };
   for (uint64_t i = 0; i < nops; ++i) {
     const ss_op& op = ops[i];
     if (is_branching(op.kind)) {
-      rc = flush_run(st, run, run_start);
+      rc = flush(i);
       if (!rc) rc = do_branching(st, op, i);
       if (rc) {
         if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
@@ -1658,12 +1719,10 @@ int plan_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst
       }
     } else {
       if (st->grouped && !keeps_grouping(st, op, st->gmask)) st->grouped = false;
-      if (run.empty()) run_start = i;
-      run.push_back(op);
       sup_op(st, op);
     }
   }
-  rc = flush_run(st, run, run_start);
+  rc = flush(nops);
   if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
   set_mark(st, nops);
   return finish(rc, nops);
