@@ -47,6 +47,75 @@ def counter_traffic(kernel_label):
     return float(kv["traffic " + kernel_label])
 
 
+def summarize_profile(pdir):
+    """Write profiles/c2_kernel_stats.txt and profiles/c2_hbm_counters.txt
+    from the CSV output of the rocprofv3 runs named in their headers
+    (<pdir>/trace: --kernel-trace --stats; <pdir>/fetch, <pdir>/write: one
+    --pmc counter each)."""
+    import collections
+    import csv
+    import hashlib
+    src = os.path.join(ROOT, "paper_2503_15118_amd", "csrc")
+    sha = hashlib.sha256(open(os.path.join(src, "kernels.hip"), "rb").read()
+                         + open(os.path.join(src, "kernels_common.hpp"), "rb").read()).hexdigest()[:16]
+    base = "python3 bench.py --no-cpu-baseline --calibrate-copy"
+    out = ["# rocprofv3 kernel statistics: arithmetic-heavy sparse circuit (97-bit key, 2^20 -> 2^21 entries, "
+           "1001 ops)",
+           "# command (from /tmp, TMPDIR=/tmp; bench.py's default run: autotuning, warm-up, entry count, timed "
+           "steps, traced steps, graph replays):",
+           f"#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/trace -o c2 -- {base} --steps 5 "
+           "--warmup 1",
+           f"# summarised by: python3 bench.py --summarize-profile <dir>",
+           f"# kernel sources sha256[:16] = {sha}",
+           f'{"kernel":62s} {"calls":>6s} {"avg_us":>9s} {"total_ms":>9s} {"pct":>6s}']
+    for r in csv.DictReader(open(os.path.join(pdir, "trace", "c2_kernel_stats.csv"))):
+        name = r["Name"].split("(")[0][:62]
+        out.append(f'{name:62s} {int(r["Calls"]):6d} {float(r["AverageNs"]) / 1e3:9.1f} '
+                   f'{float(r["TotalDurationNs"]) / 1e6:9.3f} {float(r["Percentage"]):6.2f}')
+    with open(os.path.join(ROOT, "profiles", "c2_kernel_stats.txt"), "w") as f:
+        f.write("\n".join(out) + "\n")
+
+    def agg(path):
+        a = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            a[r["Kernel_Name"].split("(")[0]].append(float(r["Counter_Value"]))
+        return a
+    fe = agg(os.path.join(pdir, "fetch", "c2_counter_collection.csv"))
+    wr = agg(os.path.join(pdir, "write", "c2_counter_collection.csv"))
+    # calibration: the 64 MiB device copy (the largest copyBuffer dispatch)
+    copy_f, copy_w = max(fe["__amd_rocclr_copyBuffer"]), max(wr["__amd_rocclr_copyBuffer"])
+    fs, ws = 65536.0 / copy_f, 65536.0 / copy_w
+    pmc = f"{base} --steps 2 --warmup 0 --no-tune --graph-steps 0"
+    lines = ["# HBM traffic from rocprofv3 PMC counters: arithmetic-heavy sparse circuit (97-bit key, "
+             "2^20 -> 2^21 entries)",
+             "# commands (from /tmp, TMPDIR=/tmp), one counter per run:",
+             f"#   timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o c2 -- {pmc}",
+             f"#   timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o c2 -- {pmc}",
+             "# summarised by: python3 bench.py --summarize-profile <dir>",
+             f"# kernel sources sha256[:16] = {sha}",
+             "# calibration: --calibrate-copy runs one plain device copy of 64 MiB (65536 KiB read + 65536 KiB "
+             "written)",
+             f"#   copy FETCH_SIZE = {copy_f:.1f} KiB -> fetch_scale = {fs:.3f};  copy WRITE_SIZE = {copy_w:.1f} KiB "
+             f"-> write_scale = {ws:.3f}",
+             f'{"kernel":50s} {"n":>4s} {"FETCH_KiB":>11s} {"WRITE_KiB":>11s} {"scaled_MB":>10s}']
+    for k in sorted(set(fe) | set(wr), key=lambda x: -sum(fe.get(x, [0]))):
+        fv, wv = fe.get(k, [0]), wr.get(k, [0])
+        af, aw = sum(fv) / len(fv), sum(wv) / len(wv)
+        lines.append(f"{k[:50]:50s} {len(fv):4d} {af:11.1f} {aw:11.1f} {(af * fs + aw * ws) * 1024 / 1e6:10.2f}")
+    lines.append("")
+    for label in ("k_perm_fast<2, 8, false>", "k_perm_fast<2, 4, false>", "k_pair<2, 0, 4>", "k_pair<2, 1, 4>",
+                  "k_pair<2, 0, 2>", "k_pair<2, 1, 2>", "k_group<2, 5, 1, 1>"):
+        pk = "void sparqs::" + label
+        if pk not in fe or pk not in wr:
+            continue
+        af, aw = sum(fe[pk]) / len(fe[pk]), sum(wr[pk]) / len(wr[pk])
+        lines.append(f"traffic {label}: {(af * fs + aw * ws) * 1024:.0f}")
+    lines += [f"fetch_scale: {fs:.4f}", f"write_scale: {ws:.4f}", f"sources_sha: {sha}"]
+    with open(os.path.join(ROOT, "profiles", "c2_hbm_counters.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(out + lines))
+
+
 def set_opts(st, opts):
     for kv in opts:
         k, v = kv.split("=", 1)
@@ -399,7 +468,12 @@ def main():
     ap.add_argument("--chunk-ops", type=int, default=256)
     ap.add_argument("--ninst", type=int, default=1024)
     ap.add_argument("--batch-cap-log2", type=int, default=28)
+    ap.add_argument("--summarize-profile", default=None, metavar="DIR",
+                    help="write the profiles/ summaries from rocprofv3 CSV output under DIR and exit")
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding is a design note, not an implemented path", file=sys.stderr)
