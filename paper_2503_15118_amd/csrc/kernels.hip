@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_perm(KeyPtrs<W> keys, double2* __res
 // switch case per (kind, half indices), so every case is straight-line code;
 // each thread carries E entries so the per-op scalar decode is shared.
 // ---------------------------------------------------------------------------
-#define SQ_E for (int j = 0; j < E; ++j)
+#define SQ_E _Pragma("unroll") for (int j = 0; j < E; ++j)
 template <int W, int E, bool AMP>
 __device__ __forceinline__ void fast_step(uint32_t (&h)[E][4], double2 (&a)[E], const FastOp& op,
                                           const PermOp* __restrict__ gops) {

@@ -1028,7 +1028,8 @@ void launch_perm_w(ss_state* st, const void* dev, uint32_t nfast, const PermOp* 
                    bool amp, uint32_t ep) {
   if (W <= 2) {
     const FastOp* f = static_cast<const FastOp*>(dev);
-    if (st->perm_entries == 8) launch_perm_fast<W, 8>(st, f, nfast, gops, write_words, amp, ep);
+    if (st->perm_entries == 16) launch_perm_fast<W, 16>(st, f, nfast, gops, write_words, amp, ep);
+    else if (st->perm_entries == 8) launch_perm_fast<W, 8>(st, f, nfast, gops, write_words, amp, ep);
     else launch_perm_fast<W, 4>(st, f, nfast, gops, write_words, amp, ep);
   } else {
     const Buf& b = st->buf[st->cur];
@@ -2490,7 +2491,7 @@ int ss_set_option(ss_state* st, const char* key, int64_t value) {
     // streams of one GPU must use 0)
     st->tile_order_opt = value ? 1 : 0;
   } else if (k == "perm_entries") {
-    if (value != 4 && value != 8) return SS_E_ARG;
+    if (value != 4 && value != 8 && value != 16) return SS_E_ARG;
     st->perm_entries = (int)value;
   } else if (k == "group_items") {
     if (value != 1 && value != 2 && value != 4) return SS_E_ARG;

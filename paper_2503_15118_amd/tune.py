@@ -24,7 +24,7 @@ import statistics
 from typing import Callable, Dict, Iterable, Optional
 
 SPACE: Dict[str, tuple] = {
-    "perm_entries": (4, 8),
+    "perm_entries": (4, 8, 16),
     "group_items": (1, 2, 4),
     "sort_items": (8, 16),
 }

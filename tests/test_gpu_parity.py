@@ -389,3 +389,15 @@ def test_host_superset_decisions(abi):
         mk("H", 0, qmask=2), mk("H", 0, qmask=1), mk("H", 1, qmask=4), mk("H", 1, qmask=1),
         mk("RY", 2, qmask=1, theta=1.1)]), init_values=vals, init_amps=amps, name="superset-import")
     _check(abi, c2)
+
+
+@pytest.mark.parametrize("entries", [4, 16])
+def test_perm_entries_variants(abi, entries):
+    """Entries per lane of the interpreter change the tiling only: every op
+    kind on 1- and 2-word keys, with and without a phase op in the run."""
+    kinds = ("X", "ADD", "SUB", "MULC", "XOR", "XORC", "QRAM_LOAD", "QRAM_UNLOAD", "REFLECT0")
+    for seed in range(3):
+        c = wl.random_small_circuit(40 + seed, kinds=kinds, nops=120, with_init=True)
+        s = _check(abi, c, opts={"perm_entries": entries})
+        assert s["bit_exact"] == s["shared"] == s["n_oracle"]
+    _check(abi, wl.c2_circuit(6, nops=150, n_ry=3, h_qubits=12), opts={"perm_entries": entries})

@@ -13,7 +13,7 @@ class FakeState:
         self.opts = {}
         self.tr = None
         self.calls = 0
-        self.perm_cost = perm_cost or {4: 1.0, 8: 2.0}
+        self.perm_cost = perm_cost or {4: 1.0, 8: 2.0, 16: 3.0}
         self.group_cost = group_cost or {1: 3.0, 2: 1.0, 4: 2.0}
         self.sort_cost = sort_cost or {8: 2.0, 16: 1.0}
 
@@ -79,7 +79,7 @@ def test_lookup_nearest_bucket_same_shape_only(tmp_path):
 
 def test_ties_keep_current_value_and_idle_options_untouched(tmp_path):
     t = tune.Tuner(str(tmp_path / "c.json"), trials=1)
-    st = FakeState(perm_cost={4: 1.0, 8: 1.0}, sort_cost={8: 0.0, 16: 0.0})
+    st = FakeState(perm_cost={4: 1.0, 8: 1.0, 16: 1.0}, sort_cost={8: 0.0, 16: 0.0})
     best = t.tune(st, st.run, "gfx950/W1/n16/plain")
     assert best["perm_entries"] == tune.DEFAULTS["perm_entries"]   # tie: keep the default
     assert best["sort_items"] == tune.DEFAULTS["sort_items"]       # category never ran
