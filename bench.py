@@ -388,6 +388,55 @@ def bench_m6(args):
                                   "(W=1: a:20 b:20 t:1; W=2: a,b,c:32 t:1)", "rows": rows}), flush=True)
 
 
+def bench_m7(args):
+    """Stand-ins for the paper's benchmark circuits (textbook constructions with
+    the printed qubit and branch counts): GHZ 23/40/255, QRAM 20 from one
+    branch, swap test 25.  Per circuit: 2 warm-up runs, then the median of 10.
+    The paper's CPU times (two 64-core Xeons; Table 1 one thread, Table 2 64
+    threads) are printed beside them as context, not as a baseline."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2503_15118_amd import _abi
+
+    paper = {"ghz23": (0.0005, 0.0006), "ghz40": (0.0006, 0.0005), "ghz255": (0.0006, 0.0008),
+             "qram20": (1e-4, 0.4743), "swap_test25": (14.8518, 5.6675)}
+    circuits = [("ghz23", wl.ghz_circuit(23)), ("ghz40", wl.ghz_circuit(40)), ("ghz255", wl.ghz_circuit(255)),
+                ("qram20", wl.qram_circuit(1, 10, 10, superpose=False)), ("swap_test25", wl.swap_test_circuit(12))]
+    rows = []
+    for name, c in circuits:
+        cap = 1 << 26 if name.startswith("swap") else 1 << 12
+        st = _abi.state_for_circuit(c, cap_entries=cap)
+        ops = _abi.to_ss_ops(c.ops)
+        zero = np.zeros((1, len(c.regs)), dtype=np.uint64)
+        one = np.array([1.0 + 0j])
+        times = []
+        for r in range(12):
+            st.set_entries(0, zero, one)
+            e0 = st.stats()["entries_updated"]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st.apply(ops)
+            torch.cuda.synchronize()
+            if r >= 2:
+                times.append(time.perf_counter() - t0)
+        ent = st.stats()["entries_updated"] - e0
+        row = {"circuit": name, "qubits": c.nqubits, "peak_branches": st.peak(), "final_branches": st.nnz(),
+               "median_ms": 1e3 * float(np.median(times)), "entries_per_s": ent / float(np.median(times)),
+               "paper_cpu_s_1_thread": paper[name][0], "paper_cpu_s_64_threads": paper[name][1]}
+        if name.startswith("swap"):
+            st.set_entries(0, zero, one)
+            st.set_option("trace", 1)
+            st.set_option("trace_reset", 1)
+            st.apply(ops)
+            row["kernels"] = _kernel_table(st.trace(), 1)
+            st.set_option("trace", 0)
+        st.close()
+        rows.append(row)
+        print(f"[m7] {name}: {row['median_ms']:.3f} ms", file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "paper benchmark stand-ins (GHZ, QRAM, swap test)", "rows": rows}), flush=True)
+
+
 def bench_serving(args):
     """Serving: a Poisson request stream mixing the four workload forms, served
     with footprint admission and continuous batching, against the same trace
@@ -454,7 +503,7 @@ def main():
                     help="also time this many steps replayed from a captured HIP graph (default: --steps; 0: off)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 64 MiB device copy first (reference for HBM counters)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "m6"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "m6", "m7"])
     ap.add_argument("--c1-seeds", type=int, default=32)
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--c4-trials", type=int, default=3)
@@ -490,6 +539,9 @@ def main():
         return
     if args.workload == "m6":
         bench_m6(args)
+        return
+    if args.workload == "m7":
+        bench_m7(args)
         return
     if args.workload == "c5":
         bench_serving(args)

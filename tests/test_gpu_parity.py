@@ -401,3 +401,24 @@ def test_perm_entries_variants(abi, entries):
         s = _check(abi, c, opts={"perm_entries": entries})
         assert s["bit_exact"] == s["shared"] == s["n_oracle"]
     _check(abi, wl.c2_circuit(6, nops=150, n_ry=3, h_qubits=12), opts={"perm_entries": entries})
+
+
+def test_swap_test_form(abi):
+    """Swap-test form: small size against the oracle; at the printed 25 qubits
+    the peak equals the paper's branch count and the final state is the closed
+    form (every (x, y) with the ancilla 0 and amplitude c^24)."""
+    import json
+    import os
+    _check(abi, wl.swap_test_circuit(4))
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_branch_counts.json")))
+    nq, branches = g["swap_test"][0]
+    c = wl.swap_test_circuit((nq - 1) // 2)
+    print(f"[case] {c.name} full size", flush=True)
+    st = abi.state_for_circuit(c, cap_entries=1 << 26)
+    st.apply(c.ops)
+    assert st.peak() == branches
+    k, a = st.export()
+    assert len(k) == branches // 2
+    assert np.array_equal(k[:, 0], np.arange(branches // 2, dtype=np.uint64))
+    assert np.max(np.abs(a - C ** (nq - 1))) <= 1e-12
+    st.close()

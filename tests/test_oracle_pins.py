@@ -340,3 +340,25 @@ def test_prune_threshold_is_strict():
     assert st.nnz == 3
     st.prune(1.0001e-5)
     assert st.nnz == 2
+
+
+@pytest.mark.parametrize("n", [1, 3])
+def test_swap_test_closed_form(n):
+    """Swap test on symmetric inputs: the ancilla ends in |0> for every (x, y),
+    each with amplitude c^(2n) (2 c^(2n+2) = c^(2n)); the peak is 2^(2n+1)."""
+    c = wl.swap_test_circuit(n)
+    st, _, _ = run_circuit(c)
+    _, v, a = st.export()
+    assert st.nnz == 2 ** (2 * n)
+    assert st.peak == 2 ** (2 * n + 1)
+    assert sorted((int(x), int(y)) for x, y, _ in v) == [(x, y) for x in range(2 ** n) for y in range(2 ** n)]
+    assert np.all(v[:, 2] == 0)
+    expect = C ** (2 * n)
+    assert np.allclose(a, expect, rtol=0, atol=1e-15)
+    # dense brute force agrees on the whole state
+    d = DenseState.from_circuit(c)
+    d.apply(c.ops)
+    dv, da = _sorted_entries(*d.entries())
+    v, a = _sorted_entries(v, a)
+    assert np.array_equal(dv, v)
+    assert np.allclose(da, a, rtol=0, atol=1e-15)

@@ -446,6 +446,23 @@ def qram_circuit(seed, addr_bits: int, word_bits: int, superpose: bool = True) -
                    name=f"qram{addr_bits}x{word_bits}")
 
 
+def swap_test_circuit(n: int) -> Circuit:
+    """Swap-test form on 2n + 1 qubits: H on every qubit of two n-qubit
+    registers x and y (2^(2n) branches), then the textbook swap test: H on the
+    ancilla, a controlled swap of x_i and y_i for every i (CNOT, Toffoli, CNOT),
+    H on the ancilla.  The peak is 2^(2n+1) branches; x and y being symmetric,
+    every ancilla-1 amplitude cancels exactly, leaving 2^(2n) branches."""
+    regs = [("x", n), ("y", n), ("anc", 1)]
+    full = (1 << n) - 1
+    ops = [make_op("H", 0, qmask=full), make_op("H", 1, qmask=full), make_op("H", 2, qmask=1)]
+    for i in range(n):
+        ops.append(make_op("X", 0, qmask=1 << i, ctls=[(1, i, 1)]))
+        ops.append(make_op("X", 1, qmask=1 << i, ctls=[(2, 0, 1), (0, i, 1)]))
+        ops.append(make_op("X", 0, qmask=1 << i, ctls=[(1, i, 1)]))
+    ops.append(make_op("H", 2, qmask=1))
+    return Circuit(regs=regs, ops=ops_array(ops), name=f"swap_test{2 * n + 1}")
+
+
 # ---------------------------------------------------------------------------
 # C5: a Poisson request stream mixing the C1..C4 forms
 # ---------------------------------------------------------------------------
