@@ -229,7 +229,13 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
  * entry count, default 2^23, 0 = never: a one-target expansion on at least
  * that many entries first places both children of every entry at fixed
  * positions, and the compacting launch after it redoes the op only when some
- * entry does not have two children; results are identical either way), "trace" (1: time
+ * entry does not have two children; results are identical either way),
+ * "chain" (1, default: up to 16 consecutive H / Ry ops on the same single
+ * target qubit run as one launch in which each group gets the product of the
+ * matrices whose controls hold for it, pruned once after the last; 0: one
+ * launch per op; results agree within rounding and the prune band),
+ * "speculate_group" (as "speculate" for one-target ops on grouped entries;
+ * default 0 = never), "trace" (1: time
  * every kernel launch with a HIP event pair on the state's stream),
  * "trace_reset". */
 int ss_set_option(ss_state* st, const char* key, int64_t value);

@@ -745,7 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const doub
   __shared__ uint32_t s_tile;
   uint64_t n;
   if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
-  if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) meta->upd += n;
+  if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) meta->upd += n * op.upd;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + TILE - 1) / TILE;
   if (tile_out_of_range(tile, ntiles, &meta->err)) return;
@@ -939,13 +939,35 @@ __device__ __forceinline__ void pair_tile(const KeyPtrs<W>& in_keys, const doubl
     if (e < n) {
       const double2 a = amp[it];
       const uint32_t b = (uint32_t)((sel_word<W>(key[it], tw) >> tb) & 1ull);
-      const bool ctl = !op.has_ctl || controls_hold<W>(key[it], op.cmask, op.cval);
-      if (!ctl) {
-        // pass through (selects, not a runtime index: keeps `out` in registers)
-        if (b) out[it][1] = a;
-        else out[it][0] = a;
-        if (keep_amp(a.x, a.y, op.eps2)) keepm[it] = 1u << b;
+      // The matrix this entry's group gets: the op's own when its controls
+      // hold, else the identity (the entry passes through); for a chain, the
+      // product of the matrices of the ops whose controls hold, in op order.
+      double mm[2][2];
+      if (op.nchain == 0) {
+        const bool ctl = !op.has_ctl || controls_hold<W>(key[it], op.cmask, op.cval);
+        mm[0][0] = ctl ? op.m[0][0] : 1.0;
+        mm[0][1] = ctl ? op.m[0][1] : 0.0;
+        mm[1][0] = ctl ? op.m[1][0] : 0.0;
+        mm[1][1] = ctl ? op.m[1][1] : 1.0;
       } else {
+        mm[0][0] = 1.0;
+        mm[0][1] = 0.0;
+        mm[1][0] = 0.0;
+        mm[1][1] = 1.0;
+        for (uint32_t q = 0; q < op.nchain; ++q) {
+          const ChainStep& cs = op.chain[q];
+          if (!controls_hold<W>(key[it], cs.cmask, cs.cval)) continue;
+          const double t00 = cs.m[0][0] * mm[0][0] + cs.m[0][1] * mm[1][0];
+          const double t01 = cs.m[0][0] * mm[0][1] + cs.m[0][1] * mm[1][1];
+          const double t10 = cs.m[1][0] * mm[0][0] + cs.m[1][1] * mm[1][0];
+          const double t11 = cs.m[1][0] * mm[0][1] + cs.m[1][1] * mm[1][1];
+          mm[0][0] = t00;
+          mm[0][1] = t01;
+          mm[1][0] = t10;
+          mm[1][1] = t11;
+        }
+      }
+      {
         bool has_p = false;
         double2 ap = make_double2(0.0, 0.0);
         if (MODE == MODE_GROUP) {
@@ -971,11 +993,13 @@ __device__ __forceinline__ void pair_tile(const KeyPtrs<W>& in_keys, const doubl
         for (uint32_t r = 0; r < 2; ++r) {
           // a member of a full pair writes only the child with its own value
           if (has_p && r != b) continue;
+          const double m0 = r ? mm[1][0] : mm[0][0];
+          const double m1 = r ? mm[1][1] : mm[0][1];
           double2 v;
-          v.x = op.m[r][0] * a0.x + op.m[r][1] * a1.x;
-          v.y = op.m[r][0] * a0.y + op.m[r][1] * a1.y;
-          const double mrb = b ? op.m[r][1] : op.m[r][0];
-          const bool exists = has_p ? (op.m[r][0] != 0.0 || op.m[r][1] != 0.0) : (mrb != 0.0);
+          v.x = m0 * a0.x + m1 * a1.x;
+          v.y = m0 * a0.y + m1 * a1.y;
+          const double mrb = b ? m1 : m0;
+          const bool exists = has_p ? (m0 != 0.0 || m1 != 0.0) : (mrb != 0.0);
           out[it][r] = v;
           if (exists && keep_amp(v.x, v.y, op.eps2)) keepm[it] |= 1u << r;
         }
@@ -1089,7 +1113,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
   __shared__ uint64_t s_stage[MODE == MODE_GROUP ? (W + 2) * (TILE + 2) : 1];
   uint64_t n;
   if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
-  if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) meta->upd += n;
+  if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) meta->upd += n * op.upd;
   if (spec_ep != 0 && *reinterpret_cast<volatile unsigned int*>(&meta->spec_irr[spec_ep % kRing]) == 0u) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       const uint64_t m = f * n;

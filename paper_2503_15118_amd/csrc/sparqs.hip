@@ -224,6 +224,9 @@ struct ss_state {
   DevMeta* hmeta = nullptr;       // pinned read-back block
   PermOp* hops = nullptr;         // pinned op staging (kMaxOpsPerCall)
   uint32_t ops_used = 0;
+  // bytes at the start of the op ring that hold records uploaded for launches
+  // not made yet: a synchronisation frees the ring only above them
+  uint32_t ops_keep = 0;
   // options
   int sort_items = 16;
   int grouping = 1;
@@ -235,6 +238,7 @@ struct ss_state {
   // more than it saves.
   uint64_t speculate = 1ull << 23;
   uint64_t spec_group = 0;       // the same for one-target ops on grouped entries (0: never)
+  int chain = 1;                 // option: consecutive one-target ops on one target in one launch
   uint32_t xcd_order = 0;        // 1 when workgroups spread round-robin over 8 XCDs
   int tile_order_opt = 1;        // option: 1 use XCD tickets when possible, 0 one counter
   uint64_t stats[8]{};
@@ -448,7 +452,7 @@ int sync_state(ss_state* st) {
       st->snaps.emplace_back(p, p + kStatus);
     }
   }
-  st->ops_used = 0;
+  st->ops_used = st->ops_keep;
   const DevMeta* hm = st->hmeta;
   st->dev_err |= hm->err;
   trace_flush(st);
@@ -1052,6 +1056,7 @@ int ring_upload(ss_state* st, const void* src, uint64_t bytes, char** dev) {
   if (st->ops_used + need > kOpRingBytes) {
     const int rc = sync_state(st);
     if (rc) return rc;
+    if (st->ops_used + need > kOpRingBytes) return SS_E_ARG;
   }
   char* h = reinterpret_cast<char*>(st->hops) + st->ops_used;
   char* d = reinterpret_cast<char*>(st->dev_ops) + st->ops_used;
@@ -1164,13 +1169,8 @@ int launch_chunk(ss_state* st, const RunChunk& c) {
 }
 
 // One branching op: chunks of at most kMaxGroupBits target qubits, ascending.
-int do_branching(ss_state* st, const ss_op& op, uint64_t op_index) {
-  set_mark(st, op_index);
-  const RegInfo& d = st->L.regs[op.reg];
-  std::vector<uint32_t> qs;
-  for (uint32_t q = 0; q < d.width; ++q)
-    if ((op.qmask >> q) & 1ull) qs.push_back(q);
-  double m[2][2];
+// The real 2x2 matrix of a branching op, m[out][in] (host libm).
+void gate_matrix(const ss_op& op, double (&m)[2][2]) {
   if (op.kind == SS_H) {
     const double c = 0.70710678118654752440;  // nearest double to 1/sqrt(2)
     m[0][0] = c; m[0][1] = c; m[1][0] = c; m[1][1] = -c;
@@ -1179,6 +1179,26 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index) {
     const double c = std::cos(h), s = std::sin(h);
     m[0][0] = c; m[0][1] = -s; m[1][0] = s; m[1][1] = c;
   }
+}
+
+// Ops that can follow `a` in one chained launch: branching on the same one
+// target qubit (H or Ry, any controls; controls never include the target).
+bool chains_with(const ss_op& a, const ss_op& b) {
+  return is_branching(b.kind) && b.reg == a.reg && b.qmask == a.qmask && __builtin_popcountll(a.qmask) == 1;
+}
+
+// One branching op, or (nchain >= 2) the one-target ops chain_ops[0..nchain)
+// on the same target applied in one launch: each group gets the product of
+// the matrices whose controls hold for it, and the prune follows the last.
+int do_branching(ss_state* st, const ss_op& op, uint64_t op_index, const ss_op* chain_ops = nullptr,
+                 uint32_t nchain = 0) {
+  set_mark(st, op_index);
+  const RegInfo& d = st->L.regs[op.reg];
+  std::vector<uint32_t> qs;
+  for (uint32_t q = 0; q < d.width; ++q)
+    if ((op.qmask >> q) & 1ull) qs.push_back(q);
+  double m[2][2];
+  gate_matrix(op, m);
   // An op split over several launches cannot be rolled back once its first
   // part has run, so it is admitted only if the worst case fits.
   if (qs.size() > (size_t)kMaxGroupBits) {
@@ -1210,6 +1230,19 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index) {
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) g.m[a][b] = m[a][b];
     g.eps2 = last ? st->eps * st->eps : 0.0;
+    if (nchain >= 2) {
+      std::vector<ChainStep> steps(nchain);
+      for (uint32_t q = 0; q < nchain; ++q) {
+        gate_matrix(chain_ops[q], steps[q].m);
+        ctl_masks(st, chain_ops[q], steps[q].cmask, steps[q].cval);
+      }
+      char* dchain = nullptr;
+      int rc = ring_upload(st, steps.data(), steps.size() * sizeof(ChainStep), &dchain);
+      if (rc) return rc;
+      g.nchain = nchain;
+      g.chain = reinterpret_cast<const ChainStep*>(dchain);
+      g.upd = nchain;
+    }
 
     int mode;
     bool same = st->grouped && st->grouping;
@@ -1247,8 +1280,9 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index) {
     // without a child, and the speculative launch would be wasted.
     uint32_t ep_spec = 0, ep;
     int rc = SS_OK;
-    if (g.k == 1 && ((mode == MODE_EXPAND && st->speculate && st->n_ub >= st->speculate) ||
-                     (mode == MODE_GROUP && st->spec_group && st->n_ub >= st->spec_group)))
+    if (g.k == 1 && g.nchain == 0 &&
+        ((mode == MODE_EXPAND && st->speculate && st->n_ub >= st->speculate) ||
+         (mode == MODE_GROUP && st->spec_group && st->n_ub >= st->spec_group)))
       rc = begin_launch(st, &ep_spec);
     if (!rc) rc = begin_launch(st, &ep);
     if (rc) return rc;
@@ -1658,6 +1692,7 @@ int plan_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst
   auto finish = [&](int code, uint64_t op) {
     // the status is final only after a synchronisation; a capacity failure
     // found there names the op (batched: round) whose launch was rolled back
+    st->ops_keep = 0;           // no launch of this call is still to come
     st->final_sync = true;
     const int sc = st->poisoned ? SS_OK : sync_state(st);
     st->final_sync = false;
@@ -1674,6 +1709,7 @@ int plan_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst
     return code;
   };
   int rc;
+  st->ops_keep = 0;
   if (inst_offsets) {
     rc = apply_batched(st, ops, nops, inst_offsets, res);
     if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
@@ -1703,21 +1739,27 @@ int plan_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst
         const int r = upload_chunks(st, ops, chunks, ci, b);
         if (r) return r;
         up = b;
+        st->ops_keep = st->ops_used;
       }
       const int r = launch_chunk(st, chunks[ci]);
       if (r) return r;
+      if (ci + 1 == up) st->ops_keep = 0;
     }
     return SS_OK;
   };
   for (uint64_t i = 0; i < nops; ++i) {
     const ss_op& op = ops[i];
     if (is_branching(op.kind)) {
+      uint64_t j = i + 1;
+      if (st->chain)
+        while (j < nops && j - i < (uint64_t)kMaxChain && chains_with(op, ops[j])) ++j;
       rc = flush(i);
-      if (!rc) rc = do_branching(st, op, i);
+      if (!rc) rc = j - i >= 2 ? do_branching(st, op, i, ops + i, (uint32_t)(j - i)) : do_branching(st, op, i);
       if (rc) {
         if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
         return finish(rc, i);
       }
+      i = j - 1;
     } else {
       if (st->grouped && !keeps_grouping(st, op, st->gmask)) st->grouped = false;
       sup_op(st, op);
@@ -2501,6 +2543,8 @@ int ss_set_option(ss_state* st, const char* key, int64_t value) {
   } else if (k == "speculate") {
     if (value < 0) return SS_E_ARG;
     st->speculate = (uint64_t)value;
+  } else if (k == "chain") {
+    st->chain = value ? 1 : 0;
   } else if (k == "speculate_group") {
     if (value < 0) return SS_E_ARG;
     st->spec_group = (uint64_t)value;

@@ -118,11 +118,24 @@ struct alignas(64) FastOp {       // 64 bytes: four 16-byte LDS words
   const uint32_t* table;        // QRAM words (uint32)
 };
 
+constexpr int kMaxChain = 16;       // one-target ops on one target fused into one launch
+
+// One op of a chain: its real 2x2 matrix (m[out][in]) and its controls
+// (cmask 0: uncontrolled).  The controls never include the target bit, so
+// both members of a group see the same ones.
+struct ChainStep {
+  double m[2][2];
+  uint64_t cmask[kMaxW];
+  uint64_t cval[kMaxW];
+};
+
 // One branching (interference) op as seen by the group/expand kernel.
 struct GroupOp {
   uint32_t k;                   // number of target qubits (1..kMaxGroupBits); 0 = plain filter
   uint32_t has_ctl;
-  uint32_t upd;                 // 1: add the input count to the update counter
+  uint32_t upd;                 // ops to count: the update counter gains upd x the input count
+  uint32_t nchain;              // k == 1 only: > 0 applies chain[0..nchain) (m, cmask, cval unused)
+  const ChainStep* chain;       // device array
   uint32_t tword[kMaxGroupBits];  // target j: key word and bit, ascending qubit order
   uint32_t tbit[kMaxGroupBits];
   uint64_t tmask[kMaxW];        // all target bits per word

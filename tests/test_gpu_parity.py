@@ -422,3 +422,60 @@ def test_swap_test_form(abi):
     assert np.array_equal(k[:, 0], np.arange(branches // 2, dtype=np.uint64))
     assert np.max(np.abs(a - C ** (nq - 1))) <= 1e-12
     st.close()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_chained_one_target_ops(abi, seed):
+    """Runs of H / Ry on one target qubit with varied controls (including
+    none, H.H pairs and singleton groups) run as one launch: the result must
+    match the oracle (which prunes after every op) and the unchained path."""
+    rng = np.random.default_rng(500 + seed)
+    mk = wl.make_op
+    regs = [("a", 4), ("b", 3), ("f", 1)]
+    ops = [mk("H", 0, qmask=0b0101)]
+    for blk in range(6):
+        reg, q = [(2, 0), (0, int(rng.integers(0, 4))), (1, int(rng.integers(0, 3)))][blk % 3]
+        for _ in range(int(rng.integers(2, 20))):
+            ctls = []
+            for _c in range(int(rng.integers(0, 3))):
+                cr = int(rng.integers(0, 3))
+                cq = int(rng.integers(0, [4, 3, 1][cr]))
+                if (cr, cq) != (reg, q) and all((cr, cq) != (x, y) for x, y, _ in ctls):
+                    ctls.append((cr, cq, int(rng.integers(0, 2))))
+            if rng.random() < 0.3:
+                ops.append(mk("H", reg, qmask=1 << q, ctls=ctls))
+            else:
+                ops.append(mk("RY", reg, qmask=1 << q, theta=float(rng.uniform(0, 2 * np.pi)), ctls=ctls))
+        ops.append(mk("ADD", 1, reg2=0))
+        ops.append(mk("X", 0, qmask=1 << int(rng.integers(0, 4)), ctls=[(2, 0, 1)]))
+    c = wl.Circuit(regs=regs, ops=wl.ops_array(ops), eps=(1e-14 if seed % 2 else 0.0), name=f"chains-{seed}")
+    s1 = _check(abi, c, opts={"chain": 1})
+    s0 = _check(abi, c, opts={"chain": 0})
+    assert s1["n_oracle"] == s0["n_oracle"]
+    st1 = _gpu(abi, c, opts={"chain": 1})
+    st0 = _gpu(abi, c, opts={"chain": 0})
+    k1, a1 = st1.export()
+    k0, a0 = st0.export()
+    compare(k1, a1, k0, a0, c.eps)
+    st1.close()
+    st0.close()
+
+
+@pytest.mark.parametrize("chunk", [7, 16])
+def test_op_list_split_over_calls(abi, chunk):
+    """The same circuit applied as many short calls: every call ends with a
+    read-back and starts from the previous call's host view (grouping, masks,
+    op-record ring), so chains, runs and their uploaded records meet
+    synchronisations at every position.  Must equal the oracle."""
+    for seed in (0, 3, 11):
+        c = wl.c1_circuit(seed)
+        print(f"[case] {c.name} in calls of {chunk} ops", flush=True)
+        st = abi.state_for_circuit(c)
+        ops = abi.to_ss_ops(c.ops)
+        for a in range(0, len(ops), chunk):
+            st.apply(ops[a:a + chunk])
+        gk, ga = st.export()
+        ora, _, _ = run_circuit(c)
+        ok, _, oa = ora.export()
+        compare(gk, ga, ok, oa, c.eps)
+        st.close()
