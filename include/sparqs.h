@@ -234,6 +234,9 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
  * target qubit run as one launch in which each group gets the product of the
  * matrices whose controls hold for it, pruned once after the last; 0: one
  * launch per op; results agree within rounding and the prune band),
+ * "fuse_runs" (default 16, 0 = never: a one-target op whose next ops form a
+ * run of at most that many non-branching ops applies the run to its outputs
+ * in the same launch; results are identical either way),
  * "speculate_group" (as "speculate" for one-target ops on grouped entries;
  * default 0 = never), "trace" (1: time
  * every kernel launch with a HIP event pair on the state's stream),

@@ -448,6 +448,23 @@ __global__ __launch_bounds__(kBlock) void k_perm_fast(KeyPtrs<W> keys, double2* 
   publish_masks<W>(meta, epoch, orv, andv, s_red);
 }
 
+// A run of non-branching ops on E entries per thread, its records staged
+// through LDS (`s_ops`, kOpChunk records) a chunk at a time.  Every thread of
+// the workgroup calls it (it synchronises the workgroup).
+template <int W, int E>
+__device__ __forceinline__ void run_ops_lds(uint32_t (&h)[E][4], double2 (&a)[E], const FastOp* __restrict__ ops,
+                                            uint32_t nops, const PermOp* __restrict__ gops, uint4* s_ops) {
+  for (uint32_t c0 = 0; c0 < nops; c0 += kOpChunk) {
+    const uint32_t cn = nops - c0 < (uint32_t)kOpChunk ? nops - c0 : (uint32_t)kOpChunk;
+    __syncthreads();
+    const uint4* src = reinterpret_cast<const uint4*>(ops + c0);
+    for (uint32_t q = threadIdx.x; q < cn * (uint32_t)(sizeof(FastOp) / 16); q += kBlock) s_ops[q] = src[q];
+    __syncthreads();
+    const FastOp* lops = reinterpret_cast<const FastOp*>(s_ops);
+    for (uint32_t o = 0; o < cn; ++o) fast_step<W, E, true>(h, a, lops[o], gops);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // radix sort
 // ---------------------------------------------------------------------------
@@ -745,7 +762,7 @@ __global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const doub
   __shared__ uint32_t s_tile;
   uint64_t n;
   if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
-  if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) meta->upd += n * op.upd;
+  if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&meta->upd, (unsigned long long)(n * op.upd));
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + TILE - 1) / TILE;
   if (tile_out_of_range(tile, ntiles, &meta->err)) return;
@@ -1096,12 +1113,17 @@ __global__ __launch_bounds__(kBlock) void k_pair_spec(KeyPtrs<W> in_keys, const 
 // The compacting launch.  With spec_ep != 0 it follows k_pair_spec (launch
 // spec_ep): when that launch met no irregular tile, its outputs stand and
 // workgroup 0 only records the count f * n, the peak and the key masks.
-template <int W, int MODE, int ITEMS>
+// RUN: the run of non-branching ops that follows the op (rops[0..rn), generic
+// records rgops) is applied to the kept children before they are written, in
+// place of a separate permutation launch (keys of at most 2 words).  Children
+// keep their positions, so the result equals the two launches bit for bit.
+template <int W, int MODE, int ITEMS, bool RUN>
 __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                  KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
                                                  uint32_t ns, uint64_t cap, GroupOp op, uint64_t* lb,
                                                  DevMeta* meta, uint32_t epoch, uint32_t xo, uint32_t spec_ep,
-                                                 uint32_t f) {
+                                                 uint32_t f, const FastOp* __restrict__ rops, uint32_t rn,
+                                                 const PermOp* __restrict__ rgops) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   __shared__ uint32_t s_wtot[ITEMS][kBlock / 64];
   __shared__ uint64_t s_off;
@@ -1109,11 +1131,14 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
   // group mode: the tile's keys (W words) and amplitudes plus one entry on
-  // each side, for the partner test
-  __shared__ uint64_t s_stage[MODE == MODE_GROUP ? (W + 2) * (TILE + 2) : 1];
+  // each side, for the partner test; with RUN the same space then stages the
+  // run's op records
+  constexpr uint32_t kStageWords = MODE == MODE_GROUP ? (W + 2) * (TILE + 2) : 1;
+  constexpr uint32_t kRunWords = RUN ? kOpChunk * (uint32_t)sizeof(FastOp) / 8 : 1;
+  __shared__ __align__(16) uint64_t s_stage[kStageWords > kRunWords ? kStageWords : kRunWords];
   uint64_t n;
   if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
-  if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) meta->upd += n * op.upd;
+  if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&meta->upd, (unsigned long long)(n * op.upd));
   if (spec_ep != 0 && *reinterpret_cast<volatile unsigned int*>(&meta->spec_irr[spec_ep % kRing]) == 0u) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       const uint64_t m = f * n;
@@ -1148,6 +1173,8 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
         meta->nring[(ns & 1) ^ 1] = ex + tile_total;
         if (ex + tile_total > cap) raise_error(meta, kErrCapacity, epoch);
         else atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
+        // (atomic: workgroup 0 adds the op's own count at the same time)
+        if (RUN) atomicAdd(&meta->upd, (unsigned long long)((ex + tile_total) * rn));
       }
     }
   }
@@ -1161,7 +1188,54 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
   uint64_t pos[ITEMS];
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) pos[it] = s_off + off[it];
-  pair_write<W, ITEMS>(out_keys, out_amp, cap, op, key, out, keepm, pos, orv, andv);
+  if constexpr (RUN) {
+    static_assert(W <= 2, "runs are fused for keys of at most 2 words");
+    // The tile's prefix is published (the look-back above), so later tiles do
+    // not wait for this work.  Pass 0 runs the ops on the lower kept child of
+    // every item, pass 1 on the upper child of items that keep both.
+    const uint32_t tw = op.tword[0];
+    const uint64_t tbit = 1ull << op.tbit[0];
+#pragma nounroll
+    for (uint32_t pass = 0; pass < 2; ++pass) {
+      uint32_t h[ITEMS][4];
+      double2 ca[ITEMS];
+      bool has[ITEMS];
+      bool any = false;
+#pragma unroll
+      for (int it = 0; it < ITEMS; ++it) {
+        const uint32_t km = keepm[it];
+        has[it] = pass == 0 ? km != 0u : km == 3u;
+        const uint32_t r = pass == 0 ? ((km & 1u) ? 0u : 1u) : 1u;
+        h[it][2] = h[it][3] = 0u;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          uint64_t v = key[it][w];
+          if ((uint32_t)w == tw) v = r ? (v | tbit) : (v & ~tbit);
+          h[it][2 * w] = (uint32_t)v;
+          h[it][2 * w + 1] = (uint32_t)(v >> 32);
+        }
+        ca[it] = r ? out[it][1] : out[it][0];
+        any = any || has[it];
+      }
+      if (pass == 1 && !__syncthreads_or(any)) break;
+      run_ops_lds<W, ITEMS>(h, ca, rops, rn, rgops, reinterpret_cast<uint4*>(s_stage));
+#pragma unroll
+      for (int it = 0; it < ITEMS; ++it) {
+        if (!has[it]) continue;
+        const uint64_t p = pos[it] + pass;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const uint64_t v = (uint64_t)h[it][2 * w] | ((uint64_t)h[it][2 * w + 1] << 32);
+          if (p < cap) out_keys.w[w][p] = v;
+          orv[w] |= v;
+          andv[w] &= v;
+        }
+        if (p < cap) out_amp[p] = ca[it];
+      }
+    }
+  } else {
+    pair_write<W, ITEMS>(out_keys, out_amp, cap, op, key, out, keepm, pos, orv, andv);
+  }
   publish_masks<W>(meta, epoch, orv, andv, s_red);
 }
 

@@ -239,6 +239,11 @@ struct ss_state {
   uint64_t speculate = 1ull << 23;
   uint64_t spec_group = 0;       // the same for one-target ops on grouped entries (0: never)
   int chain = 1;                 // option: consecutive one-target ops on one target in one launch
+  // option: a one-target op applies the run that follows it when the run has
+  // at most this many ops (0: never).  A long run is issue-bound and runs
+  // faster in its own launch (8 entries per lane, higher occupancy); a short
+  // one costs little more than a read and a write of the state.
+  uint32_t fuse_runs = 16;
   uint32_t xcd_order = 0;        // 1 when workgroups spread round-robin over 8 XCDs
   int tile_order_opt = 1;        // option: 1 use XCD tickets when possible, 0 one counter
   uint64_t stats[8]{};
@@ -687,8 +692,16 @@ int sort_canonical(ss_state* st) {
 // ---------------------------------------------------------------------------
 // emitting kernels (group / expand / filter): read buf[cur], write buf[cur^1]
 // ---------------------------------------------------------------------------
+// A run of non-branching ops fused into a one-target launch (rn == 0: none).
+struct FusedRun {
+  const FastOp* ops;
+  uint32_t n;
+  const PermOp* gops;
+};
+
 template <int W, int K, int ITEMS>
-void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec) {
+void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec,
+                      const FusedRun& run) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
   const uint32_t ns = st->nslot;
@@ -696,20 +709,33 @@ void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uin
   if (K == 1) {
     // one child per entry in group mode, two in expand mode
     const uint32_t f = mode == MODE_GROUP ? 1u : 2u;
+    if constexpr (W <= 2) {
+      if (run.n) {
+        if (mode == MODE_GROUP)
+          k_pair<W, MODE_GROUP, ITEMS, true><<<ntiles, kBlock, 0, st->stream>>>(
+              kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), 0u, f,
+              run.ops, run.n, run.gops);
+        else
+          k_pair<W, MODE_EXPAND, ITEMS, true><<<ntiles, kBlock, 0, st->stream>>>(
+              kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), 0u, f,
+              run.ops, run.n, run.gops);
+        return;
+      }
+    }
     if (mode == MODE_GROUP) {
       if (ep_spec)
         k_pair_spec<W, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
                                                                              ns, st->cap, g, f, st->meta, ep_spec);
-      k_pair<W, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
-                                                                       ns, st->cap, g, st->lb, st->meta, ep, xo(st),
-                                                                       ep_spec, f);
+      k_pair<W, MODE_GROUP, ITEMS, false><<<ntiles, kBlock, 0, st->stream>>>(
+          kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), ep_spec, f,
+          nullptr, 0u, nullptr);
     } else {
       if (ep_spec)
         k_pair_spec<W, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
                                                                               ns, st->cap, g, f, st->meta, ep_spec);
-      k_pair<W, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
-                                                                        ns, st->cap, g, st->lb, st->meta, ep, xo(st),
-                                                                        ep_spec, f);
+      k_pair<W, MODE_EXPAND, ITEMS, false><<<ntiles, kBlock, 0, st->stream>>>(
+          kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), ep_spec, f,
+          nullptr, 0u, nullptr);
     }
     return;
   }
@@ -724,23 +750,24 @@ void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uin
 // Items per thread: several for one or two targets (bigger tiles, fewer
 // tile-id atomics), one for 8..32-member groups (register budget).
 template <int W, int K>
-void launch_group_wk(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec) {
+void launch_group_wk(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec, const FusedRun& run) {
   const int items = K <= 2 ? st->group_items : 1;
-  if (K <= 2 && items >= 4) launch_group_wki<W, K, (K <= 2 ? 4 : 1)>(st, mode, g, ep, ep_spec);
-  else if (K <= 2 && items == 2) launch_group_wki<W, K, (K <= 2 ? 2 : 1)>(st, mode, g, ep, ep_spec);
-  else launch_group_wki<W, K, 1>(st, mode, g, ep, ep_spec);
+  if (K <= 2 && items >= 4) launch_group_wki<W, K, (K <= 2 ? 4 : 1)>(st, mode, g, ep, ep_spec, run);
+  else if (K <= 2 && items == 2) launch_group_wki<W, K, (K <= 2 ? 2 : 1)>(st, mode, g, ep, ep_spec, run);
+  else launch_group_wki<W, K, 1>(st, mode, g, ep, ep_spec, run);
 }
 
 // ep_spec != 0 (one target only): a speculative fixed-fan-out launch of that
 // epoch runs first.
 template <int W>
-void launch_group_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec) {
+void launch_group_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec, const FusedRun& run) {
+  const FusedRun none{nullptr, 0u, nullptr};
   switch (g.k) {
-    case 1: launch_group_wk<W, 1>(st, mode, g, ep, ep_spec); break;
-    case 2: launch_group_wk<W, 2>(st, mode, g, ep, 0); break;
-    case 3: launch_group_wk<W, 3>(st, mode, g, ep, 0); break;
-    case 4: launch_group_wk<W, 4>(st, mode, g, ep, 0); break;
-    default: launch_group_wk<W, 5>(st, mode, g, ep, 0); break;
+    case 1: launch_group_wk<W, 1>(st, mode, g, ep, ep_spec, run); break;
+    case 2: launch_group_wk<W, 2>(st, mode, g, ep, 0, none); break;
+    case 3: launch_group_wk<W, 3>(st, mode, g, ep, 0, none); break;
+    case 4: launch_group_wk<W, 4>(st, mode, g, ep, 0, none); break;
+    default: launch_group_wk<W, 5>(st, mode, g, ep, 0, none); break;
   }
 }
 
@@ -1191,7 +1218,7 @@ bool chains_with(const ss_op& a, const ss_op& b) {
 // on the same target applied in one launch: each group gets the product of
 // the matrices whose controls hold for it, and the prune follows the last.
 int do_branching(ss_state* st, const ss_op& op, uint64_t op_index, const ss_op* chain_ops = nullptr,
-                 uint32_t nchain = 0) {
+                 uint32_t nchain = 0, const FusedRun& run = FusedRun{nullptr, 0u, nullptr}) {
   set_mark(st, op_index);
   const RegInfo& d = st->L.regs[op.reg];
   std::vector<uint32_t> qs;
@@ -1280,7 +1307,7 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index, const ss_op* 
     // without a child, and the speculative launch would be wasted.
     uint32_t ep_spec = 0, ep;
     int rc = SS_OK;
-    if (g.k == 1 && g.nchain == 0 &&
+    if (g.k == 1 && g.nchain == 0 && run.n == 0 &&
         ((mode == MODE_EXPAND && st->speculate && st->n_ub >= st->speculate) ||
          (mode == MODE_GROUP && st->spec_group && st->n_ub >= st->spec_group)))
       rc = begin_launch(st, &ep_spec);
@@ -1289,9 +1316,9 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index, const ss_op* 
     const uint32_t cat = mode == MODE_GROUP ? SS_TRACE_GROUP : SS_TRACE_EXPAND;
     const int tr = trace_begin(st, cat);
     switch (st->L.W) {
-      case 1: launch_group_w<1>(st, mode, g, ep, ep_spec); break;
-      case 2: launch_group_w<2>(st, mode, g, ep, ep_spec); break;
-      default: launch_group_w<4>(st, mode, g, ep, ep_spec); break;
+      case 1: launch_group_w<1>(st, mode, g, ep, ep_spec, run); break;
+      case 2: launch_group_w<2>(st, mode, g, ep, ep_spec, run); break;
+      default: launch_group_w<4>(st, mode, g, ep, ep_spec, FusedRun{nullptr, 0u, nullptr}); break;
     }
     trace_end(st, tr, entry_bytes(st->L.W), 1, ep, entry_bytes(st->L.W));
     rc = check_launch(st);
@@ -1719,29 +1746,34 @@ int plan_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst
   std::vector<RunChunk> chunks;
   plan_runs(ops, nops, chunks);
   size_t ci = 0, up = 0;
-  // launch the chunks of ops before `upto`; records are encoded and uploaded
-  // a group of chunks (>= kUploadOps ops) at a time, so that the host encodes
-  // while the device runs earlier launches and one copy serves several runs
+  // Records are encoded and uploaded a group of chunks (>= kUploadOps ops) at
+  // a time, when the first of them is needed, so that the host encodes while
+  // the device runs earlier launches and one copy serves several runs.
+  auto ensure_up = [&](size_t c) -> int {
+    if (c < up) return SS_OK;
+    size_t b = c;
+    uint64_t nops_group = 0, bytes = 0;
+    while (b < chunks.size() && (b == c || nops_group < kUploadOps)) {
+      const uint64_t cb = (uint64_t)chunks[b].len * (sizeof(FastOp) + sizeof(PermOp)) + 2 * kAlign;
+      if (b > c && bytes + cb > kOpRingBytes / 2) break;
+      nops_group += chunks[b].len;
+      bytes += cb;
+      ++b;
+    }
+    const int r = upload_chunks(st, ops, chunks, c, b);
+    if (r) return r;
+    up = b;
+    st->ops_keep = st->ops_used;
+    return SS_OK;
+  };
+  // launch the chunks of ops before `upto`
   auto flush = [&](uint64_t upto) -> int {
     for (; ci < chunks.size() && chunks[ci].first < upto; ++ci) {
       if (st->n_ub == 0) continue;
       set_mark(st, chunks[ci].first);
-      if (ci >= up) {
-        size_t b = ci;
-        uint64_t nops_group = 0, bytes = 0;
-        while (b < chunks.size() && (b == ci || nops_group < kUploadOps)) {
-          const uint64_t cb = (uint64_t)chunks[b].len * (sizeof(FastOp) + sizeof(PermOp)) + 2 * kAlign;
-          if (b > ci && bytes + cb > kOpRingBytes / 2) break;
-          nops_group += chunks[b].len;
-          bytes += cb;
-          ++b;
-        }
-        const int r = upload_chunks(st, ops, chunks, ci, b);
-        if (r) return r;
-        up = b;
-        st->ops_keep = st->ops_used;
-      }
-      const int r = launch_chunk(st, chunks[ci]);
+      int r = ensure_up(ci);
+      if (r) return r;
+      r = launch_chunk(st, chunks[ci]);
       if (r) return r;
       if (ci + 1 == up) st->ops_keep = 0;
     }
@@ -1754,7 +1786,26 @@ int plan_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst
       if (st->chain)
         while (j < nops && j - i < (uint64_t)kMaxChain && chains_with(op, ops[j])) ++j;
       rc = flush(i);
-      if (!rc) rc = j - i >= 2 ? do_branching(st, op, i, ops + i, (uint32_t)(j - i)) : do_branching(st, op, i);
+      // a one-target op takes the run that follows it into its own launch
+      FusedRun fr{nullptr, 0u, nullptr};
+      const bool fuse = !rc && st->L.W <= 2 && __builtin_popcountll(op.qmask) == 1 && ci < chunks.size() &&
+                        chunks[ci].first == j && chunks[ci].len <= st->fuse_runs && st->n_ub > 0;
+      if (fuse) {
+        set_mark(st, i);
+        rc = ensure_up(ci);
+        fr = FusedRun{reinterpret_cast<const FastOp*>(chunks[ci].dev), chunks[ci].len,
+                      reinterpret_cast<const PermOp*>(chunks[ci].dev + chunks[ci].fbytes)};
+      }
+      if (!rc) {
+        const uint32_t nch = j - i >= 2 ? (uint32_t)(j - i) : 0u;
+        rc = do_branching(st, op, i, nch ? ops + i : nullptr, nch, fr);
+      }
+      if (!rc && fuse) {
+        // the run went with the op
+        ++ci;
+        if (ci >= up) st->ops_keep = 0;
+        st->stats[5]++;
+      }
       if (rc) {
         if (rc == SS_E_CAPACITY && st->rolled_back) return finish(rc, st->rb_op);
         return finish(rc, i);
@@ -2545,6 +2596,9 @@ int ss_set_option(ss_state* st, const char* key, int64_t value) {
     st->speculate = (uint64_t)value;
   } else if (k == "chain") {
     st->chain = value ? 1 : 0;
+  } else if (k == "fuse_runs") {
+    if (value < 0 || value > (int64_t)kRunChunk) return SS_E_ARG;
+    st->fuse_runs = (uint32_t)value;
   } else if (k == "speculate_group") {
     if (value < 0) return SS_E_ARG;
     st->spec_group = (uint64_t)value;

@@ -479,3 +479,28 @@ def test_op_list_split_over_calls(abi, chunk):
         ok, _, oa = ora.export()
         compare(gk, ga, ok, oa, c.eps)
         st.close()
+
+
+@pytest.mark.parametrize("items", [1, 2, 4])
+def test_fused_runs_bit_identical(abi, items):
+    """A one-target op that takes the following run of non-branching ops into
+    its launch writes the same entries at the same positions as the two
+    launches: keys and amplitudes bit for bit, and equal to the oracle.  Runs
+    with every op kind (QRAM, phase) on 1- and 2-word keys, expansions and
+    groups, chains and singletons."""
+    kinds = ("X", "H", "RY", "ADD", "SUB", "MULC", "XOR", "XORC", "QRAM_LOAD", "QRAM_UNLOAD", "REFLECT0")
+    circs = [wl.random_small_circuit(70 + s, kinds=kinds, nops=120, with_init=bool(s % 2)) for s in range(3)]
+    circs += [wl.c1_circuit(21), wl.c2_circuit(22, nops=200, n_ry=5, h_qubits=12)]
+    for c in circs:
+        print(f"[case] {c.name} fused runs, group_items {items}", flush=True)
+        outs = []
+        for fuse in (4096, 0):        # fuse every run / none
+            st = _gpu(abi, c, opts={"fuse_runs": fuse, "group_items": items})
+            outs.append(st.export())
+            st.close()
+        (k1, a1), (k0, a0) = outs
+        assert np.array_equal(k1, k0)
+        assert np.array_equal(a1.view(np.uint64), a0.view(np.uint64))
+        ora, _, _ = run_circuit(c)
+        ok, _, oa = ora.export()
+        compare(k1, a1, ok, oa, c.eps)
