@@ -103,8 +103,9 @@ def summarize_profile(pdir):
         af, aw = sum(fv) / len(fv), sum(wv) / len(wv)
         lines.append(f"{k[:50]:50s} {len(fv):4d} {af:11.1f} {aw:11.1f} {(af * fs + aw * ws) * 1024 / 1e6:10.2f}")
     lines.append("")
-    for label in ("k_perm_fast<2, 8, false>", "k_perm_fast<2, 4, false>", "k_pair<2, 0, 4>", "k_pair<2, 1, 4>",
-                  "k_pair<2, 0, 2>", "k_pair<2, 1, 2>", "k_group<2, 5, 1, 1>"):
+    for label in ("k_perm_fast<2, 8, false>", "k_perm_fast<2, 4, false>", "k_pair<2, 0, 4, false>",
+                  "k_pair<2, 1, 4, false>", "k_pair<2, 1, 4, true>", "k_pair<2, 0, 2, false>",
+                  "k_pair<2, 1, 2, false>", "k_group<2, 5, 1, 1>"):
         pk = "void sparqs::" + label
         if pk not in fe or pk not in wr:
             continue
@@ -664,8 +665,8 @@ def main():
     achieved = d["bytes"] / d["seconds"] / 1e9
     # the kernel behind each category at this configuration (W = 2 keys)
     label = {"perm": "k_perm_fast<2, %d, false>" % args.perm_entries,
-             "group": "k_pair<2, 0, %d>" % args.group_items,
-             "expand": "k_pair<2, 1, %d>" % args.group_items}.get(dom)
+             "group": "k_pair<2, 0, %d, false>" % args.group_items,
+             "expand": "k_pair<2, 1, %d, false>" % args.group_items}.get(dom)
     traffic = counter_traffic(label)
     gpu_kernel_ms = sum(k["ms_per_step"] for k in kernels.values())
 

@@ -10,7 +10,9 @@ computes:
 Because each option touches only its own category, the search is coordinate-wise:
 for one option at a time, every value is tried with the others held at their
 current best. It is scored by the HIP-event time of that option's categories over
-a caller-supplied workload (``run(state)``), taking the median of a few trials.
+a caller-supplied workload (``run(state)``), taking the median of a few trials;
+a value replaces the current one only when it is faster by more than a margin
+(5 %), so that run-to-run noise does not move the choice.
 Results are cached in a JSON file keyed by (GPU arch, key words, log2 of the
 entry count, batched or plain), so a later state of the same shape starts from
 the tuned values (``Tuner.apply``).
@@ -55,9 +57,12 @@ def bucket_key(arch: str, key_words: int, nnz: int, batched: bool) -> str:
 
 
 class Tuner:
-    def __init__(self, path: Optional[str] = None, trials: int = 3):
+    def __init__(self, path: Optional[str] = None, trials: int = 3, margin: float = 0.05):
         self.path = path or default_cache_path()
         self.trials = int(trials)
+        # a value replaces the current one only when faster by more than this
+        # fraction: run-to-run noise then leaves the choice where it was
+        self.margin = float(margin)
         self.cache: Dict[str, Dict[str, int]] = {}
         if os.path.exists(self.path):
             with open(self.path) as f:
@@ -146,7 +151,9 @@ class Tuner:
             if all(t == 0.0 for t in res.values()):
                 state.set_option(opt, best[opt])
                 continue
-            best[opt] = min(values, key=lambda x: (res[x], x != best[opt]))
+            cand = min(values, key=lambda x: (res[x], x != best[opt]))
+            if best[opt] not in res or res[cand] < res[best[opt]] * (1.0 - self.margin):
+                best[opt] = cand
             state.set_option(opt, best[opt])
         self.cache[key] = dict(best)
         self.last_scores = scores

@@ -91,3 +91,12 @@ def test_corrupt_or_foreign_entries_are_ignored(tmp_path):
     path.write_text(json.dumps({"k": {"perm_entries": 5, "group_items": 2, "bogus": 1}}))
     t = tune.Tuner(str(path))
     assert t.cache == {"k": {"group_items": 2}}
+
+
+def test_margin_keeps_current_value_unless_clearly_faster(tmp_path):
+    t = tune.Tuner(str(tmp_path / "c.json"), trials=1, margin=0.05)
+    # 4 entries 3 % faster than the default 8: kept; 16 entries 10 % faster: taken
+    st = FakeState(perm_cost={4: 0.97, 8: 1.0, 16: 1.5})
+    assert t.tune(st, st.run, "gfx950/W2/n21/plain")["perm_entries"] == 8
+    st = FakeState(perm_cost={4: 1.2, 8: 1.0, 16: 0.9})
+    assert t.tune(st, st.run, "gfx950/W2/n22/plain")["perm_entries"] == 16
