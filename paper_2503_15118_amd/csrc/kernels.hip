@@ -560,7 +560,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(KeyPtrs<W> in_keys, const 
   __shared__ uint32_t s_toff[kRadix];
   __shared__ uint64_t s_gbase[kRadix];
   __shared__ uint8_t s_digit[TILE];
-  __shared__ uint64_t s_stage[TILE];
+  __shared__ __align__(16) uint64_t s_stage[TILE];
   __shared__ uint64_t s_scan[4];
   __shared__ uint32_t s_tile;
 
@@ -654,29 +654,25 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(KeyPtrs<W> in_keys, const 
     const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
     av[i] = le < tile_n ? in_amp[base + le] : make_double2(0.0, 0.0);
   }
-  double im_part[ITEMS];
+  // Amplitudes go out as whole 16-byte values (two 8-byte passes would write
+  // every output line in two halves at different times), staged half a tile
+  // at a time in the same LDS.
+  double2* s_amp = reinterpret_cast<double2*>(s_stage);
+  constexpr uint32_t HALF = TILE / 2;
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
-    if (le < tile_n) s_stage[pos[i]] = __double_as_longlong(av[i].x);
-    im_part[i] = av[i].y;
-  }
-  __syncthreads();
-  double* out_d = reinterpret_cast<double*>(out_amp);
-  for (uint32_t j = tid; j < tile_n; j += kBlock) {
-    const uint64_t dst = s_gbase[s_digit[j]] + j;
-    if (dst < n) out_d[2 * dst] = __longlong_as_double(s_stage[j]);
-  }
-  __syncthreads();
+  for (uint32_t h0 = 0; h0 < (uint32_t)TILE; h0 += HALF) {
+    if (h0) __syncthreads();
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
-    if (le < tile_n) s_stage[pos[i]] = __double_as_longlong(im_part[i]);
-  }
-  __syncthreads();
-  for (uint32_t j = tid; j < tile_n; j += kBlock) {
-    const uint64_t dst = s_gbase[s_digit[j]] + j;
-    if (dst < n) out_d[2 * dst + 1] = __longlong_as_double(s_stage[j]);
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t le = wave * (ITEMS * 64) + i * 64 + lane;
+      if (le < tile_n && pos[i] >= h0 && pos[i] < h0 + HALF) s_amp[pos[i] - h0] = av[i];
+    }
+    __syncthreads();
+    const uint32_t hn = tile_n > h0 ? min(HALF, tile_n - h0) : 0u;
+    for (uint32_t j = tid; j < hn; j += kBlock) {
+      const uint64_t dst = s_gbase[s_digit[h0 + j]] + h0 + j;
+      if (dst < n) out_amp[dst] = s_amp[j];
+    }
   }
 }
 
