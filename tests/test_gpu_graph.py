@@ -162,3 +162,26 @@ def test_graph_outliving_state_is_refused(abi):
     res = g.launch(raise_on_error=False)
     assert res.status == abi.SS_E_STATE
     g.close()
+
+
+def test_capture_empty_state_and_rebind_refused(abi):
+    """An empty state captures a graph that does nothing and replays cleanly;
+    a graph of a state that moved to another arena is refused."""
+    c = wl.random_small_circuit(9, nops=40, with_init=True)
+    ops = abi.to_ss_ops(c.ops)
+    st = abi.state_for_circuit(c)
+    st.set_entries(0, np.zeros((0, len(c.regs)), dtype=np.uint64), np.zeros(0, dtype=np.complex128))
+    g = st.capture(ops)
+    assert st.nnz() == 0
+    assert g.launch().status == 0 and st.nnz() == 0
+    g.close()
+    v, a = _init(c)
+    st.set_entries(0, v, a)
+    g = st.capture(ops)
+    want = st.export()
+    st.rebind(st.capacity * 2)
+    res = g.launch(raise_on_error=False)
+    assert res.status == abi.SS_E_ARG
+    _same(st.export(), want)              # the refused launch changed nothing
+    g.close()
+    st.close()

@@ -504,3 +504,43 @@ def test_fused_runs_bit_identical(abi, items):
         ora, _, _ = run_circuit(c)
         ok, _, oa = ora.export()
         compare(k1, a1, ok, oa, c.eps)
+
+
+@pytest.mark.parametrize("form", ["chain", "fused"])
+def test_capacity_failure_in_chain_or_fused_run(abi, form):
+    """Capacity failure in a launch that carries a chain of one-target ops, or
+    a one-target op with its following run: the state returns to the first
+    op of the launch, failed_op names it, and resuming in a larger arena gives
+    the oracle's result."""
+    regs = [("a", 7 if form == "chain" else 8), ("b", 6), ("f", 1)]
+    mk = wl.make_op
+    if form == "chain":
+        tail = [mk("RY", 1, qmask=1 << q, theta=0.3 + 0.2 * q) for q in range(3)]   # not a chain: targets differ
+        body = [mk("RY", 2, qmask=1, theta=0.9), mk("RY", 2, qmask=1, theta=-0.4, ctls=[(0, 2, 1)]),
+                mk("H", 2, qmask=1, ctls=[(0, 5, 0)])]
+    else:
+        tail = []
+        body = [mk("RY", 2, qmask=1, theta=0.9), mk("ADD", 1, reg2=0), mk("XORC", 0, imm=0x2B),
+                mk("X", 1, qmask=3, ctls=[(2, 0, 1)])]
+    ops = wl.ops_array([mk("H", 0, qmask=(1 << regs[0][1]) - 1)] + tail + body + [mk("H", 0, qmask=0x01)])
+    c = wl.Circuit(name=f"cap-{form}", regs=regs, ops=ops, eps=1e-14)
+    print(f"[case] capacity failure in a {form} launch", flush=True)
+    first = 1 + len(tail)                                  # index of the launch's first op
+    st = abi.State(regs, eps=c.eps, cap_entries=1024 if form == "chain" else 256, table_bytes=0)
+    n_before = 1024 if form == "chain" else 256
+    assert st.capacity < 2 * n_before
+    res = st.apply(ops, raise_on_error=False)
+    assert res.status == abi.SS_E_CAPACITY and res.failed_op == first, (res.status, res.failed_op)
+    gk, ga = st.export()
+    ora, _, _ = run_circuit(c, ops=ops[:first])
+    ok, _, oa = ora.export()
+    s = compare(gk, ga, ok, oa, c.eps)
+    assert s["n_gpu"] == n_before
+    st.rebind(1 << 14)
+    res = st.apply(ops[first:], raise_on_error=False)
+    assert res.status == 0, abi.strerror(res.status)
+    gk, ga = st.export()
+    ora, _, _ = run_circuit(c)
+    ok, _, oa = ora.export()
+    compare(gk, ga, ok, oa, c.eps)
+    st.close()
