@@ -438,6 +438,24 @@ def bench_m7(args):
     print(json.dumps({"workload": "paper benchmark stand-ins (GHZ, QRAM, swap test)", "rows": rows}), flush=True)
 
 
+def _same_state(k1, a1, k0, a0, eps):
+    """(within the comparison rule, bit-identical, max amplitude error) for two
+    exports in ascending key order: keys with |a| > eps + 1e-9 on either side
+    must appear on both; shared keys' amplitudes within 1e-12."""
+    import numpy as np
+    if len(k1) == len(k0) and np.array_equal(k1, k0):
+        err = float(np.max(np.abs(a1 - a0))) if len(a1) else 0.0
+        return err <= 1e-12, bool(np.array_equal(a1.view(np.uint64), a0.view(np.uint64))), err
+    band = eps + 1e-9
+    s1 = {tuple(int(x) for x in k): a for k, a in zip(k1, a1)}
+    s0 = {tuple(int(x) for x in k): a for k, a in zip(k0, a0)}
+    ok = all(k in s0 for k, a in s1.items() if abs(a) > band) and \
+        all(k in s1 for k, a in s0.items() if abs(a) > band)
+    shared = [k for k in s1 if k in s0]
+    err = max((abs(s1[k] - s0[k]) for k in shared), default=0.0)
+    return bool(ok and err <= 1e-12), False, float(err)
+
+
 def bench_serving(args):
     """Serving: a Poisson request stream mixing the four workload forms, served
     with footprint admission and continuous batching, against the same trace
@@ -463,8 +481,23 @@ def bench_serving(args):
         r.arrival = 0.0
     serve.Server(ex, budget_bytes=budget, max_active=4, chunk_ops=args.chunk_ops).run(warm)
     srv = serve.Server(ex, budget_bytes=budget, max_active=args.slots, chunk_ops=args.chunk_ops)
-    m = srv.run(reqs())
-    seq = serve.plain_sequential(reqs(), ex)
+    served = reqs()
+    m = srv.run(served)
+    seq_reqs = reqs()
+    seq = serve.plain_sequential(seq_reqs, ex)
+    # the first 50 requests: result in the mix against the same request served
+    # alone (keys exactly equal outside the prune band, amplitudes within 1e-12)
+    checked = within = ident = 0
+    worst = 0.0
+    alone = {r.rid: r for r in seq_reqs}
+    for r in sorted((x for x in served if x.error is None), key=lambda x: x.rid)[:50]:
+        checked += 1
+        ok_all, id_all = True, True
+        for inst, ((gk, ga), (ak, aa)) in enumerate(zip(r.result, alone[r.rid].result)):
+            ok, ident_i, err = _same_state(gk, ga, ak, aa, r.circuits[inst].eps)
+            ok_all, id_all, worst = ok_all and ok, id_all and ident_i, max(worst, err)
+        within += int(ok_all)
+        ident += int(id_all)
     kinds = {}
     for t in tr:
         kinds[t.kind] = kinds.get(t.kind, 0) + 1
@@ -478,6 +511,8 @@ def bench_serving(args):
         "p99_vs_plain": seq["p99_s"] / m["p99_s"],
         "throughput_vs_plain": m["entries_per_s"] / seq["entries_per_s"],
         "slots": args.slots, "budget_bytes": budget, "generation_s": gen_s,
+        "mix_vs_alone": {"checked": checked, "within_rule": within, "bit_identical": ident,
+                         "max_abs_amp_err": worst},
     }
     print(json.dumps(out), flush=True)
 
