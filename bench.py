@@ -141,13 +141,19 @@ def bench_batched(args):
     [2^6, 2^18], 200..1000 ops each) in one state, against the same instances
     run one at a time through the plain path on the same GPU."""
     import numpy as np
-    import torch
     import workloads as wl
-    from paper_2503_15118_amd import _abi, batch
 
     t0 = time.perf_counter()
     circ = wl.c3_batch(args.seed, ninst=args.ninst)
     gen_s = time.perf_counter() - t0
+    # the oracle first: its worker processes fork before the GPU library loads
+    cpu = None
+    if not args.no_cpu_baseline:
+        import dataclasses
+        cpu = oracle_pool([dataclasses.replace(c, ops=c.ops[:150]) for c in circ[:16]],
+                          "the first 150 ops of the first 16 instances of the batch")
+    import torch
+    from paper_2503_15118_amd import _abi, batch
     ops, off = batch.concat_ops(circ)
     # plain path, one instance at a time (apply calls timed)
     st = _abi.State(circ[0].regs, eps=circ[0].eps, cap_entries=1 << 20, table_bytes=0)
@@ -203,7 +209,33 @@ def bench_batched(args):
                     for k, v in tr.items() if v["launches"]},
         "generation_s": gen_s,
     }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
+
+
+def _oracle_run(c):
+    from oracle.oracle import OracleState
+    o = OracleState.from_circuit(c)
+    sec, ent = o.apply(c.ops)
+    return sec, ent
+
+
+def oracle_pool(circuits, what):
+    """The oracle over host cores (one instance per process, forked before the
+    GPU is touched): entries/s over the makespan, and per core."""
+    import multiprocessing as mp
+    workers = max(1, min(16, len(os.sched_getaffinity(0)), len(circuits)))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_run, circuits, chunksize=1)
+    wall = time.perf_counter() - t0
+    sec = sum(r[0] for r in res)
+    ent = sum(r[1] for r in res)
+    return {"value": ent / wall, "unit": "entries/s", "cores": workers, "kind": "oracle",
+            "single_core_entries_per_s": ent / sec if sec > 0 else None,
+            "sample": f"{what}: {len(circuits)} instances over {workers} processes, {ent} entry updates, "
+                      f"makespan {wall:.2f} s, single-core sum {sec:.2f} s"}
 
 
 def _kernel_table(tr, steps=1):
@@ -266,8 +298,14 @@ def bench_c4(args):
     """The linear-solver walk: 64 right-hand sides as instances of one state
     (52-bit key), each step QRAM load, 16 controlled Ry, unload, reflection."""
     import numpy as np
-    import torch
     import workloads as wl
+
+    # the oracle first: its worker processes fork before the GPU library loads
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = oracle_pool(wl.c4_batch(args.seed, nrhs=8, steps=20),
+                          "8 right-hand sides of the same matrix, 20 walk steps")
+    import torch
     from paper_2503_15118_amd import _abi
 
     circ = wl.c4_batch(args.seed, nrhs=args.nrhs, steps=args.c4_steps)
@@ -309,6 +347,8 @@ def bench_c4(args):
            "entries_per_s": ent / float(np.median(times)), "nnz_final": st.nnz(),
            "kernels": kernels, "dominant": dom,
            "dominant_frac_of_8TBps": kernels[dom]["GBps"] / HBM_PEAK_GBS if kernels[dom]["GBps"] else None}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 
