@@ -386,8 +386,10 @@ def bench_m6(args):
                 st.set_option("grouping", 1)
         st.set_option("trace", 0)
 
+    sizes = ([int(x) for x in args.m6_sizes.split(",")] if args.m6_sizes
+             else list(range(args.m6_min_log2, args.m6_max_log2 + 1, 3)))
     for W, regs in layouts.items():
-        for lg in range(args.m6_min_log2, args.m6_max_log2 + 1, 3):
+        for lg in sizes:
             n = 1 << lg
             w0, w1 = regs[0][1], regs[1][1]
             tb = (1 << 22) + 4096 if W == 1 else 4096
@@ -425,8 +427,31 @@ def bench_m6(args):
             run(st, [h], reps=1, grouping_first=0)
             trace_rows(st, W, lg + 1, "sort", ["sort_hist", "sort_pass", "group"])
             st.close()
+    # QRAM gathers from tables of 2^A 32-bit words at random addresses
+    # (2^24 entries; bytes counted: key read and write, not the gathered word)
+    for A in ([int(x) for x in args.m6_qram_bits.split(",")] if args.m6_qram_bits else []):
+        n = 1 << 24
+        # data in the low 32 bits, the address above it: both fields inside one
+        # 32-bit half of the key, the interpreter's gather case
+        regs = [("data", 32), ("addr", A)]
+        st = _abi.State(regs, eps=1e-14, cap_entries=2 * n, table_bytes=(4 << A) + 4096)
+        st.load_qram(wl.Table(values=rng.integers(0, 2 ** 32, size=2 ** A, dtype=np.uint64),
+                              addr_bits=A, word_bits=32))
+        v = np.unique(rng.integers(0, np.uint64(2 ** (A + 32) - 1), size=int(n * 1.1) + 16,
+                                   dtype=np.uint64))[:n]
+        rng.shuffle(v)
+        vals = np.zeros((len(v), 2), dtype=np.uint64)
+        vals[:, 0] = v & np.uint64(0xFFFFFFFF)
+        vals[:, 1] = v >> np.uint64(32)
+        st.set_entries(0, vals, np.full(len(v), 1.0 / np.sqrt(len(v)), dtype=np.complex128))
+        op = wl.make_op("QRAM_LOAD", 0, reg2=1, table=0)
+        run(st, [op], reps=1)
+        run(st, [op])
+        trace_rows(st, 1, 24, f"QRAM table 2^{A}", ["perm"])
+        st.close()
     print(json.dumps({"workload": "roofline sweep: one op per launch on random distinct keys "
-                                  "(W=1: a:20 b:20 t:1; W=2: a,b,c:32 t:1)", "rows": rows}), flush=True)
+                                  "(W=1: a:20 b:20 t:1; W=2: a,b,c:32 t:1; QRAM: data:32 addr:A)",
+                      "rows": rows}), flush=True)
 
 
 def bench_m7(args):
@@ -585,6 +610,8 @@ def main():
     ap.add_argument("--c4-trials", type=int, default=3)
     ap.add_argument("--m6-min-log2", type=int, default=16)
     ap.add_argument("--m6-max-log2", type=int, default=25)
+    ap.add_argument("--m6-sizes", default=None, help="comma-separated log2 sizes (overrides min/max)")
+    ap.add_argument("--m6-qram-bits", default="16,20,24,28", help="QRAM table address widths to sweep ('' = none)")
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--duration", type=float, default=2.0)
     ap.add_argument("--serve-hi-bits", type=float, default=24.0)
