@@ -486,11 +486,14 @@ __device__ __forceinline__ uint32_t digit_of(const uint64_t (&k)[W], const PassD
 // loads issued together.  Keys are often nearly sorted, so a wave whose lanes
 // all carry the same digit adds its count with one LDS atomic.
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_sort_hist(KeyPtrs<W> keys, uint64_t n, SortPlan plan,
-                                                      uint32_t* __restrict__ partial) {
+__global__ __launch_bounds__(kBlock) void k_sort_hist(KeyPtrs<W> keys, uint32_t ns, const DevMeta* meta,
+                                                      SortPlan plan, uint32_t* __restrict__ partial) {
   constexpr int U = 4;
   extern __shared__ uint32_t s_h[];  // npass * 256
   const uint32_t np = plan.npass;
+  // the entry count of slot ns (the grid comes from an upper bound; every
+  // workgroup writes its partial histograms, empty ones included)
+  const uint64_t n = meta->nring[ns & 1];
   for (uint32_t i = threadIdx.x; i < np * kRadix; i += kBlock) s_h[i] = 0;
   __syncthreads();
   const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
@@ -552,7 +555,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scan(const uint32_t* __restrict
 template <int W, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_sort_pass(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                       KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
-                                                      uint64_t n, PassDesc pd,
+                                                      uint32_t ns, PassDesc pd,
                                                       const uint64_t* __restrict__ digit_start,
                                                       uint64_t* lb, DevMeta* meta, uint32_t epoch, uint32_t xo) {
   constexpr int TILE = kBlock * ITEMS;
@@ -566,6 +569,12 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(KeyPtrs<W> in_keys, const 
 
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   if (launch_prologue(meta, epoch)) return;
+  // The count is read on the device (a sort does not change it) and the grid
+  // comes from an upper bound: workgroups past the count's tiles leave before
+  // taking a tile ticket, so the tickets cover exactly the count's tiles.
+  const uint64_t n = meta->nring[ns & 1];
+  if (blockIdx.x == 0 && tid == 0 && (uint64_t)gridDim.x * TILE < n) raise_error(meta, kErrGrid, epoch);
+  if ((uint64_t)blockIdx.x * TILE >= n) return;
 #pragma unroll
   for (int w = 0; w < kBlock / 64; ++w) s_wcount[w][tid] = 0;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);

@@ -31,6 +31,7 @@ constexpr uint32_t kMaxOpsPerCall = 16384;  // device op ring, in PermOp records
 constexpr uint64_t kOpRingBytes = (uint64_t)kMaxOpsPerCall * sizeof(PermOp);
 constexpr uint32_t kRunChunk = 4096;        // ops per fused launch
 constexpr uint64_t kUploadOps = 256;        // non-branching ops whose records one copy uploads
+constexpr uint64_t kSmallSort = 1ull << 16; // at most this many entries: sort plans from the host superset
 constexpr uint32_t kHistBlocksMax = 1024;
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
@@ -629,15 +630,16 @@ void build_plan(uint32_t W, const std::vector<std::pair<uint32_t, uint32_t>>& lo
 
 template <int W>
 int run_sort_w(ss_state* st, const SortPlan& plan) {
-  const uint64_t n = st->n;
+  // the kernels read the count on the device; grids come from the host's bound
+  const uint64_t n = st->n_known ? st->n : st->n_ub;
   if (plan.npass == 0 || n <= 1) return SS_OK;
   if (plan.npass > max_passes(W)) return hip_fail(st);  // the histogram area is sized for this
   const int items = (W == 4) ? 8 : st->sort_items;
   const uint64_t tile = (uint64_t)kBlock * items;
   const uint32_t nb = (uint32_t)std::min<uint64_t>(st->cv.hist_blocks, (n + 4095) / 4096);
   int tr = trace_begin(st, SS_TRACE_SORT_HIST);
-  k_sort_hist<W><<<nb, kBlock, plan.npass * kRadix * 4, st->stream>>>(kp<W>(st->buf[st->cur]), n, plan,
-                                                                       st->hist);
+  k_sort_hist<W><<<nb, kBlock, plan.npass * kRadix * 4, st->stream>>>(kp<W>(st->buf[st->cur]), st->nslot,
+                                                                       st->meta, plan, st->hist);
   k_sort_scan<<<plan.npass, kBlock, 0, st->stream>>>(st->hist, nb, plan.npass, st->digit_start);
   trace_end(st, tr, 8ull * W, 1, 0, 0);
   st->stats[0] += 2;
@@ -650,11 +652,11 @@ int run_sort_w(ss_state* st, const SortPlan& plan) {
     const Buf& out = st->buf[st->cur ^ 1];
     tr = trace_begin(st, SS_TRACE_SORT_PASS);
     if (items == 16)
-      k_sort_pass<W, 16><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, n,
+      k_sort_pass<W, 16><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
                                                              plan.pass[p], st->digit_start + p * kRadix,
                                                              st->lb, st->meta, ep, xo(st));
     else
-      k_sort_pass<W, 8><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, n,
+      k_sort_pass<W, 8><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
                                                             plan.pass[p], st->digit_start + p * kRadix,
                                                             st->lb, st->meta, ep, xo(st));
     trace_end(st, tr, 2 * entry_bytes(W), 1, 0, 0);
@@ -667,10 +669,8 @@ int run_sort_w(ss_state* st, const SortPlan& plan) {
   return check_launch(st);
 }
 
-// LSD sort of the current entries; needs the exact count.
+// LSD sort of the current entries (count read on the device).
 int run_sort(ss_state* st, const SortPlan& plan) {
-  int rc = ensure_n(st);
-  if (rc) return rc;
   switch (st->L.W) {
     case 1: return run_sort_w<1>(st, plan);
     case 2: return run_sort_w<2>(st, plan);
@@ -1281,6 +1281,17 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index, const ss_op* 
     } else if (sup_const) {
       // no target bit can vary: every group has one member
       mode = MODE_EXPAND;
+    } else if (!st->masks_valid && st->sup_valid && st->n_ub <= kSmallSort) {
+      // a small state sorts on the bits that may vary rather than wait for
+      // the exact masks (an extra radix pass costs less than a read-back);
+      // group mode also handles the groups that have one member
+      uint64_t var[kMaxW];
+      for (int w = 0; w < kMaxW; ++w) var[w] = st->sorm[w] & ~st->sandm[w];
+      SortPlan plan;
+      build_plan(st->L.W, tl, g.tmask, var, plan);
+      int rc = run_sort(st, plan);
+      if (rc) return rc;
+      mode = MODE_GROUP;
     } else {
       int rc = ensure_masks(st);
       if (rc) return rc;
