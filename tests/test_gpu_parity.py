@@ -544,3 +544,58 @@ def test_capacity_failure_in_chain_or_fused_run(abi, form):
     ok, _, oa = ora.export()
     compare(gk, ga, ok, oa, c.eps)
     st.close()
+
+
+def test_c4_full_size_closed_form(abi):
+    """The linear-solver walk at its full size (64 right-hand sides, 1024 rows
+    x 8 slots, 200 steps, the bench's launch configuration: chained walk steps
+    and fused runs) against its closed form for every entry: instance r, row
+    rho, slot s, ancilla a has amplitude b_r[rho] c^3 [(R Ry(theta))^200 e0]_a,
+    with theta = pi q16 / 2^15 from the table word and R = diag(i, -i)."""
+    circ = wl.c4_batch(0, nrhs=64, steps=200)
+    c0 = circ[0]
+    print(f"[case] C4 full size: {len(circ)} right-hand sides, {len(c0.ops)} ops", flush=True)
+    st = abi.State(c0.regs, ninst=len(circ), eps=c0.eps, cap_entries=1 << 22, table_bytes=1 << 16)
+    st.load_qram(c0.tables[0])
+    for i, c in enumerate(circ):
+        st.set_entries(i, c.init_values, c.init_amps)
+    st.apply(c0.ops)
+    words = c0.tables[0].values.astype(np.int64)
+    q = (words >> 16) & 0xFFFF
+    q = np.where(q >= 0x8000, q - 0x10000, q).astype(np.float64)
+    th = np.pi * q / 2.0 ** 15
+    cth, sth = np.cos(th / 2), np.sin(th / 2)
+    ry = np.stack([np.stack([cth, -sth], -1), np.stack([sth, cth], -1)], -2).astype(np.complex128)
+    R = np.diag([1j, -1j])
+    v = np.linalg.matrix_power(R @ ry, 200)[:, :, 0]          # (8192, 2): column e0
+    addr = np.arange(8192, dtype=np.uint64)
+    keys = np.concatenate([(addr << np.uint64(32)), (addr << np.uint64(32)) | np.uint64(1 << 45)])
+    order = np.argsort(keys)
+    for i in (0, 1, 31, 63):
+        b = circ[i].init_amps
+        amp = np.concatenate([b[addr >> np.uint64(3)] * C ** 3 * v[:, 0], b[addr >> np.uint64(3)] * C ** 3 * v[:, 1]])
+        gk, ga = st.export(i)
+        compare(gk, ga, keys[order].reshape(-1, 1), amp[order], c0.eps)
+    assert st.nnz() <= 64 * 2 ** 14
+    st.close()
+
+
+def test_c3_full_size_sampled(abi):
+    """The batching workload at its full size (1024 instances, caps 2^6..2^18, capacity 2^28 entries)
+    in the bench's configuration: every instance keeps norm 1, and the three
+    smallest instances equal the oracle entry by entry."""
+    from paper_2503_15118_amd import batch
+    circ = wl.c3_batch(0, ninst=1024)
+    print(f"[case] C3 full size: {len(circ)} instances", flush=True)
+    st, res = batch.run_batched(circ, cap_entries=1 << 28, table_bytes=0)
+    assert res.status == 0
+    small = sorted(range(len(circ)), key=lambda i: (circ[i].cap_bits, i))[:3]
+    for i in range(len(circ)):
+        gk, ga = st.export(i)
+        norm = float(np.sum(ga.real ** 2 + ga.imag ** 2))
+        assert abs(norm - 1.0) < 1e-9, (i, norm)
+        if i in small:
+            ora, _, _ = run_circuit(circ[i])
+            ok, _, oa = ora.export()
+            compare(gk, ga, ok, oa, circ[i].eps)
+    st.close()
