@@ -103,9 +103,10 @@ def summarize_profile(pdir):
         af, aw = sum(fv) / len(fv), sum(wv) / len(wv)
         lines.append(f"{k[:50]:50s} {len(fv):4d} {af:11.1f} {aw:11.1f} {(af * fs + aw * ws) * 1024 / 1e6:10.2f}")
     lines.append("")
-    for label in ("k_perm_fast<2, 8, false>", "k_perm_fast<2, 4, false>", "k_pair<2, 0, 4, false>",
-                  "k_pair<2, 1, 4, false>", "k_pair<2, 1, 4, true>", "k_pair<2, 0, 2, false>",
-                  "k_pair<2, 1, 2, false>", "k_group<2, 5, 1, 1>"):
+    for label in ("k_perm_fast<2, 8, false>", "k_perm_fast<2, 4, false>", "k_perm_fast<2, 16, false>",
+                  "k_pair<2, 0, 4, false>", "k_pair<2, 1, 4, false>", "k_pair<2, 1, 4, true>",
+                  "k_pair<2, 0, 2, false>", "k_pair<2, 1, 2, false>", "k_pair_spec<2, 0, 1, false>",
+                  "k_pair_spec<2, 0, 2, false>", "k_pair_spec<2, 0, 4, false>", "k_group<2, 5, 1, 1>"):
         pk = "void sparqs::" + label
         if pk not in fe or pk not in wr:
             continue
@@ -594,6 +595,7 @@ def main():
     ap.add_argument("--group-items", type=int, default=4)
     ap.add_argument("--sort-items", type=int, default=16)
     ap.add_argument("--perm-entries", type=int, default=8)
+    ap.add_argument("--spec-items", type=int, default=2)
     ap.add_argument("--tile-order", type=int, default=1)
     ap.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
                     help="extra ss_set_option on the state (c2, c4)")
@@ -670,6 +672,7 @@ def main():
     st.set_option("group_items", args.group_items)
     st.set_option("sort_items", args.sort_items)
     st.set_option("perm_entries", args.perm_entries)
+    st.set_option("spec_items", args.spec_items)
     st.set_option("tile_order", args.tile_order)
     set_opts(st, args.opt)
     zero = np.zeros((1, len(circ.regs)), dtype=np.uint64)
@@ -695,6 +698,7 @@ def main():
         args.group_items = tuned["group_items"]
         args.sort_items = tuned["sort_items"]
         args.perm_entries = tuned["perm_entries"]
+        args.spec_items = tuned["spec_items"]
 
     for _ in range(args.warmup):
         step()
@@ -765,9 +769,16 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     d = tr[dom]
     achieved = d["bytes"] / d["seconds"] / 1e9
-    # the kernel behind each category at this configuration (W = 2 keys)
+    # the kernel behind each category at this configuration (W = 2 keys); the
+    # Ry ops on grouped entries (2^21) take the speculative fixed placement
+    # unless it is switched off, and the compacting launch after it then only
+    # records the count
+    spec_group = dict((kv.split("=", 1)[0], int(kv.split("=", 1)[1])) for kv in args.opt).get(
+        "speculate_group", 1 << 21)
+    group_label = ("k_pair_spec<2, 0, %d, false>" % args.spec_items if 0 < spec_group <= 1 << 21
+                   else "k_pair<2, 0, %d, false>" % args.group_items)
     label = {"perm": "k_perm_fast<2, %d, false>" % args.perm_entries,
-             "group": "k_pair<2, 0, %d, false>" % args.group_items,
+             "group": group_label,
              "expand": "k_pair<2, 1, %d, false>" % args.group_items}.get(dom)
     traffic = counter_traffic(label)
     gpu_kernel_ms = sum(k["ms_per_step"] for k in kernels.values())
@@ -796,6 +807,7 @@ def main():
             "group_items": args.group_items,
             "sort_items": args.sort_items,
             "perm_entries": args.perm_entries,
+            "spec_items": args.spec_items,
             "tile_order": args.tile_order,
             "autotuned": tuned is not None,
         },

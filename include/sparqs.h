@@ -237,8 +237,13 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
  * "fuse_runs" (default 16, 0 = never: a one-target op whose next ops form a
  * run of at most that many non-branching ops applies the run to its outputs
  * in the same launch; results are identical either way),
- * "speculate_group" (as "speculate" for one-target ops on grouped entries;
- * default 0 = never), "trace" (1: time
+ * "speculate_group" (as "speculate" for one-target ops on grouped entries,
+ * default 2^21; there a merge or an entry without its partner defeats the
+ * fixed placement, so after a wasted speculative launch the next 64
+ * eligible launches skip themselves, and after a read-back that sees it the
+ * next 64 eligible ops do not speculate, twice as many each time this
+ * repeats), "spec_items" (1|2|4,
+ * default 2: entries per thread of the speculative launch), "trace" (1: time
  * every kernel launch with a HIP event pair on the state's stream),
  * "trace_reset". */
 int ss_set_option(ss_state* st, const char* key, int64_t value);
@@ -262,10 +267,12 @@ enum ss_trace_cat {
 int ss_trace_read(ss_state* st, uint32_t cat, uint64_t* launches, double* seconds, uint64_t* bytes,
                   uint64_t* entries);
 
-/* Counters since creation: [0] kernels launched, [1] sort passes, [2] sorts,
- * [3] group launches, [4] expand launches, [5] permutation runs, [6] host
- * syncs, [7] entries updated (sum over ops of input nnz). */
-int ss_stats(const ss_state* st, uint64_t* out8);
+/* Counters since creation (out9: 9 words): [0] kernels launched, [1] sort
+ * passes, [2] sorts, [3] group launches, [4] expand launches, [5] permutation
+ * runs, [6] host syncs, [7] entries updated (sum over ops of input nnz),
+ * [8] speculative placements that did not fit and were redone by compaction
+ * (as of the last read-back). */
+int ss_stats(const ss_state* st, uint64_t* out9);
 
 /* Kernel-side error bits seen so far (diagnostics after SS_E_HIP): 1 = a
  * branching op's survivors exceeded the capacity, 2 = a tile wait gave up,

@@ -323,10 +323,10 @@ class State:
         return out
 
     def stats(self) -> dict:
-        a = (ctypes.c_uint64 * 8)()
+        a = (ctypes.c_uint64 * 9)()
         _check(lib.ss_stats(self.h, a), "ss_stats")
         names = ("kernels", "sort_passes", "sorts", "group_launches", "expand_launches", "perm_runs",
-                 "host_syncs", "entries_updated")
+                 "host_syncs", "entries_updated", "speculation_wasted")
         return {k: int(v) for k, v in zip(names, a)}
 
 

@@ -1066,21 +1066,88 @@ __device__ __forceinline__ void pair_write(KeyPtrs<W>& out_keys, double2* __rest
   }
 }
 
+// The fused run of a one-target launch: the ops rops[0..rn) (generic records
+// rgops) are applied to the kept children of every item before they are
+// written at pos[it] (the upper child of an item that keeps both at pos + 1).
+// Pass 0 takes the lower kept child of every item, pass 1 the upper child of
+// items that keep both (in group mode: an entry without its partner whose
+// matrix mixes).  Every thread of the workgroup calls it (it synchronises the
+// workgroup, reusing `s_stage` for the op records).
+template <int W, int ITEMS>
+__device__ __forceinline__ void run_children(const GroupOp& op, const uint64_t (&key)[ITEMS][W],
+                                             const double2 (&out)[ITEMS][2], const uint32_t (&keepm)[ITEMS],
+                                             const uint64_t (&pos)[ITEMS], const FastOp* __restrict__ rops,
+                                             uint32_t rn, const PermOp* __restrict__ rgops, uint64_t* s_stage,
+                                             KeyPtrs<W> out_keys, double2* __restrict__ out_amp, uint64_t cap,
+                                             uint64_t (&orv)[W], uint64_t (&andv)[W]) {
+  static_assert(W <= 2, "runs are fused for keys of at most 2 words");
+  const uint32_t tw = op.tword[0];
+  const uint64_t tbit = 1ull << op.tbit[0];
+#pragma nounroll
+  for (uint32_t pass = 0; pass < 2; ++pass) {
+    uint32_t h[ITEMS][4];
+    double2 ca[ITEMS];
+    bool has[ITEMS];
+    bool any = false;
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const uint32_t km = keepm[it];
+      has[it] = pass == 0 ? km != 0u : km == 3u;
+      const uint32_t r = pass == 0 ? ((km & 1u) ? 0u : 1u) : 1u;
+      h[it][2] = h[it][3] = 0u;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        uint64_t v = key[it][w];
+        if ((uint32_t)w == tw) v = r ? (v | tbit) : (v & ~tbit);
+        h[it][2 * w] = (uint32_t)v;
+        h[it][2 * w + 1] = (uint32_t)(v >> 32);
+      }
+      ca[it] = r ? out[it][1] : out[it][0];
+      any = any || has[it];
+    }
+    if (pass == 1 && !__syncthreads_or(any)) break;
+    run_ops_lds<W, ITEMS>(h, ca, rops, rn, rgops, reinterpret_cast<uint4*>(s_stage));
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      if (!has[it]) continue;
+      const uint64_t p = pos[it] + pass;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const uint64_t v = (uint64_t)h[it][2 * w] | ((uint64_t)h[it][2 * w + 1] << 32);
+        if (p < cap) out_keys.w[w][p] = v;
+        orv[w] |= v;
+        andv[w] &= v;
+      }
+      if (p < cap) out_amp[p] = ca[it];
+    }
+  }
+}
+
 // Speculative placement without look-back: when every entry of the op has
 // exactly `f` kept children (f = 1: full pairs or pass-through in group mode;
 // f = 2: both children in expand mode) the compacted position of entry e's
 // children is f * e.  A tile that finds an entry with another count (or an
 // output past the capacity) writes nothing and flags the launch; k_pair then
-// compacts the whole op.  Tile = workgroup, no tickets.
-template <int W, int MODE, int ITEMS>
+// compacts the whole op.  Tile = workgroup, no tickets.  RUN: the run that
+// follows the op is applied to the children before they are written, as in
+// the compacting launch (which, with RUN, then only counts its updates).
+template <int W, int MODE, int ITEMS, bool RUN>
 __global__ __launch_bounds__(kBlock) void k_pair_spec(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                       KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
                                                       uint32_t ns, uint64_t cap, GroupOp op, uint32_t f,
-                                                      DevMeta* meta, uint32_t epoch) {
+                                                      DevMeta* meta, uint32_t epoch, const FastOp* __restrict__ rops,
+                                                      uint32_t rn, const PermOp* __restrict__ rgops) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   __shared__ uint64_t s_red[2 * kMaxW * 4];
-  __shared__ uint64_t s_stage[MODE == MODE_GROUP ? (W + 2) * (TILE + 2) : 1];
+  constexpr uint32_t kStageWords = MODE == MODE_GROUP ? (W + 2) * (TILE + 2) : 1;
+  constexpr uint32_t kRunWords = RUN ? kOpChunk * (uint32_t)sizeof(FastOp) / 8 : 1;
+  __shared__ __align__(16) uint64_t s_stage[kStageWords > kRunWords ? kStageWords : kRunWords];
   if (launch_prologue(meta, epoch)) return;
+  // cooling down after a wasted speculation: the compacting launch does the op
+  if (*reinterpret_cast<volatile unsigned int*>(&meta->spec_cool) != 0u) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) meta->spec_irr[epoch % kRing] = kSpecSkipped;
+    return;
+  }
   const uint64_t n = meta->nring[ns & 1];
   const uint64_t e0 = (uint64_t)blockIdx.x * TILE;
   if (e0 >= n) return;
@@ -1111,7 +1178,11 @@ __global__ __launch_bounds__(kBlock) void k_pair_spec(KeyPtrs<W> in_keys, const 
     orv[w] = 0;
     andv[w] = ~0ull;
   }
-  pair_write<W, ITEMS>(out_keys, out_amp, cap, op, key, out, keepm, pos, orv, andv);
+  if constexpr (RUN)
+    run_children<W, ITEMS>(op, key, out, keepm, pos, rops, rn, rgops, s_stage, out_keys, out_amp, cap,
+                                 orv, andv);
+  else
+    pair_write<W, ITEMS>(out_keys, out_amp, cap, op, key, out, keepm, pos, orv, andv);
   publish_masks<W>(meta, epoch, orv, andv, s_red);
 }
 
@@ -1144,12 +1215,28 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
   uint64_t n;
   if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
   if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&meta->upd, (unsigned long long)(n * op.upd));
-  if (spec_ep != 0 && *reinterpret_cast<volatile unsigned int*>(&meta->spec_irr[spec_ep % kRing]) == 0u) {
+  const unsigned int sflag =
+      spec_ep != 0 ? *reinterpret_cast<volatile unsigned int*>(&meta->spec_irr[spec_ep % kRing]) : 0u;
+  if (sflag != 0u) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (sflag == kSpecSkipped) {
+        const unsigned int c = meta->spec_cool;
+        meta->spec_cool = c ? c - 1u : 0u;
+      } else {
+        // the speculative launch was wasted: counted (the host stops trying at
+        // its next read-back) and the next kSpecCool launches skip themselves
+        atomicAdd(&meta->spec_fail, 1ull);
+        meta->spec_cool = kSpecCool;
+      }
+    }
+  } else if (spec_ep != 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       const uint64_t m = f * n;
       meta->nnz_out[epoch % kRing] = m;
       meta->nring[(ns & 1) ^ 1] = m;
       atomicMax(&meta->peak, (unsigned long long)m);
+      // (atomic: the op's own count above is added at the same time)
+      if (RUN) atomicAdd(&meta->upd, (unsigned long long)(m * rn));
       for (int w = 0; w < kMaxW; ++w) {
         meta->or_mask[epoch % kRing][w] = meta->or_mask[spec_ep % kRing][w];
         meta->and_mask[epoch % kRing][w] = meta->and_mask[spec_ep % kRing][w];
@@ -1194,50 +1281,10 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) pos[it] = s_off + off[it];
   if constexpr (RUN) {
-    static_assert(W <= 2, "runs are fused for keys of at most 2 words");
     // The tile's prefix is published (the look-back above), so later tiles do
-    // not wait for this work.  Pass 0 runs the ops on the lower kept child of
-    // every item, pass 1 on the upper child of items that keep both.
-    const uint32_t tw = op.tword[0];
-    const uint64_t tbit = 1ull << op.tbit[0];
-#pragma nounroll
-    for (uint32_t pass = 0; pass < 2; ++pass) {
-      uint32_t h[ITEMS][4];
-      double2 ca[ITEMS];
-      bool has[ITEMS];
-      bool any = false;
-#pragma unroll
-      for (int it = 0; it < ITEMS; ++it) {
-        const uint32_t km = keepm[it];
-        has[it] = pass == 0 ? km != 0u : km == 3u;
-        const uint32_t r = pass == 0 ? ((km & 1u) ? 0u : 1u) : 1u;
-        h[it][2] = h[it][3] = 0u;
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          uint64_t v = key[it][w];
-          if ((uint32_t)w == tw) v = r ? (v | tbit) : (v & ~tbit);
-          h[it][2 * w] = (uint32_t)v;
-          h[it][2 * w + 1] = (uint32_t)(v >> 32);
-        }
-        ca[it] = r ? out[it][1] : out[it][0];
-        any = any || has[it];
-      }
-      if (pass == 1 && !__syncthreads_or(any)) break;
-      run_ops_lds<W, ITEMS>(h, ca, rops, rn, rgops, reinterpret_cast<uint4*>(s_stage));
-#pragma unroll
-      for (int it = 0; it < ITEMS; ++it) {
-        if (!has[it]) continue;
-        const uint64_t p = pos[it] + pass;
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          const uint64_t v = (uint64_t)h[it][2 * w] | ((uint64_t)h[it][2 * w + 1] << 32);
-          if (p < cap) out_keys.w[w][p] = v;
-          orv[w] |= v;
-          andv[w] &= v;
-        }
-        if (p < cap) out_amp[p] = ca[it];
-      }
-    }
+    // not wait for this work.
+    run_children<W, ITEMS>(op, key, out, keepm, pos, rops, rn, rgops, s_stage, out_keys, out_amp, cap,
+                                 orv, andv);
   } else {
     pair_write<W, ITEMS>(out_keys, out_amp, cap, op, key, out, keepm, pos, orv, andv);
   }
@@ -1819,6 +1866,8 @@ __global__ void k_meta_init(DevMeta* meta) {
     }
     meta->peak = 0;
     meta->upd = 0;
+    meta->spec_fail = 0;
+    meta->spec_cool = 0;
     meta->nring[0] = meta->nring[1] = 0;
     meta->err = 0;
     meta->err_epoch = 0;

@@ -238,7 +238,19 @@ struct ss_state {
   // million entries the look-back chain is short and the extra launch costs
   // more than it saves.
   uint64_t speculate = 1ull << 23;
-  uint64_t spec_group = 0;       // the same for one-target ops on grouped entries (0: never)
+  // option: the same for one-target ops on grouped entries (0: never).  There
+  // a merge (destructive interference) or a member without its partner
+  // leaves the fixed placement; after a wasted launch the next kSpecCool
+  // eligible launches skip themselves on the device, and once a read-back sees
+  // it the host does not launch them for the next kSpecCool eligible ops (twice
+  // as many each time that repeats; back to kSpecCool after a read-back that
+  // finds speculative launches and none wasted).
+  uint64_t spec_group = 1ull << 21;
+  uint32_t spec_items = 2;       // option: entries per thread of the speculative launch (1|2|4)
+  uint64_t spec_fail_seen = 0;   // device count of wasted speculative launches at the last read-back
+  uint32_t spec_skip = 0;        // eligible ops left that do not speculate
+  uint32_t spec_backoff = kSpecCool;  // the next skip length (doubles while launches keep being wasted)
+  uint32_t spec_tries = 0;       // speculative launches since the last read-back
   int chain = 1;                 // option: consecutive one-target ops on one target in one launch
   // option: a one-target op applies the run that follows it when the run has
   // at most this many ops (0: never).  A long run is issue-bound and runs
@@ -464,6 +476,16 @@ int sync_state(ss_state* st) {
   trace_flush(st);
   st->peak = hm->peak;
   st->stats[7] = hm->upd;
+  if (hm->spec_fail != st->spec_fail_seen) {
+    // wasted speculation since the last read-back: skip it for a while, twice
+    // as long each time this repeats
+    st->spec_fail_seen = hm->spec_fail;
+    st->spec_skip = st->spec_backoff;
+    st->spec_backoff = std::min<uint32_t>(st->spec_backoff * 2u, 1u << 20);
+  } else if (st->spec_tries) {
+    st->spec_backoff = kSpecCool;
+  }
+  st->spec_tries = 0;
   if (hm->err & ~(kErrCapacity | kErrPlan)) {
     st->emits.clear();
     st->plan_log.clear();
@@ -713,30 +735,23 @@ void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uin
       if (run.n) {
         if (mode == MODE_GROUP)
           k_pair<W, MODE_GROUP, ITEMS, true><<<ntiles, kBlock, 0, st->stream>>>(
-              kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), 0u, f,
+              kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), ep_spec, f,
               run.ops, run.n, run.gops);
         else
           k_pair<W, MODE_EXPAND, ITEMS, true><<<ntiles, kBlock, 0, st->stream>>>(
-              kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), 0u, f,
+              kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), ep_spec, f,
               run.ops, run.n, run.gops);
         return;
       }
     }
-    if (mode == MODE_GROUP) {
-      if (ep_spec)
-        k_pair_spec<W, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
-                                                                             ns, st->cap, g, f, st->meta, ep_spec);
+    if (mode == MODE_GROUP)
       k_pair<W, MODE_GROUP, ITEMS, false><<<ntiles, kBlock, 0, st->stream>>>(
           kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), ep_spec, f,
           nullptr, 0u, nullptr);
-    } else {
-      if (ep_spec)
-        k_pair_spec<W, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
-                                                                              ns, st->cap, g, f, st->meta, ep_spec);
+    else
       k_pair<W, MODE_EXPAND, ITEMS, false><<<ntiles, kBlock, 0, st->stream>>>(
           kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), ep_spec, f,
           nullptr, 0u, nullptr);
-    }
     return;
   }
   if (mode == MODE_GROUP)
@@ -745,6 +760,45 @@ void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uin
   else
     k_group<W, K, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
                                                                           ns, st->cap, g, st->lb, st->meta, ep, xo(st));
+}
+
+// The speculative fixed-placement launch of a one-target op (launch
+// `ep_spec`), with its own tile size: its workgroups hold no look-back state,
+// and two entries per thread keep the group-mode neighbour staging small
+// enough for full occupancy.
+template <int W, int ITEMS>
+void launch_spec_wi(ss_state* st, int mode, const GroupOp& g, uint32_t ep_spec, const FusedRun& run) {
+  const Buf& in = st->buf[st->cur];
+  const Buf& out = st->buf[st->cur ^ 1];
+  const uint32_t ns = st->nslot;
+  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock * ITEMS - 1) / (kBlock * ITEMS));
+  const uint32_t f = mode == MODE_GROUP ? 1u : 2u;
+  if constexpr (W <= 2) {
+    if (run.n) {
+      if (mode == MODE_GROUP)
+        k_pair_spec<W, MODE_GROUP, ITEMS, true><<<ntiles, kBlock, 0, st->stream>>>(
+            kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, f, st->meta, ep_spec, run.ops, run.n, run.gops);
+      else
+        k_pair_spec<W, MODE_EXPAND, ITEMS, true><<<ntiles, kBlock, 0, st->stream>>>(
+            kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, f, st->meta, ep_spec, run.ops, run.n, run.gops);
+      return;
+    }
+  }
+  if (mode == MODE_GROUP)
+    k_pair_spec<W, MODE_GROUP, ITEMS, false><<<ntiles, kBlock, 0, st->stream>>>(
+        kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, f, st->meta, ep_spec, nullptr, 0u, nullptr);
+  else
+    k_pair_spec<W, MODE_EXPAND, ITEMS, false><<<ntiles, kBlock, 0, st->stream>>>(
+        kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, f, st->meta, ep_spec, nullptr, 0u, nullptr);
+}
+
+template <int W>
+void launch_spec_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep_spec, const FusedRun& run) {
+  switch (st->spec_items) {
+    case 1: launch_spec_wi<W, 1>(st, mode, g, ep_spec, run); break;
+    case 4: launch_spec_wi<W, 4>(st, mode, g, ep_spec, run); break;
+    default: launch_spec_wi<W, 2>(st, mode, g, ep_spec, run); break;
+  }
 }
 
 // Items per thread: several for one or two targets (bigger tiles, fewer
@@ -763,7 +817,10 @@ template <int W>
 void launch_group_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec, const FusedRun& run) {
   const FusedRun none{nullptr, 0u, nullptr};
   switch (g.k) {
-    case 1: launch_group_wk<W, 1>(st, mode, g, ep, ep_spec, run); break;
+    case 1:
+      if (ep_spec) launch_spec_w<W>(st, mode, g, ep_spec, run);
+      launch_group_wk<W, 1>(st, mode, g, ep, ep_spec, run);
+      break;
     case 2: launch_group_wk<W, 2>(st, mode, g, ep, 0, none); break;
     case 3: launch_group_wk<W, 3>(st, mode, g, ep, 0, none); break;
     case 4: launch_group_wk<W, 4>(st, mode, g, ep, 0, none); break;
@@ -1312,16 +1369,20 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index, const ss_op* 
       }
       if (st->n_ub == 0) return SS_OK;
     }
-    // one-target expansion: try the fixed two-children placement first (no
-    // look-back); the compacting launch after it finishes the op either way.
-    // Not in group mode: a merge (destructive interference) leaves members
-    // without a child, and the speculative launch would be wasted.
+    // one-target op on many entries: try the fixed placement first (two
+    // children per entry in expand mode, one in group mode; no look-back);
+    // the compacting launch after it finishes the op either way.
     uint32_t ep_spec = 0, ep;
     int rc = SS_OK;
-    if (g.k == 1 && g.nchain == 0 && run.n == 0 &&
-        ((mode == MODE_EXPAND && st->speculate && st->n_ub >= st->speculate) ||
-         (mode == MODE_GROUP && st->spec_group && st->n_ub >= st->spec_group)))
-      rc = begin_launch(st, &ep_spec);
+    if (g.k == 1 && ((mode == MODE_EXPAND && st->speculate && st->n_ub >= st->speculate) ||
+                     (mode == MODE_GROUP && st->spec_group && st->n_ub >= st->spec_group))) {
+      if (st->spec_skip) {
+        --st->spec_skip;
+      } else {
+        rc = begin_launch(st, &ep_spec);
+        ++st->spec_tries;
+      }
+    }
     if (!rc) rc = begin_launch(st, &ep);
     if (rc) return rc;
     const uint32_t cat = mode == MODE_GROUP ? SS_TRACE_GROUP : SS_TRACE_EXPAND;
@@ -1840,7 +1901,8 @@ struct PlanSnap {
   uint32_t nslot;
   uint64_t n, n_ub, peak;
   bool n_known, masks_valid, grouped, poisoned, sup_valid;
-  uint32_t n_src_ep, mask_ep, epoch, ops_used, dev_err;
+  uint32_t n_src_ep, mask_ep, epoch, ops_used, dev_err, spec_skip, spec_backoff, spec_tries;
+  uint64_t spec_fail_seen;
   uint64_t orm[kMaxW], andm[kMaxW], gmask[kMaxW], sorm[kMaxW], sandm[kMaxW];
   uint64_t stats[8];
 };
@@ -1862,6 +1924,10 @@ PlanSnap save_plan(const ss_state* st) {
   p.epoch = st->epoch;
   p.ops_used = st->ops_used;
   p.dev_err = st->dev_err;
+  p.spec_skip = st->spec_skip;
+  p.spec_backoff = st->spec_backoff;
+  p.spec_tries = st->spec_tries;
+  p.spec_fail_seen = st->spec_fail_seen;
   for (int w = 0; w < kMaxW; ++w) {
     p.orm[w] = st->orm[w];
     p.andm[w] = st->andm[w];
@@ -1889,6 +1955,10 @@ void restore_plan(ss_state* st, const PlanSnap& p) {
   st->epoch = p.epoch;
   st->ops_used = p.ops_used;
   st->dev_err = p.dev_err;
+  st->spec_skip = p.spec_skip;
+  st->spec_backoff = p.spec_backoff;
+  st->spec_tries = p.spec_tries;
+  st->spec_fail_seen = p.spec_fail_seen;
   for (int w = 0; w < kMaxW; ++w) {
     st->orm[w] = p.orm[w];
     st->andm[w] = p.andm[w];
@@ -2386,8 +2456,10 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes) {
   for (auto& t : st->tables) t.dev = st->tab_base + (static_cast<char*>(t.dev) - old_tab);
   rc = init_device(st);
   if (rc) return rc;
+  const uint64_t spec_fail = st->spec_fail_seen;
   if (hipMemcpyAsync(&st->meta->peak, &peak, 8, hipMemcpyHostToDevice, st->stream) != hipSuccess ||
-      hipMemcpyAsync(&st->meta->upd, &upd, 8, hipMemcpyHostToDevice, st->stream) != hipSuccess)
+      hipMemcpyAsync(&st->meta->upd, &upd, 8, hipMemcpyHostToDevice, st->stream) != hipSuccess ||
+      hipMemcpyAsync(&st->meta->spec_fail, &spec_fail, 8, hipMemcpyHostToDevice, st->stream) != hipSuccess)
     return hip_fail(st);
   set_known(st, n);
   k_set_n<<<1, 64, 0, st->stream>>>(st->meta, st->nslot, n);
@@ -2610,6 +2682,9 @@ int ss_set_option(ss_state* st, const char* key, int64_t value) {
   } else if (k == "fuse_runs") {
     if (value < 0 || value > (int64_t)kRunChunk) return SS_E_ARG;
     st->fuse_runs = (uint32_t)value;
+  } else if (k == "spec_items") {
+    if (value != 1 && value != 2 && value != 4) return SS_E_ARG;
+    st->spec_items = (uint32_t)value;
   } else if (k == "speculate_group") {
     if (value < 0) return SS_E_ARG;
     st->spec_group = (uint64_t)value;
@@ -2646,9 +2721,10 @@ int ss_device_error(const ss_state* st, uint32_t* bits) {
   return SS_OK;
 }
 
-int ss_stats(const ss_state* st, uint64_t* out8) {
-  if (!st || !out8) return SS_E_ARG;
-  for (int i = 0; i < 8; ++i) out8[i] = st->stats[i];
+int ss_stats(const ss_state* st, uint64_t* out9) {
+  if (!st || !out9) return SS_E_ARG;
+  for (int i = 0; i < 8; ++i) out9[i] = st->stats[i];
+  out9[8] = st->spec_fail_seen;
   return SS_OK;
 }
 

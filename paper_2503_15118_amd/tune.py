@@ -5,6 +5,7 @@ computes:
 
 - ``perm_entries``: entries per lane of the key-permutation interpreter;
 - ``group_items``: entries per lane of the interference (group / expand) kernels;
+- ``spec_items``: entries per lane of their speculative fixed-placement launch;
 - ``sort_items``: entries per lane of a radix-sort scatter pass.
 
 Because each option touches only its own category, the search is coordinate-wise:
@@ -28,12 +29,14 @@ from typing import Callable, Dict, Iterable, Optional
 SPACE: Dict[str, tuple] = {
     "perm_entries": (4, 8, 16),
     "group_items": (1, 2, 4),
+    "spec_items": (1, 2, 4),
     "sort_items": (8, 16),
 }
-DEFAULTS: Dict[str, int] = {"perm_entries": 8, "group_items": 4, "sort_items": 16}
+DEFAULTS: Dict[str, int] = {"perm_entries": 8, "group_items": 4, "spec_items": 2, "sort_items": 16}
 CATEGORIES: Dict[str, tuple] = {
     "perm_entries": ("perm",),
     "group_items": ("group", "expand"),
+    "spec_items": ("group", "expand"),
     "sort_items": ("sort_pass",),
 }
 

@@ -243,6 +243,32 @@ def test_speculative_placement_is_exact(abi, seed):
         compare(k1, a1, ok, oa, c.eps)
 
 
+def test_wasted_speculation_cools_down(abi):
+    """H on a flag qubit again and again: every expansion fits the fixed
+    placement and every merge defeats it.  After a wasted speculative launch
+    the next ones skip themselves, so only a few are wasted over 400 eligible
+    ops; the result equals the compacting path bit for bit."""
+    mk = wl.make_op
+    regs = [("a", 6), ("f", 1)]
+    ops = [mk("H", 0, qmask=0x3F)]
+    for i in range(200):
+        ops += [mk("H", 1, qmask=1), mk("X", 0, qmask=1 << (i % 6))]
+    c = wl.Circuit(regs=regs, ops=wl.ops_array(ops), eps=1e-14, name="flag-h-pairs")
+    print(f"[case] {c.name} wasted speculation", flush=True)
+    outs = []
+    for opts in ({"speculate": 1, "speculate_group": 1}, {"speculate": 0, "speculate_group": 0}):
+        st = _gpu(abi, c, opts=opts)
+        outs.append(st.export() + (st.stats()["speculation_wasted"],))
+        st.close()
+    (k1, a1, w1), (k0, a0, w0) = outs
+    assert np.array_equal(k1, k0)
+    assert np.array_equal(a1.view(np.uint64), a0.view(np.uint64))
+    assert w0 == 0 and 1 <= w1 <= 20, w1
+    ora, _, _ = run_circuit(c)
+    ok, _, oa = ora.export()
+    compare(k1, a1, ok, oa, c.eps)
+
+
 def test_deterministic_reruns(abi):
     c = wl.c1_circuit(9)
     k1, a1 = _gpu(abi, c).export()
@@ -452,11 +478,17 @@ def test_chained_one_target_ops(abi, seed):
     s1 = _check(abi, c, opts={"chain": 1})
     s0 = _check(abi, c, opts={"chain": 0})
     assert s1["n_oracle"] == s0["n_oracle"]
-    st1 = _gpu(abi, c, opts={"chain": 1})
+    st1 = _gpu(abi, c, opts={"chain": 1, "speculate": 0, "speculate_group": 0})
     st0 = _gpu(abi, c, opts={"chain": 0})
     k1, a1 = st1.export()
     k0, a0 = st0.export()
     compare(k1, a1, k0, a0, c.eps)
+    # chains placed speculatively first (at any size): bit for bit the same
+    st2 = _gpu(abi, c, opts={"chain": 1, "speculate": 1, "speculate_group": 1})
+    k2, a2 = st2.export()
+    assert np.array_equal(k2, k1)
+    assert np.array_equal(a2.view(np.uint64), a1.view(np.uint64))
+    st2.close()
     st1.close()
     st0.close()
 
@@ -487,20 +519,27 @@ def test_fused_runs_bit_identical(abi, items):
     its launch writes the same entries at the same positions as the two
     launches: keys and amplitudes bit for bit, and equal to the oracle.  Runs
     with every op kind (QRAM, phase) on 1- and 2-word keys, expansions and
-    groups, chains and singletons."""
+    groups, chains and singletons; with the fixed-fan-out placement tried
+    first (it carries the run too) and without."""
     kinds = ("X", "H", "RY", "ADD", "SUB", "MULC", "XOR", "XORC", "QRAM_LOAD", "QRAM_UNLOAD", "REFLECT0")
     circs = [wl.random_small_circuit(70 + s, kinds=kinds, nops=120, with_init=bool(s % 2)) for s in range(3)]
     circs += [wl.c1_circuit(21), wl.c2_circuit(22, nops=200, n_ry=5, h_qubits=12)]
     for c in circs:
         print(f"[case] {c.name} fused runs, group_items {items}", flush=True)
         outs = []
-        for fuse in (4096, 0):        # fuse every run / none
-            st = _gpu(abi, c, opts={"fuse_runs": fuse, "group_items": items})
-            outs.append(st.export())
+        # fuse every run (speculating at any size / never) / fuse none
+        for opts in ({"fuse_runs": 4096, "speculate": 1, "speculate_group": 1},
+                     {"fuse_runs": 4096, "speculate": 0, "speculate_group": 0},
+                     {"fuse_runs": 0, "speculate": 0, "speculate_group": 0}):
+            st = _gpu(abi, c, opts=dict(opts, group_items=items))
+            outs.append(st.export() + (st.stats()["entries_updated"],))
             st.close()
-        (k1, a1), (k0, a0) = outs
-        assert np.array_equal(k1, k0)
-        assert np.array_equal(a1.view(np.uint64), a0.view(np.uint64))
+        k0, a0, u0 = outs[-1]
+        for k1, a1, u1 in outs[:-1]:
+            assert np.array_equal(k1, k0)
+            assert np.array_equal(a1.view(np.uint64), a0.view(np.uint64))
+            assert u1 == u0                 # every op counted once on each path
+        k1, a1, _ = outs[0]
         ora, _, _ = run_circuit(c)
         ok, _, oa = ora.export()
         compare(k1, a1, ok, oa, c.eps)

@@ -45,7 +45,8 @@ def test_coordinate_search_picks_fastest_and_caches(tmp_path):
     key = tune.bucket_key("gfx950", 2, 1 << 21, False)
     assert key == "gfx950/W2/n21/plain"
     best = t.tune(st, st.run, key)
-    assert best == {"perm_entries": 4, "group_items": 2, "sort_items": 16}
+    # spec_items changes no time here: the default stays
+    assert best == {"perm_entries": 4, "group_items": 2, "spec_items": 2, "sort_items": 16}
     # the winners stay set on the state
     for k, v in best.items():
         assert st.opts[k] == v
