@@ -243,7 +243,10 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
  * eligible launches skip themselves, and after a read-back that sees it the
  * next 64 eligible ops do not speculate, twice as many each time this
  * repeats), "spec_items" (1|2|4,
- * default 2: entries per thread of the speculative launch), "trace" (1: time
+ * default 2: entries per thread of the speculative launch), "expand_slots"
+ * (1, default: an expansion on 2..5 target qubits runs one thread per child,
+ * so that consecutive lanes write consecutive outputs; 0: one thread per
+ * entry and its children), "trace" (1: time
  * every kernel launch with a HIP event pair on the state's stream),
  * "trace_reset". */
 int ss_set_option(ss_state* st, const char* key, int64_t value);

@@ -900,6 +900,113 @@ __global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const doub
 }
 
 // ---------------------------------------------------------------------------
+// k_expand_slots: expand mode on K >= 2 targets (every entry alone in its
+// group), one thread per (entry, child) slot: slot q is child c = q mod 2^K of
+// entry q / 2^K, so consecutive lanes write consecutive outputs.  With the
+// entry's target value s0, child c gets a0 * m[c_0][s0_0] * ... * m[c_K-1][s0_K-1]
+// (real factors taken in ascending j, as the butterfly stages of k_group
+// would, so the two agree bit for bit) and exists when every factor is
+// nonzero; where the controls fail only c = s0 exists (the entry passes
+// through).  Kept children are compacted (tile scan and look-back over slots).
+// ---------------------------------------------------------------------------
+template <int W, int K, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_expand_slots(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
+                                                         KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
+                                                         uint32_t ns, uint64_t cap, GroupOp op, uint64_t* lb,
+                                                         DevMeta* meta, uint32_t epoch, uint32_t xo) {
+  constexpr uint32_t G = 1u << K;
+  constexpr uint32_t TILE = kBlock * ITEMS;     // slots per tile
+  static_assert(TILE % G == 0, "a tile holds whole entries");
+  __shared__ uint32_t s_wtot[ITEMS][kBlock / 64];
+  __shared__ uint64_t s_off;
+  __shared__ uint64_t s_lb[12];
+  __shared__ uint64_t s_red[2 * kMaxW * 4];
+  __shared__ uint32_t s_tile;
+  uint64_t n;
+  if (!emit_begin(meta, ns, epoch, TILE / G, &n)) return;
+  if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&meta->upd, (unsigned long long)(n * op.upd));
+  const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
+  const uint64_t ntiles = (n * G + TILE - 1) / TILE;
+  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
+  uint64_t key[ITEMS][W];
+  double2 v[ITEMS];
+  uint32_t cnt[ITEMS];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t q = (uint64_t)tile * TILE + (uint64_t)it * kBlock + threadIdx.x;
+    const uint64_t e = q >> K;
+    const uint32_t c = (uint32_t)q & (G - 1u);
+    cnt[it] = 0;
+    v[it] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int w = 0; w < W; ++w) key[it][w] = 0;
+    if (e < n) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) key[it][w] = in_keys.w[w][e];
+      const double2 a0 = in_amp[e];
+      const uint32_t s0 = target_value<W, K>(key[it], op);
+      const bool ctl = !op.has_ctl || controls_hold<W>(key[it], op.cmask, op.cval);
+      bool exists;
+      if (ctl) {
+        double2 x = a0;
+        exists = true;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const uint32_t cj = (c >> j) & 1u, sj = (s0 >> j) & 1u;
+          const double f = cj ? (sj ? op.m[1][1] : op.m[1][0]) : (sj ? op.m[0][1] : op.m[0][0]);
+          x.x = f * x.x;
+          x.y = f * x.y;
+          exists = exists && f != 0.0;
+        }
+        v[it] = x;
+      } else {
+        exists = c == s0;
+        v[it] = a0;
+      }
+      with_target_value<W, K>(key[it], op, c);
+      cnt[it] = (exists && keep_amp(v[it].x, v[it].y, op.eps2)) ? 1u : 0u;
+    }
+  }
+  uint32_t off[ITEMS];
+  const uint64_t tile_total = tile_offsets<ITEMS>(cnt, off, s_wtot);
+  {
+    const uint64_t ex = lookback_block(lb, tile, tile_total, epoch, &meta->err, s_lb);
+    if (threadIdx.x == 0) {
+      s_off = ex;
+      if (tile == ntiles - 1) {
+        meta->nnz_out[epoch % kRing] = ex + tile_total;
+        meta->nring[(ns & 1) ^ 1] = ex + tile_total;
+        if (ex + tile_total > cap) raise_error(meta, kErrCapacity, epoch);
+        else atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
+      }
+    }
+  }
+  __syncthreads();
+  uint64_t orv[W], andv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    orv[w] = 0;
+    andv[w] = ~0ull;
+  }
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    if (!cnt[it]) continue;
+    const uint64_t p = s_off + off[it];
+    if (p < cap) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) out_keys.w[w][p] = key[it][w];
+      out_amp[p] = v[it];
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      orv[w] |= key[it][w];
+      andv[w] &= key[it][w];
+    }
+  }
+  publish_masks<W>(meta, epoch, orv, andv, s_red);
+}
+
+// ---------------------------------------------------------------------------
 // k_pair: a branching op on one target qubit, one thread per entry.  In a
 // full pair (the two members adjacent, in either order) each member writes the
 // child with its own target value; a member without partner writes both children;

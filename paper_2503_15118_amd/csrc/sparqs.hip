@@ -247,6 +247,7 @@ struct ss_state {
   // finds speculative launches and none wasted).
   uint64_t spec_group = 1ull << 21;
   uint32_t spec_items = 2;       // option: entries per thread of the speculative launch (1|2|4)
+  int expand_slots = 1;          // option: expansions on 2..5 targets one thread per child (0: per entry)
   uint64_t spec_fail_seen = 0;   // device count of wasted speculative launches at the last read-back
   uint32_t spec_skip = 0;        // eligible ops left that do not speculate
   uint32_t spec_backoff = kSpecCool;  // the next skip length (doubles while launches keep being wasted)
@@ -754,12 +755,20 @@ void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uin
           nullptr, 0u, nullptr);
     return;
   }
-  if (mode == MODE_GROUP)
+  if (mode == MODE_GROUP) {
     k_group<W, K, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
                                                                          ns, st->cap, g, st->lb, st->meta, ep, xo(st));
-  else
+  } else if (st->expand_slots) {
+    // one thread per child: 2^K slots per entry, 4 per thread
+    constexpr uint32_t kSlotTile = kBlock * 4;
+    const uint64_t slots = st->n_ub << K;
+    const uint32_t nt = (uint32_t)std::max<uint64_t>(1, (slots + kSlotTile - 1) / kSlotTile);
+    k_expand_slots<W, K, 4><<<nt, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g,
+                                                           st->lb, st->meta, ep, xo(st));
+  } else {
     k_group<W, K, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
                                                                           ns, st->cap, g, st->lb, st->meta, ep, xo(st));
+  }
 }
 
 // The speculative fixed-placement launch of a one-target op (launch
@@ -2682,6 +2691,8 @@ int ss_set_option(ss_state* st, const char* key, int64_t value) {
   } else if (k == "fuse_runs") {
     if (value < 0 || value > (int64_t)kRunChunk) return SS_E_ARG;
     st->fuse_runs = (uint32_t)value;
+  } else if (k == "expand_slots") {
+    st->expand_slots = value ? 1 : 0;
   } else if (k == "spec_items") {
     if (value != 1 && value != 2 && value != 4) return SS_E_ARG;
     st->spec_items = (uint32_t)value;
