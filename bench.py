@@ -105,8 +105,8 @@ def summarize_profile(pdir):
     lines.append("")
     for label in ("k_perm_fast<2, 8, false>", "k_perm_fast<2, 4, false>", "k_perm_fast<2, 16, false>",
                   "k_pair<2, 0, 4, false>", "k_pair<2, 1, 4, false>", "k_pair<2, 1, 4, true>",
-                  "k_pair<2, 0, 2, false>", "k_pair<2, 1, 2, false>", "k_pair_spec<2, 0, 1, false>",
-                  "k_pair_spec<2, 0, 2, false>", "k_pair_spec<2, 0, 4, false>", "k_group<2, 5, 1, 1>"):
+                  "k_pair<2, 0, 2, false>", "k_pair<2, 1, 2, false>", "k_expand_slots<2, 5, 4>") + tuple(
+                      "k_pair_spec<2, 0, %d, false, %d>" % (i, x) for i in (1, 2, 4) for x in (0, 1, 2)):
         pk = "void sparqs::" + label
         if pk not in fe or pk not in wr:
             continue
@@ -595,7 +595,8 @@ def main():
     ap.add_argument("--group-items", type=int, default=4)
     ap.add_argument("--sort-items", type=int, default=16)
     ap.add_argument("--perm-entries", type=int, default=8)
-    ap.add_argument("--spec-items", type=int, default=2)
+    ap.add_argument("--spec-items", type=int, default=4)
+    ap.add_argument("--pair-exchange", type=int, default=2)
     ap.add_argument("--tile-order", type=int, default=1)
     ap.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
                     help="extra ss_set_option on the state (c2, c4)")
@@ -673,6 +674,7 @@ def main():
     st.set_option("sort_items", args.sort_items)
     st.set_option("perm_entries", args.perm_entries)
     st.set_option("spec_items", args.spec_items)
+    st.set_option("pair_exchange", args.pair_exchange)
     st.set_option("tile_order", args.tile_order)
     set_opts(st, args.opt)
     zero = np.zeros((1, len(circ.regs)), dtype=np.uint64)
@@ -699,6 +701,7 @@ def main():
         args.sort_items = tuned["sort_items"]
         args.perm_entries = tuned["perm_entries"]
         args.spec_items = tuned["spec_items"]
+        args.pair_exchange = tuned["pair_exchange"]
 
     for _ in range(args.warmup):
         step()
@@ -775,8 +778,8 @@ def main():
     # records the count
     spec_group = dict((kv.split("=", 1)[0], int(kv.split("=", 1)[1])) for kv in args.opt).get(
         "speculate_group", 1 << 21)
-    group_label = ("k_pair_spec<2, 0, %d, false>" % args.spec_items if 0 < spec_group <= 1 << 21
-                   else "k_pair<2, 0, %d, false>" % args.group_items)
+    group_label = ("k_pair_spec<2, 0, %d, false, %d>" % (args.spec_items, args.pair_exchange)
+                   if 0 < spec_group <= 1 << 21 else "k_pair<2, 0, %d, false>" % args.group_items)
     label = {"perm": "k_perm_fast<2, %d, false>" % args.perm_entries,
              "group": group_label,
              "expand": "k_pair<2, 1, %d, false>" % args.group_items}.get(dom)
@@ -808,6 +811,7 @@ def main():
             "sort_items": args.sort_items,
             "perm_entries": args.perm_entries,
             "spec_items": args.spec_items,
+            "pair_exchange": args.pair_exchange,
             "tile_order": args.tile_order,
             "autotuned": tuned is not None,
         },

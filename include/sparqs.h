@@ -242,8 +242,12 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
  * fixed placement, so after a wasted speculative launch the next 64
  * eligible launches skip themselves, and after a read-back that sees it the
  * next 64 eligible ops do not speculate, twice as many each time this
- * repeats), "spec_items" (1|2|4,
- * default 2: entries per thread of the speculative launch), "expand_slots"
+ * repeats), "spec_items" (1|2|4, default 4: entries per thread of the
+ * speculative launch), "pair_exchange" (how a speculative group-mode launch
+ * finds partners: 2, default, only at e ^ 1 through a lane-pair exchange, a
+ * tile without that alignment defeating the speculation; 1 the same with
+ * staging as fallback; 0 always by staging the tile's neighbours in LDS;
+ * results are identical either way), "expand_slots"
  * (1, default: an expansion on 2..5 target qubits runs one thread per child,
  * so that consecutive lanes write consecutive outputs; 0: one thread per
  * entry and its children), "trace" (1: time

@@ -1017,8 +1017,16 @@ __global__ __launch_bounds__(kBlock) void k_expand_slots(KeyPtrs<W> in_keys, con
 // The children of the ITEMS entries e0 + it * kBlock + threadIdx.x of one
 // tile: keep mask (bit r: child with target value r) and amplitudes.  Every
 // thread of the workgroup calls it (group mode stages the tile in LDS).
-template <int W, int MODE, int ITEMS>
-__device__ __forceinline__ void pair_tile(const KeyPtrs<W>& in_keys, const double2* __restrict__ in_amp,
+// The value held by lane t ^ 1 (the other lane of the pair): a DPP quad
+// permutation [1, 0, 3, 2] on each 32-bit half, no LDS traffic.
+__device__ __forceinline__ uint64_t lane_pair_swap(uint64_t x) {
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)x, 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(x >> 32), 0xB1, 0xF, 0xF, false);
+  return (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32);
+}
+
+template <int W, int MODE, int ITEMS, int NB = 0>
+__device__ __forceinline__ bool pair_tile(const KeyPtrs<W>& in_keys, const double2* __restrict__ in_amp,
                                           uint64_t n, uint64_t e0, const GroupOp& op, uint64_t* s_stage,
                                           uint64_t (&key)[ITEMS][W], double2 (&out)[ITEMS][2],
                                           uint32_t (&keepm)[ITEMS]) {
@@ -1038,7 +1046,30 @@ __device__ __forceinline__ void pair_tile(const KeyPtrs<W>& in_keys, const doubl
       amp[it] = in_amp[e];
     }
   }
-  if (MODE == MODE_GROUP) {
+  // Group mode, NB = 1 or 2: when every entry of the tile has its partner at
+  // e ^ 1, the partners are exchanged between lane pairs (e and e ^ 1 sit in
+  // lanes t and t ^ 1 of one wave) and nothing is staged.  The partner found
+  // is the one the staged search finds, so the results are the same.
+  // Otherwise NB = 1 stages the tile (as NB = 0 always does) and NB = 2
+  // returns false with nothing computed (s_stage is then never touched).
+  bool aligned = false;
+  double2 pamp[ITEMS];
+  if (MODE == MODE_GROUP && NB != 0) {
+    bool ok = true;
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
+      uint64_t pk[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) pk[w] = lane_pair_swap(key[it][w]);
+      pamp[it].x = __longlong_as_double((long long)lane_pair_swap((uint64_t)__double_as_longlong(amp[it].x)));
+      pamp[it].y = __longlong_as_double((long long)lane_pair_swap((uint64_t)__double_as_longlong(amp[it].y)));
+      if (e < n) ok = ok && (e ^ 1ull) < n && same_idle<W>(key[it], pk, op.tmask);
+    }
+    aligned = __syncthreads_and(ok) != 0;
+    if (NB == 2 && !aligned) return false;
+  }
+  if (MODE == MODE_GROUP && NB != 2 && !aligned) {
     // Neighbours come from LDS: slot 1 + i holds tile entry i, slot 0 the
     // entry before the tile and slot TILE + 1 the one after (when present).
     uint64_t* s_key = s_stage;
@@ -1099,7 +1130,10 @@ __device__ __forceinline__ void pair_tile(const KeyPtrs<W>& in_keys, const doubl
       {
         bool has_p = false;
         double2 ap = make_double2(0.0, 0.0);
-        if (MODE == MODE_GROUP) {
+        if (MODE == MODE_GROUP && aligned) {
+          has_p = true;
+          ap = pamp[it];
+        } else if (MODE == MODE_GROUP && NB != 2) {
           // the partner is a neighbour on either side: grouped order keeps the
           // two members adjacent but not necessarily bit 0 first
           const uint64_t* s_key = s_stage;
@@ -1135,6 +1169,7 @@ __device__ __forceinline__ void pair_tile(const KeyPtrs<W>& in_keys, const doubl
       }
     }
   }
+  return true;
 }
 
 // Write the kept children of one tile: the child of item `it` with target
@@ -1238,7 +1273,7 @@ __device__ __forceinline__ void run_children(const GroupOp& op, const uint64_t (
 // compacts the whole op.  Tile = workgroup, no tickets.  RUN: the run that
 // follows the op is applied to the children before they are written, as in
 // the compacting launch (which, with RUN, then only counts its updates).
-template <int W, int MODE, int ITEMS, bool RUN>
+template <int W, int MODE, int ITEMS, bool RUN, int NB>
 __global__ __launch_bounds__(kBlock) void k_pair_spec(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                       KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
                                                       uint32_t ns, uint64_t cap, GroupOp op, uint32_t f,
@@ -1246,7 +1281,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_spec(KeyPtrs<W> in_keys, const 
                                                       uint32_t rn, const PermOp* __restrict__ rgops) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   __shared__ uint64_t s_red[2 * kMaxW * 4];
-  constexpr uint32_t kStageWords = MODE == MODE_GROUP ? (W + 2) * (TILE + 2) : 1;
+  constexpr uint32_t kStageWords = MODE == MODE_GROUP && NB != 2 ? (W + 2) * (TILE + 2) : 1;
   constexpr uint32_t kRunWords = RUN ? kOpChunk * (uint32_t)sizeof(FastOp) / 8 : 1;
   __shared__ __align__(16) uint64_t s_stage[kStageWords > kRunWords ? kStageWords : kRunWords];
   if (launch_prologue(meta, epoch)) return;
@@ -1266,7 +1301,11 @@ __global__ __launch_bounds__(kBlock) void k_pair_spec(KeyPtrs<W> in_keys, const 
   uint64_t key[ITEMS][W];
   double2 out[ITEMS][2];
   uint32_t keepm[ITEMS];
-  pair_tile<W, MODE, ITEMS>(in_keys, in_amp, n, e0, op, s_stage, key, out, keepm);
+  if (!pair_tile<W, MODE, ITEMS, NB>(in_keys, in_amp, n, e0, op, s_stage, key, out, keepm)) {
+    // partners not aligned (NB = 2): the compacting launch does the op
+    if (threadIdx.x == 0) atomicOr(&meta->spec_irr[epoch % kRing], 1u);
+    return;
+  }
   bool reg = true;
   uint64_t pos[ITEMS];
 #pragma unroll

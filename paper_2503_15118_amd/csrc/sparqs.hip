@@ -246,8 +246,9 @@ struct ss_state {
   // as many each time that repeats; back to kSpecCool after a read-back that
   // finds speculative launches and none wasted).
   uint64_t spec_group = 1ull << 21;
-  uint32_t spec_items = 2;       // option: entries per thread of the speculative launch (1|2|4)
+  uint32_t spec_items = 4;       // option: entries per thread of the speculative launch (1|2|4)
   int expand_slots = 1;          // option: expansions on 2..5 targets one thread per child (0: per entry)
+  uint32_t pair_exchange = 2;    // option: how speculative group launches find partners (0 | 1 | 2)
   uint64_t spec_fail_seen = 0;   // device count of wasted speculative launches at the last read-back
   uint32_t spec_skip = 0;        // eligible ops left that do not speculate
   uint32_t spec_backoff = kSpecCool;  // the next skip length (doubles while launches keep being wasted)
@@ -772,11 +773,11 @@ void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uin
 }
 
 // The speculative fixed-placement launch of a one-target op (launch
-// `ep_spec`), with its own tile size: its workgroups hold no look-back state,
-// and two entries per thread keep the group-mode neighbour staging small
-// enough for full occupancy.
-template <int W, int ITEMS>
-void launch_spec_wi(ss_state* st, int mode, const GroupOp& g, uint32_t ep_spec, const FusedRun& run) {
+// `ep_spec`), with its own tile size: its workgroups hold no look-back state.
+// In group mode, with partners taken from the lane pair (no staging) four
+// entries per thread run at full occupancy; with staging, two.
+template <int W, int ITEMS, int NB>
+void launch_spec_wn(ss_state* st, int mode, const GroupOp& g, uint32_t ep_spec, const FusedRun& run) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
   const uint32_t ns = st->nslot;
@@ -785,20 +786,33 @@ void launch_spec_wi(ss_state* st, int mode, const GroupOp& g, uint32_t ep_spec, 
   if constexpr (W <= 2) {
     if (run.n) {
       if (mode == MODE_GROUP)
-        k_pair_spec<W, MODE_GROUP, ITEMS, true><<<ntiles, kBlock, 0, st->stream>>>(
+        k_pair_spec<W, MODE_GROUP, ITEMS, true, NB><<<ntiles, kBlock, 0, st->stream>>>(
             kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, f, st->meta, ep_spec, run.ops, run.n, run.gops);
       else
-        k_pair_spec<W, MODE_EXPAND, ITEMS, true><<<ntiles, kBlock, 0, st->stream>>>(
+        k_pair_spec<W, MODE_EXPAND, ITEMS, true, 0><<<ntiles, kBlock, 0, st->stream>>>(
             kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, f, st->meta, ep_spec, run.ops, run.n, run.gops);
       return;
     }
   }
   if (mode == MODE_GROUP)
-    k_pair_spec<W, MODE_GROUP, ITEMS, false><<<ntiles, kBlock, 0, st->stream>>>(
+    k_pair_spec<W, MODE_GROUP, ITEMS, false, NB><<<ntiles, kBlock, 0, st->stream>>>(
         kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, f, st->meta, ep_spec, nullptr, 0u, nullptr);
   else
-    k_pair_spec<W, MODE_EXPAND, ITEMS, false><<<ntiles, kBlock, 0, st->stream>>>(
+    k_pair_spec<W, MODE_EXPAND, ITEMS, false, 0><<<ntiles, kBlock, 0, st->stream>>>(
         kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, f, st->meta, ep_spec, nullptr, 0u, nullptr);
+}
+
+// Group mode: pair_exchange 0 stages every tile's neighbours in LDS, 1 takes
+// aligned partners from the lane pair and stages only tiles that are not
+// aligned, 2 takes only aligned partners (no LDS staging; a tile that is not
+// aligned defeats the speculation).
+template <int W, int ITEMS>
+void launch_spec_wi(ss_state* st, int mode, const GroupOp& g, uint32_t ep_spec, const FusedRun& run) {
+  switch (st->pair_exchange) {
+    case 0: launch_spec_wn<W, ITEMS, 0>(st, mode, g, ep_spec, run); break;
+    case 2: launch_spec_wn<W, ITEMS, 2>(st, mode, g, ep_spec, run); break;
+    default: launch_spec_wn<W, ITEMS, 1>(st, mode, g, ep_spec, run); break;
+  }
 }
 
 template <int W>
@@ -2691,6 +2705,9 @@ int ss_set_option(ss_state* st, const char* key, int64_t value) {
   } else if (k == "fuse_runs") {
     if (value < 0 || value > (int64_t)kRunChunk) return SS_E_ARG;
     st->fuse_runs = (uint32_t)value;
+  } else if (k == "pair_exchange") {
+    if (value < 0 || value > 2) return SS_E_ARG;
+    st->pair_exchange = (uint32_t)value;
   } else if (k == "expand_slots") {
     st->expand_slots = value ? 1 : 0;
   } else if (k == "spec_items") {

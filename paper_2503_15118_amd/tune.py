@@ -5,6 +5,7 @@ computes:
 
 - ``perm_entries``: entries per lane of the key-permutation interpreter;
 - ``group_items``: entries per lane of the interference (group / expand) kernels;
+- ``pair_exchange``: how that launch finds partners in group mode (lane pairs or LDS);
 - ``spec_items``: entries per lane of their speculative fixed-placement launch;
 - ``sort_items``: entries per lane of a radix-sort scatter pass.
 
@@ -29,13 +30,16 @@ from typing import Callable, Dict, Iterable, Optional
 SPACE: Dict[str, tuple] = {
     "perm_entries": (4, 8, 16),
     "group_items": (1, 2, 4),
+    "pair_exchange": (0, 1, 2),
     "spec_items": (1, 2, 4),
     "sort_items": (8, 16),
 }
-DEFAULTS: Dict[str, int] = {"perm_entries": 8, "group_items": 4, "spec_items": 2, "sort_items": 16}
+DEFAULTS: Dict[str, int] = {"perm_entries": 8, "group_items": 4, "pair_exchange": 2, "spec_items": 4,
+                            "sort_items": 16}
 CATEGORIES: Dict[str, tuple] = {
     "perm_entries": ("perm",),
     "group_items": ("group", "expand"),
+    "pair_exchange": ("group",),
     "spec_items": ("group", "expand"),
     "sort_items": ("sort_pass",),
 }

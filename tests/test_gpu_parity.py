@@ -228,8 +228,12 @@ def test_speculative_placement_is_exact(abi, seed):
               wl.random_small_circuit(seed, nops=80, with_init=True)):
         print(f"[case] {c.name} speculation on/off", flush=True)
         outs = []
-        # 1: speculate at any size (expansions; grouped entries too)
-        for opts in ({"speculate": 1, "speculate_group": 1}, {"speculate": 1}, {"speculate": 0}):
+        # 1: speculate at any size (expansions; grouped entries too, with each
+        # way of finding partners and tile size)
+        for opts in ({"speculate": 1, "speculate_group": 1, "pair_exchange": 2, "spec_items": 4},
+                     {"speculate": 1, "speculate_group": 1, "pair_exchange": 1, "spec_items": 2},
+                     {"speculate": 1, "speculate_group": 1, "pair_exchange": 0, "spec_items": 1},
+                     {"speculate": 1, "speculate_group": 0}, {"speculate": 0, "speculate_group": 0}):
             st = _gpu(abi, c, opts=opts)
             outs.append(st.export())
             st.close()

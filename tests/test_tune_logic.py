@@ -46,7 +46,7 @@ def test_coordinate_search_picks_fastest_and_caches(tmp_path):
     assert key == "gfx950/W2/n21/plain"
     best = t.tune(st, st.run, key)
     # spec_items changes no time here: the default stays
-    assert best == {"perm_entries": 4, "group_items": 2, "spec_items": 2, "sort_items": 16}
+    assert best == {"perm_entries": 4, "group_items": 2, "pair_exchange": 2, "spec_items": 4, "sort_items": 16}
     # the winners stay set on the state
     for k, v in best.items():
         assert st.opts[k] == v
