@@ -167,6 +167,10 @@ struct ss_state {
   uint64_t n = 0;                 // exact count (valid when n_known)
   bool n_known = true;
   uint64_t n_ub = 0;              // upper bound of the count (== n when known)
+  // estimate of the count for launch heuristics: exact at read-backs, times
+  // 2^k per expansion, kept by group ops (which grow only where a member
+  // without its partner meets a mixing matrix) and by compactions
+  uint64_t n_est = 0;
   uint32_t n_src_ep = 0;          // launch whose output count is current (0: n is exact)
   uint64_t peak = 0;
   // key masks: OR / AND over all keys, per word
@@ -420,6 +424,7 @@ void set_known(ss_state* st, uint64_t n) {
   st->n = n;
   st->n_known = true;
   st->n_ub = n;
+  st->n_est = n;
   st->n_src_ep = 0;
 }
 
@@ -587,6 +592,7 @@ void after_emit(ss_state* st, uint32_t ep, uint64_t bound, bool logged, uint64_t
   st->nslot ^= 1;
   st->n_known = false;
   st->n_ub = std::min(st->cap, bound);
+  st->n_est = std::min(st->n_est, st->n_ub);
   st->n_src_ep = ep;
   st->masks_valid = false;
   st->mask_ep = ep;
@@ -1397,8 +1403,8 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index, const ss_op* 
     // the compacting launch after it finishes the op either way.
     uint32_t ep_spec = 0, ep;
     int rc = SS_OK;
-    if (g.k == 1 && ((mode == MODE_EXPAND && st->speculate && st->n_ub >= st->speculate) ||
-                     (mode == MODE_GROUP && st->spec_group && st->n_ub >= st->spec_group))) {
+    if (g.k == 1 && ((mode == MODE_EXPAND && st->speculate && st->n_est >= st->speculate) ||
+                     (mode == MODE_GROUP && st->spec_group && st->n_est >= st->spec_group))) {
       if (st->spec_skip) {
         --st->spec_skip;
       } else {
@@ -1419,7 +1425,9 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index, const ss_op* 
     rc = check_launch(st);
     if (rc) return rc;
     st->stats[mode == MODE_GROUP ? 3 : 4]++;
+    const uint64_t est = mode == MODE_EXPAND ? st->n_est << g.k : st->n_est;
     after_emit(st, ep, st->n_ub << g.k, true, op_index);
+    st->n_est = std::min(est, st->n_ub);
     for (int w = 0; w < kMaxW; ++w) sup_vary(st, (uint32_t)w, g.tmask[w]);
     st->grouped = true;
     for (int w = 0; w < kMaxW; ++w) st->gmask[w] = g.tmask[w];
@@ -1922,7 +1930,7 @@ int plan_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst
 struct PlanSnap {
   int cur;
   uint32_t nslot;
-  uint64_t n, n_ub, peak;
+  uint64_t n, n_ub, n_est, peak;
   bool n_known, masks_valid, grouped, poisoned, sup_valid;
   uint32_t n_src_ep, mask_ep, epoch, ops_used, dev_err, spec_skip, spec_backoff, spec_tries;
   uint64_t spec_fail_seen;
@@ -1936,6 +1944,7 @@ PlanSnap save_plan(const ss_state* st) {
   p.nslot = st->nslot;
   p.n = st->n;
   p.n_ub = st->n_ub;
+  p.n_est = st->n_est;
   p.peak = st->peak;
   p.n_known = st->n_known;
   p.masks_valid = st->masks_valid;
@@ -1967,6 +1976,7 @@ void restore_plan(ss_state* st, const PlanSnap& p) {
   st->nslot = p.nslot;
   st->n = p.n;
   st->n_ub = p.n_ub;
+  st->n_est = p.n_est;
   st->peak = p.peak;
   st->n_known = p.n_known;
   st->masks_valid = p.masks_valid;
@@ -2653,6 +2663,7 @@ int ss_graph_launch(ss_graph* g, ss_result* res) {
   st->nslot = g->nslot0;
   st->n_known = false;
   st->n_ub = g->n_end;
+  st->n_est = g->n_end;
   st->n_src_ep = 0;
   st->masks_valid = false;
   st->sup_valid = false;
