@@ -828,6 +828,10 @@ def main():
             "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
             "timing": "HIP event pair around every launch of the kernel on the state's stream, over a second "
                       "pass of the same steps right after the timed one",
+            "limiter": {"perm": "instruction issue of the op interpreter, not HBM: the vector pipe is busy about "
+                                "40 % of the time (SQ counters, profiles/c2_perm_sq_counters.txt)",
+                        "group": "HBM stream of the fixed-placement launch plus a count-only launch",
+                        "expand": "HBM stream with compaction"}.get(dom),
         },
         "hbm_gbps": achieved,
         "gpu_kernel_ms_per_step": gpu_kernel_ms,
