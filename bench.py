@@ -41,7 +41,8 @@ def counter_traffic(kernel_label):
             kv[k.strip()] = v.strip()
     src = os.path.join(ROOT, "paper_2503_15118_amd", "csrc")
     sha = hashlib.sha256(open(os.path.join(src, "kernels.hip"), "rb").read()
-                         + open(os.path.join(src, "kernels_common.hpp"), "rb").read()).hexdigest()[:16]
+                         + open(os.path.join(src, "kernels_common.hpp"), "rb").read()
+                         + open(os.path.join(src, "sparqs_internal.h"), "rb").read()).hexdigest()[:16]
     if kv.get("sources_sha") != sha or ("traffic " + kernel_label) not in kv:
         return None
     return float(kv["traffic " + kernel_label])
@@ -57,7 +58,8 @@ def summarize_profile(pdir):
     import hashlib
     src = os.path.join(ROOT, "paper_2503_15118_amd", "csrc")
     sha = hashlib.sha256(open(os.path.join(src, "kernels.hip"), "rb").read()
-                         + open(os.path.join(src, "kernels_common.hpp"), "rb").read()).hexdigest()[:16]
+                         + open(os.path.join(src, "kernels_common.hpp"), "rb").read()
+                         + open(os.path.join(src, "sparqs_internal.h"), "rb").read()).hexdigest()[:16]
     base = "python3 bench.py --no-cpu-baseline --calibrate-copy"
     out = ["# rocprofv3 kernel statistics: arithmetic-heavy sparse circuit (97-bit key, 2^20 -> 2^21 entries, "
            "1001 ops)",

@@ -762,19 +762,23 @@ void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uin
           nullptr, 0u, nullptr);
     return;
   }
-  if (mode == MODE_GROUP) {
-    k_group<W, K, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
-                                                                         ns, st->cap, g, st->lb, st->meta, ep, xo(st));
-  } else if (st->expand_slots) {
-    // one thread per child: 2^K slots per entry, 4 per thread
+  if (K > kMaxGroupBits || (mode == MODE_EXPAND && st->expand_slots)) {
+    // one thread per child: 2^K slots per entry, 4 per thread (more than
+    // kMaxGroupBits targets come here only as pure expansions that fit)
     constexpr uint32_t kSlotTile = kBlock * 4;
     const uint64_t slots = st->n_ub << K;
     const uint32_t nt = (uint32_t)std::max<uint64_t>(1, (slots + kSlotTile - 1) / kSlotTile);
     k_expand_slots<W, K, 4><<<nt, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g,
                                                            st->lb, st->meta, ep, xo(st));
-  } else {
-    k_group<W, K, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp,
-                                                                          ns, st->cap, g, st->lb, st->meta, ep, xo(st));
+    return;
+  }
+  if constexpr (K <= kMaxGroupBits) {
+    if (mode == MODE_GROUP)
+      k_group<W, K, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(
+          kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st));
+    else
+      k_group<W, K, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(
+          kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st));
   }
 }
 
@@ -853,7 +857,12 @@ void launch_group_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint3
     case 2: launch_group_wk<W, 2>(st, mode, g, ep, 0, none); break;
     case 3: launch_group_wk<W, 3>(st, mode, g, ep, 0, none); break;
     case 4: launch_group_wk<W, 4>(st, mode, g, ep, 0, none); break;
-    default: launch_group_wk<W, 5>(st, mode, g, ep, 0, none); break;
+    case 5: launch_group_wk<W, 5>(st, mode, g, ep, 0, none); break;
+    case 6: launch_group_wk<W, 6>(st, mode, g, ep, 0, none); break;
+    case 7: launch_group_wk<W, 7>(st, mode, g, ep, 0, none); break;
+    case 8: launch_group_wk<W, 8>(st, mode, g, ep, 0, none); break;
+    case 9: launch_group_wk<W, 9>(st, mode, g, ep, 0, none); break;
+    default: launch_group_wk<W, 10>(st, mode, g, ep, 0, none); break;
   }
 }
 
@@ -1323,9 +1332,21 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index, const ss_op* 
       if (!fits(st->n)) return SS_E_CAPACITY;
     }
   }
-  for (size_t c0 = 0; c0 < qs.size(); c0 += kMaxGroupBits) {
+  // A pure expansion (no target bit can vary, by the exact masks or by the
+  // host superset) takes up to kMaxExpandBits targets per launch, one thread
+  // per child; the check above bounds its output by the capacity.
+  size_t chunk = kMaxGroupBits;
+  if (st->expand_slots && nchain < 2 && qs.size() > (size_t)kMaxGroupBits) {
+    uint64_t tm = 0;
+    for (uint32_t q : qs) tm |= 1ull << (d.shift + q);
+    const uint64_t var = st->masks_valid ? (st->orm[d.word] & ~st->andm[d.word])
+                         : st->sup_valid  ? (st->sorm[d.word] & ~st->sandm[d.word])
+                                          : ~0ull;
+    if ((var & tm) == 0) chunk = kMaxExpandBits;
+  }
+  for (size_t c0 = 0; c0 < qs.size(); c0 += chunk) {
     if (st->n_ub == 0) return SS_OK;
-    const size_t c1 = std::min(qs.size(), c0 + kMaxGroupBits);
+    const size_t c1 = std::min(qs.size(), c0 + chunk);
     const bool last = c1 == qs.size();
     GroupOp g{};
     g.k = (uint32_t)(c1 - c0);
@@ -1398,6 +1419,8 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index, const ss_op* 
       }
       if (st->n_ub == 0) return SS_OK;
     }
+    // more than kMaxGroupBits targets only as a pure expansion
+    if (g.k > (uint32_t)kMaxGroupBits && mode != MODE_EXPAND) return SS_E_STATE;
     // one-target op on many entries: try the fixed placement first (two
     // children per entry in expand mode, one in group mode; no look-back);
     // the compacting launch after it finishes the op either way.

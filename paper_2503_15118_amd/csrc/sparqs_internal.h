@@ -14,6 +14,7 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxFields = 8;       // contiguous bit runs that make up one digit
 constexpr int kMaxPasses = 40;      // up to 256 key bits + 5 target bits, 8 bits per pass
 constexpr int kMaxGroupBits = 5;    // targets fused into one interference op (2^5 group)
+constexpr int kMaxExpandBits = 10;  // targets of one pure expansion (one thread per child, 2^10 children)
 constexpr int kRing = 128;          // per-launch slots (tile counter, count, key masks)
 constexpr int kOpChunk = 128;       // op records staged in LDS at a time by the interpreter
 constexpr int kXcds = 8;            // XCDs of an MI355X
@@ -138,13 +139,13 @@ struct ChainStep {
 
 // One branching (interference) op as seen by the group/expand kernel.
 struct GroupOp {
-  uint32_t k;                   // number of target qubits (1..kMaxGroupBits); 0 = plain filter
+  uint32_t k;                   // target qubits (1..kMaxGroupBits; up to kMaxExpandBits in expand mode)
   uint32_t has_ctl;
   uint32_t upd;                 // ops to count: the update counter gains upd x the input count
   uint32_t nchain;              // k == 1 only: > 0 applies chain[0..nchain) (m, cmask, cval unused)
   const ChainStep* chain;       // device array
-  uint32_t tword[kMaxGroupBits];  // target j: key word and bit, ascending qubit order
-  uint32_t tbit[kMaxGroupBits];
+  uint32_t tword[kMaxExpandBits];  // target j: key word and bit, ascending qubit order
+  uint32_t tbit[kMaxExpandBits];
   uint64_t tmask[kMaxW];        // all target bits per word
   uint64_t cmask[kMaxW];
   uint64_t cval[kMaxW];
