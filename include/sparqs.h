@@ -223,7 +223,7 @@ int ss_graph_destroy(ss_graph* g);
 int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
 
 /* Tuning/debug knobs: "sort_items" (8|16), "grouping" (1: reuse grouped
- * order across ops, 0: always sort), "group_items" (1|2|4), "perm_entries"
+ * order across ops, 0: always sort), "group_items" (1|2|4, default 2), "perm_entries"
  * (4|8|16), "tile_order" (1: per-XCD tile tickets when the device allows, 0: one
  * counter; required when states run concurrently on one GPU), "speculate" (an
  * entry count, default 2^23, 0 = never: a one-target expansion on at least

@@ -235,7 +235,7 @@ struct ss_state {
   // options
   int sort_items = 16;
   int grouping = 1;
-  int group_items = 4;
+  int group_items = 2;
   int perm_entries = 8;
   // option: a one-target expansion on at least this many entries (upper
   // bound) first tries the fixed-fan-out placement; 0 never.  Below a few
