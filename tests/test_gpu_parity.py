@@ -247,6 +247,36 @@ def test_speculative_placement_is_exact(abi, seed):
         compare(k1, a1, ok, oa, c.eps)
 
 
+@pytest.mark.parametrize("form", ["pure", "controlled", "varying"])
+def test_many_target_expansions(abi, form):
+    """H / Ry on 6..10 target qubits of one register: as one launch of one
+    thread per child when no target bit can vary (with and without a control
+    that fails for some entries), in launches of at most 5 targets with
+    grouping when some do; all against the oracle, and the one-launch path
+    against the one-thread-per-entry path of at most 5 targets."""
+    mk = wl.make_op
+    regs = [("a", 10), ("b", 4), ("f", 1)]
+    rng = np.random.default_rng(90 + len(form))
+    ops = [mk("H", 1, qmask=0xF)]
+    if form == "varying":
+        ops.append(mk("H", 0, qmask=0b1000100))            # targets 2 and 6 now vary
+    ctls = [(1, 2, 1)] if form == "controlled" else []
+    ops.append(mk("H", 0, qmask=0x3FF, ctls=ctls))
+    ops.append(mk("ADD", 0, reg2=1))
+    ops.append(mk("RY", 0, qmask=0x3F0, theta=float(rng.uniform(0, 6.28))))
+    c = wl.Circuit(regs=regs, ops=wl.ops_array(ops), eps=1e-14, name=f"many-targets-{form}")
+    # (an op split over several launches is admitted when n 2^k fits)
+    s = _check(abi, c, cap=1 << 21)
+    assert s["n_oracle"] > 0
+    outs = []
+    for opts in ({}, {"expand_slots": 0}):
+        st = _gpu(abi, c, cap=1 << 21, opts=opts)
+        outs.append(st.export())
+        st.close()
+    (k1, a1), (k0, a0) = outs
+    compare(k1, a1, k0, a0, c.eps)
+
+
 def test_wasted_speculation_cools_down(abi):
     """H on a flag qubit again and again: every expansion fits the fixed
     placement and every merge defeats it.  After a wasted speculative launch
