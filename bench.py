@@ -594,7 +594,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-ops", type=int, default=16)
     ap.add_argument("--grouping", type=int, default=1, help="0: sort before every interference op")
-    ap.add_argument("--group-items", type=int, default=2)
+    ap.add_argument("--group-items", type=int, default=4)
     ap.add_argument("--sort-items", type=int, default=16)
     ap.add_argument("--perm-entries", type=int, default=8)
     ap.add_argument("--spec-items", type=int, default=4)

@@ -223,7 +223,8 @@ int ss_graph_destroy(ss_graph* g);
 int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
 
 /* Tuning/debug knobs: "sort_items" (8|16), "grouping" (1: reuse grouped
- * order across ops, 0: always sort), "group_items" (1|2|4, default 2), "perm_entries"
+ * order across ops, 0: always sort), "group_items" (1|2|4, default 4; launches that carry a chain or
+ * a run use at most 2), "perm_entries"
  * (4|8|16), "tile_order" (1: per-XCD tile tickets when the device allows, 0: one
  * counter; required when states run concurrently on one GPU), "speculate" (an
  * entry count, default 2^23, 0 = never: a one-target expansion on at least
@@ -240,9 +241,9 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
  * "speculate_group" (as "speculate" for one-target ops on grouped entries,
  * default 2^21; there a merge or an entry without its partner defeats the
  * fixed placement, so after a wasted speculative launch the next 64
- * eligible launches skip themselves, and after a read-back that sees it the
- * next 64 eligible ops do not speculate, twice as many each time this
- * repeats), "spec_items" (1|2|4, default 4: entries per thread of the
+ * eligible launches of the same mode (group or expand) skip themselves, and
+ * after a read-back that sees it the next 64 eligible ops of that mode do not
+ * speculate, twice as many each time this repeats), "spec_items" (1|2|4, default 4: entries per thread of the
  * speculative launch), "pair_exchange" (how a speculative group-mode launch
  * finds partners: 2, default, only at e ^ 1 through a lane-pair exchange, a
  * tile without that alignment defeating the speculation; 1 the same with

@@ -1286,7 +1286,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_spec(KeyPtrs<W> in_keys, const 
   __shared__ __align__(16) uint64_t s_stage[kStageWords > kRunWords ? kStageWords : kRunWords];
   if (launch_prologue(meta, epoch)) return;
   // cooling down after a wasted speculation: the compacting launch does the op
-  if (*reinterpret_cast<volatile unsigned int*>(&meta->spec_cool) != 0u) {
+  if (*reinterpret_cast<volatile unsigned int*>(&meta->spec_cool[MODE]) != 0u) {
     if (blockIdx.x == 0 && threadIdx.x == 0) meta->spec_irr[epoch % kRing] = kSpecSkipped;
     return;
   }
@@ -1366,13 +1366,13 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
   if (sflag != 0u) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       if (sflag == kSpecSkipped) {
-        const unsigned int c = meta->spec_cool;
-        meta->spec_cool = c ? c - 1u : 0u;
+        const unsigned int c = meta->spec_cool[MODE];
+        meta->spec_cool[MODE] = c ? c - 1u : 0u;
       } else {
         // the speculative launch was wasted: counted (the host stops trying at
         // its next read-back) and the next kSpecCool launches skip themselves
-        atomicAdd(&meta->spec_fail, 1ull);
-        meta->spec_cool = kSpecCool;
+        atomicAdd(&meta->spec_fail[MODE], 1ull);
+        meta->spec_cool[MODE] = kSpecCool;
       }
     }
   } else if (spec_ep != 0) {
@@ -2012,8 +2012,8 @@ __global__ void k_meta_init(DevMeta* meta) {
     }
     meta->peak = 0;
     meta->upd = 0;
-    meta->spec_fail = 0;
-    meta->spec_cool = 0;
+    meta->spec_fail[0] = meta->spec_fail[1] = 0;
+    meta->spec_cool[0] = meta->spec_cool[1] = 0;
     meta->nring[0] = meta->nring[1] = 0;
     meta->err = 0;
     meta->err_epoch = 0;

@@ -235,7 +235,7 @@ struct ss_state {
   // options
   int sort_items = 16;
   int grouping = 1;
-  int group_items = 2;
+  int group_items = 4;
   int perm_entries = 8;
   // option: a one-target expansion on at least this many entries (upper
   // bound) first tries the fixed-fan-out placement; 0 never.  Below a few
@@ -253,10 +253,11 @@ struct ss_state {
   uint32_t spec_items = 4;       // option: entries per thread of the speculative launch (1|2|4)
   int expand_slots = 1;          // option: expansions on 2..5 targets one thread per child (0: per entry)
   uint32_t pair_exchange = 2;    // option: how speculative group launches find partners (0 | 1 | 2)
-  uint64_t spec_fail_seen = 0;   // device count of wasted speculative launches at the last read-back
-  uint32_t spec_skip = 0;        // eligible ops left that do not speculate
-  uint32_t spec_backoff = kSpecCool;  // the next skip length (doubles while launches keep being wasted)
-  uint32_t spec_tries = 0;       // speculative launches since the last read-back
+  // per mode (group, expand):
+  uint64_t spec_fail_seen[2] = {0, 0};  // device count of wasted speculative launches at the last read-back
+  uint32_t spec_skip[2] = {0, 0};       // eligible ops left that do not speculate
+  uint32_t spec_backoff[2] = {kSpecCool, kSpecCool};  // the next skip length (doubles while wasted)
+  uint32_t spec_tries[2] = {0, 0};      // speculative launches since the last read-back
   int chain = 1;                 // option: consecutive one-target ops on one target in one launch
   // option: a one-target op applies the run that follows it when the run has
   // at most this many ops (0: never).  A long run is issue-bound and runs
@@ -483,16 +484,18 @@ int sync_state(ss_state* st) {
   trace_flush(st);
   st->peak = hm->peak;
   st->stats[7] = hm->upd;
-  if (hm->spec_fail != st->spec_fail_seen) {
-    // wasted speculation since the last read-back: skip it for a while, twice
-    // as long each time this repeats
-    st->spec_fail_seen = hm->spec_fail;
-    st->spec_skip = st->spec_backoff;
-    st->spec_backoff = std::min<uint32_t>(st->spec_backoff * 2u, 1u << 20);
-  } else if (st->spec_tries) {
-    st->spec_backoff = kSpecCool;
+  for (int md = 0; md < 2; ++md) {
+    if (hm->spec_fail[md] != st->spec_fail_seen[md]) {
+      // wasted speculation since the last read-back: skip it for a while,
+      // twice as long each time this repeats
+      st->spec_fail_seen[md] = hm->spec_fail[md];
+      st->spec_skip[md] = st->spec_backoff[md];
+      st->spec_backoff[md] = std::min<uint32_t>(st->spec_backoff[md] * 2u, 1u << 20);
+    } else if (st->spec_tries[md]) {
+      st->spec_backoff[md] = kSpecCool;
+    }
+    st->spec_tries[md] = 0;
   }
-  st->spec_tries = 0;
   if (hm->err & ~(kErrCapacity | kErrPlan)) {
     st->emits.clear();
     st->plan_log.clear();
@@ -838,7 +841,11 @@ void launch_spec_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep_spec, c
 // tile-id atomics), one for 8..32-member groups (register budget).
 template <int W, int K>
 void launch_group_wk(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec, const FusedRun& run) {
-  const int items = K <= 2 ? st->group_items : 1;
+  int items = K <= 2 ? st->group_items : 1;
+  // A chained or run-carrying launch is latency-bound (a product of up to 16
+  // matrices, an interpreted run): at most 2 entries per thread, for more
+  // waves per SIMD.
+  if ((g.nchain || run.n) && items > 2) items = 2;
   if (K <= 2 && items >= 4) launch_group_wki<W, K, (K <= 2 ? 4 : 1)>(st, mode, g, ep, ep_spec, run);
   else if (K <= 2 && items == 2) launch_group_wki<W, K, (K <= 2 ? 2 : 1)>(st, mode, g, ep, ep_spec, run);
   else launch_group_wki<W, K, 1>(st, mode, g, ep, ep_spec, run);
@@ -1428,11 +1435,11 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index, const ss_op* 
     int rc = SS_OK;
     if (g.k == 1 && ((mode == MODE_EXPAND && st->speculate && st->n_est >= st->speculate) ||
                      (mode == MODE_GROUP && st->spec_group && st->n_est >= st->spec_group))) {
-      if (st->spec_skip) {
-        --st->spec_skip;
+      if (st->spec_skip[mode]) {
+        --st->spec_skip[mode];
       } else {
         rc = begin_launch(st, &ep_spec);
-        ++st->spec_tries;
+        ++st->spec_tries[mode];
       }
     }
     if (!rc) rc = begin_launch(st, &ep);
@@ -1955,8 +1962,8 @@ struct PlanSnap {
   uint32_t nslot;
   uint64_t n, n_ub, n_est, peak;
   bool n_known, masks_valid, grouped, poisoned, sup_valid;
-  uint32_t n_src_ep, mask_ep, epoch, ops_used, dev_err, spec_skip, spec_backoff, spec_tries;
-  uint64_t spec_fail_seen;
+  uint32_t n_src_ep, mask_ep, epoch, ops_used, dev_err, spec_skip[2], spec_backoff[2], spec_tries[2];
+  uint64_t spec_fail_seen[2];
   uint64_t orm[kMaxW], andm[kMaxW], gmask[kMaxW], sorm[kMaxW], sandm[kMaxW];
   uint64_t stats[8];
 };
@@ -1979,10 +1986,12 @@ PlanSnap save_plan(const ss_state* st) {
   p.epoch = st->epoch;
   p.ops_used = st->ops_used;
   p.dev_err = st->dev_err;
-  p.spec_skip = st->spec_skip;
-  p.spec_backoff = st->spec_backoff;
-  p.spec_tries = st->spec_tries;
-  p.spec_fail_seen = st->spec_fail_seen;
+  for (int md = 0; md < 2; ++md) {
+    p.spec_skip[md] = st->spec_skip[md];
+    p.spec_backoff[md] = st->spec_backoff[md];
+    p.spec_tries[md] = st->spec_tries[md];
+    p.spec_fail_seen[md] = st->spec_fail_seen[md];
+  }
   for (int w = 0; w < kMaxW; ++w) {
     p.orm[w] = st->orm[w];
     p.andm[w] = st->andm[w];
@@ -2011,10 +2020,12 @@ void restore_plan(ss_state* st, const PlanSnap& p) {
   st->epoch = p.epoch;
   st->ops_used = p.ops_used;
   st->dev_err = p.dev_err;
-  st->spec_skip = p.spec_skip;
-  st->spec_backoff = p.spec_backoff;
-  st->spec_tries = p.spec_tries;
-  st->spec_fail_seen = p.spec_fail_seen;
+  for (int md = 0; md < 2; ++md) {
+    st->spec_skip[md] = p.spec_skip[md];
+    st->spec_backoff[md] = p.spec_backoff[md];
+    st->spec_tries[md] = p.spec_tries[md];
+    st->spec_fail_seen[md] = p.spec_fail_seen[md];
+  }
   for (int w = 0; w < kMaxW; ++w) {
     st->orm[w] = p.orm[w];
     st->andm[w] = p.andm[w];
@@ -2512,10 +2523,10 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes) {
   for (auto& t : st->tables) t.dev = st->tab_base + (static_cast<char*>(t.dev) - old_tab);
   rc = init_device(st);
   if (rc) return rc;
-  const uint64_t spec_fail = st->spec_fail_seen;
+  const uint64_t spec_fail[2] = {st->spec_fail_seen[0], st->spec_fail_seen[1]};
   if (hipMemcpyAsync(&st->meta->peak, &peak, 8, hipMemcpyHostToDevice, st->stream) != hipSuccess ||
       hipMemcpyAsync(&st->meta->upd, &upd, 8, hipMemcpyHostToDevice, st->stream) != hipSuccess ||
-      hipMemcpyAsync(&st->meta->spec_fail, &spec_fail, 8, hipMemcpyHostToDevice, st->stream) != hipSuccess)
+      hipMemcpyAsync(st->meta->spec_fail, spec_fail, 16, hipMemcpyHostToDevice, st->stream) != hipSuccess)
     return hip_fail(st);
   set_known(st, n);
   k_set_n<<<1, 64, 0, st->stream>>>(st->meta, st->nslot, n);
@@ -2786,7 +2797,7 @@ int ss_device_error(const ss_state* st, uint32_t* bits) {
 int ss_stats(const ss_state* st, uint64_t* out9) {
   if (!st || !out9) return SS_E_ARG;
   for (int i = 0; i < 8; ++i) out9[i] = st->stats[i];
-  out9[8] = st->spec_fail_seen;
+  out9[8] = st->spec_fail_seen[0] + st->spec_fail_seen[1];
   return SS_OK;
 }
 

@@ -36,8 +36,9 @@ constexpr uint32_t kErrGroup = 1u << 2;      // two group members share a target
 constexpr uint32_t kErrGrid = 1u << 3;       // a grid was sized below the entry count (host bug)
 constexpr uint32_t kErrPlan = 1u << 4;       // a graph replay met a count or key mask its plan did not
 // After a speculative fixed-placement launch is wasted, this many eligible
-// ops skip speculation (on the device until the next read-back, then on the
-// host); a skipped launch leaves kSpecSkipped in its flag.
+// ops of the same mode (group or expand) skip speculation (on the device
+// until the next read-back, then on the host); a skipped launch leaves
+// kSpecSkipped in its flag.
 constexpr uint32_t kSpecCool = 64;
 constexpr unsigned int kSpecSkipped = 2u;
 
@@ -51,7 +52,7 @@ struct DevMeta {
   unsigned int err;                          // kErr* bits, sticky until the host clears them
   unsigned int err_epoch;                    // epoch of the launch that raised the first error
   unsigned long long upd;                    // entries updated: sum over ops of the input count
-  unsigned long long spec_fail;              // speculative launches that met an irregular tile
+  unsigned long long spec_fail[2];           // speculative launches that met an irregular tile, per mode
   unsigned long long nnz_out[kRing];         // entry count written by an emitting kernel
   unsigned long long or_mask[kRing][kMaxW];  // OR of the produced keys, per word
   unsigned long long and_mask[kRing][kMaxW]; // AND of the produced keys, per word
@@ -60,7 +61,7 @@ struct DevMeta {
   unsigned long long uscratch[16];
   unsigned long long counters[kRing];        // dynamic tile ids (one ticket per launch)
   unsigned int spec_irr[kRing];              // speculative launch: 1 met an irregular tile, kSpecSkipped skipped
-  unsigned int spec_cool;                    // speculative launches left to skip after a wasted one
+  unsigned int spec_cool[2];                 // speculative launches left to skip after a wasted one, per mode
   unsigned long long xcd_ctr[kRing][kXcds * kXcdStride];  // per-XCD tickets
 };
 

@@ -34,7 +34,7 @@ SPACE: Dict[str, tuple] = {
     "spec_items": (1, 2, 4),
     "sort_items": (8, 16),
 }
-DEFAULTS: Dict[str, int] = {"perm_entries": 8, "group_items": 2, "pair_exchange": 2, "spec_items": 4,
+DEFAULTS: Dict[str, int] = {"perm_entries": 8, "group_items": 4, "pair_exchange": 2, "spec_items": 4,
                             "sort_items": 16}
 CATEGORIES: Dict[str, tuple] = {
     "perm_entries": ("perm",),
