@@ -1184,6 +1184,23 @@ __device__ __forceinline__ void pair_write(KeyPtrs<W>& out_keys, double2* __rest
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     uint64_t p = pos[it];
+    if (keepm[it] == 3u && (p & 1ull) == 0 && p + 1 < cap) {
+      // both children at an even position: one 16-byte store per key word
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        uint64_t k0 = key[it][w], k1 = key[it][w];
+        if ((uint32_t)w == tw) {
+          k0 &= ~tbit;
+          k1 |= tbit;
+        }
+        *reinterpret_cast<ulonglong2*>(&out_keys.w[w][p]) = make_ulonglong2(k0, k1);
+        orv[w] |= k0 | k1;
+        andv[w] &= k0 & k1;
+      }
+      out_amp[p] = out[it][0];
+      out_amp[p + 1] = out[it][1];
+      continue;
+    }
 #pragma unroll
     for (uint32_t r = 0; r < 2; ++r) {
       if (!((keepm[it] >> r) & 1u)) continue;
@@ -1225,11 +1242,8 @@ __device__ __forceinline__ void run_children(const GroupOp& op, const uint64_t (
   static_assert(W <= 2, "runs are fused for keys of at most 2 words");
   const uint32_t tw = op.tword[0];
   const uint64_t tbit = 1ull << op.tbit[0];
-#pragma nounroll
-  for (uint32_t pass = 0; pass < 2; ++pass) {
-    uint32_t h[ITEMS][4];
-    double2 ca[ITEMS];
-    bool has[ITEMS];
+  // the children of one pass as 32-bit key halves and amplitudes
+  auto load = [&](uint32_t pass, uint32_t (&h)[ITEMS][4], double2 (&ca)[ITEMS], bool (&has)[ITEMS]) {
     bool any = false;
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
@@ -1247,20 +1261,52 @@ __device__ __forceinline__ void run_children(const GroupOp& op, const uint64_t (
       ca[it] = r ? out[it][1] : out[it][0];
       any = any || has[it];
     }
-    if (pass == 1 && !__syncthreads_or(any)) break;
-    run_ops_lds<W, ITEMS>(h, ca, rops, rn, rgops, reinterpret_cast<uint4*>(s_stage));
+    return any;
+  };
+  uint32_t h0[ITEMS][4], h1[ITEMS][4];
+  double2 a0[ITEMS], a1[ITEMS];
+  bool has0[ITEMS], has1[ITEMS];
+  (void)load(0, h0, a0, has0);
+  run_ops_lds<W, ITEMS>(h0, a0, rops, rn, rgops, reinterpret_cast<uint4*>(s_stage));
+  const bool two = __syncthreads_or(load(1, h1, a1, has1)) != 0;
+  if (two) run_ops_lds<W, ITEMS>(h1, a1, rops, rn, rgops, reinterpret_cast<uint4*>(s_stage));
+  // Both children of an item are written together: at an even position the
+  // key words of the pair go out as one 16-byte store per word, so a wave's
+  // stores cover whole lines instead of every other word.
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      if (!has[it]) continue;
-      const uint64_t p = pos[it] + pass;
+  for (int it = 0; it < ITEMS; ++it) {
+    if (!has0[it]) continue;
+    const uint64_t p = pos[it];
+    const bool pair = two && has1[it];
+    uint64_t v0[W], v1[W];
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const uint64_t v = (uint64_t)h[it][2 * w] | ((uint64_t)h[it][2 * w + 1] << 32);
-        if (p < cap) out_keys.w[w][p] = v;
-        orv[w] |= v;
-        andv[w] &= v;
+    for (int w = 0; w < W; ++w) {
+      v0[w] = (uint64_t)h0[it][2 * w] | ((uint64_t)h0[it][2 * w + 1] << 32);
+      v1[w] = (uint64_t)h1[it][2 * w] | ((uint64_t)h1[it][2 * w + 1] << 32);
+      orv[w] |= v0[w];
+      andv[w] &= v0[w];
+      if (pair) {
+        orv[w] |= v1[w];
+        andv[w] &= v1[w];
       }
-      if (p < cap) out_amp[p] = ca[it];
+    }
+    if (pair && (p & 1ull) == 0 && p + 1 < cap) {
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        *reinterpret_cast<ulonglong2*>(&out_keys.w[w][p]) = make_ulonglong2(v0[w], v1[w]);
+      out_amp[p] = a0[it];
+      out_amp[p + 1] = a1[it];
+    } else {
+      if (p < cap) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) out_keys.w[w][p] = v0[w];
+        out_amp[p] = a0[it];
+      }
+      if (pair && p + 1 < cap) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) out_keys.w[w][p + 1] = v1[w];
+        out_amp[p + 1] = a1[it];
+      }
     }
   }
 }
