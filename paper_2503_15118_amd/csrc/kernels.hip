@@ -531,7 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(KeyPtrs<W> keys, uint32_t 
 
 // Sum the per-workgroup histograms of pass blockIdx.x and scan them into the
 // first global position of every digit.
-__global__ __launch_bounds__(kBlock) void k_sort_scan(const uint32_t* __restrict__ partial,
+static __global__ __launch_bounds__(kBlock) void k_sort_scan(const uint32_t* __restrict__ partial,
                                                       uint32_t nblk, uint32_t np,
                                                       uint64_t* __restrict__ digit_start) {
   __shared__ uint64_t s_tmp[4];
@@ -1947,12 +1947,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
 // ---------------------------------------------------------------------------
 // utility kernels
 // ---------------------------------------------------------------------------
-__global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+static __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
-__global__ void k_ring_init(DevMeta* meta) {
+static __global__ void k_ring_init(DevMeta* meta) {
   if (blockIdx.x != 0) return;
   for (int r = threadIdx.x; r < kRing; r += blockDim.x) {
     meta->counters[r] = 0;
@@ -1971,7 +1971,7 @@ __global__ void k_ring_init(DevMeta* meta) {
 // over the entries, per the OR / AND masks in that ring slot, must lie inside
 // `allowed`.  Otherwise raise kErrPlan tagged `epoch`; every later launch then
 // changes nothing.  An earlier error takes precedence.
-__global__ void k_plan_guard(DevMeta* meta, uint32_t ns, uint64_t n_expect, int mask_slot, PlanVar allowed,
+static __global__ void k_plan_guard(DevMeta* meta, uint32_t ns, uint64_t n_expect, int mask_slot, PlanVar allowed,
                              uint32_t epoch) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (*reinterpret_cast<volatile unsigned int*>(&meta->err) != 0u) return;
@@ -1999,11 +1999,11 @@ __global__ __launch_bounds__(kBlock) void k_copy_state(KeyPtrs<W> in_keys, const
 }
 
 // XCD of each of the first gridDim.x workgroups (checks the round-robin spread).
-__global__ void k_xcc_probe(uint64_t* out) {
+static __global__ void k_xcc_probe(uint64_t* out) {
   if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
-__global__ void k_clear_err(DevMeta* meta) {
+static __global__ void k_clear_err(DevMeta* meta) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     meta->err = 0;
     meta->err_epoch = 0;
@@ -2011,7 +2011,7 @@ __global__ void k_clear_err(DevMeta* meta) {
 }
 
 // Host-known entry count into ring slot `ns` (after imports and rebinds).
-__global__ void k_set_n(DevMeta* meta, uint32_t ns, uint64_t n) {
+static __global__ void k_set_n(DevMeta* meta, uint32_t ns, uint64_t n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     meta->nring[ns & 1] = n;
     if (n > meta->peak) meta->peak = n;
@@ -2044,7 +2044,7 @@ __global__ __launch_bounds__(kBlock) void k_masks(KeyPtrs<W> keys, uint32_t ns, 
   publish_masks<W>(meta, epoch, orv, andv, s_red);
 }
 
-__global__ void k_meta_init(DevMeta* meta) {
+static __global__ void k_meta_init(DevMeta* meta) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     for (int r = 0; r < kRing; ++r) {
       meta->counters[r] = 0;
@@ -2170,7 +2170,7 @@ __global__ __launch_bounds__(kBlock) void k_prob_tiles(KeyPtrs<W> keys, const do
 }
 
 // Sequential exclusive scan of the tile sums (one thread; fixed order).
-__global__ void k_prob_scan(double* tile_sum, uint64_t ntiles, double* total) {
+static __global__ void k_prob_scan(double* tile_sum, uint64_t ntiles, double* total) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double run = 0.0;
   for (uint64_t t = 0; t < ntiles; ++t) {

@@ -1,0 +1,36 @@
+// Launchers of the LSD radix sort (digit histograms, their scan, scatter
+// passes) for every key width.
+#include "kernels.hip"
+#include "launch.h"
+
+namespace sparqs {
+
+template <int W>
+void launch_sort_hist(const LaunchCtx& c, uint32_t nb, const SortPlan& plan, uint32_t* hist, uint64_t* digit_start) {
+  KeyPtrs<W> k;
+  for (int w = 0; w < W; ++w) k.w[w] = c.in.key[w];
+  k_sort_hist<W><<<nb, kBlock, plan.npass * kRadix * 4, c.stream>>>(k, c.ns, c.meta, plan, hist);
+  k_sort_scan<<<plan.npass, kBlock, 0, c.stream>>>(hist, nb, plan.npass, digit_start);
+}
+
+template <int W>
+void launch_sort_pass(const LaunchCtx& c, int items, uint32_t ntiles, const PassDesc& pd,
+                      const uint64_t* digit_start, uint32_t ep) {
+  KeyPtrs<W> ik, ok;
+  for (int w = 0; w < W; ++w) { ik.w[w] = c.in.key[w]; ok.w[w] = c.out.key[w]; }
+  if (items == 16)
+    k_sort_pass<W, 16><<<ntiles, kBlock, 0, c.stream>>>(ik, c.in.amp, ok, c.out.amp, c.ns, pd, digit_start, c.lb,
+                                                         c.meta, ep, c.xo);
+  else
+    k_sort_pass<W, 8><<<ntiles, kBlock, 0, c.stream>>>(ik, c.in.amp, ok, c.out.amp, c.ns, pd, digit_start, c.lb,
+                                                        c.meta, ep, c.xo);
+}
+
+template void launch_sort_hist<1>(const LaunchCtx&, uint32_t, const SortPlan&, uint32_t*, uint64_t*);
+template void launch_sort_hist<2>(const LaunchCtx&, uint32_t, const SortPlan&, uint32_t*, uint64_t*);
+template void launch_sort_hist<4>(const LaunchCtx&, uint32_t, const SortPlan&, uint32_t*, uint64_t*);
+template void launch_sort_pass<1>(const LaunchCtx&, int, uint32_t, const PassDesc&, const uint64_t*, uint32_t);
+template void launch_sort_pass<2>(const LaunchCtx&, int, uint32_t, const PassDesc&, const uint64_t*, uint32_t);
+template void launch_sort_pass<4>(const LaunchCtx&, int, uint32_t, const PassDesc&, const uint64_t*, uint32_t);
+
+}  // namespace sparqs

@@ -14,6 +14,7 @@
 // count and key masks after each branching op (a pinned 2 KB block).
 #include "../../include/sparqs.h"
 #include "kernels.hip"
+#include "launch.h"
 
 #include <algorithm>
 #include <cmath>
@@ -45,11 +46,6 @@ struct TableInfo {
   void* dev;
   uint32_t addr_bits, word_bits;
   bool w32;
-};
-
-struct Buf {
-  uint64_t* key[kMaxW];
-  double2* amp;
 };
 
 struct Layout {
@@ -307,6 +303,21 @@ int hip_fail(ss_state* st) {
 }
 
 uint32_t xo(const ss_state* st) { return (st->xcd_order && st->tile_order_opt) ? 1u : 0u; }
+
+// Launch context: read buf[cur], write buf[cur ^ 1].
+LaunchCtx ctx(const ss_state* st) {
+  LaunchCtx c;
+  c.stream = st->stream;
+  c.in = st->buf[st->cur];
+  c.out = st->buf[st->cur ^ 1];
+  c.ns = st->nslot;
+  c.cap = st->cap;
+  c.n_ub = st->n_ub;
+  c.lb = st->lb;
+  c.meta = st->meta;
+  c.xo = xo(st);
+  return c;
+}
 
 int check_launch(ss_state* st) {
   if (hipGetLastError() != hipSuccess) return hip_fail(st);
@@ -671,9 +682,7 @@ int run_sort_w(ss_state* st, const SortPlan& plan) {
   const uint64_t tile = (uint64_t)kBlock * items;
   const uint32_t nb = (uint32_t)std::min<uint64_t>(st->cv.hist_blocks, (n + 4095) / 4096);
   int tr = trace_begin(st, SS_TRACE_SORT_HIST);
-  k_sort_hist<W><<<nb, kBlock, plan.npass * kRadix * 4, st->stream>>>(kp<W>(st->buf[st->cur]), st->nslot,
-                                                                       st->meta, plan, st->hist);
-  k_sort_scan<<<plan.npass, kBlock, 0, st->stream>>>(st->hist, nb, plan.npass, st->digit_start);
+  launch_sort_hist<W>(ctx(st), nb, plan, st->hist, st->digit_start);
   trace_end(st, tr, 8ull * W, 1, 0, 0);
   st->stats[0] += 2;
   const uint32_t ntiles = (uint32_t)((n + tile - 1) / tile);
@@ -681,17 +690,8 @@ int run_sort_w(ss_state* st, const SortPlan& plan) {
     uint32_t ep;
     int rc = begin_launch(st, &ep);
     if (rc) return rc;
-    const Buf& in = st->buf[st->cur];
-    const Buf& out = st->buf[st->cur ^ 1];
     tr = trace_begin(st, SS_TRACE_SORT_PASS);
-    if (items == 16)
-      k_sort_pass<W, 16><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
-                                                             plan.pass[p], st->digit_start + p * kRadix,
-                                                             st->lb, st->meta, ep, xo(st));
-    else
-      k_sort_pass<W, 8><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
-                                                            plan.pass[p], st->digit_start + p * kRadix,
-                                                            st->lb, st->meta, ep, xo(st));
+    launch_sort_pass<W>(ctx(st), items, ntiles, plan.pass[p], st->digit_start + p * kRadix, ep);
     trace_end(st, tr, 2 * entry_bytes(W), 1, 0, 0);
     st->cur ^= 1;
     st->flips++;
@@ -725,152 +725,24 @@ int sort_canonical(ss_state* st) {
 // ---------------------------------------------------------------------------
 // emitting kernels (group / expand / filter): read buf[cur], write buf[cur^1]
 // ---------------------------------------------------------------------------
-// A run of non-branching ops fused into a one-target launch (rn == 0: none).
-struct FusedRun {
-  const FastOp* ops;
-  uint32_t n;
-  const PermOp* gops;
-};
-
-template <int W, int K, int ITEMS>
-void launch_group_wki(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec,
-                      const FusedRun& run) {
-  const Buf& in = st->buf[st->cur];
-  const Buf& out = st->buf[st->cur ^ 1];
-  const uint32_t ns = st->nslot;
-  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock * ITEMS - 1) / (kBlock * ITEMS));
-  if (K == 1) {
-    // one child per entry in group mode, two in expand mode
-    const uint32_t f = mode == MODE_GROUP ? 1u : 2u;
-    if constexpr (W <= 2) {
-      if (run.n) {
-        if (mode == MODE_GROUP)
-          k_pair<W, MODE_GROUP, ITEMS, true><<<ntiles, kBlock, 0, st->stream>>>(
-              kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), ep_spec, f,
-              run.ops, run.n, run.gops);
-        else
-          k_pair<W, MODE_EXPAND, ITEMS, true><<<ntiles, kBlock, 0, st->stream>>>(
-              kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), ep_spec, f,
-              run.ops, run.n, run.gops);
-        return;
-      }
-    }
-    if (mode == MODE_GROUP)
-      k_pair<W, MODE_GROUP, ITEMS, false><<<ntiles, kBlock, 0, st->stream>>>(
-          kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), ep_spec, f,
-          nullptr, 0u, nullptr);
-    else
-      k_pair<W, MODE_EXPAND, ITEMS, false><<<ntiles, kBlock, 0, st->stream>>>(
-          kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st), ep_spec, f,
-          nullptr, 0u, nullptr);
-    return;
-  }
-  if (K > kMaxGroupBits || (mode == MODE_EXPAND && st->expand_slots)) {
-    // one thread per child: 2^K slots per entry, 4 per thread (more than
-    // kMaxGroupBits targets come here only as pure expansions that fit)
-    constexpr uint32_t kSlotTile = kBlock * 4;
-    const uint64_t slots = st->n_ub << K;
-    const uint32_t nt = (uint32_t)std::max<uint64_t>(1, (slots + kSlotTile - 1) / kSlotTile);
-    k_expand_slots<W, K, 4><<<nt, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g,
-                                                           st->lb, st->meta, ep, xo(st));
-    return;
-  }
-  if constexpr (K <= kMaxGroupBits) {
-    if (mode == MODE_GROUP)
-      k_group<W, K, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(
-          kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st));
-    else
-      k_group<W, K, MODE_EXPAND, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(
-          kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, st->lb, st->meta, ep, xo(st));
-  }
-}
-
-// The speculative fixed-placement launch of a one-target op (launch
-// `ep_spec`), with its own tile size: its workgroups hold no look-back state.
-// In group mode, with partners taken from the lane pair (no staging) four
-// entries per thread run at full occupancy; with staging, two.
-template <int W, int ITEMS, int NB>
-void launch_spec_wn(ss_state* st, int mode, const GroupOp& g, uint32_t ep_spec, const FusedRun& run) {
-  const Buf& in = st->buf[st->cur];
-  const Buf& out = st->buf[st->cur ^ 1];
-  const uint32_t ns = st->nslot;
-  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock * ITEMS - 1) / (kBlock * ITEMS));
-  const uint32_t f = mode == MODE_GROUP ? 1u : 2u;
-  if constexpr (W <= 2) {
-    if (run.n) {
-      if (mode == MODE_GROUP)
-        k_pair_spec<W, MODE_GROUP, ITEMS, true, NB><<<ntiles, kBlock, 0, st->stream>>>(
-            kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, f, st->meta, ep_spec, run.ops, run.n, run.gops);
-      else
-        k_pair_spec<W, MODE_EXPAND, ITEMS, true, 0><<<ntiles, kBlock, 0, st->stream>>>(
-            kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, f, st->meta, ep_spec, run.ops, run.n, run.gops);
-      return;
-    }
-  }
-  if (mode == MODE_GROUP)
-    k_pair_spec<W, MODE_GROUP, ITEMS, false, NB><<<ntiles, kBlock, 0, st->stream>>>(
-        kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, f, st->meta, ep_spec, nullptr, 0u, nullptr);
-  else
-    k_pair_spec<W, MODE_EXPAND, ITEMS, false, 0><<<ntiles, kBlock, 0, st->stream>>>(
-        kp<W>(in), in.amp, kp<W>(out), out.amp, ns, st->cap, g, f, st->meta, ep_spec, nullptr, 0u, nullptr);
-}
-
-// Group mode: pair_exchange 0 stages every tile's neighbours in LDS, 1 takes
-// aligned partners from the lane pair and stages only tiles that are not
-// aligned, 2 takes only aligned partners (no LDS staging; a tile that is not
-// aligned defeats the speculation).
-template <int W, int ITEMS>
-void launch_spec_wi(ss_state* st, int mode, const GroupOp& g, uint32_t ep_spec, const FusedRun& run) {
-  switch (st->pair_exchange) {
-    case 0: launch_spec_wn<W, ITEMS, 0>(st, mode, g, ep_spec, run); break;
-    case 2: launch_spec_wn<W, ITEMS, 2>(st, mode, g, ep_spec, run); break;
-    default: launch_spec_wn<W, ITEMS, 1>(st, mode, g, ep_spec, run); break;
-  }
-}
-
-template <int W>
-void launch_spec_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep_spec, const FusedRun& run) {
-  switch (st->spec_items) {
-    case 1: launch_spec_wi<W, 1>(st, mode, g, ep_spec, run); break;
-    case 4: launch_spec_wi<W, 4>(st, mode, g, ep_spec, run); break;
-    default: launch_spec_wi<W, 2>(st, mode, g, ep_spec, run); break;
-  }
-}
-
-// Items per thread: several for one or two targets (bigger tiles, fewer
-// tile-id atomics), one for 8..32-member groups (register budget).
-template <int W, int K>
-void launch_group_wk(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec, const FusedRun& run) {
-  int items = K <= 2 ? st->group_items : 1;
-  // A chained or run-carrying launch is latency-bound (a product of up to 16
-  // matrices, an interpreted run): at most 2 entries per thread, for more
-  // waves per SIMD.
-  if ((g.nchain || run.n) && items > 2) items = 2;
-  if (K <= 2 && items >= 4) launch_group_wki<W, K, (K <= 2 ? 4 : 1)>(st, mode, g, ep, ep_spec, run);
-  else if (K <= 2 && items == 2) launch_group_wki<W, K, (K <= 2 ? 2 : 1)>(st, mode, g, ep, ep_spec, run);
-  else launch_group_wki<W, K, 1>(st, mode, g, ep, ep_spec, run);
-}
 
 // ep_spec != 0 (one target only): a speculative fixed-fan-out launch of that
-// epoch runs first.
+// epoch runs first.  Group mode's speculative launch finds partners as option
+// pair_exchange says.
 template <int W>
 void launch_group_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec, const FusedRun& run) {
-  const FusedRun none{nullptr, 0u, nullptr};
-  switch (g.k) {
-    case 1:
-      if (ep_spec) launch_spec_w<W>(st, mode, g, ep_spec, run);
-      launch_group_wk<W, 1>(st, mode, g, ep, ep_spec, run);
-      break;
-    case 2: launch_group_wk<W, 2>(st, mode, g, ep, 0, none); break;
-    case 3: launch_group_wk<W, 3>(st, mode, g, ep, 0, none); break;
-    case 4: launch_group_wk<W, 4>(st, mode, g, ep, 0, none); break;
-    case 5: launch_group_wk<W, 5>(st, mode, g, ep, 0, none); break;
-    case 6: launch_group_wk<W, 6>(st, mode, g, ep, 0, none); break;
-    case 7: launch_group_wk<W, 7>(st, mode, g, ep, 0, none); break;
-    case 8: launch_group_wk<W, 8>(st, mode, g, ep, 0, none); break;
-    case 9: launch_group_wk<W, 9>(st, mode, g, ep, 0, none); break;
-    default: launch_group_wk<W, 10>(st, mode, g, ep, 0, none); break;
+  const LaunchCtx c = ctx(st);
+  if (g.k == 1) {
+    if (ep_spec) launch_spec<W>(c, mode, (int)st->spec_items, (int)st->pair_exchange, g, ep_spec, run);
+    // A chained or run-carrying launch is latency-bound (a product of up to
+    // 16 matrices, an interpreted run): at most 2 entries per thread, for
+    // more waves per SIMD.
+    int items = st->group_items;
+    if ((g.nchain || run.n) && items > 2) items = 2;
+    launch_pair<W>(c, mode, items, g, ep, ep_spec, run);
+    return;
   }
+  launch_multi<W>(c, mode, st->group_items, st->expand_slots != 0, g, ep);
 }
 
 template <int W>
@@ -1143,37 +1015,10 @@ FastOp encode_fast(const ss_state* st, const ss_op& op, uint32_t gi) {
   }
 }
 
-template <int W, int E>
-void launch_perm_fast(ss_state* st, const FastOp* f, uint32_t nfast, const PermOp* gops, uint32_t write_words,
-                      bool amp, uint32_t ep) {
-  const Buf& b = st->buf[st->cur];
-  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock * E - 1) / (kBlock * E));
-  if (amp)
-    k_perm_fast<W, E, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->nslot, f, nfast, gops,
-                                                             write_words, st->meta, ep);
-  else
-    k_perm_fast<W, E, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->nslot, f, nfast, gops,
-                                                              write_words, st->meta, ep);
-}
-
 template <int W>
 void launch_perm_w(ss_state* st, const void* dev, uint32_t nfast, const PermOp* gops, uint32_t write_words,
                    bool amp, uint32_t ep) {
-  if (W <= 2) {
-    const FastOp* f = static_cast<const FastOp*>(dev);
-    if (st->perm_entries == 16) launch_perm_fast<W, 16>(st, f, nfast, gops, write_words, amp, ep);
-    else if (st->perm_entries == 8) launch_perm_fast<W, 8>(st, f, nfast, gops, write_words, amp, ep);
-    else launch_perm_fast<W, 4>(st, f, nfast, gops, write_words, amp, ep);
-  } else {
-    const Buf& b = st->buf[st->cur];
-    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((st->n_ub + kBlock - 1) / kBlock, 8192));
-    if (amp)
-      k_perm<W, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->nslot, gops, nfast, write_words,
-                                                       st->meta, ep);
-    else
-      k_perm<W, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->nslot, gops, nfast, write_words,
-                                                        st->meta, ep);
-  }
+  launch_perm<W>(ctx(st), st->perm_entries, amp, static_cast<const FastOp*>(dev), nfast, gops, write_words, ep);
 }
 
 // Copy `bytes` into the pinned staging ring and on to the device op ring (on
