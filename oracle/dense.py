@@ -10,6 +10,13 @@ and quantum operations" with qubit q of a register as bit q of its value.
   amplitude to f(index) through an index array; the map is checked to be a
   bijection (QRAM equation; non-interference ops);
 * REFLECT0 multiplies by +i / -i (the QLSS reflection R);
+* Y, Z, S, S^-1, T, T^-1 and diag(1, e^{i theta}) (Sec. "Qubits and quantum
+  operations"; phase gates among the non-interference ops) and ROT (a 2x2
+  complex matrix, the supplementary Rot_Int) update each (bit=0, bit=1) pair
+  with their matrix where the controls hold, one qubit at a time; only a ROT
+  whose matrix is neither diagonal nor off-diagonal is followed by the
+  clear-zero step;
+* ADDC, MUL, DIV (register arithmetic oracles) are permutations like ADD;
 * H and Ry update each (bit=0, bit=1) pair with the 2x2 matrix where the
   controls hold (controlled-U definition), one target qubit at a time in
   ascending order, and after the whole op every amplitude with
@@ -25,7 +32,7 @@ C_H = 0.70710678118654752440
 
 
 class DenseState:
-    def __init__(self, regs, eps=1e-14, tables=(), init_values=None, init_amps=None):
+    def __init__(self, regs, eps=1e-14, tables=(), init_values=None, init_amps=None, matrices=()):
         self.widths = [int(w) for _, w in regs]
         self.offs = np.cumsum([0] + self.widths[:-1]).tolist()
         self.nq = sum(self.widths)
@@ -33,6 +40,7 @@ class DenseState:
             raise ValueError("dense checker is limited to 24 qubits")
         self.eps = float(eps)
         self.tables = list(tables)
+        self.matrices = [np.asarray(m, dtype=np.complex128).reshape(2, 2) for m in matrices]
         self.v = np.zeros(1 << self.nq, dtype=np.complex128)
         self.idx = np.arange(1 << self.nq, dtype=np.uint64)
         if init_values is None:
@@ -43,7 +51,7 @@ class DenseState:
 
     @classmethod
     def from_circuit(cls, c: "wl.Circuit") -> "DenseState":
-        return cls(c.regs, c.eps, c.tables, c.init_values, c.init_amps)
+        return cls(c.regs, c.eps, c.tables, c.init_values, c.init_amps, c.matrices)
 
     def flat_of(self, values: np.ndarray) -> np.ndarray:
         out = np.zeros(values.shape[0], dtype=np.uint64)
@@ -98,6 +106,31 @@ class DenseState:
             a2 = self.v.real * self.v.real + self.v.imag * self.v.imag
             self.v[a2 < self.eps * self.eps] = 0.0
             return
+        mats = {"Y": [[0, -1j], [1j, 0]], "Z": [[1, 0], [0, -1]], "S": [[1, 0], [0, 1j]],
+                "SDG": [[1, 0], [0, -1j]], "T": [[1, 0], [0, complex(C_H, C_H)]],
+                "TDG": [[1, 0], [0, complex(C_H, -C_H)]]}
+        if kind in mats or kind in ("PHASE", "ROT"):
+            if kind == "PHASE":
+                m = np.array([[1, 0], [0, complex(np.cos(float(op["theta"])), np.sin(float(op["theta"])))]])
+            elif kind == "ROT":
+                m = self.matrices[int(op["table"])]
+            else:
+                m = np.array(mats[kind], dtype=np.complex128)
+            for q in range(w):
+                if not (int(op["qmask"]) >> q) & 1:
+                    continue
+                bit = np.uint64(1 << (self.offs[r] + q))
+                i0 = idx[((idx & bit) == 0) & on].astype(np.int64)
+                i1 = (i0.astype(np.uint64) | bit).astype(np.int64)
+                a0 = self.v[i0].copy()
+                a1 = self.v[i1].copy()
+                self.v[i0] = m[0, 0] * a0 + m[0, 1] * a1
+                self.v[i1] = m[1, 0] * a0 + m[1, 1] * a1
+            one_to_one = (m[0, 1] == 0 and m[1, 0] == 0) or (m[0, 0] == 0 and m[1, 1] == 0)
+            if not one_to_one:
+                a2 = self.v.real * self.v.real + self.v.imag * self.v.imag
+                self.v[a2 < self.eps * self.eps] = 0.0
+            return
         if kind == "REFLECT0":
             z = self.field(idx, r) == 0
             ph = np.where(z, 1j, -1j)
@@ -118,6 +151,31 @@ class DenseState:
             new = (val * np.uint64(op["imm"])) & wm
         elif kind == "XORC":
             new = val ^ (np.uint64(op["imm"]) & wm)
+        elif kind == "ADDC":
+            new = (val + (np.uint64(op["imm"]) & wm)) & wm
+        elif kind == "MUL":
+            x = self.field(idx, int(op["reg2"]))
+            y = self.field(idx, int(op["reg3"]))
+            with np.errstate(over="ignore"):
+                new = (val ^ (x * y)) & wm
+        elif kind == "DIV":
+            x = self.field(idx, int(op["reg2"]))
+            y = self.field(idx, int(op["reg3"]))
+            r4 = int(op["reg4"])
+            wm4 = np.uint64((1 << self.widths[r4]) - 1)
+            ysafe = np.where(y == 0, np.uint64(1), y)
+            quo = np.where(y == 0, ~np.uint64(0), x // ysafe)
+            rem = np.where(y == 0, x, x % ysafe)
+            new = (val ^ quo) & wm
+            nr4 = (self.field(idx, r4) ^ rem) & wm4
+            idx = self.with_field(idx, r4, nr4)
+            dst = np.where(on, self.with_field(idx, r, new), self.idx).astype(np.int64)
+            if len(np.unique(dst)) != len(dst):
+                raise AssertionError("permutation op is not a bijection")
+            out = np.zeros_like(self.v)
+            out[dst] = self.v
+            self.v = out
+            return
         elif kind in ("QRAM_LOAD", "QRAM_UNLOAD"):
             t = self.tables[int(op["table"])]
             addr = self.field(idx, int(op["reg2"])).astype(np.int64)

@@ -22,15 +22,17 @@ _SRC = os.path.join(_HERE, "sparse_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 ORA_OP = np.dtype([
-    ("kind", "u4"), ("nctl", "u4"), ("reg", "u4"), ("reg2", "u4"), ("table", "u4"), ("pad", "u4"),
+    ("kind", "u4"), ("nctl", "u4"), ("reg", "u4"), ("reg2", "u4"), ("table", "u4"), ("reg3", "u4"),
     ("qmask", "u8"), ("imm", "u8"), ("theta", "f8"),
-    ("ctl_reg", "u4", (3,)), ("ctl_qubit", "u4", (3,)), ("ctl_val", "u4", (3,)), ("pad2", "u4"),
+    ("ctl_reg", "u4", (3,)), ("ctl_qubit", "u4", (3,)), ("ctl_val", "u4", (3,)), ("reg4", "u4"),
 ])
 assert ORA_OP.itemsize == 88  # matches struct ora_op
 
 # oracle kind codes (its own enumeration) by op name
 _ORA_KIND = {"X": 0, "H": 1, "RY": 2, "ADD": 3, "SUB": 4, "MULC": 5, "XOR": 6, "XORC": 7,
-             "QRAM_LOAD": 8, "QRAM_UNLOAD": 9, "REFLECT0": 10}
+             "QRAM_LOAD": 8, "QRAM_UNLOAD": 9, "REFLECT0": 10,
+             "Y": 11, "Z": 12, "S": 13, "SDG": 14, "T": 15, "TDG": 16, "PHASE": 17, "ROT": 18,
+             "ADDC": 19, "MUL": 20, "DIV": 21}
 
 
 def build(force: bool = False) -> str:
@@ -57,6 +59,7 @@ def lib():
         L.ora_destroy.argtypes = [vp]
         L.ora_layout.argtypes = [vp, u32, P(u32), P(u32)]
         L.ora_add_table.argtypes = [vp, P(u64), u64, u32, u32]
+        L.ora_add_matrix.argtypes = [vp, P(f64)]
         L.ora_set_entries.argtypes = [vp, P(u64), P(f64), u64]
         L.ora_apply.argtypes = [vp, vp, u64, P(f64), P(u64)]
         L.ora_prune.argtypes = [vp, f64]
@@ -79,7 +82,7 @@ def to_oracle_ops(ops: np.ndarray) -> np.ndarray:
     out = np.zeros(len(ops), dtype=ORA_OP)
     names = [wl.KINDS[int(k)] for k in ops["kind"]]
     out["kind"] = [_ORA_KIND[n] for n in names]
-    for f in ("nctl", "reg", "reg2", "table", "qmask", "imm", "theta"):
+    for f in ("nctl", "reg", "reg2", "reg3", "reg4", "table", "qmask", "imm", "theta"):
         out[f] = ops[f]
     out["ctl_reg"] = ops["ctl_reg"]
     out["ctl_qubit"] = ops["ctl_qubit"]
@@ -90,7 +93,7 @@ def to_oracle_ops(ops: np.ndarray) -> np.ndarray:
 class OracleState:
     """One oracle instance: a std::map from packed key to complex amplitude."""
 
-    def __init__(self, regs, eps: float = 1e-14, tables=(), init_values=None, init_amps=None):
+    def __init__(self, regs, eps: float = 1e-14, tables=(), init_values=None, init_amps=None, matrices=()):
         L = lib()
         self.nregs = len(regs)
         widths = np.array([w for _, w in regs], dtype=np.uint32)
@@ -102,12 +105,15 @@ class OracleState:
             rc = L.ora_add_table(self.h, _ptr(v, ctypes.c_uint64), len(v), t.addr_bits, t.word_bits)
             if rc < 0:
                 raise ValueError("oracle: bad table")
+        for m in matrices:
+            m8 = np.ascontiguousarray(np.asarray(m, dtype=np.complex128).reshape(2, 2)).view(np.float64).ravel()
+            L.ora_add_matrix(self.h, _ptr(m8, ctypes.c_double))
         if init_values is not None:
             self.set_entries(init_values, init_amps)
 
     @classmethod
     def from_circuit(cls, c: "wl.Circuit") -> "OracleState":
-        return cls(c.regs, c.eps, c.tables, c.init_values, c.init_amps)
+        return cls(c.regs, c.eps, c.tables, c.init_values, c.init_amps, c.matrices)
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -22,6 +22,15 @@
 //  * QRAM  U|i>_A|j>_D = |i>_A|j xor d_i>_D (QRAM section, its equation);
 //    the inverse is the same map.
 //  * reflection R = i(2|0><0|_anc - I_anc) (x) I (QLSS section, equation of R).
+//  * Y = [[0, -i], [i, 0]], Z = diag(1, -1) (Sec. "Qubits and quantum
+//    operations"); the phase gates S = diag(1, i), T = diag(1, e^{i pi/4}) and
+//    their inverses, named among the non-interference ops (Sec.
+//    "Non-interference operations"), and diag(1, e^{i theta});
+//  * a general single-qubit rotation by a 2x2 complex matrix (Rot_Int in the
+//    supplementary details of quantum operations), which there dispatches on
+//    a diagonal, an off-diagonal or a general matrix;
+//  * register arithmetic as oracles: add a constant, multiply, divide (Sec.
+//    "Non-interference operations", quantum arithmetic).
 //
 // Readings where the paper is silent (all listed in the design notes):
 //  * qubit q of a register is bit q of its value; registers are packed in
@@ -35,6 +44,17 @@
 //    removed when re*re + im*im < eps*eps, or when it is exactly zero.
 //  * ADD/SUB/XOR: dst <- dst op src, src truncated to the width of dst,
 //    result mod 2^width(dst).  MULC: dst <- dst*c mod 2^width, c odd.
+//  * Y, Z, S, S^-1, T, T^-1, the phase gate and a rotation whose matrix is
+//    diagonal or off-diagonal map every branch to one branch: they are
+//    non-interference ops (no pruning after them).  On several qubits they
+//    act on each qubit of the mask in ascending order.  A rotation by any
+//    other matrix is an interference op on one qubit (pruned afterwards); an
+//    element is "zero" when its real and imaginary parts are both 0.0.
+//  * complex products are written out: (a + ib)(c + id) = (ac - bd) + i(ad + bc).
+//  * ADDC: dst <- dst + c mod 2^width.  MUL: dst <- dst xor (x * y mod
+//    2^width(dst)).  DIV: q <- q xor (x div y), r <- r xor (x mod y), each
+//    truncated to its register; for y = 0 the quotient is all ones and the
+//    remainder x (the xor form keeps both maps bijections).
 //  * measurement: p(v) = sum of |a|^2 over entries whose field equals v
 //    (ascending key), P = sum of p(v) over ascending v; the outcome is the
 //    smallest v whose running sum exceeds u*P; survivors are divided by
@@ -68,7 +88,14 @@ using State = std::map<Key, Amp, KeyLess>;
 
 enum OracleKind : uint32_t {
   K_X = 0, K_H = 1, K_RY = 2, K_ADD = 3, K_SUB = 4, K_MULC = 5, K_XOR = 6,
-  K_XORC = 7, K_QLOAD = 8, K_QUNLOAD = 9, K_REFLECT0 = 10
+  K_XORC = 7, K_QLOAD = 8, K_QUNLOAD = 9, K_REFLECT0 = 10,
+  K_Y = 11, K_Z = 12, K_S = 13, K_SDG = 14, K_T = 15, K_TDG = 16, K_PHASE = 17,
+  K_ROT = 18, K_ADDC = 19, K_MUL = 20, K_DIV = 21
+};
+
+// A 2x2 complex matrix, m[out][in].
+struct Mat {
+  Amp m[2][2];
 };
 
 struct Field {
@@ -87,8 +114,18 @@ struct Oracle {
   double eps;
   State state;
   std::vector<QTable> tables;
+  std::vector<Mat> mats;
   uint64_t peak = 0;
 };
+
+Amp cmul(const Amp& a, const Amp& b) {
+  Amp r;
+  r.re = a.re * b.re - a.im * b.im;
+  r.im = a.re * b.im + a.im * b.re;
+  return r;
+}
+
+bool is_zero(const Amp& a) { return a.re == 0.0 && a.im == 0.0; }
 
 uint64_t low_mask(int width) { return width >= 64 ? ~0ull : ((1ull << width) - 1ull); }
 
@@ -108,12 +145,15 @@ bool get_bit(const Key& k, const Field& f, int q) { return (k[f.word] >> (f.offs
 extern "C" {
 
 // Op record understood by the oracle.  Kinds follow OracleKind above.
+// MUL: reg <- reg xor (reg2 * reg3).  DIV: reg (quotient) and reg4
+// (remainder) from reg2 (dividend) and reg3 (divisor).  ROT: table is the
+// matrix index from ora_add_matrix.
 struct ora_op {
-  uint32_t kind, nctl, reg, reg2, table, pad;
+  uint32_t kind, nctl, reg, reg2, table, reg3;
   uint64_t qmask, imm;
   double theta;
   uint32_t ctl_reg[3], ctl_qubit[3], ctl_val[3];
-  uint32_t pad2;
+  uint32_t reg4;
 };
 
 void* ora_create(const uint32_t* widths, uint32_t nregs, double eps) {
@@ -158,6 +198,17 @@ int ora_add_table(void* h, const uint64_t* vals, uint64_t len, uint32_t addr_bit
     if (word_bits < 64 && (v >> word_bits) != 0) return -1;
   o->tables.push_back(std::move(t));
   return (int)o->tables.size() - 1;
+}
+
+// Register a 2x2 complex matrix (8 doubles: m00, m01, m10, m11 as re, im;
+// row = output bit) for ROT ops; returns its index.
+int ora_add_matrix(void* h, const double* m8) {
+  Oracle* o = static_cast<Oracle*>(h);
+  Mat m;
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) m.m[r][c] = Amp{m8[4 * r + 2 * c], m8[4 * r + 2 * c + 1]};
+  o->mats.push_back(m);
+  return (int)o->mats.size() - 1;
 }
 
 // Replace the state by the given entries (register values, row-major n x nregs).
@@ -220,6 +271,20 @@ int apply_permutation(Oracle* o, const ora_op& op) {
           a = b;
           break;
         }
+        case K_ADDC: v = (v + op.imm) & wmask; break;
+        case K_MUL: {
+          uint64_t x = get_field(k, o->regs[op.reg2]), y = get_field(k, o->regs[op.reg3]);
+          v = (v ^ (x * y)) & wmask;
+          break;
+        }
+        case K_DIV: {
+          uint64_t x = get_field(k, o->regs[op.reg2]), y = get_field(k, o->regs[op.reg3]);
+          const Field& rf = o->regs[op.reg4];
+          uint64_t q = y ? x / y : ~0ull, r = y ? x % y : x;
+          v = (v ^ q) & wmask;
+          set_field(k, rf, (get_field(k, rf) ^ r) & low_mask(rf.width));
+          break;
+        }
         default: return -2;
       }
       set_field(k, dst, v);
@@ -259,6 +324,78 @@ void apply_single_qubit(Oracle* o, const ora_op& op, const Field& f, int q, cons
     }
   }
   o->state.swap(out);
+}
+
+// The same step with a complex matrix (ROT): children whose matrix element
+// has both parts 0.0 are not created.
+void apply_single_qubit_complex(Oracle* o, const ora_op& op, const Field& f, int q, const Mat& m) {
+  State out;
+  for (const auto& kv : o->state) {
+    const Key& k = kv.first;
+    const Amp& a = kv.second;
+    if (!controls_hold(o, op, k)) {
+      Amp& d = out[k];
+      d.re = d.re + a.re;
+      d.im = d.im + a.im;
+      continue;
+    }
+    int b = get_bit(k, f, q) ? 1 : 0;
+    for (int s = 0; s < 2; ++s) {
+      const Amp& c = m.m[s][b];
+      if (is_zero(c)) continue;
+      Key child = k;
+      uint64_t bit = 1ull << (f.offset + q);
+      if (s) child[f.word] |= bit; else child[f.word] &= ~bit;
+      Amp p = cmul(a, c);
+      Amp& d = out[child];
+      d.re = d.re + p.re;
+      d.im = d.im + p.im;
+    }
+  }
+  o->state.swap(out);
+}
+
+// A single-qubit gate that keeps each branch one branch, on every qubit of
+// the mask in ascending order: where the controls hold, bit b of qubit q
+// becomes b ^ flip and the amplitude is multiplied by fac[b].
+int apply_one_to_one(Oracle* o, const ora_op& op, bool flip, const Amp fac[2]) {
+  const Field& f = o->regs[op.reg];
+  for (int q = 0; q < f.width; ++q) {
+    if (!((op.qmask >> q) & 1ull)) continue;
+    State out;
+    for (const auto& kv : o->state) {
+      Key k = kv.first;
+      Amp a = kv.second;
+      if (controls_hold(o, op, k)) {
+        int b = get_bit(k, f, q) ? 1 : 0;
+        a = cmul(a, fac[b]);
+        if (flip) k[f.word] ^= 1ull << (f.offset + q);
+      }
+      if (out.count(k)) return -3;
+      out[k] = a;
+    }
+    o->state.swap(out);
+  }
+  return 0;
+}
+
+// The diagonal / off-diagonal gates: fac[b] is the matrix element that takes
+// input bit b to its output bit.
+int apply_phase_family(Oracle* o, const ora_op& op) {
+  const double c = 0.70710678118654752440;  // cos(pi/4) = sin(pi/4) as the nearest double
+  Amp fac[2] = {Amp{1.0, 0.0}, Amp{1.0, 0.0}};
+  bool flip = false;
+  switch (op.kind) {
+    case K_Y: flip = true; fac[0] = Amp{0.0, 1.0}; fac[1] = Amp{0.0, -1.0}; break;  // m10 = i, m01 = -i
+    case K_Z: fac[1] = Amp{-1.0, 0.0}; break;
+    case K_S: fac[1] = Amp{0.0, 1.0}; break;
+    case K_SDG: fac[1] = Amp{0.0, -1.0}; break;
+    case K_T: fac[1] = Amp{c, c}; break;
+    case K_TDG: fac[1] = Amp{c, -c}; break;
+    case K_PHASE: fac[1] = Amp{std::cos(op.theta), std::sin(op.theta)}; break;
+    default: return -2;
+  }
+  return apply_one_to_one(o, op, flip, fac);
 }
 
 void prune(Oracle* o, double eps) {
@@ -306,8 +443,29 @@ int ora_apply(void* h, const ora_op* ops, uint64_t nops, double* seconds, uint64
     ein += o->state.size();
     if (o->state.empty()) continue;
     int rc;
-    if (op.kind == K_H || op.kind == K_RY) rc = apply_branching(o, op);
-    else rc = apply_permutation(o, op);
+    if (op.kind == K_H || op.kind == K_RY) {
+      rc = apply_branching(o, op);
+    } else if (op.kind >= K_Y && op.kind <= K_PHASE) {
+      rc = apply_phase_family(o, op);
+    } else if (op.kind == K_ROT) {
+      if (op.table >= o->mats.size()) return -4;
+      const Mat& m = o->mats[op.table];
+      if (is_zero(m.m[0][1]) && is_zero(m.m[1][0])) {
+        const Amp fac[2] = {m.m[0][0], m.m[1][1]};
+        rc = apply_one_to_one(o, op, false, fac);
+      } else if (is_zero(m.m[0][0]) && is_zero(m.m[1][1])) {
+        const Amp fac[2] = {m.m[1][0], m.m[0][1]};
+        rc = apply_one_to_one(o, op, true, fac);
+      } else {
+        const Field& f = o->regs[op.reg];
+        for (int q = 0; q < f.width; ++q)
+          if ((op.qmask >> q) & 1ull) apply_single_qubit_complex(o, op, f, q, m);
+        prune(o, o->eps);
+        rc = 0;
+      }
+    } else {
+      rc = apply_permutation(o, op);
+    }
     if (rc) return rc;
     if (o->state.size() > o->peak) o->peak = o->state.size();
   }

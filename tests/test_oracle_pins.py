@@ -221,57 +221,46 @@ def test_paper_branch_counts():
         assert st.nnz == branches
 
 
-def test_c2_form_closed_form():
+@pytest.mark.parametrize("seed,nops,n_ry,h", [(11, 150, 4, 6), (3, 400, 6, 10), (0, 1000, 10, 8)])
+def test_c2_form_closed_form(seed, nops, n_ry, h):
     """Keys are the classical trajectories of the initial values of a through the
-    composed permutations (replayed here with vectorised numpy), times flag in
-    {0,1}; amplitudes are c^h * (Ry(t_m)...Ry(t_1)|0>)_flag."""
-    h = 6
-    c = wl.c2_circuit(11, nops=150, n_ry=4, h_qubits=h)
+    composed permutations (vectorised numpy replay, oracle/closed_forms.py),
+    times flag in {0,1}; amplitudes are c^h * (Ry(t_m)...Ry(t_1)|0>)_flag.
+    Checked against the map oracle entry by entry."""
+    from oracle.closed_forms import c2_closed_form
+    from parity import compare_arrays
+    c = wl.c2_circuit(seed, nops=nops, n_ry=n_ry, h_qubits=h)
     st, _, _ = run_circuit(c)
-    _, v, a = st.export()
-    hmask = int(c.ops[0]["qmask"])
-    qs = [q for q in range(32) if (hmask >> q) & 1]
-    starts = np.array([sum(((i >> j) & 1) << q for j, q in enumerate(qs)) for i in range(2 ** h)],
-                      dtype=np.uint64)
-    regs = np.zeros((2 ** h, 3), dtype=np.uint64)
-    regs[:, 0] = starts
-    M = np.uint64(0xFFFFFFFF)
-    vec = np.array([1.0, 0.0])
-    for op in c.ops[1:]:
-        kind = wl.KINDS[int(op["kind"])]
-        d = int(op["reg"])
-        if kind == "RY":
-            t = float(op["theta"]) / 2
-            vec = np.array([[np.cos(t), -np.sin(t)], [np.sin(t), np.cos(t)]]) @ vec
-            continue
-        s = int(op["reg2"])
-        if kind == "ADD":
-            regs[:, d] = (regs[:, d] + regs[:, s]) & M
-        elif kind == "SUB":
-            regs[:, d] = (regs[:, d] - regs[:, s]) & M
-        elif kind == "MULC":
-            regs[:, d] = (regs[:, d] * np.uint64(op["imm"])) & M
-        elif kind == "XOR":
-            regs[:, d] ^= regs[:, s]
-        elif kind == "XORC":
-            regs[:, d] ^= np.uint64(op["imm"])
-        elif kind == "X":
-            on = np.ones(len(regs), dtype=bool)
-            for j in range(int(op["nctl"])):
-                on &= ((regs[:, int(op["ctl_reg"][j])] >> np.uint64(op["ctl_qubit"][j])) & np.uint64(1)) == 1
-            regs[on, d] ^= np.uint64(op["qmask"])
-    expect = {}
-    amp0 = 1.0
-    for _ in range(h):
-        amp0 = C * amp0
-    for r in regs:
-        for f in (0, 1):
-            if abs(vec[f]) >= 1e-14:
-                expect[(int(r[0]), int(r[1]), int(r[2]), f)] = amp0 * vec[f]
-    got = {tuple(int(x) for x in row): amp for row, amp in zip(v, a)}
-    assert set(got) == set(expect)
-    for k, amp in got.items():
-        assert abs(amp - expect[k]) < 1e-13
+    ok, _, oa = st.export()
+    ck, ca = c2_closed_form(c)
+    s = compare_arrays(ck, ca, ok, oa, c.eps, atol=1e-13)
+    assert s["n_gpu"] == s["n_oracle"] == s["shared"] == 2 ** (h + 1)
+
+
+def test_compare_arrays_catches_mistakes():
+    """The vectorised comparison flags a missing key, a wrong key word, a
+    wrong amplitude and a non-ascending export; band keys may be missing."""
+    from parity import compare_arrays
+    rng = np.random.default_rng(0)
+    w1 = np.sort(rng.choice(1 << 40, size=300, replace=False)).astype(np.uint64)
+    keys = np.stack([rng.integers(0, 1 << 62, size=300).astype(np.uint64), w1], axis=1)
+    amps = rng.normal(size=300) + 1j * rng.normal(size=300)
+    compare_arrays(keys, amps, keys, amps, 1e-14)
+    with pytest.raises(AssertionError):
+        compare_arrays(keys[1:], amps[1:], keys, amps, 1e-14)
+    k2 = keys.copy()
+    k2[5, 0] ^= np.uint64(1)
+    with pytest.raises(AssertionError):
+        compare_arrays(k2, amps, keys, amps, 1e-14)
+    a2 = amps.copy()
+    a2[7] += 2e-12
+    with pytest.raises(AssertionError):
+        compare_arrays(keys, a2, keys, amps, 1e-14)
+    with pytest.raises(AssertionError):
+        compare_arrays(keys[::-1], amps[::-1], keys, amps, 1e-14)
+    a3 = amps.copy()
+    a3[9] = 1e-10
+    compare_arrays(np.delete(keys, 9, 0), np.delete(amps, 9), keys, a3, 1e-14)
 
 
 def test_c4_form_closed_form():
@@ -362,3 +351,175 @@ def test_swap_test_closed_form(n):
     v, a = _sorted_entries(v, a)
     assert np.array_equal(dv, v)
     assert np.allclose(da, a, rtol=0, atol=1e-15)
+
+
+def test_measure_extreme_draws():
+    """u = 0 picks the smallest field value with weight, u just below 1 the
+    largest; the probabilities are the marginals."""
+    vals = np.array([[1, 0], [3, 1], [3, 2], [6, 3]], dtype=np.uint64)
+    amps = np.array([0.5, 0.5j, -0.5, 0.5], dtype=np.complex128)
+    for u, expect, p in ((0.0, 1, 0.25), (np.nextafter(1.0, 0.0), 6, 0.25), (0.3, 3, 0.5)):
+        st = OracleState([("x", 3), ("y", 2)], 1e-14, init_values=vals, init_amps=amps)
+        v, prob = st.measure(0, float(u))
+        assert v == expect and prob == p
+        _, kv, ka = st.export()
+        keep = vals[:, 0] == expect
+        assert kv.tolist() == vals[keep].tolist()
+        assert np.allclose(ka, amps[keep] / np.sqrt(p), rtol=0, atol=1e-15)
+
+
+def test_measure_fallback_takes_largest_value():
+    """When no running sum exceeds u*P (here P is subnormal, 2e-322, and
+    0.99*P rounds back to P) the outcome is the largest field value with
+    weight: the fallback branch of the reading."""
+    a = 1e-161
+    assert a * a > 0 and 0.99 * (a * a + a * a) == a * a + a * a
+    vals = np.array([[2], [5]], dtype=np.uint64)
+    st = OracleState([("x", 3)], 0.0, init_values=vals, init_amps=np.array([a, a], dtype=np.complex128))
+    v, prob = st.measure(0, 0.99)
+    assert v == 5 and prob == 0.5
+
+
+# ---------------------------------------------------------------------------
+# The rest of the gate and oracle set: Y, Z, S, T (and inverses), the phase
+# gate, a general 2x2 rotation (diagonal, off-diagonal and general matrices),
+# add-constant, multiply and divide.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(14))
+def test_oracle_matches_dense_all_kinds(seed):
+    c = wl.random_small_circuit(seed, kinds=wl.KINDS, nops=70, with_init=bool(seed % 2),
+                                eps=(0.0 if seed % 4 == 3 else 1e-14))
+    kinds = {wl.KINDS[int(k)] for k in c.ops["kind"]}
+    assert len(kinds) >= 12
+    _oracle_vs_dense(c)
+
+
+def _run_ops(c, ops, matrices=()):
+    st = OracleState(c.regs, c.eps, c.tables, c.init_values, c.init_amps, matrices)
+    st.apply(wl.ops_array(ops))
+    return st.export()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_phase_gate_identities(seed):
+    """Z.Z = I, S.S = Z and S.S^-1 = I bit for bit (factors -1 and +-i are
+    exact); T.T = S and T.T^-1 = I within rounding; the phase gate at pi/2
+    is S within rounding; Y equals i X Z."""
+    c = _start(seed)
+    ctl = [(1, 0, 1)]
+    k0, _, a0 = _run_ops(c, [])
+    kz, _, az = _run_ops(c, [wl.make_op("Z", 0, qmask=0b0110, ctls=ctl)])
+    k1, _, a1 = _run_ops(c, [wl.make_op("Z", 0, qmask=0b0110, ctls=ctl)] * 2)
+    assert np.array_equal(k0, k1) and np.array_equal(a0.view(np.uint64), a1.view(np.uint64))
+    ks, _, as_ = _run_ops(c, [wl.make_op("S", 0, qmask=0b0110, ctls=ctl)] * 2)
+    assert np.array_equal(ks, kz) and np.array_equal(np.abs(as_ - az), np.zeros(len(az)))
+    k2, _, a2 = _run_ops(c, [wl.make_op("S", 0, qmask=0b1011), wl.make_op("SDG", 0, qmask=0b1011)])
+    assert np.array_equal(k2, k0) and np.array_equal(a2.view(np.uint64), a0.view(np.uint64))
+    kt, _, at = _run_ops(c, [wl.make_op("T", 0, qmask=0b0110, ctls=ctl)] * 2)
+    ks1, _, as1 = _run_ops(c, [wl.make_op("S", 0, qmask=0b0110, ctls=ctl)])
+    assert np.array_equal(kt, ks1) and np.max(np.abs(at - as1)) < 1e-15
+    k3, _, a3 = _run_ops(c, [wl.make_op("T", 0, qmask=0b1111), wl.make_op("TDG", 0, qmask=0b1111)])
+    assert np.array_equal(k3, k0) and np.max(np.abs(a3 - a0)) < 1e-15
+    kp, _, ap = _run_ops(c, [wl.make_op("PHASE", 0, qmask=0b0110, theta=np.pi / 2, ctls=ctl)])
+    assert np.array_equal(kp, ks1) and np.max(np.abs(ap - as1)) < 1e-15
+    ky, vy, ay = _run_ops(c, [wl.make_op("Y", 0, qmask=0b0101, ctls=ctl)])
+    kxz, _, axz = _run_ops(c, [wl.make_op("Z", 0, qmask=0b0101, ctls=ctl), wl.make_op("X", 0, qmask=0b0101, ctls=ctl)])
+    # on each qubit Y = i X Z: two qubits give i^2 = -1 where the control holds
+    assert np.array_equal(ky, kxz)
+    on = (vy[:, 1] & 1) == 1
+    assert np.max(np.abs(ay - np.where(on, -axz, axz))) < 1e-15
+
+
+def test_y_on_basis_states():
+    # Y|0> = i|1>, Y|1> = -i|0>
+    st = OracleState([("q", 1)], init_values=np.array([[0], [1]], dtype=np.uint64),
+                     init_amps=np.array([0.6, 0.8], dtype=np.complex128))
+    st.apply(wl.ops_array([wl.make_op("Y", 0, qmask=1)]))
+    _, v, a = st.export()
+    assert v[:, 0].tolist() == [0, 1]
+    assert a[0] == -0.8j and a[1] == 0.6j
+
+
+def test_hzh_is_x_and_hyh_is_minus_y():
+    c = _start(2)
+    kx, _, ax = _run_ops(c, [wl.make_op("X", 0, qmask=0b0100)])
+    kh, _, ah = _run_ops(c, [wl.make_op("H", 0, qmask=0b0100), wl.make_op("Z", 0, qmask=0b0100),
+                             wl.make_op("H", 0, qmask=0b0100)])
+    assert np.array_equal(kx, kh) and np.max(np.abs(ax - ah)) < 1e-15
+    ky, _, ay = _run_ops(c, [wl.make_op("Y", 0, qmask=0b0100)])
+    kh, _, ah = _run_ops(c, [wl.make_op("H", 0, qmask=0b0100), wl.make_op("Y", 0, qmask=0b0100),
+                             wl.make_op("H", 0, qmask=0b0100)])
+    assert np.array_equal(ky, kh) and np.max(np.abs(ay + ah)) < 1e-15
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_rotation_matrices(seed):
+    """ROT by a Haar-random U then by U^dagger is the identity (stray keys
+    cancel below eps); ROT by a diagonal or off-diagonal unitary keeps nnz and
+    every |a| (one branch per branch); ROT by H's matrix equals the H op."""
+    rng = np.random.default_rng(seed)
+    c = _start(seed)
+    U = wl.random_unitary(rng)
+    D = wl.random_unitary(rng, "diag")
+    A = wl.random_unitary(rng, "anti")
+    Hm = np.array([[C, C], [C, -C]], dtype=np.complex128)
+    mats = [U, U.conj().T, D, A, Hm]
+    k0, _, a0 = _run_ops(c, [])
+    ctl = [(2, 1, 0)]
+    k1, _, a1 = _run_ops(c, [wl.make_op("ROT", 0, qmask=4, table=0, ctls=ctl),
+                             wl.make_op("ROT", 0, qmask=4, table=1, ctls=ctl)], mats)
+    assert np.array_equal(k0, k1) and np.max(np.abs(a1 - a0)) < 1e-15
+    for t in (2, 3):
+        k2, _, a2 = _run_ops(c, [wl.make_op("ROT", 0, qmask=2, table=t, ctls=ctl)], mats)
+        assert len(k2) == len(k0)
+        assert np.allclose(np.sort(np.abs(a2)), np.sort(np.abs(a0)), rtol=0, atol=1e-15)
+    kh, _, ah = _run_ops(c, [wl.make_op("H", 0, qmask=8, ctls=ctl)])
+    kr, _, ar = _run_ops(c, [wl.make_op("ROT", 0, qmask=8, table=4, ctls=ctl)], mats)
+    assert np.array_equal(kh, kr) and np.max(np.abs(ah - ar)) < 1e-16
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_arithmetic_oracle_inverses(seed):
+    """ADDC(c) then ADDC(-c), MUL twice and DIV twice are the identity, bit for bit."""
+    c = _start(seed, widths=(4, 3, 3, 2))
+    k0, _, a0 = _run_ops(c, [])
+    ops = [wl.make_op("ADDC", 0, imm=11, ctls=[(1, 2, 1)]), wl.make_op("ADDC", 0, imm=16 - 11, ctls=[(1, 2, 1)]),
+           wl.make_op("MUL", 1, reg2=0, reg3=2), wl.make_op("MUL", 1, reg2=0, reg3=2),
+           wl.make_op("DIV", 1, reg2=0, reg3=3, reg4=2), wl.make_op("DIV", 1, reg2=0, reg3=3, reg4=2)]
+    k1, _, a1 = _run_ops(c, ops)
+    assert np.array_equal(k0, k1) and np.array_equal(a0.view(np.uint64), a1.view(np.uint64))
+
+
+def test_multiply_and_divide_closed_form():
+    """On every basis state |x>|y>|0>|0> (x: 5 qubits, y: 3) MUL writes x*y
+    mod 2^6 and DIV writes x div y and x mod y (all ones and x for y = 0)."""
+    st = OracleState([("x", 5), ("y", 3), ("p", 6), ("q", 5), ("r", 3)])
+    st.apply(wl.ops_array([wl.make_op("H", 0, qmask=0b11111), wl.make_op("H", 1, qmask=0b111),
+                           wl.make_op("MUL", 2, reg2=0, reg3=1), wl.make_op("DIV", 3, reg2=0, reg3=1, reg4=4)]))
+    _, v, a = st.export()
+    assert len(v) == 256
+    for x, y, p, q, r in v.tolist():
+        assert p == (x * y) % 64
+        assert (q, r) == ((x // y, x % y) if y else (31, x & 7))
+    assert np.all(np.abs(a - 1 / 16) < 1e-16)
+
+
+def _bitrev(y, n):
+    return int(format(y, f"0{n}b")[::-1], 2)
+
+
+@pytest.mark.parametrize("n,x", [(5, 0b10110), (8, 201), (11, 1234)])
+def test_qft_closed_form(n, x):
+    """Textbook QFT of |x> without the final swaps: amplitude of |y> is
+    2^(-n/2) e^(2 pi i x rev(y) / 2^n) (rev: bit reversal); with the swaps,
+    the same at y itself.  Pins the controlled phase gate and H together;
+    also oracle against the dense checker."""
+    for swaps in (False, True):
+        c = wl.qft_circuit(n, x, swaps=swaps)
+        st = _oracle_vs_dense(c, tol=1e-12)
+        _, v, a = st.export()
+        assert len(v) == 2 ** n
+        ys = v[:, 0].astype(np.int64)
+        yy = ys if swaps else np.array([_bitrev(int(y), n) for y in ys])
+        expect = np.exp(2j * np.pi * ((x * yy) % 2 ** n) / 2 ** n) / 2 ** (n / 2)
+        assert np.max(np.abs(a - expect)) < 1e-13

@@ -23,6 +23,18 @@ Op records use ``OP_DTYPE``.  Field meaning per kind:
 * ``QRAM_LOAD``/``QRAM_UNLOAD``  reg (data) <- reg ^ table[reg2 (address)].
 * ``REFLECT0``  amplitude *= +i if register ``reg`` is 0, else -i.
 
+Further gates of Sec. "Qubits and quantum operations" / "Non-interference
+operations" and the general single-qubit rotation of the supplementary
+details of quantum operations (Rot_Int):
+
+* ``Y``, ``Z``, ``S``, ``SDG``, ``T``, ``TDG`` on every qubit of ``qmask``;
+  ``PHASE`` diag(1, e^{i theta}) on every qubit of ``qmask``.
+* ``ROT``    the 2x2 complex matrix ``Circuit.matrices[table]`` on the single
+  qubit of ``qmask``.
+* ``ADDC``   reg <- reg + imm (mod 2^width(reg)).
+* ``MUL``    reg <- reg ^ (reg2 * reg3 mod 2^width(reg)).
+* ``DIV``    reg <- reg ^ (reg2 div reg3), reg4 <- reg4 ^ (reg2 mod reg3).
+
 Up to three controls ``(ctl_reg[j], ctl_qubit[j], ctl_val[j])`` gate any op.
 """
 from __future__ import annotations
@@ -32,8 +44,10 @@ from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
-KINDS = ("X", "H", "RY", "ADD", "SUB", "MULC", "XOR", "XORC",
-         "QRAM_LOAD", "QRAM_UNLOAD", "REFLECT0")
+BASE_KINDS = ("X", "H", "RY", "ADD", "SUB", "MULC", "XOR", "XORC",
+              "QRAM_LOAD", "QRAM_UNLOAD", "REFLECT0")
+EXT_KINDS = ("Y", "Z", "S", "SDG", "T", "TDG", "PHASE", "ROT", "ADDC", "MUL", "DIV")
+KINDS = BASE_KINDS + EXT_KINDS
 KIND = {name: i for i, name in enumerate(KINDS)}
 BRANCHING = (KIND["H"], KIND["RY"])
 
@@ -42,6 +56,7 @@ OP_DTYPE = np.dtype([
     ("reg", "u4"), ("reg2", "u4"), ("table", "u4"),
     ("qmask", "u8"), ("imm", "u8"), ("theta", "f8"),
     ("ctl_reg", "u4", (3,)), ("ctl_qubit", "u2", (3,)), ("ctl_val", "u1", (3,)),
+    ("reg3", "u4"), ("reg4", "u4"),
 ])
 
 
@@ -69,6 +84,7 @@ class Circuit:
     init_amps: Optional[np.ndarray] = None
     cap_bits: Optional[int] = None   # generator's bound: peak nnz <= 2**cap_bits
     name: str = ""
+    matrices: List[np.ndarray] = dataclasses.field(default_factory=list)  # 2x2 complex (ROT)
 
     @property
     def nqubits(self) -> int:
@@ -80,11 +96,13 @@ class Circuit:
 
 def make_op(kind: str, reg: int, *, qmask: int = 0, reg2: int = 0, table: int = 0,
             imm: int = 0, theta: float = 0.0,
-            ctls: Sequence[Tuple[int, int, int]] = ()) -> np.ndarray:
+            ctls: Sequence[Tuple[int, int, int]] = (), reg3: int = 0, reg4: int = 0) -> np.ndarray:
     rec = np.zeros((), dtype=OP_DTYPE)
     rec["kind"] = KIND[kind]
     rec["reg"] = reg
     rec["reg2"] = reg2
+    rec["reg3"] = reg3
+    rec["reg4"] = reg4
     rec["table"] = table
     rec["qmask"] = np.uint64(qmask)
     rec["imm"] = np.uint64(imm)
@@ -327,7 +345,7 @@ def c4_batch(seed, nrhs: int = 64, steps: int = 200, n: int = 1024, nnz_row: int
 # Small and structural circuits for pins and edge cases
 # ---------------------------------------------------------------------------
 def random_small_circuit(seed, widths=(4, 3, 3, 2), nops: int = 60,
-                         kinds: Sequence[str] = KINDS, max_h: int = 3,
+                         kinds: Sequence[str] = BASE_KINDS, max_h: int = 3,
                          eps: float = 1e-14, with_init: bool = False) -> Circuit:
     """Every op kind on a few small registers (<= 20 qubits in total), random
     controls (0-3, on qubits outside the destination register) and a random
@@ -342,6 +360,10 @@ def random_small_circuit(seed, widths=(4, 3, 3, 2), nops: int = 60,
     ab, wb = int(widths[amin]), int(widths[dmax])
     tables.append(Table(values=rng.integers(0, 2 ** wb, size=2 ** ab, dtype=np.uint64),
                         addr_bits=ab, word_bits=wb))
+    matrices = []
+    if any(k in kinds for k in ("ROT",)):
+        # a general unitary, a diagonal one and an anti-diagonal one
+        matrices = [random_unitary(rng), random_unitary(rng, "diag"), random_unitary(rng, "anti")]
     ops = []
     while len(ops) < nops:
         kind = str(rng.choice(list(kinds)))
@@ -350,22 +372,40 @@ def random_small_circuit(seed, widths=(4, 3, 3, 2), nops: int = 60,
         others = [x for x in range(nr) if x != r]
         nctl = int(rng.integers(0, 4))
         ctl_pool = [(x, q) for x in range(nr) for q in range(widths[x])]
-        if kind in ("ADD", "SUB", "MULC", "XOR", "XORC", "QRAM_LOAD", "QRAM_UNLOAD", "REFLECT0"):
+        if kind in ("ADD", "SUB", "MULC", "XOR", "XORC", "QRAM_LOAD", "QRAM_UNLOAD", "REFLECT0", "ADDC"):
             ctl_pool = [(x, q) for (x, q) in ctl_pool if x != r]
         qmask = 0
-        if kind == "X":
+        reg3 = reg4 = 0
+        table = 0
+        if kind in ("X", "Y", "Z", "S", "SDG", "T", "TDG", "PHASE"):
             k = int(rng.integers(1, w + 1))
             for q in rng.choice(w, size=k, replace=False):
                 qmask |= 1 << int(q)
+        elif kind == "ROT":
+            qmask = 1 << int(rng.integers(0, w))
+            table = int(rng.integers(0, len(matrices)))
+        elif kind == "MUL":
+            if nr < 2:
+                continue
+            reg2, reg3 = (int(x) for x in rng.choice(others, size=2, replace=True))
+            ctl_pool = [(x, q) for (x, q) in ctl_pool if x != r]
+        elif kind == "DIV":
+            if nr < 4:
+                continue
+            r, r4, reg2, reg3 = (int(x) for x in rng.choice(nr, size=4, replace=False))
+            w = int(widths[r])
+            reg4 = r4
+            ctl_pool = [(x, q) for x in range(nr) for q in range(widths[x]) if x not in (r, r4)]
         elif kind == "H":
             k = int(rng.integers(1, min(max_h, w) + 1))
             for q in rng.choice(w, size=k, replace=False):
                 qmask |= 1 << int(q)
         elif kind == "RY":
             qmask = 1 << int(rng.integers(0, w))
-        if kind in ("X", "H", "RY"):
+        if kind in ("X", "H", "RY", "Y", "Z", "S", "SDG", "T", "TDG", "PHASE", "ROT"):
             ctl_pool = [(x, q) for (x, q) in ctl_pool if not (x == r and (qmask >> q) & 1)]
-        reg2 = 0
+        if kind not in ("MUL", "DIV"):
+            reg2 = 0
         if kind in ("ADD", "SUB", "XOR"):
             reg2 = int(rng.choice(others))
             ctl_pool = [(x, q) for (x, q) in ctl_pool]
@@ -384,11 +424,11 @@ def random_small_circuit(seed, widths=(4, 3, 3, 2), nops: int = 60,
         imm = 0
         if kind == "MULC":
             imm = int(rng.integers(0, 2 ** w)) | 1
-        elif kind == "XORC":
+        elif kind in ("XORC", "ADDC"):
             imm = int(rng.integers(0, 2 ** w))
-        theta = float(rng.uniform(0, 2 * np.pi)) if kind == "RY" else 0.0
-        ops.append(make_op(kind, r, qmask=qmask, reg2=reg2, table=0, imm=imm,
-                           theta=theta, ctls=ctls))
+        theta = float(rng.uniform(0, 2 * np.pi)) if kind in ("RY", "PHASE") else 0.0
+        ops.append(make_op(kind, r, qmask=qmask, reg2=reg2, table=table, imm=imm,
+                           theta=theta, ctls=ctls, reg3=reg3, reg4=reg4))
     init_values = init_amps = None
     if with_init:
         n0 = int(rng.integers(1, 40))
@@ -402,7 +442,49 @@ def random_small_circuit(seed, widths=(4, 3, 3, 2), nops: int = 60,
         a = rng.standard_normal(n0) + 1j * rng.standard_normal(n0)
         init_amps = (a / np.linalg.norm(a)).astype(np.complex128)
     return Circuit(regs=regs, ops=ops_array(ops), eps=eps, tables=tables,
-                   init_values=init_values, init_amps=init_amps, name=f"small-seed{seed}")
+                   init_values=init_values, init_amps=init_amps, name=f"small-seed{seed}",
+                   matrices=matrices)
+
+
+def random_unitary(rng, form: str = "general") -> np.ndarray:
+    """A seeded 2x2 unitary: Haar-random (QR of a complex Gaussian matrix,
+    phases fixed by the diagonal of R), or diagonal / anti-diagonal with
+    random phases."""
+    if form == "diag":
+        ph = rng.uniform(0, 2 * np.pi, size=2)
+        return np.diag(np.exp(1j * ph)).astype(np.complex128)
+    if form == "anti":
+        ph = rng.uniform(0, 2 * np.pi, size=2)
+        return np.array([[0, np.exp(1j * ph[0])], [np.exp(1j * ph[1]), 0]], dtype=np.complex128)
+    z = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+    q, rr = np.linalg.qr(z)
+    d = np.diag(rr)
+    return (q * (d / np.abs(d))).astype(np.complex128)
+
+
+def qft_circuit(nqubits: int, x: int, swaps: bool = False) -> Circuit:
+    """Textbook quantum Fourier transform of the basis state |x> on one
+    register of ``nqubits`` (<= 64) qubits: X on the set bits of x, then for
+    j = n-1 down to 0: H on qubit j and, for k = j-1 down to 0, the phase gate
+    diag(1, e^{i pi / 2^(j-k)}) on qubit j controlled by qubit k.  Without the
+    final swaps the output register holds the transform in bit-reversed
+    order; with ``swaps`` each pair (q, n-1-q) is exchanged by three CNOTs.
+    Reaches 2^n branches (the qft row of the paper's Table 1 has 29 qubits)."""
+    ops = []
+    if x:
+        ops.append(make_op("X", 0, qmask=int(x)))
+    for j in range(nqubits - 1, -1, -1):
+        ops.append(make_op("H", 0, qmask=1 << j))
+        for k in range(j - 1, -1, -1):
+            ops.append(make_op("PHASE", 0, qmask=1 << j, theta=float(np.pi / 2 ** (j - k)), ctls=[(0, k, 1)]))
+    if swaps:
+        for q in range(nqubits // 2):
+            a, b = q, nqubits - 1 - q
+            ops += [make_op("X", 0, qmask=1 << b, ctls=[(0, a, 1)]),
+                    make_op("X", 0, qmask=1 << a, ctls=[(0, b, 1)]),
+                    make_op("X", 0, qmask=1 << b, ctls=[(0, a, 1)])]
+    return Circuit(regs=[("q", nqubits)], ops=ops_array(ops), eps=1e-14, cap_bits=nqubits,
+                   name=f"qft{nqubits}-x{x}")
 
 
 def ghz_circuit(nqubits: int) -> Circuit:
