@@ -68,7 +68,26 @@ enum ss_kind {
   SS_XORC = 7,        /* reg <- reg xor imm (truncated) */
   SS_QRAM_LOAD = 8,   /* reg (data) <- reg xor table[reg2 (address)] */
   SS_QRAM_UNLOAD = 9, /* the inverse, the same map */
-  SS_REFLECT0 = 10    /* amplitude *= +i if reg == 0 else -i */
+  SS_REFLECT0 = 10,   /* amplitude *= +i if reg == 0 else -i */
+  /* Gates that keep each branch one branch (non-interference ops, never
+   * followed by a prune), on each qubit of qmask in ascending order: */
+  SS_Y = 11,          /* Y = [[0, -i], [i, 0]] */
+  SS_Z = 12,          /* Z = diag(1, -1) (CZ: Z with a control) */
+  SS_S = 13,          /* S = diag(1, i) */
+  SS_SDG = 14,        /* S^-1 = diag(1, -i) */
+  SS_T = 15,          /* T = diag(1, e^{i pi/4}), e^{i pi/4} = (c, c), c the double nearest 1/sqrt 2 */
+  SS_TDG = 16,        /* T^-1 = diag(1, (c, -c)) */
+  SS_PHASE = 17,      /* diag(1, cos theta + i sin theta) (host libm) */
+  /* The 2x2 complex matrix aux (from ss_load_matrix) on the single qubit of
+   * qmask: a diagonal or off-diagonal matrix keeps each branch one branch (no
+   * prune); any other is an interference op (grouped, combined, pruned). */
+  SS_ROT = 18,
+  SS_ADDC = 19,       /* reg <- reg + imm mod 2^width(reg) */
+  SS_MUL = 20,        /* reg <- reg xor (reg2 * aux mod 2^width(reg)); aux = a register */
+  /* reg <- reg xor (reg2 div aux), imm (a register index) <- imm xor (reg2 mod
+   * aux), each truncated to its register; for aux = 0 the quotient is all
+   * ones and the remainder reg2 */
+  SS_DIV = 21
 };
 
 typedef struct ss_reg {
@@ -88,11 +107,12 @@ typedef struct ss_op {
   uint8_t nctl;           /* 0..3 controls */
   uint8_t flags;          /* must be 0 */
   uint32_t reg;           /* target / destination register */
-  uint32_t reg2;          /* source register (ADD/SUB/XOR) or address register (QRAM) */
-  uint32_t qram_id;       /* table id from ss_load_qram */
-  uint64_t qmask;         /* qubits of reg (X, H, RY) */
-  uint64_t imm;           /* MULC multiplier, XORC constant */
-  double theta;           /* RY angle */
+  uint32_t reg2;          /* source register (ADD/SUB/XOR/MUL/DIV) or address register (QRAM) */
+  uint32_t aux;           /* QRAM: table id (ss_load_qram); ROT: matrix id (ss_load_matrix);
+                             MUL: second factor register; DIV: divisor register */
+  uint64_t qmask;         /* qubits of reg (X, H, RY, Y, Z, S, SDG, T, TDG, PHASE, ROT) */
+  uint64_t imm;           /* MULC multiplier, XORC / ADDC constant, DIV remainder register */
+  double theta;           /* RY / PHASE angle */
   ss_ctl ctl[3];
 } ss_op;
 
@@ -108,20 +128,34 @@ typedef struct ss_state ss_state;
 
 /* Device bytes an arena needs for `cap_entries` entries of this layout plus
  * `table_bytes` of QRAM tables.  Entries cost 2*(8W+16) bytes (state and its
- * alternate buffer) plus look-back scratch. */
+ * alternate buffer) plus look-back scratch.
+ * Defined by: the paper is silent; this is the footprint model behind
+ * admission by predicted peak memory (memory is dominated by the branch
+ * list, Sec. "Sparse state representation and data structure").  It takes an
+ * entry capacity rather than (peak nnz, fan-out): a caller that knows a peak
+ * and the widest fan-out of its ops passes peak * 2^fanout, and the same
+ * capacity is what ss_create_state will carve.
+ * Errors: SS_E_ARG (bad registers, null output). */
 int ss_required_bytes(const ss_reg* regs, uint32_t nregs, uint32_t ninst, uint64_t cap_entries,
                       uint64_t table_bytes, size_t* bytes);
 
 /* Create a state of `ninst` instances, each |0...0> with amplitude 1, in the
  * caller's device arena [arena, arena + arena_bytes) (256-byte aligned) on
  * `hip_stream` (a hipStream_t, NULL = default stream).  `table_bytes` of the
- * arena are reserved for QRAM tables.  Blocking.
+ * arena are reserved for QRAM tables (an argument the paper's problem
+ * statement does not need; it fixes where the tables end and the entry
+ * buffers begin, so the capacity is known at creation).  Blocking.
+ * Defined by: the state |psi> = sum_i a_i |v^0_i>...|v^{K-1}_i> with each
+ * register a fixed-width binary string (Sec. "Sparse state representation
+ * and data structure", its equation); the registers are given up front.
  * Errors: SS_E_ARG (bad registers, more than 256 key bits, ninst == 0),
  * SS_E_NOMEM (arena too small for the instances), SS_E_HIP. */
 int ss_create_state(const ss_reg* regs, uint32_t nregs, uint32_t ninst, double eps, void* arena,
                     size_t arena_bytes, uint64_t table_bytes, void* hip_stream, ss_state** out);
 
-/* Free host-side metadata; the arena stays the caller's. */
+/* Free host-side metadata (and the state's pinned read-back block) after
+ * waiting for the stream; the arena stays the caller's.  SS_E_STATE for a
+ * null state. */
 int ss_destroy_state(ss_state* st);
 
 /* Entry capacity of the arena (all instances together). */
@@ -134,40 +168,88 @@ int ss_layout(const ss_state* st, uint32_t reg, uint32_t* word, uint32_t* offset
 int ss_key_words(const ss_state* st, uint32_t* w);
 
 /* Copy a QRAM table (host array of `len` words) into the arena.  Requires
- * len == 2^addr_bits and every word < 2^word_bits (SS_E_QRAM otherwise). */
+ * len == 2^addr_bits and every word < 2^word_bits (SS_E_QRAM otherwise;
+ * SS_E_NOMEM when the reserved table bytes are used up).  *qram_id names it in
+ * SS_QRAM_LOAD / SS_QRAM_UNLOAD ops.  Blocking.
+ * Defined by: U_QRAM |i>_A |j>_D = |i>_A |j xor d_i>_D, with address length =
+ * width of A and word length = width of D (QRAM section, its equation). */
 int ss_load_qram(ss_state* st, const uint64_t* table, uint64_t len, uint32_t addr_bits,
                  uint32_t word_bits, uint32_t* qram_id);
 
+/* Register a 2x2 complex matrix for SS_ROT ops: m = 8 doubles, the elements
+ * m00, m01, m10, m11 (row = output bit, column = input bit) each as (re, im).
+ * The matrix must be unitary to within 1e-12 (max-norm of M^H M - I), else
+ * SS_E_NOT_UNITARY; *matrix_id names it in ops.  Host-side only (the values
+ * travel in each op's launch arguments).
+ * Defined by: the general rotation on a single qubit by a 2x2 matrix (Rot_Int
+ * in the supplementary details of quantum operations), with the controlled
+ * form CU = |0><0| (x) I + |1><1| (x) U (Sec. "Qubits and quantum
+ * operations"). */
+int ss_load_matrix(ss_state* st, const double* m, uint32_t* matrix_id);
+
 /* Replace the entries of instance `inst` by n entries given as register values
  * (host, row-major n x nregs) and amplitudes (host, 2n doubles).  Values are
- * truncated to the register widths; keys must be distinct (not checked).
- * Blocking. */
+ * truncated to the register widths.  Register values rather than packed keys
+ * are taken so that callers need not know the packing (ss_layout reports it).
+ * Errors: SS_E_ARG (bad instance, null arrays, two entries with the same
+ * key: checked before anything changes), SS_E_CAPACITY (the state keeps the
+ * other instances' entries; this instance is then empty).  Blocking.
+ * Defined by: the state equation of Sec. "Sparse state representation and
+ * data structure" (one amplitude per distinct basis key). */
 int ss_set_entries(ss_state* st, uint32_t inst, const uint64_t* values, const double* amps, uint64_t n);
 
 /* Apply `nops` ops.  With inst_offsets == NULL every instance gets the same
  * ops.  Returns when the work is done (the status is final).  On
  * SS_E_CAPACITY the state holds the result of ops [0, res->failed_op) and the
- * caller may rebind a larger arena and resume from failed_op. */
+ * caller may rebind a larger arena and resume from failed_op.
+ * Errors: SS_E_ARG (a bad op: register, qubit, dst == src, a control inside
+ * dst, an empty mask, ROT on more than one qubit or an unknown matrix;
+ * nothing applied), SS_E_NOT_UNITARY, SS_E_QRAM, SS_E_CAPACITY, SS_E_HIP.
+ * Defined by: non-branching kinds (X and its controlled forms, ADD, SUB,
+ * MULC, XOR, XORC, QRAM, ADDC, MUL, DIV, the Pauli and phase gates Y, Z, S,
+ * T and their inverses) rewrite each branch on its own (Sec.
+ * "Non-interference operations"; Y and Z as in Sec. "Qubits and quantum
+ * operations"); ROT dispatches on its matrix as Rot_Int does (supplementary
+ * details of quantum operations); the QRAM kinds follow the QRAM section's
+ * equation; REFLECT0 is R = i(2|0><0|_anc - I) (x) I of the QLSS section;
+ * H and RY group coherent branches, combine each group with the gate matrix
+ * (Sec. "Qubits and quantum operations" for the matrices, controlled-U =
+ * |0><0| (x) I + |1><1| (x) U) and then drop zero branches (Sec.
+ * "Interference operations"; ClearZero after Rot_Int in the supplementary
+ * details of quantum operations). */
 int ss_apply_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst_offsets,
                  ss_result* res);
 
-/* Remove entries with |a|^2 < eps^2 or a == 0.  Blocking. */
+/* Remove entries with |a|^2 < eps^2 or a == 0 (eps >= 0, else SS_E_ARG).
+ * Blocking.
+ * Defined by: the zero-branch removal after interference ops (Sec.
+ * "Interference operations"; ClearZero in the supplementary details of
+ * quantum operations), with the paper's "zero" read as |a| < eps. */
 int ss_prune(ss_state* st, double eps);
 
 /* Collapsing measurement of register `reg` of instance `inst` with the caller's
  * uniform draw u in [0, 1): p(v) = sum of |a|^2 over entries with field v,
  * P = sum over v; the outcome is the smallest v whose running sum (ascending
- * v) exceeds u*P; the survivors are divided by sqrt(p(v)); *prob = p(v)/P.
- * Blocking. */
+ * v) exceeds u*P (the largest v with weight if rounding leaves none); the
+ * survivors are divided by sqrt(p(v)); *prob = p(v)/P.
+ * Errors: SS_E_ARG (bad instance or register, u outside [0, 1), an empty
+ * instance).  Blocking.
+ * Defined by: the paper is silent on measurement; this is the textbook
+ * projective measurement of one register in the computational basis, on the
+ * state of Sec. "Sparse state representation and data structure". */
 int ss_measure(ss_state* st, uint32_t inst, uint32_t reg, double u, uint64_t* outcome, double* prob);
 
 /* Entry count of instance `inst` (UINT32_MAX: all instances) and the running
- * peak of the whole state.  Blocking. */
+ * peak of the whole state (the paper's max_system_size, supplementary Table
+ * S1).  Blocking. */
 int ss_nnz(ss_state* st, uint32_t inst, uint64_t* nnz, uint64_t* peak);
 
 /* Copy instance `inst`'s entries to host arrays in ascending key order:
  * keys (W words per entry, instance field cleared) and amps (2 doubles per
- * entry).  Writes min(cap, nnz) entries; *n gets nnz.  Blocking. */
+ * entry).  Writes min(cap, nnz) entries; *n gets nnz.  Blocking.
+ * Defined by: the branch list of Sec. "Sparse state representation and data
+ * structure"; the ascending order is a canonical choice (the paper keeps
+ * branches in the order its sorts leave them). */
 int ss_export(ss_state* st, uint32_t inst, uint64_t* keys, double* amps, uint64_t cap, uint64_t* n);
 
 /* Wait for the stream and report kernel-side errors. */
@@ -233,8 +315,10 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
  * entry does not have two children; results are identical either way),
  * "chain" (1, default: up to 16 consecutive H / Ry ops on the same single
  * target qubit run as one launch in which each group gets the product of the
- * matrices whose controls hold for it, pruned once after the last; 0: one
- * launch per op; results agree within rounding and the prune band),
+ * matrices whose controls hold for it, pruned once after the last; fewer when
+ * eps > 1e-12/(15 sqrt 2), so that the prunes left out move no amplitude by
+ * more than 1e-12; 0: one launch per op; results agree within 1e-12 and the
+ * prune band),
  * "fuse_runs" (default 16, 0 = never: a one-target op whose next ops form a
  * run of at most that many non-branching ops applies the run to its outputs
  * in the same launch; results are identical either way),

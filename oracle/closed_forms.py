@@ -41,7 +41,7 @@ def _ry(theta):
 def c2_closed_form(c: "wl.Circuit", eps_margin: float = 1e-10):
     """The arithmetic-heavy circuit (registers a, b, c of 32 qubits and a
     1-qubit flag; H on some qubits of a, then register arithmetic, X with
-    controls and Ry on the flag only).
+    controls and Ry, or a rotation by a 2x2 complex matrix, on the flag only).
 
     Each initial value of a follows one classical trajectory through the
     permutation ops (Sec. "Non-interference operations": every branch is
@@ -67,13 +67,14 @@ def c2_closed_form(c: "wl.Circuit", eps_margin: float = 1e-10):
     amp0 = 1.0
     for _ in range(h):
         amp0 = C * amp0
-    vec = np.array([amp0, 0.0])
+    vec = np.array([amp0, 0.0], dtype=np.complex128)
     for op in ops[1:]:
         kind = wl.KINDS[int(op["kind"])]
         d = int(op["reg"])
-        if kind == "RY":
+        if kind in ("RY", "ROT"):
             assert d == 3 and int(op["nctl"]) == 0
-            vec = _ry(float(op["theta"])) @ vec
+            m = _ry(float(op["theta"])) if kind == "RY" else np.asarray(c.matrices[int(op["table"])])
+            vec = m @ vec
             small = np.abs(vec)[np.abs(vec) > 0]
             assert not np.any(np.abs(small - c.eps) < eps_margin) and not np.any(
                 (small < c.eps) & (small > 0)), "a flag amplitude near the prune threshold"
@@ -104,7 +105,7 @@ def c2_closed_form(c: "wl.Circuit", eps_margin: float = 1e-10):
     w0 = regs[0] | (regs[1] << np.uint64(32))
     keys, amps = [], []
     for f in (0, 1):
-        if vec[f] * vec[f] < c.eps * c.eps or vec[f] == 0.0:
+        if abs(vec[f]) ** 2 < c.eps * c.eps or vec[f] == 0.0:
             continue
         w1 = regs[2] | (np.uint64(f) << np.uint64(32))
         keys.append(np.stack([w0, w1], axis=1))

@@ -23,11 +23,13 @@ SS_OK, SS_E_ARG, SS_E_NOT_UNITARY, SS_E_QRAM, SS_E_CAPACITY, SS_E_NOMEM, SS_E_HI
 
 # enum ss_kind of include/sparqs.h
 SS_KIND = {"X": 0, "H": 1, "RY": 2, "ADD": 3, "SUB": 4, "MULC": 5, "XOR": 6, "XORC": 7,
-           "QRAM_LOAD": 8, "QRAM_UNLOAD": 9, "REFLECT0": 10}
+           "QRAM_LOAD": 8, "QRAM_UNLOAD": 9, "REFLECT0": 10,
+           "Y": 11, "Z": 12, "S": 13, "SDG": 14, "T": 15, "TDG": 16, "PHASE": 17, "ROT": 18,
+           "ADDC": 19, "MUL": 20, "DIV": 21}
 
 SS_OP = np.dtype([
     ("kind", "<u2"), ("nctl", "u1"), ("flags", "u1"),
-    ("reg", "<u4"), ("reg2", "<u4"), ("qram_id", "<u4"),
+    ("reg", "<u4"), ("reg2", "<u4"), ("aux", "<u4"),
     ("qmask", "<u8"), ("imm", "<u8"), ("theta", "<f8"),
     ("ctl", [("reg", "<u4"), ("qubit", "<u2"), ("value", "<u2")], (3,)),
 ])
@@ -70,6 +72,7 @@ def _load():
         "ss_layout": [vp, u32, P(u32), P(u32), P(u32)],
         "ss_key_words": [vp, P(u32)],
         "ss_load_qram": [vp, P(u64), u64, u32, u32, P(u32)],
+        "ss_load_matrix": [vp, P(f64), P(u32)],
         "ss_set_entries": [vp, u32, P(u64), P(f64), u64],
         "ss_apply_ops": [vp, vp, u64, P(u64), P(_Result)],
         "ss_prune": [vp, f64],
@@ -98,7 +101,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("ss_required_bytes", "ss_create_state", "ss_destroy_state", "ss_capacity", "ss_layout",
-            "ss_key_words", "ss_load_qram", "ss_set_entries", "ss_apply_ops", "ss_prune", "ss_measure",
+            "ss_key_words", "ss_load_qram", "ss_load_matrix", "ss_set_entries", "ss_apply_ops", "ss_prune", "ss_measure",
             "ss_nnz", "ss_export", "ss_sync", "ss_rebind_arena", "ss_set_option", "ss_stats",
             "ss_trace_read", "ss_device_error", "ss_strerror", "ss_graph_capture", "ss_graph_launch",
             "ss_graph_destroy")
@@ -129,9 +132,13 @@ def to_ss_ops(ops: np.ndarray) -> np.ndarray:
     out["nctl"] = ops["nctl"]
     out["reg"] = ops["reg"]
     out["reg2"] = ops["reg2"]
-    out["qram_id"] = ops["table"]
+    # aux: the QRAM table or ROT matrix index, or MUL / DIV's third register;
+    # DIV's remainder register travels in imm
+    kinds = np.array(names)
+    third = (kinds == "MUL") | (kinds == "DIV")
+    out["aux"] = np.where(third, ops["reg3"], ops["table"])
     out["qmask"] = ops["qmask"]
-    out["imm"] = ops["imm"]
+    out["imm"] = np.where(kinds == "DIV", ops["reg4"].astype(np.uint64), ops["imm"])
     out["theta"] = ops["theta"]
     out["ctl"]["reg"] = ops["ctl_reg"]
     out["ctl"]["qubit"] = ops["ctl_qubit"]
@@ -222,6 +229,13 @@ class State:
                                 ctypes.byref(qid)), "ss_load_qram")
         self.table_ids.append(int(qid.value))
         return int(qid.value)
+
+    def load_matrix(self, m) -> int:
+        """Register a 2x2 complex matrix (row = output bit) for ROT ops."""
+        m8 = np.ascontiguousarray(np.asarray(m, dtype=np.complex128).reshape(2, 2)).view(np.float64).ravel()
+        mid = ctypes.c_uint32(0)
+        _check(lib.ss_load_matrix(self.h, _p(m8, ctypes.c_double), ctypes.byref(mid)), "ss_load_matrix")
+        return int(mid.value)
 
     def set_entries(self, inst: int, values, amps):
         v = np.ascontiguousarray(values, dtype=np.uint64).reshape(-1, len(self.regs))
@@ -368,6 +382,8 @@ def state_for_circuit(c: "wl.Circuit", cap_entries: Optional[int] = None, ninst:
     st = State(c.regs, ninst=ninst, eps=c.eps, cap_entries=cap_entries, table_bytes=tb, **kw)
     for t in c.tables:
         st.load_qram(t)
+    for m in c.matrices:
+        st.load_matrix(m)
     if c.init_values is not None:
         st.set_entries(0, c.init_values, c.init_amps)
     return st

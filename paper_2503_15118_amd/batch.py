@@ -26,7 +26,7 @@ def concat_ops(circuits) -> tuple:
 
 def batch_state(circuits, cap_entries: int, table_bytes: int = 1 << 20, **kw) -> "_abi.State":
     """A state holding every circuit as one instance (same registers, eps and
-    QRAM tables, which the first circuit supplies)."""
+    QRAM tables and rotation matrices, which the first circuit supplies)."""
     c0 = circuits[0]
     for c in circuits:
         if list(c.regs) != list(c0.regs):
@@ -35,6 +35,8 @@ def batch_state(circuits, cap_entries: int, table_bytes: int = 1 << 20, **kw) ->
                     table_bytes=table_bytes, **kw)
     for t in c0.tables:
         st.load_qram(t)
+    for m in c0.matrices:
+        st.load_matrix(m)
     for i, c in enumerate(circuits):
         if c.init_values is not None:
             st.set_entries(i, c.init_values, c.init_amps)

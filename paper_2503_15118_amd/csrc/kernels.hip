@@ -55,6 +55,15 @@ __device__ __forceinline__ bool controls_hold(const uint64_t (&k)[W], const uint
   return on;
 }
 
+// Complex product with every product and sum rounded on its own:
+// (a + ib)(c + id) = (ac - bd) + i(ad + bc).
+__device__ __forceinline__ double2 cmul(double2 a, double cr, double ci) {
+  double2 r;
+  r.x = a.x * cr - a.y * ci;
+  r.y = a.x * ci + a.y * cr;
+  return r;
+}
+
 // Keep an amplitude unless |a|^2 < eps^2 or it is exactly zero.  The product
 // and sum are rounded separately (the file is built without contraction).
 __device__ __forceinline__ bool keep_amp(double re, double im, double eps2) {
@@ -105,6 +114,40 @@ __device__ __forceinline__ void perm_apply(uint64_t (&k)[W], double2& a, const P
         a.x = im;
         a.y = -re;
       }
+      return;
+    }
+    case PK_DIAG:
+    case PK_ADIAG: {
+      // one qubit at a time, ascending: the factor of the matrix element
+      // that takes this qubit's bit to its output bit
+      for (uint64_t m = op.imm; m; m &= m - 1) {
+        const uint32_t b = (uint32_t)((dw >> __builtin_ctzll(m)) & 1ull);
+        a = cmul(a, op.fac[b][0], op.fac[b][1]);
+      }
+      if (op.kind == PK_ADIAG) put_word<W>(k, op.dst_word, dw ^ op.imm);
+      return;
+    }
+    case PK_ADDC:
+      nv = (dv + op.imm) & op.dst_mask;
+      break;
+    case PK_MUL: {
+      const uint64_t x = (sel_word<W>(k, op.src_word) >> op.src_shift) & op.src_mask;
+      const uint64_t y = (sel_word<W>(k, op.src2_word) >> op.src2_shift) & op.src2_mask;
+      nv = (dv ^ (x * y)) & op.dst_mask;
+      break;
+    }
+    case PK_DIV: {
+      const uint64_t x = (sel_word<W>(k, op.src_word) >> op.src_shift) & op.src_mask;
+      const uint64_t y = (sel_word<W>(k, op.src2_word) >> op.src2_shift) & op.src2_mask;
+      const uint64_t q = y ? x / y : ~0ull, r = y ? x % y : x;
+      // remainder register first (it never overlaps the quotient's)
+      const uint64_t w2 = sel_word<W>(k, op.dst2_word);
+      const uint64_t m2 = op.dst2_mask << op.dst2_shift;
+      const uint64_t r2 = (((w2 >> op.dst2_shift) & op.dst2_mask) ^ r) & op.dst2_mask;
+      put_word<W>(k, op.dst2_word, (w2 & ~m2) | (r2 << op.dst2_shift));
+      const uint64_t dw2 = sel_word<W>(k, op.dst_word);
+      const uint64_t mq = op.dst_mask << op.dst_shift;
+      put_word<W>(k, op.dst_word, (dw2 & ~mq) | ((((dv ^ q) & op.dst_mask) << op.dst_shift) & mq));
       return;
     }
     default:
@@ -1103,12 +1146,19 @@ __device__ __forceinline__ bool pair_tile(const KeyPtrs<W>& in_keys, const doubl
       // hold, else the identity (the entry passes through); for a chain, the
       // product of the matrices of the ops whose controls hold, in op order.
       double mm[2][2];
+      double mmi[2][2] = {{0.0, 0.0}, {0.0, 0.0}};   // imaginary parts (complex op only)
       if (op.nchain == 0) {
         const bool ctl = !op.has_ctl || controls_hold<W>(key[it], op.cmask, op.cval);
         mm[0][0] = ctl ? op.m[0][0] : 1.0;
         mm[0][1] = ctl ? op.m[0][1] : 0.0;
         mm[1][0] = ctl ? op.m[1][0] : 0.0;
         mm[1][1] = ctl ? op.m[1][1] : 1.0;
+        if (op.cplx) {
+          mmi[0][0] = ctl ? op.mi[0][0] : 0.0;
+          mmi[0][1] = ctl ? op.mi[0][1] : 0.0;
+          mmi[1][0] = ctl ? op.mi[1][0] : 0.0;
+          mmi[1][1] = ctl ? op.mi[1][1] : 0.0;
+        }
       } else {
         mm[0][0] = 1.0;
         mm[0][1] = 0.0;
@@ -1159,10 +1209,23 @@ __device__ __forceinline__ bool pair_tile(const KeyPtrs<W>& in_keys, const doubl
           const double m0 = r ? mm[1][0] : mm[0][0];
           const double m1 = r ? mm[1][1] : mm[0][1];
           double2 v;
-          v.x = m0 * a0.x + m1 * a1.x;
-          v.y = m0 * a0.y + m1 * a1.y;
-          const double mrb = b ? m1 : m0;
-          const bool exists = has_p ? (m0 != 0.0 || m1 != 0.0) : (mrb != 0.0);
+          bool nz0, nz1;
+          if (op.cplx) {
+            // complex matrix (a general rotation): same order, complex products
+            const double i0 = r ? mmi[1][0] : mmi[0][0];
+            const double i1 = r ? mmi[1][1] : mmi[0][1];
+            const double2 p0 = cmul(a0, m0, i0), p1 = cmul(a1, m1, i1);
+            v.x = p0.x + p1.x;
+            v.y = p0.y + p1.y;
+            nz0 = m0 != 0.0 || i0 != 0.0;
+            nz1 = m1 != 0.0 || i1 != 0.0;
+          } else {
+            v.x = m0 * a0.x + m1 * a1.x;
+            v.y = m0 * a0.y + m1 * a1.y;
+            nz0 = m0 != 0.0;
+            nz1 = m1 != 0.0;
+          }
+          const bool exists = has_p ? (nz0 || nz1) : (b ? nz1 : nz0);
           out[it][r] = v;
           if (exists && keep_amp(v.x, v.y, op.eps2)) keepm[it] |= 1u << r;
         }
@@ -1747,9 +1810,9 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
         cnt[it] = 1;
         for (uint32_t j = 0; j < k[it]; ++j) {
           const uint32_t bj = (b[it] >> j) & 1u;
-          const double c0 = bj ? op.m[0][1] : op.m[0][0];
-          const double c1 = bj ? op.m[1][1] : op.m[1][0];
-          cnt[it] *= (uint32_t)(c0 != 0.0) + (uint32_t)(c1 != 0.0);
+          const bool c0 = (bj ? op.m[0][1] : op.m[0][0]) != 0.0 || (op.cplx && (bj ? op.mi[0][1] : op.mi[0][0]) != 0.0);
+          const bool c1 = (bj ? op.m[1][1] : op.m[1][0]) != 0.0 || (op.cplx && (bj ? op.mi[1][1] : op.mi[1][0]) != 0.0);
+          cnt[it] *= (uint32_t)c0 + (uint32_t)c1;
         }
       }
     }
@@ -1791,9 +1854,15 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
         for (uint32_t j = 0; j < k[it]; ++j) {
           const uint32_t sj = (sv >> j) & 1u, bj = (b[it] >> j) & 1u;
           const double c = sj ? (bj ? op.m[1][1] : op.m[1][0]) : (bj ? op.m[0][1] : op.m[0][0]);
-          if (c == 0.0) exists = false;
-          v.x = c * v.x;
-          v.y = c * v.y;
+          if (op.cplx) {
+            const double ci = sj ? (bj ? op.mi[1][1] : op.mi[1][0]) : (bj ? op.mi[0][1] : op.mi[0][0]);
+            if (c == 0.0 && ci == 0.0) exists = false;
+            v = cmul(v, c, ci);
+          } else {
+            if (c == 0.0) exists = false;
+            v.x = c * v.x;
+            v.y = c * v.y;
+          }
           const uint64_t bit = 1ull << op.tbit[j];
 #pragma unroll
           for (int w = 0; w < W; ++w)
@@ -2182,8 +2251,12 @@ static __global__ void k_prob_scan(double* tile_sum, uint64_t ntiles, double* to
 }
 
 // Each entry of the instance gets its inclusive running sum (ascending field
-// order).  The entry whose running sum first exceeds u*P records its field
-// value; the first and last entries of every field run record their bounds.
+// order).  The outcome is the field value of the first entry (lowest index)
+// whose running sum exceeds u*P: out[0] gets that index by an atomic minimum,
+// so exactly one entry is chosen even where rounding makes the sums of
+// neighbouring entries overlap or leave a gap.  out[2] gets the largest field
+// value with weight, the outcome when no running sum exceeds u*P (u*P at the
+// total by rounding).
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_prob_find(KeyPtrs<W> keys, const double2* __restrict__ amp,
                                                       uint64_t n, FilterOp f, const double* __restrict__ tile_pre,
@@ -2206,20 +2279,26 @@ __global__ __launch_bounds__(kBlock) void k_prob_find(KeyPtrs<W> keys, const dou
   double tot;
   const double ex = block_excl_scan<double>(w, s_scan, tot);
   if (e < n) {
-    const double before = tile_pre[blockIdx.x] + ex;
-    const double after = before + w;
+    const double after = (tile_pre[blockIdx.x] + ex) + w;
     incl[e] = after;
     const double target = u * (*total);
-    // out[0], out[1]: index and field value of the one entry whose running sum
-    // crosses u*P; out[2]: the largest field value with weight (fallback)
     if (mine && w > 0.0) {
       atomicMax(&out[2], (unsigned long long)fv);
-      if (before <= target && after > target) {
-        out[0] = e;
-        out[1] = fv;
-      }
+      if (after > target) atomicMin(&out[0], (unsigned long long)e);
     }
   }
+}
+
+// Field value of the chosen entry (out[0]) into out[1].
+template <int W>
+__global__ void k_prob_pick(KeyPtrs<W> keys, FilterOp f, unsigned long long* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint64_t e = out[0];
+  if (e == ~0ull) return;
+  uint64_t k[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) k[j] = keys.w[j][e];
+  out[1] = (sel_word<W>(k, f.fword) >> f.fshift) & f.fmask;
 }
 
 }  // namespace sparqs

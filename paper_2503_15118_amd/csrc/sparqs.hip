@@ -48,6 +48,11 @@ struct TableInfo {
   bool w32;
 };
 
+// A 2x2 complex matrix, m[out][in] as (re, im).
+struct Mat2 {
+  double re[2][2], im[2][2];
+};
+
 struct Layout {
   std::vector<RegInfo> regs;
   uint32_t W = 1;
@@ -156,6 +161,7 @@ struct ss_state {
   char* tab_base = nullptr;
   uint64_t tab_used = 0;
   std::vector<TableInfo> tables;
+  std::vector<Mat2> mats;         // ROT matrices (ss_load_matrix)
   // Host view of the entry count.  The count itself lives on the device in
   // meta->nring[nslot]: an emitting launch reads slot nslot and writes the
   // other one.  Between synchronisations the host knows an upper bound only.
@@ -401,6 +407,71 @@ void take_masks(ss_state* st, uint32_t ep) {
 }
 
 // The superset after an op that may set `bits` of `word` to anything.
+// Shape of a ROT matrix: 1 diagonal, 2 off-diagonal (each branch stays one
+// branch), 0 general.  An element is zero when both its parts are 0.0.
+int mat_shape(const Mat2& m) {
+  auto zero = [&](int r, int c) { return m.re[r][c] == 0.0 && m.im[r][c] == 0.0; };
+  if (zero(0, 1) && zero(1, 0)) return 1;
+  if (zero(0, 0) && zero(1, 1)) return 2;
+  return 0;
+}
+
+// Interference (branching) ops: H, Ry and a rotation by a general matrix.
+bool is_branching(const ss_state* st, const ss_op& op) {
+  if (op.kind == SS_H || op.kind == SS_RY) return true;
+  return op.kind == SS_ROT && op.aux < st->mats.size() && mat_shape(st->mats[op.aux]) == 0;
+}
+
+// The one-to-one single-qubit gates: a key bit flip (off-diagonal) or not,
+// and the factor taking input bit b to its output bit.
+bool one_to_one(const ss_state* st, const ss_op& op, bool* flip, double (&fac)[2][2]) {
+  const double c = 0.70710678118654752440;  // cos(pi/4) = sin(pi/4) as the nearest double
+  fac[0][0] = 1.0; fac[0][1] = 0.0; fac[1][0] = 1.0; fac[1][1] = 0.0;
+  *flip = false;
+  switch (op.kind) {
+    case SS_Y: *flip = true; fac[0][0] = 0.0; fac[0][1] = 1.0; fac[1][0] = 0.0; fac[1][1] = -1.0; return true;
+    case SS_Z: fac[1][0] = -1.0; return true;
+    case SS_S: fac[1][0] = 0.0; fac[1][1] = 1.0; return true;
+    case SS_SDG: fac[1][0] = 0.0; fac[1][1] = -1.0; return true;
+    case SS_T: fac[1][0] = c; fac[1][1] = c; return true;
+    case SS_TDG: fac[1][0] = c; fac[1][1] = -c; return true;
+    case SS_PHASE: fac[1][0] = std::cos(op.theta); fac[1][1] = std::sin(op.theta); return true;
+    case SS_ROT: {
+      if (op.aux >= st->mats.size()) return false;
+      const Mat2& m = st->mats[op.aux];
+      const int sh = mat_shape(m);
+      if (sh == 0) return false;
+      // diagonal: bit b keeps, factor m[b][b]; off-diagonal: factor m[1-b][b]
+      for (int b = 0; b < 2; ++b) {
+        const int r = sh == 1 ? b : 1 - b;
+        fac[b][0] = m.re[r][b];
+        fac[b][1] = m.im[r][b];
+      }
+      *flip = sh == 2;
+      return true;
+    }
+    default:
+      return false;
+  }
+}
+
+// Whether a non-branching op changes amplitudes, and the key words it writes.
+bool op_uses_amp(const ss_state* st, const ss_op& op) {
+  bool flip;
+  double fac[2][2];
+  return op.kind == SS_REFLECT0 || one_to_one(st, op, &flip, fac);
+}
+
+uint32_t op_write_words(const ss_state* st, const ss_op& op) {
+  bool flip;
+  double fac[2][2];
+  if (op.kind == SS_REFLECT0) return 0;
+  if (one_to_one(st, op, &flip, fac) && !flip) return 0;
+  uint32_t ww = 1u << st->L.regs[op.reg].word;
+  if (op.kind == SS_DIV) ww |= 1u << st->L.regs[op.imm].word;
+  return ww;
+}
+
 void sup_vary(ss_state* st, uint32_t word, uint64_t bits) {
   st->sorm[word] |= bits;
   st->sandm[word] &= ~bits;
@@ -416,9 +487,26 @@ void sup_flip(ss_state* st, uint32_t word, uint64_t bits) {
 // ... after a non-branching op.
 void sup_op(ss_state* st, const ss_op& op) {
   const RegInfo& d = st->L.regs[op.reg];
+  bool flip;
+  double fac[2][2];
+  if (one_to_one(st, op, &flip, fac)) {
+    // keys unchanged, or the mask bits flipped like X
+    if (flip) {
+      const uint64_t bits = (op.qmask & d.mask) << d.shift;
+      if (op.nctl == 0) sup_flip(st, d.word, bits);
+      else sup_vary(st, d.word, bits);
+    }
+    return;
+  }
   switch (op.kind) {
     case SS_REFLECT0:
       break;
+    case SS_DIV: {
+      const RegInfo& r = st->L.regs[op.imm];
+      sup_vary(st, d.word, d.mask << d.shift);
+      sup_vary(st, r.word, r.mask << r.shift);
+      break;
+    }
     case SS_X:
     case SS_XORC: {
       const uint64_t bits = ((op.kind == SS_X ? op.qmask : op.imm) & d.mask) << d.shift;
@@ -787,11 +875,10 @@ FilterOp base_filter(const ss_state* st, uint32_t inst) {
 // ---------------------------------------------------------------------------
 // op validation and conversion
 // ---------------------------------------------------------------------------
-bool is_branching(uint16_t kind) { return kind == SS_H || kind == SS_RY; }
 
 int validate_op(const ss_state* st, const ss_op& op) {
   const uint32_t nr = (uint32_t)st->L.regs.size();
-  if (op.kind > SS_REFLECT0 || op.flags != 0 || op.nctl > 3) return SS_E_ARG;
+  if (op.kind > SS_DIV || op.flags != 0 || op.nctl > 3) return SS_E_ARG;
   if (op.reg >= nr) return SS_E_ARG;
   const RegInfo& d = st->L.regs[op.reg];
   for (uint32_t j = 0; j < op.nctl; ++j) {
@@ -802,11 +889,34 @@ int validate_op(const ss_state* st, const ss_op& op) {
     case SS_X:
     case SS_H:
     case SS_RY:
+    case SS_Y:
+    case SS_Z:
+    case SS_S:
+    case SS_SDG:
+    case SS_T:
+    case SS_TDG:
+    case SS_PHASE:
+    case SS_ROT:
       if (op.qmask == 0 || (op.qmask & ~d.mask)) return SS_E_ARG;
       for (uint32_t j = 0; j < op.nctl; ++j)
         if (op.ctl[j].reg == op.reg && ((op.qmask >> op.ctl[j].qubit) & 1ull)) return SS_E_ARG;
-      if (op.kind == SS_RY && !std::isfinite(op.theta)) return SS_E_ARG;
+      if ((op.kind == SS_RY || op.kind == SS_PHASE) && !std::isfinite(op.theta)) return SS_E_ARG;
+      if (op.kind == SS_ROT && (op.aux >= st->mats.size() || __builtin_popcountll(op.qmask) != 1)) return SS_E_ARG;
       return SS_OK;
+    case SS_ADDC:
+      break;
+    case SS_MUL:
+      if (op.reg2 >= nr || op.aux >= nr || op.reg2 == op.reg || op.aux == op.reg) return SS_E_ARG;
+      break;
+    case SS_DIV: {
+      // quotient reg, remainder imm; dividend reg2, divisor aux
+      if (op.reg2 >= nr || op.aux >= nr || op.imm >= nr) return SS_E_ARG;
+      const uint64_t rr = op.imm;
+      if (rr == op.reg || op.reg2 == op.reg || op.aux == op.reg || op.reg2 == rr || op.aux == rr) return SS_E_ARG;
+      for (uint32_t j = 0; j < op.nctl; ++j)
+        if (op.ctl[j].reg == rr) return SS_E_ARG;
+      break;
+    }
     case SS_ADD:
     case SS_SUB:
     case SS_XOR:
@@ -821,8 +931,8 @@ int validate_op(const ss_state* st, const ss_op& op) {
     case SS_QRAM_LOAD:
     case SS_QRAM_UNLOAD: {
       if (op.reg2 >= nr || op.reg2 == op.reg) return SS_E_ARG;
-      if (op.qram_id >= st->tables.size()) return SS_E_QRAM;
-      const TableInfo& t = st->tables[op.qram_id];
+      if (op.aux >= st->tables.size()) return SS_E_QRAM;
+      const TableInfo& t = st->tables[op.aux];
       if (st->L.regs[op.reg2].width != t.addr_bits || d.width != t.word_bits) return SS_E_QRAM;
       break;
     }
@@ -862,15 +972,39 @@ PermOp to_perm(const ss_state* st, const ss_op& op) {
     case SS_QRAM_LOAD:
     case SS_QRAM_UNLOAD: {
       p.kind = PK_QRAM;
-      const TableInfo& t = st->tables[op.qram_id];
+      const TableInfo& t = st->tables[op.aux];
       p.table = t.dev;
       p.table_words32 = t.w32 ? 1u : 0u;
       break;
     }
     case SS_REFLECT0: p.kind = PK_REFLECT0; break;
+    case SS_ADDC: p.kind = PK_ADDC; p.imm = op.imm & d.mask; break;
+    case SS_MUL:
+    case SS_DIV: {
+      p.kind = op.kind == SS_MUL ? PK_MUL : PK_DIV;
+      const RegInfo& y = st->L.regs[op.aux];
+      p.src2_word = y.word;
+      p.src2_shift = y.shift;
+      p.src2_mask = y.mask;
+      if (op.kind == SS_DIV) {
+        const RegInfo& r = st->L.regs[op.imm];
+        p.dst2_word = r.word;
+        p.dst2_shift = r.shift;
+        p.dst2_mask = r.mask;
+      }
+      break;
+    }
+    default: {
+      bool flip;
+      if (one_to_one(st, op, &flip, p.fac)) {
+        p.kind = flip ? PK_ADIAG : PK_DIAG;
+        p.imm = (op.qmask & d.mask) << d.shift;
+      }
+      break;
+    }
   }
   if (op.kind == SS_ADD || op.kind == SS_SUB || op.kind == SS_XOR || op.kind == SS_QRAM_LOAD ||
-      op.kind == SS_QRAM_UNLOAD) {
+      op.kind == SS_QRAM_UNLOAD || op.kind == SS_MUL || op.kind == SS_DIV) {
     const RegInfo& s = st->L.regs[op.reg2];
     p.src_word = s.word;
     p.src_shift = s.shift;
@@ -883,7 +1017,10 @@ PermOp to_perm(const ss_state* st, const ss_op& op) {
 
 // Does a non-branching op keep every group of the mask g contiguous and intact?
 bool keeps_grouping(const ss_state* st, const ss_op& op, const uint64_t* g) {
-  if (op.kind == SS_REFLECT0) return true;  // phase only, keys unchanged
+  bool flip;
+  double fac[2][2];
+  const bool oto = one_to_one(st, op, &flip, fac);
+  if (op.kind == SS_REFLECT0 || (oto && !flip)) return true;  // phase only, keys unchanged
   uint64_t reads[kMaxW] = {0, 0, 0, 0}, writes[kMaxW] = {0, 0, 0, 0};
   uint64_t cm[kMaxW], cv[kMaxW];
   ctl_masks(st, op, cm, cv);
@@ -891,12 +1028,23 @@ bool keeps_grouping(const ss_state* st, const ss_op& op, const uint64_t* g) {
   const RegInfo& d = st->L.regs[op.reg];
   writes[d.word] |= d.mask << d.shift;
   if (op.kind == SS_ADD || op.kind == SS_SUB || op.kind == SS_XOR || op.kind == SS_QRAM_LOAD ||
-      op.kind == SS_QRAM_UNLOAD) {
+      op.kind == SS_QRAM_UNLOAD || op.kind == SS_MUL || op.kind == SS_DIV) {
     const RegInfo& s = st->L.regs[op.reg2];
     reads[s.word] |= s.mask << s.shift;
   }
+  if (op.kind == SS_MUL || op.kind == SS_DIV) {
+    const RegInfo& s = st->L.regs[op.aux];
+    reads[s.word] |= s.mask << s.shift;
+  }
+  if (op.kind == SS_DIV) {
+    const RegInfo& r = st->L.regs[op.imm];
+    writes[r.word] |= r.mask << r.shift;
+  }
+  // an xor by a value that does not depend on the group's bits keeps each
+  // group's members together (a one-to-one op with a flip xors its mask)
   const bool xor_like = op.kind == SS_X || op.kind == SS_XORC || op.kind == SS_XOR ||
-                        op.kind == SS_QRAM_LOAD || op.kind == SS_QRAM_UNLOAD;
+                        op.kind == SS_QRAM_LOAD || op.kind == SS_QRAM_UNLOAD || op.kind == SS_MUL ||
+                        op.kind == SS_DIV || oto;
   for (int w = 0; w < kMaxW; ++w) {
     if (reads[w] & g[w]) return false;
     if (!xor_like && (writes[w] & g[w])) return false;
@@ -998,7 +1146,7 @@ FastOp encode_fast(const ss_state* st, const ss_op& op, uint32_t gi) {
       return f;
     case SS_QRAM_LOAD:
     case SS_QRAM_UNLOAD: {
-      const TableInfo& t = st->tables[op.qram_id];
+      const TableInfo& t = st->tables[op.aux];
       const HalfField hs = half_of(st->L.regs[op.reg2]);
       if (!t.w32 || !hs.ok) return f;
       f.ssh = hs.sh;
@@ -1064,15 +1212,15 @@ struct RunChunk {
 
 // Op ranges of the launches of a call: the runs of non-branching ops, at
 // most kRunChunk ops per launch.
-void plan_runs(const ss_op* ops, uint64_t nops, std::vector<RunChunk>& chunks) {
+void plan_runs(const ss_state* st, const ss_op* ops, uint64_t nops, std::vector<RunChunk>& chunks) {
   uint64_t i = 0;
   while (i < nops) {
-    if (is_branching(ops[i].kind)) {
+    if (is_branching(st, ops[i])) {
       ++i;
       continue;
     }
     uint64_t j = i;
-    while (j < nops && !is_branching(ops[j].kind) && j - i < kRunChunk) ++j;
+    while (j < nops && !is_branching(st, ops[j]) && j - i < kRunChunk) ++j;
     RunChunk c{};
     c.first = i;
     c.len = (uint32_t)(j - i);
@@ -1095,8 +1243,8 @@ int upload_chunks(ss_state* st, const ss_op* ops, std::vector<RunChunk>& chunks,
     c.amp = false;
     for (uint64_t q = c.first; q < c.first + c.len; ++q) {
       const ss_op& op = ops[q];
-      if (op.kind == SS_REFLECT0) c.amp = true;
-      else c.write_words |= 1u << st->L.regs[op.reg].word;
+      if (op_uses_amp(st, op)) c.amp = true;
+      c.write_words |= op_write_words(st, op);
       if (W <= 2) {
         FastOp f = encode_fast(st, op, (uint32_t)gen.size());
         if (f.code == F_GEN) gen.push_back(to_perm(st, op));
@@ -1145,6 +1293,7 @@ int launch_chunk(ss_state* st, const RunChunk& c) {
 // One branching op: chunks of at most kMaxGroupBits target qubits, ascending.
 // The real 2x2 matrix of a branching op, m[out][in] (host libm).
 void gate_matrix(const ss_op& op, double (&m)[2][2]) {
+  if (op.kind == SS_ROT) return;  // complex: rot_matrix
   if (op.kind == SS_H) {
     const double c = 0.70710678118654752440;  // nearest double to 1/sqrt(2)
     m[0][0] = c; m[0][1] = c; m[1][0] = c; m[1][1] = -c;
@@ -1158,7 +1307,21 @@ void gate_matrix(const ss_op& op, double (&m)[2][2]) {
 // Ops that can follow `a` in one chained launch: branching on the same one
 // target qubit (H or Ry, any controls; controls never include the target).
 bool chains_with(const ss_op& a, const ss_op& b) {
-  return is_branching(b.kind) && b.reg == a.reg && b.qmask == a.qmask && __builtin_popcountll(a.qmask) == 1;
+  return (b.kind == SS_H || b.kind == SS_RY) && (a.kind == SS_H || a.kind == SS_RY) && b.reg == a.reg &&
+         b.qmask == a.qmask && __builtin_popcountll(a.qmask) == 1;
+}
+
+// Longest chain for a state's eps.  A chained launch prunes once, after its
+// last op, where the plain method prunes after every op.  A prune removes from
+// each group amplitudes below eps, a change of norm below sqrt(2)*eps, and the
+// later matrices are unitary, so each prune left out moves the result by less
+// than that.  The chain is cut so that the sum stays within 1e-12 (the
+// amplitude tolerance of the method's results); with eps = 0 the prunes only
+// remove exact zeros, which change nothing later.
+uint64_t max_chain(double eps) {
+  if (!(eps > 0.0)) return (uint64_t)kMaxChain;
+  const double k = std::floor(1e-12 / (std::sqrt(2.0) * eps)) + 1.0;
+  return k >= (double)kMaxChain ? (uint64_t)kMaxChain : (uint64_t)k;
 }
 
 // One branching op, or (nchain >= 2) the one-target ops chain_ops[0..nchain)
@@ -1171,8 +1334,15 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index, const ss_op* 
   std::vector<uint32_t> qs;
   for (uint32_t q = 0; q < d.width; ++q)
     if ((op.qmask >> q) & 1ull) qs.push_back(q);
-  double m[2][2];
+  double m[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   gate_matrix(op, m);
+  const bool cplx = op.kind == SS_ROT;
+  Mat2 cm{};
+  if (cplx) {
+    cm = st->mats[op.aux];
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) m[a][b] = cm.re[a][b];
+  }
   // An op split over several launches cannot be rolled back once its first
   // part has run, so it is admitted only if the worst case fits.
   if (qs.size() > (size_t)kMaxGroupBits) {
@@ -1214,7 +1384,11 @@ int do_branching(ss_state* st, const ss_op& op, uint64_t op_index, const ss_op* 
     ctl_masks(st, op, g.cmask, g.cval);
     g.has_ctl = op.nctl ? 1u : 0u;
     for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) g.m[a][b] = m[a][b];
+      for (int b = 0; b < 2; ++b) {
+        g.m[a][b] = m[a][b];
+        g.mi[a][b] = cplx ? cm.im[a][b] : 0.0;
+      }
+    g.cplx = cplx ? 1u : 0u;
     g.eps2 = last ? st->eps * st->eps : 0.0;
     if (nchain >= 2) {
       std::vector<ChainStep> steps(nchain);
@@ -1384,6 +1558,30 @@ void launch_pack(ss_state* st, const uint64_t* values, const double2* amps, uint
 // Append n entries (register values, row-major, and amplitudes; host arrays)
 // at the current exact count, staged through the alternate buffer; the
 // instance field gets `inst`, or `inst` + row index with `row_inst`.
+// Whether the n entries given as register values (row-major n x nregs,
+// truncated to the register widths) have distinct keys: the packed keys are
+// sorted on the host and neighbours compared.
+bool keys_distinct(const ss_state* st, const uint64_t* values, uint64_t n) {
+  const uint32_t nr = (uint32_t)st->L.regs.size(), W = st->L.W;
+  std::vector<uint64_t> k(n * W, 0);
+  for (uint64_t i = 0; i < n; ++i)
+    for (uint32_t r = 0; r < nr; ++r) {
+      const RegInfo& ri = st->L.regs[r];
+      k[i * W + ri.word] |= (values[i * nr + r] & ri.mask) << ri.shift;
+    }
+  std::vector<uint64_t> idx(n);
+  for (uint64_t i = 0; i < n; ++i) idx[i] = i;
+  auto less = [&](uint64_t a, uint64_t b) {
+    for (int w = (int)W - 1; w >= 0; --w)
+      if (k[a * W + w] != k[b * W + w]) return k[a * W + w] < k[b * W + w];
+    return false;
+  };
+  std::sort(idx.begin(), idx.end(), less);
+  for (uint64_t i = 1; i < n; ++i)
+    if (!less(idx[i - 1], idx[i])) return false;
+  return true;
+}
+
 int pack_entries(ss_state* st, const uint64_t* values, const double* amps, uint64_t n, uint32_t inst,
                  bool row_inst) {
   const uint32_t nr = (uint32_t)st->L.regs.size();
@@ -1533,7 +1731,7 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
         if (chunk[i] != 0) continue;
         uint64_t j = cur[i];
         uint64_t len = 0;
-        while (j + len < end[i] && !is_branching(ops[j + len].kind)) ++len;
+        while (j + len < end[i] && !is_branching(st, ops[j + len])) ++len;
         if (len == 0) continue;
         // keep one launch's op tables well inside the staging ring
         const uint64_t bytes = (fast.size() + len) * sizeof(FastOp) + (gen.size() + len) * sizeof(PermOp);
@@ -1542,8 +1740,8 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
         runs[i].len = (uint32_t)len;
         for (uint64_t q = 0; q < len; ++q) {
           const ss_op& op = ops[j + q];
-          if (op.kind == SS_REFLECT0) amp = true;
-          else ww |= 1u << st->L.regs[op.reg].word;
+          if (op_uses_amp(st, op)) amp = true;
+          ww |= op_write_words(st, op);
           FastOp f = W <= 2 ? encode_fast(st, op, (uint32_t)gen.size()) : FastOp{};
           if (W > 2) {
             f.code = F_GEN;
@@ -1606,13 +1804,16 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
       }
       ctl_masks(st, op, b.cmask, b.cval);
       b.has_ctl = op.nctl ? 1u : 0u;
-      if (op.kind == SS_H) {
-        const double c = 0.70710678118654752440;
-        b.m[0][0] = c; b.m[0][1] = c; b.m[1][0] = c; b.m[1][1] = -c;
+      if (op.kind == SS_ROT) {
+        const Mat2& mm = st->mats[op.aux];
+        b.cplx = 1;
+        for (int r = 0; r < 2; ++r)
+          for (int q = 0; q < 2; ++q) {
+            b.m[r][q] = mm.re[r][q];
+            b.mi[r][q] = mm.im[r][q];
+          }
       } else {
-        const double h = op.theta / 2.0;
-        const double c = std::cos(h), s2 = std::sin(h);
-        b.m[0][0] = c; b.m[0][1] = -s2; b.m[1][0] = s2; b.m[1][1] = c;
+        gate_matrix(op, b.m);
       }
       b.prune = 1;
       b.eps2 = last ? st->eps * st->eps : 0.0;
@@ -1722,7 +1923,7 @@ int plan_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst
   }
   set_mark(st, 0);
   std::vector<RunChunk> chunks;
-  plan_runs(ops, nops, chunks);
+  plan_runs(st, ops, nops, chunks);
   size_t ci = 0, up = 0;
   // Records are encoded and uploaded a group of chunks (>= kUploadOps ops) at
   // a time, when the first of them is needed, so that the host encodes while
@@ -1759,10 +1960,12 @@ int plan_ops(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* inst
   };
   for (uint64_t i = 0; i < nops; ++i) {
     const ss_op& op = ops[i];
-    if (is_branching(op.kind)) {
+    if (is_branching(st, op)) {
       uint64_t j = i + 1;
-      if (st->chain)
-        while (j < nops && j - i < (uint64_t)kMaxChain && chains_with(op, ops[j])) ++j;
+      if (st->chain) {
+        const uint64_t lim = max_chain(st->eps);
+        while (j < nops && j - i < lim && chains_with(op, ops[j])) ++j;
+      }
       rc = flush(i);
       // a one-target op takes the run that follows it into its own launch
       FusedRun fr{nullptr, 0u, nullptr};
@@ -2072,10 +2275,37 @@ int ss_load_qram(ss_state* st, const uint64_t* table, uint64_t len, uint32_t add
   return SS_OK;
 }
 
+int ss_load_matrix(ss_state* st, const double* m, uint32_t* matrix_id) {
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (!m || !matrix_id) return SS_E_ARG;
+  Mat2 M{};
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) {
+      M.re[r][c] = m[4 * r + 2 * c];
+      M.im[r][c] = m[4 * r + 2 * c + 1];
+      if (!std::isfinite(M.re[r][c]) || !std::isfinite(M.im[r][c])) return SS_E_ARG;
+    }
+  // unitary: (M^H M)[i][j] = sum_r conj(M[r][i]) M[r][j] within 1e-12 of I
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      double re = 0.0, im = 0.0;
+      for (int r = 0; r < 2; ++r) {
+        re += M.re[r][i] * M.re[r][j] + M.im[r][i] * M.im[r][j];
+        im += M.re[r][i] * M.im[r][j] - M.im[r][i] * M.re[r][j];
+      }
+      if (std::fabs(re - (i == j ? 1.0 : 0.0)) > 1e-12 || std::fabs(im) > 1e-12) return SS_E_NOT_UNITARY;
+    }
+  st->mats.push_back(M);
+  *matrix_id = (uint32_t)st->mats.size() - 1;
+  return SS_OK;
+}
+
 int ss_set_entries(ss_state* st, uint32_t inst, const uint64_t* values, const double* amps, uint64_t n) {
   int rc = check_state(st);
   if (rc) return rc;
   if (inst >= st->ninst || (n && (!values || !amps))) return SS_E_ARG;
+  if (!keys_distinct(st, values, n)) return SS_E_ARG;
   // drop the instance's current entries
   if (st->L.has_inst) {
     FilterOp f = base_filter(st, inst);
@@ -2265,6 +2495,9 @@ int ss_measure(ss_state* st, uint32_t inst, uint32_t reg, double u, uint64_t* ou
   if (W == 1) k_prob_find<1><<<ntiles, kBlock, 0, st->stream>>>(kp<1>(b), b.amp, n, f, tile_sum, dtot, u, incl, out);
   else if (W == 2) k_prob_find<2><<<ntiles, kBlock, 0, st->stream>>>(kp<2>(b), b.amp, n, f, tile_sum, dtot, u, incl, out);
   else k_prob_find<4><<<ntiles, kBlock, 0, st->stream>>>(kp<4>(b), b.amp, n, f, tile_sum, dtot, u, incl, out);
+  if (W == 1) k_prob_pick<1><<<1, 64, 0, st->stream>>>(kp<1>(b), f, out);
+  else if (W == 2) k_prob_pick<2><<<1, 64, 0, st->stream>>>(kp<2>(b), f, out);
+  else k_prob_pick<4><<<1, 64, 0, st->stream>>>(kp<4>(b), f, out);
   rc = check_launch(st);
   if (rc) return rc;
   unsigned long long hout[4];
@@ -2278,7 +2511,8 @@ int ss_measure(ss_state* st, uint32_t inst, uint32_t reg, double u, uint64_t* ou
   if (hout[0] != ~0ull) {
     v = hout[1];
   } else {
-    // u*P at or beyond the total (rounding): the largest field value present
+    // no running sum exceeds u*P (u*P at the total by rounding): the
+    // largest field value present
     v = hout[2];
   }
   f.use_f = 1;

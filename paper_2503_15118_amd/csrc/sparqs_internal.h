@@ -77,6 +77,11 @@ enum PermKind : uint32_t {
   PK_XORC = 5,      // same as XMASK but kept distinct for statistics
   PK_QRAM = 6,
   PK_REFLECT0 = 7,
+  PK_DIAG = 8,      // per qubit of imm (shifted, ascending): amplitude *= fac[bit]
+  PK_ADIAG = 9,     // the same, then the qubits of imm flip
+  PK_ADDC = 10,     // dst += imm
+  PK_MUL = 11,      // dst ^= src * src2
+  PK_DIV = 12,      // dst ^= src div src2, dst2 ^= src mod src2
 };
 
 struct PermOp {
@@ -92,6 +97,10 @@ struct PermOp {
   const void* table;            // QRAM words
   uint64_t cmask[kMaxW];        // control bits per word
   uint64_t cval[kMaxW];         // required values of those bits
+  uint32_t src2_word, src2_shift;  // MUL second factor / DIV divisor
+  uint32_t dst2_word, dst2_shift;  // DIV remainder
+  uint64_t src2_mask, dst2_mask;
+  double fac[2][2];             // PK_DIAG / PK_ADIAG: factor (re, im) for input bit 0 and 1
 };
 
 // Fast form of a non-branching op for keys of at most 2 words, every field
@@ -150,8 +159,11 @@ struct GroupOp {
   uint64_t tmask[kMaxW];        // all target bits per word
   uint64_t cmask[kMaxW];
   uint64_t cval[kMaxW];
-  double m[2][2];               // real matrix, m[out][in]
+  double m[2][2];               // matrix, m[out][in] (real parts)
   double eps2;                  // prune below this |a|^2 (strict)
+  uint32_t cplx;                // 1: mi holds imaginary parts (k == 1, no chain)
+  uint32_t pad;
+  double mi[2][2];
 };
 
 // Key bits a captured plan allows to vary at one of its check points.
@@ -164,7 +176,7 @@ struct RunRange {
   uint32_t start, len;          // FastOp range of the instance's non-branching run
 };
 
-struct BatchOp {
+struct alignas(16) BatchOp {     // staged in LDS as 16-byte words
   uint32_t k;                   // target qubits this round (0: the entry passes through)
   uint32_t has_ctl;
   uint32_t prune;               // 1: the instance branched this round; apply eps2 after merging
@@ -173,7 +185,11 @@ struct BatchOp {
   uint64_t cmask[kMaxW], cval[kMaxW];
   double m[2][2];
   double eps2;
+  uint32_t cplx;                // 1: mi holds imaginary parts (k == 1)
+  uint32_t pad2;
+  double mi[2][2];
 };
+static_assert(sizeof(BatchOp) % 16 == 0, "BatchOp is staged as 16-byte words");
 
 // A digit of one radix pass = sum of up to kMaxFields bit runs of the key:
 //   digit |= ((key[word] >> shift) & ((1 << width) - 1)) << dshift

@@ -237,6 +237,20 @@ def test_c2_form_closed_form(seed, nops, n_ry, h):
     assert s["n_gpu"] == s["n_oracle"] == s["shared"] == 2 ** (h + 1)
 
 
+@pytest.mark.parametrize("seed", [1, 4])
+def test_c2_rot_form_closed_form(seed):
+    """The same structure with complex rotations on the flag."""
+    from oracle.closed_forms import c2_closed_form
+    from parity import compare_arrays
+    c = wl.c2_rot_circuit(seed, nops=300, n_ry=5, h_qubits=8)
+    st, _, _ = run_circuit(c)
+    ok, _, oa = st.export()
+    ck, ca = c2_closed_form(c)
+    s = compare_arrays(ck, ca, ok, oa, c.eps, atol=1e-13)
+    assert s["n_gpu"] == s["n_oracle"] == 2 ** 9
+    assert np.max(np.abs(oa.imag)) > 0.01
+
+
 def test_compare_arrays_catches_mistakes():
     """The vectorised comparison flags a missing key, a wrong key word, a
     wrong amplitude and a non-ascending export; band keys may be missing."""

@@ -258,6 +258,25 @@ def c2_circuit(seed, nops: int = 1000, n_ry: int = 10, h_qubits: int = 20) -> Ci
 # ---------------------------------------------------------------------------
 # C3: many C1-form instances with log-uniform caps and uneven lengths
 # ---------------------------------------------------------------------------
+def c2_rot_circuit(seed, nops: int = 1000, n_ry: int = 10, h_qubits: int = 20) -> Circuit:
+    """The arithmetic-heavy circuit with each Ry on the flag replaced by a
+    rotation by a seeded Haar-random 2x2 unitary (complex amplitudes)."""
+    c = c2_circuit(seed, nops=nops, n_ry=n_ry, h_qubits=h_qubits)
+    rng = _rng(np.random.SeedSequence([int(seed), 7]))
+    ops = c.ops.copy()
+    mats = []
+    for i in range(len(ops)):
+        if KINDS[int(ops[i]["kind"])] == "RY":
+            ops[i]["kind"] = KIND["ROT"]
+            ops[i]["table"] = len(mats)
+            ops[i]["theta"] = 0.0
+            mats.append(random_unitary(rng))
+    c.ops = ops
+    c.matrices = mats
+    c.name = f"c2rot-seed{seed}"
+    return c
+
+
 def c3_batch(seed, ninst: int = 1024, lo_bits: float = 6.0, hi_bits: float = 18.0,
              len_lo: int = 200, len_hi: int = 1000) -> List[Circuit]:
     ss = np.random.SeedSequence(int(seed))
