@@ -60,6 +60,10 @@ def lib():
         L.ora_layout.argtypes = [vp, u32, P(u32), P(u32)]
         L.ora_add_table.argtypes = [vp, P(u64), u64, u32, u32]
         L.ora_add_matrix.argtypes = [vp, P(f64)]
+        L.ora_add_register.argtypes = [vp, u32]
+        L.ora_remove_register.argtypes = [vp, u32]
+        L.ora_probabilities.restype = u64
+        L.ora_probabilities.argtypes = [vp, u32, P(u64), P(f64), u64]
         L.ora_set_entries.argtypes = [vp, P(u64), P(f64), u64]
         L.ora_apply.argtypes = [vp, vp, u64, P(f64), P(u64)]
         L.ora_prune.argtypes = [vp, f64]
@@ -146,6 +150,25 @@ class OracleState:
         if lib().ora_measure(self.h, reg, float(u), ctypes.byref(out), ctypes.byref(p)):
             raise RuntimeError("oracle: measure failed")
         return out.value, p.value
+
+    def add_register(self, width: int) -> int:
+        r = lib().ora_add_register(self.h, int(width))
+        if r < 0:
+            raise ValueError("oracle: no room for the register")
+        self.nregs += 1
+        return r
+
+    def remove_register(self, reg: int):
+        if lib().ora_remove_register(self.h, int(reg)):
+            raise ValueError("oracle: the register does not hold one value in every branch")
+
+    def probabilities(self, reg: int):
+        """(values, p(v)/P) ascending, without collapse."""
+        n = int(lib().ora_probabilities(self.h, reg, None, None, 0))
+        v = np.zeros(n, dtype=np.uint64)
+        p = np.zeros(n, dtype=np.float64)
+        lib().ora_probabilities(self.h, reg, _ptr(v, ctypes.c_uint64), _ptr(p, ctypes.c_double), n)
+        return v, p
 
     def layout(self, reg: int) -> Tuple[int, int]:
         w = ctypes.c_uint32(0)

@@ -55,6 +55,14 @@
 //    2^width(dst)).  DIV: q <- q xor (x div y), r <- r xor (x mod y), each
 //    truncated to its register; for y = 0 the quotient is all ones and the
 //    remainder x (the xor form keeps both maps bijections).
+//  * registers can be added and removed while the state lives (the System
+//    class's add_register / remove_register, supplementary Table S1): a new
+//    register takes the lowest run of free bits of its width in the lowest
+//    key word that has one (a word is added when none has), every branch
+//    holding 0 there; a register can be removed when it holds one value v in
+//    every branch (the state is then that register's |v> times the rest), and
+//    its bits are cleared.  Its index stays retired.
+//  * probability readout without collapse: p(v)/P for every v with weight.
 //  * measurement: p(v) = sum of |a|^2 over entries whose field equals v
 //    (ascending key), P = sum of p(v) over ascending v; the outcome is the
 //    smallest v whose running sum exceeds u*P; survivors are divided by
@@ -101,7 +109,7 @@ struct Mat {
 struct Field {
   int word;
   int offset;
-  int width;
+  int width;    // 0: a removed register
 };
 
 struct QTable {
@@ -198,6 +206,74 @@ int ora_add_table(void* h, const uint64_t* vals, uint64_t len, uint32_t addr_bit
     if (word_bits < 64 && (v >> word_bits) != 0) return -1;
   o->tables.push_back(std::move(t));
   return (int)o->tables.size() - 1;
+}
+
+// Add a register of `width` qubits holding 0 in every branch; returns its
+// index, or -1 when no key word (of at most 4) has room.
+int ora_add_register(void* h, uint32_t width) {
+  Oracle* o = static_cast<Oracle*>(h);
+  if (width < 1 || width > 64) return -1;
+  for (int w = 0; w < 4; ++w) {
+    uint64_t used = 0;
+    for (const Field& f : o->regs)
+      if (f.width && f.word == w) used |= low_mask(f.width) << f.offset;
+    for (int off = 0; off + (int)width <= 64; ++off) {
+      if ((used & (low_mask(width) << off)) == 0) {
+        o->regs.push_back({w, off, (int)width});
+        return (int)o->regs.size() - 1;
+      }
+    }
+  }
+  return -1;
+}
+
+// Remove register r: -1 unless it holds one value in every branch; that
+// value's bits are cleared from every key.
+int ora_remove_register(void* h, uint32_t r) {
+  Oracle* o = static_cast<Oracle*>(h);
+  if (r >= o->regs.size() || o->regs[r].width == 0) return -1;
+  const Field f = o->regs[r];
+  bool first = true;
+  uint64_t v0 = 0;
+  for (const auto& kv : o->state) {
+    uint64_t v = get_field(kv.first, f);
+    if (first) { v0 = v; first = false; }
+    else if (v != v0) return -1;
+  }
+  State out;
+  for (const auto& kv : o->state) {
+    Key k = kv.first;
+    set_field(k, f, 0);
+    out[k] = kv.second;
+  }
+  o->state.swap(out);
+  o->regs[r].width = 0;
+  return 0;
+}
+
+// Probabilities of register `reg` without collapse: for each value v with
+// weight (ascending), p(v) / P with p(v) the sum of |a|^2 over its branches
+// (ascending key) and P the sum of p(v) (ascending v).  Writes up to `cap`
+// pairs; returns the number of values.
+uint64_t ora_probabilities(void* h, uint32_t reg, uint64_t* values, double* probs, uint64_t cap) {
+  Oracle* o = static_cast<Oracle*>(h);
+  const Field& f = o->regs[reg];
+  std::map<uint64_t, double> p;
+  for (const auto& kv : o->state) {
+    double n2 = kv.second.re * kv.second.re + kv.second.im * kv.second.im;
+    p[get_field(kv.first, f)] += n2;
+  }
+  double P = 0.0;
+  for (const auto& pv : p) P += pv.second;
+  uint64_t i = 0;
+  for (const auto& pv : p) {
+    if (i < cap) {
+      values[i] = pv.first;
+      probs[i] = pv.second / P;
+    }
+    ++i;
+  }
+  return i;
 }
 
 // Register a 2x2 complex matrix (8 doubles: m00, m01, m10, m11 as re, im;
