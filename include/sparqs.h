@@ -239,6 +239,43 @@ int ss_prune(ss_state* st, double eps);
  * state of Sec. "Sparse state representation and data structure". */
 int ss_measure(ss_state* st, uint32_t inst, uint32_t reg, double u, uint64_t* outcome, double* prob);
 
+/* Probabilities of register `reg` in instance `inst` without collapse: for
+ * each value v with weight, ascending, values[k] = v and probs[k] = p(v)/P,
+ * with p(v) the sum of |a|^2 over the instance's entries whose field is v and
+ * P the instance's total (both summed on the device in a fixed order).
+ * Writes min(cap, count) pairs; *n gets the count.  The state is unchanged
+ * (its entries are left ordered by the field).  Blocking.
+ * Errors: SS_E_ARG (bad instance or register, null outputs).
+ * Defined by: the paper is silent on readout; this is the marginal
+ * distribution of one register of the state of Sec. "Sparse state
+ * representation and data structure". */
+int ss_probabilities(ss_state* st, uint32_t inst, uint32_t reg, uint64_t* values, double* probs, uint64_t cap,
+                     uint64_t* n);
+
+/* Add a register of `nqubits` (1..64) qubits, |0> in every branch, to a live
+ * state; *reg gets its index (indices of removed registers are not reused).
+ * It takes the lowest run of free key bits of its width in the lowest key word
+ * that has one (bits freed by removed registers included).  When no word has
+ * room the key gains words (W 1 -> 2 -> 4): the entries are re-packed on the
+ * device inside the same arena, whose entry capacity then shrinks
+ * (SS_E_NOMEM, state unchanged, if the entries would not fit).  Graphs
+ * captured before the call are retired.  Blocking.
+ * Errors: SS_E_ARG (width, 64 registers already), SS_E_NOMEM (no room in 256
+ * key bits, or the arena after re-packing).
+ * Defined by: add_register of the System class (supplementary Table S1):
+ * activating a register (Sec. "Sparse state representation and data
+ * structure"). */
+int ss_add_register(ss_state* st, uint32_t nqubits, const char* name, uint32_t* reg);
+
+/* Remove register `reg`.  Allowed only when it holds one value v in every
+ * branch of every instance (the state is then |v> on that register times the
+ * rest); its bits are cleared and freed, its index retired (ops naming it
+ * fail with SS_E_ARG).  Blocking.
+ * Errors: SS_E_ARG (bad or removed register, more than one value).
+ * Defined by: remove_register of the System class (supplementary Table S1):
+ * deactivating a register. */
+int ss_remove_register(ss_state* st, uint32_t reg);
+
 /* Entry count of instance `inst` (UINT32_MAX: all instances) and the running
  * peak of the whole state (the paper's max_system_size, supplementary Table
  * S1).  Blocking. */

@@ -77,6 +77,9 @@ def _load():
         "ss_apply_ops": [vp, vp, u64, P(u64), P(_Result)],
         "ss_prune": [vp, f64],
         "ss_measure": [vp, u32, u32, f64, P(u64), P(f64)],
+        "ss_probabilities": [vp, u32, u32, P(u64), P(f64), u64, P(u64)],
+        "ss_add_register": [vp, u32, ctypes.c_char_p, P(u32)],
+        "ss_remove_register": [vp, u32],
         "ss_nnz": [vp, u32, P(u64), P(u64)],
         "ss_export": [vp, u32, P(u64), P(f64), u64, P(u64)],
         "ss_sync": [vp, P(_Result)],
@@ -102,6 +105,7 @@ lib = _load()
 
 EXPORTED = ("ss_required_bytes", "ss_create_state", "ss_destroy_state", "ss_capacity", "ss_layout",
             "ss_key_words", "ss_load_qram", "ss_load_matrix", "ss_set_entries", "ss_apply_ops", "ss_prune", "ss_measure",
+            "ss_probabilities", "ss_add_register", "ss_remove_register",
             "ss_nnz", "ss_export", "ss_sync", "ss_rebind_arena", "ss_set_option", "ss_stats",
             "ss_trace_read", "ss_device_error", "ss_strerror", "ss_graph_capture", "ss_graph_launch",
             "ss_graph_destroy")
@@ -271,6 +275,27 @@ class State:
         p = ctypes.c_double(0.0)
         _check(lib.ss_measure(self.h, inst, reg, float(u), ctypes.byref(out), ctypes.byref(p)), "ss_measure")
         return int(out.value), float(p.value)
+
+    def probabilities(self, inst: int, reg: int):
+        """(values, p(v)/P) of register `reg` in instance `inst`, ascending, without collapse."""
+        n = ctypes.c_uint64(0)
+        _check(lib.ss_probabilities(self.h, inst, reg, None, None, 0, ctypes.byref(n)), "ss_probabilities")
+        v = np.zeros(n.value, dtype=np.uint64)
+        p = np.zeros(n.value, dtype=np.float64)
+        m = ctypes.c_uint64(0)
+        _check(lib.ss_probabilities(self.h, inst, reg, _p(v, ctypes.c_uint64), _p(p, ctypes.c_double), len(v),
+                                    ctypes.byref(m)), "ss_probabilities")
+        assert m.value == len(v)
+        return v, p
+
+    def add_register(self, nqubits: int, name: str = "") -> int:
+        r = ctypes.c_uint32(0)
+        _check(lib.ss_add_register(self.h, int(nqubits), name.encode() or None, ctypes.byref(r)), "ss_add_register")
+        self.regs = list(self.regs) + [(name or f"r{r.value}", int(nqubits))]
+        return int(r.value)
+
+    def remove_register(self, reg: int):
+        _check(lib.ss_remove_register(self.h, int(reg)), "ss_remove_register")
 
     def nnz(self, inst: int = 0xFFFFFFFF) -> int:
         n = ctypes.c_uint64(0)

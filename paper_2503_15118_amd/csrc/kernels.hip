@@ -2301,4 +2301,134 @@ __global__ void k_prob_pick(KeyPtrs<W> keys, FilterOp f, unsigned long long* out
   out[1] = (sel_word<W>(k, f.fword) >> f.fshift) & f.fmask;
 }
 
+// ---------------------------------------------------------------------------
+// Probability readout without collapse (entries sorted by instance and the
+// register's field): per-field sums of |a|^2 in a fixed order.
+// ---------------------------------------------------------------------------
+// Segmented inclusive sums inside each tile of kBlock entries: a segment
+// starts where (instance, field) changes.  part[e] = sum from the segment's
+// start (or the tile's) to e; fhead[t] = position of the tile's first segment
+// start (kBlock if none); tail[t] = part of the tile's last entry.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_runs_tile(KeyPtrs<W> keys, const double2* __restrict__ amp, uint64_t n,
+                                                      FilterOp f, double* __restrict__ part,
+                                                      uint32_t* __restrict__ fhead, double* __restrict__ tail) {
+  __shared__ double s_v[kBlock / 64];
+  __shared__ uint32_t s_f[kBlock / 64];
+  __shared__ uint32_t s_head;
+  const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_head = kBlock;
+  double v = 0.0;
+  uint32_t head = 0;
+  if (e < n) {
+    uint64_t k[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) k[j] = keys.w[j][e];
+    const uint64_t ii = f.has_inst ? ((sel_word<W>(k, f.iword) >> f.ishift) & f.imask) : 0;
+    const uint64_t fv = (sel_word<W>(k, f.fword) >> f.fshift) & f.fmask;
+    if (!f.has_inst || ii == f.inst) {
+      const double2 a = amp[e];
+      v = a.x * a.x + a.y * a.y;
+    }
+    head = 1;
+    if (e > 0) {
+      uint64_t q[W];
+#pragma unroll
+      for (int j = 0; j < W; ++j) q[j] = keys.w[j][e - 1];
+      const uint64_t qi = f.has_inst ? ((sel_word<W>(q, f.iword) >> f.ishift) & f.imask) : 0;
+      const uint64_t qv = (sel_word<W>(q, f.fword) >> f.fshift) & f.fmask;
+      head = (qi != ii || qv != fv) ? 1u : 0u;
+    }
+  }
+  __syncthreads();
+  if (head) atomicMin(&s_head, threadIdx.x);
+  // (value, started) pairs: (a, fa) then (b, fb) gives (fb ? b : a + b, fa | fb)
+  uint32_t fl = head;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double pv = __shfl_up(v, d, 64);
+    const uint32_t pf = __shfl_up(fl, d, 64);
+    if (lane >= (uint32_t)d) {
+      if (!fl) v = pv + v;
+      fl |= pf;
+    }
+  }
+  if (lane == 63) {
+    s_v[wv] = v;
+    s_f[wv] = fl;
+  }
+  __syncthreads();
+  double cv = 0.0;
+  uint32_t cf = 0;
+  for (uint32_t j = 0; j < wv; ++j) {
+    cv = s_f[j] ? s_v[j] : cv + s_v[j];
+    cf |= s_f[j];
+  }
+  if (wv > 0 && !fl) v = cv + v;
+  if (e < n) part[e] = v;
+  const uint64_t last = ((uint64_t)blockIdx.x + 1) * kBlock < n ? ((uint64_t)blockIdx.x + 1) * kBlock - 1 : n - 1;
+  if (e == last) tail[blockIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) fhead[blockIdx.x] = s_head;
+}
+
+// Sum carried into each tile by the segment that started before it (one
+// thread, tiles in order).
+static __global__ void k_runs_carry(const uint32_t* __restrict__ fhead, const double* __restrict__ tail,
+                                    uint64_t ntiles, double* __restrict__ carry) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double c = 0.0;
+  for (uint64_t t = 0; t < ntiles; ++t) {
+    carry[t] = c;
+    c = fhead[t] < (uint32_t)kBlock ? tail[t] : c + tail[t];
+  }
+}
+
+// Each entry of the instance that ends its field's run writes the field value
+// and p(v) / P (in place of its part sum); every other entry writes -1.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_runs_out(KeyPtrs<W> keys, uint64_t n, FilterOp f,
+                                                     double* __restrict__ part, const uint32_t* __restrict__ fhead,
+                                                     const double* __restrict__ carry, const double* __restrict__ total,
+                                                     uint64_t* __restrict__ out_val) {
+  const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n) return;
+  uint64_t k[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) k[j] = keys.w[j][e];
+  const uint64_t ii = f.has_inst ? ((sel_word<W>(k, f.iword) >> f.ishift) & f.imask) : 0;
+  const uint64_t fv = (sel_word<W>(k, f.fword) >> f.fshift) & f.fmask;
+  bool end = true;
+  if (e + 1 < n) {
+    uint64_t q[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) q[j] = keys.w[j][e + 1];
+    const uint64_t qi = f.has_inst ? ((sel_word<W>(q, f.iword) >> f.ishift) & f.imask) : 0;
+    const uint64_t qv = (sel_word<W>(q, f.fword) >> f.fshift) & f.fmask;
+    end = qi != ii || qv != fv;
+  }
+  const double v = part[e];
+  double out = -1.0;
+  if (end && (!f.has_inst || ii == f.inst)) {
+    const uint32_t pos = threadIdx.x;
+    const double sum = pos < fhead[blockIdx.x] ? carry[blockIdx.x] + v : v;
+    out = sum / *total;
+    out_val[e] = fv;
+  }
+  part[e] = out;
+}
+
+// Copy n entries between buffers of key widths WI <= WO (words WI.. of the
+// output are 0): re-packing for keys that gain words.
+template <int WI, int WO>
+__global__ __launch_bounds__(kBlock) void k_relayout(KeyPtrs<WI> in_keys, const double2* __restrict__ in_amp,
+                                                     KeyPtrs<WO> out_keys, double2* __restrict__ out_amp, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock) {
+#pragma unroll
+    for (int w = 0; w < WO; ++w) out_keys.w[w][i] = w < WI ? in_keys.w[w < WI ? w : 0][i] : 0ull;
+    out_amp[i] = in_amp[i];
+  }
+}
+
 }  // namespace sparqs

@@ -121,11 +121,13 @@ Carve carve(uint32_t W, uint32_t ninst, uint64_t cap, uint64_t table_bytes) {
   off = align_up(off + (uint64_t)kMaxOpsPerCall * sizeof(PermOp), kAlign);
   c.uscr = off;
   off = align_up(off + (uint64_t)(ninst + 64) * 8, kAlign);
+  // the tables' place does not depend on the key width (a key that gains
+  // words re-carves the arena around them)
+  c.tables = off;
+  off = align_up(off + table_bytes, kAlign);
   c.hist_blocks = std::min<uint64_t>(kHistBlocksMax, std::max<uint64_t>(1, cap / 4096));
   c.hist = off;
   off = align_up(off + c.hist_blocks * max_passes(W) * kRadix * 4, kAlign);
-  c.tables = off;
-  off = align_up(off + table_bytes, kAlign);
   // look-back words: sort tiles (>= 2048 entries) x 256 digits, emit tiles (256 entries)
   c.lb_words = std::max<uint64_t>(cap / 2048 + 2, 1) * kRadix + cap / kBlock + 64;
   c.lb = off;
@@ -879,12 +881,19 @@ FilterOp base_filter(const ss_state* st, uint32_t inst) {
 int validate_op(const ss_state* st, const ss_op& op) {
   const uint32_t nr = (uint32_t)st->L.regs.size();
   if (op.kind > SS_DIV || op.flags != 0 || op.nctl > 3) return SS_E_ARG;
-  if (op.reg >= nr) return SS_E_ARG;
+  if (op.reg >= nr || st->L.regs[op.reg].width == 0) return SS_E_ARG;
   const RegInfo& d = st->L.regs[op.reg];
   for (uint32_t j = 0; j < op.nctl; ++j) {
     const ss_ctl& c = op.ctl[j];
     if (c.reg >= nr || c.qubit >= st->L.regs[c.reg].width || c.value > 1) return SS_E_ARG;
   }
+  // a second register (source, address, factor, divisor) must be live too
+  auto live = [&](uint64_t r) { return r < nr && st->L.regs[r].width > 0; };
+  if ((op.kind == SS_ADD || op.kind == SS_SUB || op.kind == SS_XOR || op.kind == SS_QRAM_LOAD ||
+       op.kind == SS_QRAM_UNLOAD || op.kind == SS_MUL || op.kind == SS_DIV) && !live(op.reg2))
+    return SS_E_ARG;
+  if ((op.kind == SS_MUL || op.kind == SS_DIV) && !live(op.aux)) return SS_E_ARG;
+  if (op.kind == SS_DIV && !live(op.imm)) return SS_E_ARG;
   switch (op.kind) {
     case SS_X:
     case SS_H:
@@ -2446,19 +2455,16 @@ int ss_export(ss_state* st, uint32_t inst, uint64_t* keys, double* amps, uint64_
   return SS_OK;
 }
 
-int ss_measure(ss_state* st, uint32_t inst, uint32_t reg, double u, uint64_t* outcome, double* prob) {
-  int rc = check_state(st);
-  if (rc) return rc;
-  if (inst >= st->ninst || reg >= st->L.regs.size() || !(u >= 0.0 && u < 1.0) || !outcome || !prob)
-    return SS_E_ARG;
-  rc = sync_state(st);
-  if (rc) return rc;
-  if (st->n == 0) return SS_E_ARG;
-  rc = ensure_masks(st);
+}  // extern "C"
+
+namespace {
+
+// Sort the entries by (instance, field of register reg), so that a running
+// sum visits the field's values in ascending order within each instance.
+int sort_by_field(ss_state* st, uint32_t reg) {
+  int rc = ensure_masks(st);
   if (rc) return rc;
   const RegInfo& r = st->L.regs[reg];
-  const uint32_t W = st->L.W;
-  // sort by (instance, field) so the running sum visits field values in ascending order
   uint64_t var[kMaxW] = {0, 0, 0, 0}, skip[kMaxW] = {0, 0, 0, 0};
   var[r.word] |= (r.mask << r.shift) & (st->orm[r.word] & ~st->andm[r.word]);
   std::vector<std::pair<uint32_t, uint32_t>> low;
@@ -2467,9 +2473,40 @@ int ss_measure(ss_state* st, uint32_t inst, uint32_t reg, double u, uint64_t* ou
   uint64_t ivar[kMaxW] = {0, 0, 0, 0};
   if (st->L.has_inst) ivar[st->L.iword] = (st->L.imask << st->L.ishift) & (st->orm[st->L.iword] & ~st->andm[st->L.iword]);
   SortPlan plan;
-  build_plan(W, low, skip, ivar, plan);
+  build_plan(st->L.W, low, skip, ivar, plan);
   rc = run_sort(st, plan);
   if (rc) return rc;
+  st->grouped = false;
+  return SS_OK;
+}
+
+template <int W>
+void launch_runs_w(ss_state* st, uint64_t n, const FilterOp& f, double* part, uint32_t* fhead, double* tail,
+                   double* carry, const double* total, uint64_t* out_val) {
+  const Buf& b = st->buf[st->cur];
+  const uint32_t ntiles = (uint32_t)((n + kBlock - 1) / kBlock);
+  k_runs_tile<W><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, n, f, part, fhead, tail);
+  k_runs_carry<<<1, 64, 0, st->stream>>>(fhead, tail, ntiles, carry);
+  k_runs_out<W><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(b), n, f, part, fhead, carry, total, out_val);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ss_measure(ss_state* st, uint32_t inst, uint32_t reg, double u, uint64_t* outcome, double* prob) {
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (inst >= st->ninst || reg >= st->L.regs.size() || st->L.regs[reg].width == 0 || !(u >= 0.0 && u < 1.0) ||
+      !outcome || !prob)
+    return SS_E_ARG;
+  rc = sync_state(st);
+  if (rc) return rc;
+  if (st->n == 0) return SS_E_ARG;
+  rc = sort_by_field(st, reg);
+  if (rc) return rc;
+  const RegInfo& r = st->L.regs[reg];
+  const uint32_t W = st->L.W;
   FilterOp f = base_filter(st, inst);
   f.fword = r.word;
   f.fshift = r.shift;
@@ -2532,6 +2569,221 @@ int ss_measure(ss_state* st, uint32_t inst, uint32_t reg, double u, uint64_t* ou
   st->grouped = false;
   *outcome = v;
   *prob = pv / P;
+  return SS_OK;
+}
+
+int ss_probabilities(ss_state* st, uint32_t inst, uint32_t reg, uint64_t* values, double* probs, uint64_t cap,
+                     uint64_t* n_out) {
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (inst >= st->ninst || reg >= st->L.regs.size() || st->L.regs[reg].width == 0 || !n_out ||
+      (cap && (!values || !probs)))
+    return SS_E_ARG;
+  rc = sync_state(st);
+  if (rc) return rc;
+  *n_out = 0;
+  if (st->n == 0) return SS_OK;
+  rc = sort_by_field(st, reg);
+  if (rc) return rc;
+  rc = sync_state(st);
+  if (rc) return rc;
+  const RegInfo& r = st->L.regs[reg];
+  const uint32_t W = st->L.W;
+  const uint64_t n = st->n;
+  FilterOp f = base_filter(st, inst);
+  f.fword = r.word;
+  f.fshift = r.shift;
+  f.fmask = r.mask;
+  f.use_f = 0;
+  // scratch in the other entry buffer: per-entry sums / results and field
+  // values, then per-tile arrays
+  const uint64_t ntiles = (n + kBlock - 1) / kBlock;
+  char* base = reinterpret_cast<char*>(st->buf[st->cur ^ 1].key[0]);
+  double* part = reinterpret_cast<double*>(base);
+  uint64_t* out_val = reinterpret_cast<uint64_t*>(base + align_up(n * 8, kAlign));
+  double* tile_sum = reinterpret_cast<double*>(base + 2 * align_up(n * 8, kAlign));
+  double* tail = tile_sum + align_up(ntiles, 64);
+  double* carry = tail + align_up(ntiles, 64);
+  uint32_t* fhead = reinterpret_cast<uint32_t*>(carry + align_up(ntiles, 64));
+  double* dtot = st->meta->dscratch + 2;
+  const Buf& b = st->buf[st->cur];
+  // P: the instance's total, tile sums then one scan in tile order
+  if (W == 1) k_prob_tiles<1><<<(uint32_t)ntiles, kBlock, 0, st->stream>>>(kp<1>(b), b.amp, n, f, tile_sum);
+  else if (W == 2) k_prob_tiles<2><<<(uint32_t)ntiles, kBlock, 0, st->stream>>>(kp<2>(b), b.amp, n, f, tile_sum);
+  else k_prob_tiles<4><<<(uint32_t)ntiles, kBlock, 0, st->stream>>>(kp<4>(b), b.amp, n, f, tile_sum);
+  k_prob_scan<<<1, 64, 0, st->stream>>>(tile_sum, ntiles, dtot);
+  switch (W) {
+    case 1: launch_runs_w<1>(st, n, f, part, fhead, tail, carry, dtot, out_val); break;
+    case 2: launch_runs_w<2>(st, n, f, part, fhead, tail, carry, dtot, out_val); break;
+    default: launch_runs_w<4>(st, n, f, part, fhead, tail, carry, dtot, out_val); break;
+  }
+  rc = check_launch(st);
+  if (rc) return rc;
+  std::vector<double> hp(n);
+  std::vector<uint64_t> hv(n);
+  if (hipMemcpyAsync(hp.data(), part, n * 8, hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
+      hipMemcpyAsync(hv.data(), out_val, n * 8, hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
+      hipStreamSynchronize(st->stream) != hipSuccess)
+    return hip_fail(st);
+  uint64_t k = 0;
+  for (uint64_t e = 0; e < n; ++e) {
+    if (!(hp[e] >= 0.0)) continue;   // not the end of one of the instance's field runs
+    if (k < cap) {
+      values[k] = hv[e];
+      probs[k] = hp[e];
+    }
+    ++k;
+  }
+  *n_out = k;
+  return SS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Lowest run of `width` free bits in the lowest key word (registers and the
+// instance field hold bits).
+bool place_register(const Layout& L, uint32_t width, uint32_t* word, uint32_t* shift) {
+  const uint64_t m0 = width >= 64 ? ~0ull : ((1ull << width) - 1);
+  for (uint32_t w = 0; w < (uint32_t)kMaxW; ++w) {
+    uint64_t used = 0;
+    for (const RegInfo& r : L.regs)
+      if (r.width && r.word == w) used |= r.mask << r.shift;
+    if (L.has_inst && L.iword == w) used |= L.imask << L.ishift;
+    for (uint32_t off = 0; off + width <= 64; ++off)
+      if ((used & (m0 << off)) == 0) {
+        *word = w;
+        *shift = off;
+        return true;
+      }
+  }
+  return false;
+}
+
+template <int WI, int WO>
+void relayout(ss_state* st, const Buf& in, const Buf& out, uint64_t n) {
+  if (n == 0) return;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + kBlock - 1) / kBlock, 8192);
+  k_relayout<WI, WO><<<grid, kBlock, 0, st->stream>>>(kp<WI>(in), in.amp, kp<WO>(out), out.amp, n);
+}
+
+void relayout_any(ss_state* st, uint32_t WI, uint32_t WO, const Buf& in, const Buf& out, uint64_t n) {
+  if (WI == 1 && WO == 1) relayout<1, 1>(st, in, out, n);
+  else if (WI == 1 && WO == 2) relayout<1, 2>(st, in, out, n);
+  else if (WI == 1) relayout<1, 4>(st, in, out, n);
+  else if (WI == 2 && WO == 2) relayout<2, 2>(st, in, out, n);
+  else if (WI == 2) relayout<2, 4>(st, in, out, n);
+  else relayout<4, 4>(st, in, out, n);
+}
+
+// Re-carve the arena for keys of W2 > W words and move the entries: into
+// buffer 0, then to a staging area at the arena's end with the wider keys
+// (new words 0), then into the new buffer 0.  The staging area lies after the
+// old buffer 0 and after the new one, so no step overwrites what it reads.
+int grow_key_words(ss_state* st, uint32_t W2) {
+  int rc = sync_state(st);
+  if (rc) return rc;
+  const uint32_t W = st->L.W;
+  const uint64_t n = st->n, peak = st->peak, upd = st->stats[7];
+  // the new capacity: largest multiple of 256 whose carve fits the arena
+  uint64_t lo = 0, hi = st->arena_bytes / (2 * entry_bytes(W2)) + 1;
+  while (lo + 1 < hi) {
+    const uint64_t mid = (lo + hi) / 2;
+    if (carve(W2, st->ninst, mid * 256, st->table_bytes).total <= st->arena_bytes) lo = mid;
+    else hi = mid;
+  }
+  const uint64_t cap2 = lo * 256;
+  if (cap2 < std::max<uint64_t>({n, 256, st->ninst})) return SS_E_NOMEM;
+  const Carve c2 = carve(W2, st->ninst, cap2, st->table_bytes);
+  const uint64_t nal = align_up(std::max<uint64_t>(n, 2), 2);
+  const uint64_t stage_off = (st->arena_bytes - nal * entry_bytes(W2)) / kAlign * kAlign;
+  if (st->arena_bytes < nal * entry_bytes(W2) + kAlign || stage_off < st->cv.buf0 + st->cap * entry_bytes(W) ||
+      stage_off < c2.buf0 + cap2 * entry_bytes(W2))
+    return SS_E_NOMEM;
+  const Buf stage = make_buf(st->arena + stage_off, W2, nal);
+  if (st->cur == 1) relayout_any(st, W, W, st->buf[1], st->buf[0], n);
+  relayout_any(st, W, W2, st->buf[0], stage, n);
+  rc = check_launch(st);
+  if (rc) return rc;
+  st->L.W = W2;
+  rc = setup_arena(st, st->arena, st->arena_bytes);
+  if (rc) return hip_fail(st);  // cannot happen: the carve was checked above
+  relayout_any(st, W2, W2, stage, st->buf[0], n);
+  st->cur = 0;
+  rc = init_device(st);
+  if (rc) return rc;
+  const uint64_t spec_fail[2] = {st->spec_fail_seen[0], st->spec_fail_seen[1]};
+  if (hipMemcpyAsync(&st->meta->peak, &peak, 8, hipMemcpyHostToDevice, st->stream) != hipSuccess ||
+      hipMemcpyAsync(&st->meta->upd, &upd, 8, hipMemcpyHostToDevice, st->stream) != hipSuccess ||
+      hipMemcpyAsync(st->meta->spec_fail, spec_fail, 16, hipMemcpyHostToDevice, st->stream) != hipSuccess)
+    return hip_fail(st);
+  set_known(st, n);
+  k_set_n<<<1, 64, 0, st->stream>>>(st->meta, st->nslot, n);
+  rc = check_launch(st);
+  if (rc) return rc;
+  return sync_state(st);
+}
+
+// Graphs capture a layout; a register change retires them.
+void detach_graphs(ss_state* st) {
+  for (ss_graph* g : st->graphs) g->st = nullptr;
+  st->graphs.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int ss_add_register(ss_state* st, uint32_t nqubits, const char* name, uint32_t* reg) {
+  (void)name;
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (nqubits < 1 || nqubits > 64 || !reg || st->L.regs.size() >= 64) return SS_E_ARG;
+  RegInfo ri{};
+  if (!place_register(st->L, nqubits, &ri.word, &ri.shift)) return SS_E_NOMEM;
+  ri.width = nqubits;
+  ri.mask = nqubits == 64 ? ~0ull : ((1ull << nqubits) - 1);
+  const uint32_t need = ri.word + 1;
+  const uint32_t W2 = need <= 1 ? 1 : (need <= 2 ? 2 : 4);
+  if (W2 > st->L.W) {
+    rc = grow_key_words(st, W2);
+    if (rc) return rc;
+  }
+  detach_graphs(st);
+  st->L.regs.push_back(ri);
+  *reg = (uint32_t)st->L.regs.size() - 1;
+  return SS_OK;
+}
+
+int ss_remove_register(ss_state* st, uint32_t reg) {
+  int rc = check_state(st);
+  if (rc) return rc;
+  if (reg >= st->L.regs.size() || st->L.regs[reg].width == 0) return SS_E_ARG;
+  rc = sync_state(st);
+  if (rc) return rc;
+  const RegInfo r = st->L.regs[reg];
+  uint64_t v = 0;
+  if (st->n) {
+    rc = ensure_masks(st);
+    if (rc) return rc;
+    const uint64_t f = r.mask << r.shift;
+    if ((st->orm[r.word] ^ st->andm[r.word]) & f) return SS_E_ARG;   // more than one value
+    v = (st->orm[r.word] >> r.shift) & r.mask;
+  }
+  detach_graphs(st);
+  if (v) {
+    // clear the register's bits: xor its one value
+    ss_op op{};
+    op.kind = SS_XORC;
+    op.reg = reg;
+    op.imm = v;
+    ss_result res{};
+    rc = ss_apply_ops(st, &op, 1, nullptr, &res);
+    if (rc) return rc;
+  }
+  st->L.regs[reg].width = 0;
+  st->L.regs[reg].mask = 0;
   return SS_OK;
 }
 
