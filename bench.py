@@ -126,6 +126,20 @@ def set_opts(st, opts):
         st.set_option(k, int(v))
 
 
+def host_info():
+    """nproc and the CPU model of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
 def cpu_baseline(circ, nops_sample):
     """The oracle (std::map, one core) on a bounded sample of the same circuit:
     the H prelude and the first `nops_sample` ops after it."""
@@ -134,12 +148,14 @@ def cpu_baseline(circ, nops_sample):
     s0, e0 = o.apply(circ.ops[:1])
     s1, e1 = o.apply(circ.ops[1:1 + nops_sample])
     sec, ent = s0 + s1, e0 + e1
-    return {"value": ent / sec, "unit": "entries/s", "cores": 1, "kind": "oracle",
-            "sample": f"prelude H on 20 qubits + first {nops_sample} ops of the same circuit "
-                      f"({ent} entry updates in {sec:.1f} s, std::map oracle, one thread)"}
+    out = {"value": ent / sec, "unit": "entries/s", "cores": 1, "kind": "oracle",
+           "sample": f"prelude H on 20 qubits + first {nops_sample} ops of the same circuit "
+                     f"({ent} entry updates in {sec:.1f} s, std::map oracle, one thread)"}
+    out.update(host_info())
+    return out
 
 
-def bench_batched(args):
+def bench_batched(args, emit=True):
     """Batching: many C1-form instances (per-instance caps log-uniform in
     [2^6, 2^18], 200..1000 ops each) in one state, against the same instances
     run one at a time through the plain path on the same GPU."""
@@ -188,6 +204,25 @@ def bench_batched(args):
     torch.cuda.synchronize()
     bat_s = time.perf_counter() - tb
     stats = {k: v - s0[k] for k, v in bs.stats().items()}
+    nnz_b = bs.nnz()
+    # the same batch replayed from a captured HIP graph (captured once from
+    # |0> in every instance; the replay starts from the same state)
+    graph = None
+    if args.graph_steps != 0:
+        for i in range(len(circ)):
+            bs.set_entries(i, zero, one)
+        g = bs.capture(ops, inst_offsets=off)
+        for i in range(len(circ)):
+            bs.set_entries(i, zero, one)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        g.launch()
+        torch.cuda.synchronize()
+        graph_s = time.perf_counter() - tg
+        assert bs.nnz() == nnz_b
+        g.close()
+        graph = {"batched_graph_s": graph_s, "batched_graph_vs_plain": seq_s / graph_s,
+                 "batched_graph_entries_per_s": entries / graph_s}
     # kernel table: the same batch again from |0>, with a HIP event pair
     # around every launch (not part of the timing above)
     for i in range(len(circ)):
@@ -196,6 +231,7 @@ def bench_batched(args):
     bs.apply(ops, inst_offsets=off)
     tr = bs.trace()
     bs.set_option("trace", 0)
+    bs.close()
     out = {
         "workload": f"batching: {args.ninst} C1-form instances (20-bit key, caps 2^6..2^18 log-uniform, "
                     f"200..1000 ops), seed {args.seed}",
@@ -212,9 +248,13 @@ def bench_batched(args):
                     for k, v in tr.items() if v["launches"]},
         "generation_s": gen_s,
     }
+    if graph is not None:
+        out.update(graph)
     if cpu is not None:
         out["cpu_baseline"] = cpu
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def _oracle_run(c):
@@ -457,6 +497,55 @@ def bench_m6(args):
                       "rows": rows}), flush=True)
 
 
+def bench_sort_merge(args, lg=25):
+    """Roofline of the sort and the merge: n = 2^lg random distinct keys, an H
+    on an unused qubit doubles them to 2n = 2^(lg+1) entries, then the same H
+    with grouping switched off sorts the 2n entries on their idle bits (every
+    idle key twice) and merges each pair back to one entry.  Past the 256 MB
+    last-level cache at these sizes.  Algorithmic bytes per launch / HIP-event
+    time of the launch, against the 8 TB/s peak."""
+    import numpy as np
+    import workloads as wl
+    from paper_2503_15118_amd import _abi
+    layouts = {1: [("a", 20), ("b", 20), ("t", 1)], 2: [("a", 32), ("b", 32), ("c", 32), ("t", 1)]}
+    n = 1 << lg
+    out = {"entries_sorted": 2 * n, "rows": []}
+    for W, regs in layouts.items():
+        st = _abi.State(regs, eps=1e-14, cap_entries=2 * n, table_bytes=4096)
+        i = np.arange(n, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            v = (i * np.uint64(0x9E3779B97F4A7C15 | 1)) & np.uint64((1 << 40) - 1)   # odd multiplier: distinct
+            v ^= v >> np.uint64(17)
+        vals = np.zeros((n, len(regs)), dtype=np.uint64)
+        vals[:, 0] = v & np.uint64((1 << 20) - 1)
+        vals[:, 1] = v >> np.uint64(20)
+        if W == 2:
+            vals[:, 2] = (i * np.uint64(2654435761)) & np.uint64(0xFFFFFFFF)
+        st.set_entries(0, vals, np.full(n, 1.0 / np.sqrt(n), dtype=np.complex128))
+        del vals, v, i
+        t = len(regs) - 1
+        h = _abi.to_ss_ops(wl.ops_array([wl.make_op("H", t, qmask=1)]))
+        for rep in range(3):
+            st.apply(h)                          # 2n entries (expansion)
+            st.set_option("grouping", 0)
+            if rep == 2:
+                st.set_option("trace", 1)
+                st.set_option("trace_reset", 1)
+            st.apply(h)                          # sort 2n, merge to n
+            st.set_option("trace", 0)
+            st.set_option("grouping", 1)
+        tr = st.trace()
+        for cat, name in (("sort_hist", "k_sort_hist"), ("sort_pass", "k_sort_pass"), ("group", "merge (k_pair)")):
+            r = tr[cat]
+            if r["launches"]:
+                gbps = r["bytes"] / r["seconds"] / 1e9
+                out["rows"].append({"W": W, "kernel": name, "launches": r["launches"],
+                                    "avg_us": 1e6 * r["seconds"] / r["launches"], "GBps": gbps,
+                                    "frac": gbps / HBM_PEAK_GBS})
+        st.close()
+    return out
+
+
 def bench_m7(args):
     """Stand-ins for the paper's benchmark circuits (textbook constructions with
     the printed qubit and branch counts): GHZ 23/40/255, QRAM 20 from one
@@ -524,7 +613,7 @@ def _same_state(k1, a1, k0, a0, eps):
     return bool(ok and err <= 1e-12), False, float(err)
 
 
-def bench_serving(args):
+def bench_serving(args, emit=True):
     """Serving: a Poisson request stream mixing the four workload forms, served
     with footprint admission and continuous batching, against the same trace
     served one request at a time through the plain path."""
@@ -582,7 +671,9 @@ def bench_serving(args):
         "mix_vs_alone": {"checked": checked, "within_rule": within, "bit_identical": ident,
                          "max_abs_amp_err": worst},
     }
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -610,6 +701,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 64 MiB device copy first (reference for HBM counters)")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "m6", "m7"])
+    ap.add_argument("--sections", default="sortmerge,c3,c5",
+                    help="with --workload c2 (the default), the other parts of the metric measured in the same "
+                         "run and added to its JSON line ('' = none)")
     ap.add_argument("--c1-seeds", type=int, default=32)
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--c4-trials", type=int, default=3)
@@ -618,7 +712,7 @@ def main():
     ap.add_argument("--m6-sizes", default=None, help="comma-separated log2 sizes (overrides min/max)")
     ap.add_argument("--m6-qram-bits", default="16,20,24,28", help="QRAM table address widths to sweep ('' = none)")
     ap.add_argument("--rate", type=float, default=200.0)
-    ap.add_argument("--duration", type=float, default=2.0)
+    ap.add_argument("--duration", type=float, default=10.0)
     ap.add_argument("--serve-hi-bits", type=float, default=24.0)
     ap.add_argument("--c4-steps", type=int, default=200)
     ap.add_argument("--slots", type=int, default=8)
@@ -844,6 +938,28 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(circ, args.cpu_ops)
+    st.close()
+    # the rest of the metric, same run: sort / merge roofline past the
+    # last-level cache, batched against plain, served against plain
+    secs = [x for x in args.sections.split(",") if x]
+    if "sortmerge" in secs:
+        out["roofline_sort_merge"] = bench_sort_merge(args)
+        print(json.dumps({"section": "roofline_sort_merge", "done": True}), file=sys.stderr, flush=True)
+    if "c3" in secs:
+        b = bench_batched(args, emit=False)
+        out["batched"] = {k: b[k] for k in ("workload", "sequential_plain_s", "batched_s", "batched_vs_plain",
+                                            "sequential_entries_per_s", "batched_entries_per_s",
+                                            "batched_graph_s", "batched_graph_vs_plain",
+                                            "batched_graph_entries_per_s", "rounds_sorts", "kernels")
+                          if k in b}
+        print(json.dumps({"section": "batched", "done": True}), file=sys.stderr, flush=True)
+    if "c5" in secs:
+        sv = bench_serving(args, emit=False)
+        out["serving"] = {k: sv[k] for k in ("workload", "requests", "p50_ms", "p99_ms", "p99_vs_plain",
+                                             "throughput_vs_plain", "mix_vs_alone", "slots")}
+        out["serving"]["served"] = sv["served"]
+        out["serving"]["sequential_plain"] = sv["sequential_plain"]
+        print(json.dumps({"section": "serving", "done": True}), file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

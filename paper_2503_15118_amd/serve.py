@@ -42,6 +42,7 @@ class Request:
     resumes: int = 0
     result: Any = None
     entries: int = 0
+    entries_before: int = 0        # entries updated by runs that ended in a checkpoint
     error: Optional[str] = None
 
 
@@ -249,6 +250,8 @@ class GpuExecutor:
             if res.status == self.abi.SS_E_CAPACITY:
                 ck = self._checkpoint(h)
                 nxt = a + int(res.failed_op)
+                # the work done so far counts once the request completes
+                h["req"].entries_before += h["st"].stats()["entries_updated"] - h["e0"]
                 cap = h["st"].capacity
                 h["st"].close()
                 h["st"] = None
@@ -262,7 +265,7 @@ class GpuExecutor:
         st = h["st"]
         r = h["req"]
         res = [st.export(i) for i in range(len(r.circuits))]
-        entries = st.stats()["entries_updated"] - h["e0"]
+        entries = r.entries_before + st.stats()["entries_updated"] - h["e0"]
         return res, entries
 
     def release(self, h):
