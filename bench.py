@@ -512,6 +512,7 @@ def bench_sort_merge(args, lg=25):
     out = {"entries_sorted": 2 * n, "rows": []}
     for W, regs in layouts.items():
         st = _abi.State(regs, eps=1e-14, cap_entries=2 * n, table_bytes=4096)
+        set_opts(st, args.opt)
         i = np.arange(n, dtype=np.uint64)
         with np.errstate(over="ignore"):
             v = (i * np.uint64(0x9E3779B97F4A7C15 | 1)) & np.uint64((1 << 40) - 1)   # odd multiplier: distinct

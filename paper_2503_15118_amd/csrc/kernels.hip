@@ -525,23 +525,34 @@ __device__ __forceinline__ uint32_t digit_of(const uint64_t (&k)[W], const PassD
 }
 
 // Per-workgroup digit histograms of every pass in one read of the keys.  Each
-// workgroup takes a contiguous chunk, four entries per thread per step with the
-// loads issued together.  Keys are often nearly sorted, so a wave whose lanes
-// all carry the same digit adds its count with one LDS atomic.
+// workgroup takes a contiguous chunk, U entries per thread per step with the
+// loads issued together; for each pass its field descriptors are read once
+// per step (into scalar registers) and applied to the U entries.  Keys are
+// often nearly sorted, so a wave whose lanes all carry the same digit adds
+// its count with one LDS atomic.
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_sort_hist(KeyPtrs<W> keys, uint32_t ns, const DevMeta* meta,
-                                                      SortPlan plan, uint32_t* __restrict__ partial) {
-  constexpr int U = 4;
+                                                      SortPlan plan, unsigned long long* __restrict__ ghist) {
+  constexpr int U = W <= 2 ? 8 : 4;
   extern __shared__ uint32_t s_h[];  // npass * 256
   const uint32_t np = plan.npass;
-  // the entry count of slot ns (the grid comes from an upper bound; every
-  // workgroup writes its partial histograms, empty ones included)
+  // the entry count of slot ns (the grid comes from an upper bound; workgroups
+  // past the count add nothing)
   const uint64_t n = meta->nring[ns & 1];
   for (uint32_t i = threadIdx.x; i < np * kRadix; i += kBlock) s_h[i] = 0;
   __syncthreads();
   const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const uint64_t lo = (uint64_t)blockIdx.x * chunk;
   const uint64_t hi = lo + chunk < n ? lo + chunk : n;
+  // software pipelined: the next step's keys are loaded before this step's
+  // digits are counted
+  uint64_t kn[U][W];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint64_t i = lo + (uint64_t)u * kBlock + threadIdx.x;
+#pragma unroll
+    for (int w = 0; w < W; ++w) kn[u][w] = i < hi ? keys.w[w][i] : 0ull;
+  }
   for (uint64_t base = lo; base < hi; base += (uint64_t)kBlock * U) {
     uint64_t k[U][W];
     bool valid[U];
@@ -550,14 +561,32 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(KeyPtrs<W> keys, uint32_t 
       const uint64_t i = base + (uint64_t)u * kBlock + threadIdx.x;
       valid[u] = i < hi;
 #pragma unroll
-      for (int w = 0; w < W; ++w) k[u][w] = valid[u] ? keys.w[w][i] : 0ull;
+      for (int w = 0; w < W; ++w) k[u][w] = kn[u][w];
     }
+    const uint64_t nb = base + (uint64_t)kBlock * U;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint64_t active = __ballot(valid[u]);
-      if (!valid[u]) continue;
-      for (uint32_t p = 0; p < np; ++p) {
-        const uint32_t d = digit_of<W>(k[u], plan.pass[p]);
+      const uint64_t i = nb + (uint64_t)u * kBlock + threadIdx.x;
+#pragma unroll
+      for (int w = 0; w < W; ++w) kn[u][w] = i < hi ? keys.w[w][i] : 0ull;
+    }
+    for (uint32_t p = 0; p < np; ++p) {
+      const uint32_t nf = plan.pass[p].nf;
+      uint32_t fw[kMaxFields];
+#pragma unroll
+      for (int j = 0; j < kMaxFields; ++j) fw[j] = (uint32_t)j < nf ? plan.pass[p].f[j] : 0u;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint64_t active = __ballot(valid[u]);
+        if (!valid[u]) continue;
+        uint32_t d = 0;
+#pragma unroll
+        for (int j = 0; j < kMaxFields; ++j) {
+          if ((uint32_t)j >= nf) break;
+          const uint32_t f = fw[j];
+          const uint32_t word = f & 3u, shift = (f >> 2) & 63u, width = (f >> 8) & 15u, ds = (f >> 12) & 15u;
+          d |= (uint32_t)((sel_word<W>(k[u], word) >> shift) & ((1ull << width) - 1ull)) << ds;
+        }
         const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
         if (__ballot(d == d0) == active) {
           if (lane_id() == (uint32_t)__builtin_ctzll(active)) atomicAdd(&s_h[p * kRadix + d0], (uint32_t)__popcll(active));
@@ -568,27 +597,19 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(KeyPtrs<W> keys, uint32_t 
     }
   }
   __syncthreads();
-  uint32_t* out = partial + (uint64_t)blockIdx.x * np * kRadix;
-  for (uint32_t i = threadIdx.x; i < np * kRadix; i += kBlock) out[i] = s_h[i];
+  // fold the workgroup's counts into the global histograms (zeroed before
+  // the launch); integer sums, so the order of the atomics does not matter
+  for (uint32_t i = threadIdx.x; i < np * kRadix; i += kBlock)
+    if (s_h[i]) atomicAdd(&ghist[i], (unsigned long long)s_h[i]);
 }
 
-// Sum the per-workgroup histograms of pass blockIdx.x and scan them into the
-// first global position of every digit.
-static __global__ __launch_bounds__(kBlock) void k_sort_scan(const uint32_t* __restrict__ partial,
-                                                      uint32_t nblk, uint32_t np,
+// Scan the digit counts of pass blockIdx.x into the first global position of
+// every digit.
+static __global__ __launch_bounds__(kBlock) void k_sort_scan(const unsigned long long* __restrict__ ghist,
                                                       uint64_t* __restrict__ digit_start) {
   __shared__ uint64_t s_tmp[4];
   const uint32_t p = blockIdx.x, d = threadIdx.x;
-  uint64_t c = 0;
-  uint32_t b = 0;
-  for (; b + 8 <= nblk; b += 8) {
-    uint32_t v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = partial[((uint64_t)(b + u) * np + p) * kRadix + d];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) c += v[u];
-  }
-  for (; b < nblk; ++b) c += partial[((uint64_t)b * np + p) * kRadix + d];
+  const uint64_t c = ghist[p * kRadix + d];
   uint64_t tot;
   const uint64_t ex = block_excl_scan<uint64_t>(c, s_tmp, tot);
   digit_start[p * kRadix + d] = ex;

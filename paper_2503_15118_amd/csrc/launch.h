@@ -59,10 +59,12 @@ template <int W>
 void launch_perm(const LaunchCtx& c, int e, bool amp, const FastOp* f, uint32_t nfast, const PermOp* gops,
                  uint32_t write_words, uint32_t ep);
 
-// Radix sort: all-pass digit histograms (nb workgroups), their scan, and one
+// Radix sort: all-pass digit histograms (nb workgroups adding into one global
+// histogram per pass, np x 256 u64 at `hist`), their scan, and one
 // scatter pass from `in` to `out` over ntiles tiles of kBlock*items entries.
 template <int W>
-void launch_sort_hist(const LaunchCtx& c, uint32_t nb, const SortPlan& plan, uint32_t* hist, uint64_t* digit_start);
+void launch_sort_hist(const LaunchCtx& c, uint32_t nb, const SortPlan& plan, unsigned long long* hist,
+                      uint64_t* digit_start);
 template <int W>
 void launch_sort_pass(const LaunchCtx& c, int items, uint32_t ntiles, const PassDesc& pd,
                       const uint64_t* digit_start, uint32_t ep);

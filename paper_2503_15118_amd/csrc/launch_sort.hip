@@ -6,11 +6,13 @@
 namespace sparqs {
 
 template <int W>
-void launch_sort_hist(const LaunchCtx& c, uint32_t nb, const SortPlan& plan, uint32_t* hist, uint64_t* digit_start) {
+void launch_sort_hist(const LaunchCtx& c, uint32_t nb, const SortPlan& plan, unsigned long long* hist,
+                      uint64_t* digit_start) {
   KeyPtrs<W> k;
   for (int w = 0; w < W; ++w) k.w[w] = c.in.key[w];
+  k_fill_u64<<<1, kBlock, 0, c.stream>>>(reinterpret_cast<uint64_t*>(hist), (uint64_t)plan.npass * kRadix, 0ull);
   k_sort_hist<W><<<nb, kBlock, plan.npass * kRadix * 4, c.stream>>>(k, c.ns, c.meta, plan, hist);
-  k_sort_scan<<<plan.npass, kBlock, 0, c.stream>>>(hist, nb, plan.npass, digit_start);
+  k_sort_scan<<<plan.npass, kBlock, 0, c.stream>>>(hist, digit_start);
 }
 
 template <int W>
@@ -26,9 +28,9 @@ void launch_sort_pass(const LaunchCtx& c, int items, uint32_t ntiles, const Pass
                                                         c.meta, ep, c.xo);
 }
 
-template void launch_sort_hist<1>(const LaunchCtx&, uint32_t, const SortPlan&, uint32_t*, uint64_t*);
-template void launch_sort_hist<2>(const LaunchCtx&, uint32_t, const SortPlan&, uint32_t*, uint64_t*);
-template void launch_sort_hist<4>(const LaunchCtx&, uint32_t, const SortPlan&, uint32_t*, uint64_t*);
+template void launch_sort_hist<1>(const LaunchCtx&, uint32_t, const SortPlan&, unsigned long long*, uint64_t*);
+template void launch_sort_hist<2>(const LaunchCtx&, uint32_t, const SortPlan&, unsigned long long*, uint64_t*);
+template void launch_sort_hist<4>(const LaunchCtx&, uint32_t, const SortPlan&, unsigned long long*, uint64_t*);
 template void launch_sort_pass<1>(const LaunchCtx&, int, uint32_t, const PassDesc&, const uint64_t*, uint32_t);
 template void launch_sort_pass<2>(const LaunchCtx&, int, uint32_t, const PassDesc&, const uint64_t*, uint32_t);
 template void launch_sort_pass<4>(const LaunchCtx&, int, uint32_t, const PassDesc&, const uint64_t*, uint32_t);

@@ -127,7 +127,7 @@ Carve carve(uint32_t W, uint32_t ninst, uint64_t cap, uint64_t table_bytes) {
   off = align_up(off + table_bytes, kAlign);
   c.hist_blocks = std::min<uint64_t>(kHistBlocksMax, std::max<uint64_t>(1, cap / 4096));
   c.hist = off;
-  off = align_up(off + c.hist_blocks * max_passes(W) * kRadix * 4, kAlign);
+  off = align_up(off + max_passes(W) * kRadix * 8, kAlign);
   // look-back words: sort tiles (>= 2048 entries) x 256 digits, emit tiles (256 entries)
   c.lb_words = std::max<uint64_t>(cap / 2048 + 2, 1) * kRadix + cap / kBlock + 64;
   c.lb = off;
@@ -156,7 +156,7 @@ struct ss_state {
   int cur = 0;
   DevMeta* meta = nullptr;
   uint64_t* lb = nullptr;
-  uint32_t* hist = nullptr;
+  unsigned long long* hist = nullptr;   // global digit counts, one histogram per pass
   uint64_t* digit_start = nullptr;
   PermOp* dev_ops = nullptr;
   uint64_t* uscr = nullptr;
@@ -1518,7 +1518,7 @@ int setup_arena(ss_state* st, char* arena, size_t bytes) {
   st->digit_start = reinterpret_cast<uint64_t*>(arena + st->cv.digit_start);
   st->dev_ops = reinterpret_cast<PermOp*>(arena + st->cv.dev_ops);
   st->uscr = reinterpret_cast<uint64_t*>(arena + st->cv.uscr);
-  st->hist = reinterpret_cast<uint32_t*>(arena + st->cv.hist);
+  st->hist = reinterpret_cast<unsigned long long*>(arena + st->cv.hist);
   st->tab_base = arena + st->cv.tables;
   st->lb = reinterpret_cast<uint64_t*>(arena + st->cv.lb);
   st->buf[0] = make_buf(arena + st->cv.buf0, W, cap);
@@ -2818,7 +2818,7 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes) {
     uint64_t* digit_start;
     PermOp* dev_ops;
     uint64_t* uscr;
-    uint32_t* hist;
+    unsigned long long* hist;
     char* tab_base;
     uint64_t* lb;
     Buf b0, b1;
