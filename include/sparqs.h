@@ -153,6 +153,25 @@ int ss_required_bytes(const ss_reg* regs, uint32_t nregs, uint32_t ninst, uint64
 int ss_create_state(const ss_reg* regs, uint32_t nregs, uint32_t ninst, double eps, void* arena,
                     size_t arena_bytes, uint64_t table_bytes, void* hip_stream, ss_state** out);
 
+/* ss_create_state for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * state, but its scratch (meta block, digit starts, op ring, instance
+ * scratch, radix histograms, look-back words) lives in a 64 MiB device array
+ * inside the library, one per GPU, held until the process ends; the caller's
+ * `entries` memory (256-byte aligned) holds only the QRAM tables and the two
+ * entry buffers (table_bytes + 2 x capacity x (8W + 16) bytes, the capacity
+ * being the largest multiple of 256 that fits both).  The call and the state
+ * allocate no device or pinned host memory (host read-back and op staging are
+ * static arrays); the "trace" option and ss_graph_capture still allocate.
+ * One such state may live per GPU at a time: while it lives another call on
+ * that GPU returns SS_E_STATE (its array holds the first state's scratch).
+ * The device is the current one.  ss_rebind_arena and key growth in
+ * ss_add_register are refused (SS_E_ARG, SS_E_NOMEM): the carve is fixed.
+ * Errors: as ss_create_state; SS_E_NOMEM when the capacity that the 64 MiB
+ * scratch or the entry memory allows is below max(256, ninst). */
+int ss_create_state_noalloc(const ss_reg* regs, uint32_t nregs, uint32_t ninst, double eps, void* entries,
+                            size_t entry_bytes, uint64_t table_bytes, void* hip_stream, ss_state** out);
+
 /* Free host-side metadata (and the state's pinned read-back block) after
  * waiting for the stream; the arena stays the caller's.  SS_E_STATE for a
  * null state. */

@@ -67,6 +67,7 @@ def _load():
     sig = {
         "ss_required_bytes": [P(_Reg), u32, u32, u64, u64, P(ctypes.c_size_t)],
         "ss_create_state": [P(_Reg), u32, u32, f64, vp, ctypes.c_size_t, u64, vp, P(vp)],
+        "ss_create_state_noalloc": [P(_Reg), u32, u32, f64, vp, ctypes.c_size_t, u64, vp, P(vp)],
         "ss_destroy_state": [vp],
         "ss_capacity": [vp, P(u64)],
         "ss_layout": [vp, u32, P(u32), P(u32), P(u32)],
@@ -103,7 +104,7 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("ss_required_bytes", "ss_create_state", "ss_destroy_state", "ss_capacity", "ss_layout",
+EXPORTED = ("ss_required_bytes", "ss_create_state", "ss_create_state_noalloc", "ss_destroy_state", "ss_capacity", "ss_layout",
             "ss_key_words", "ss_load_qram", "ss_load_matrix", "ss_set_entries", "ss_apply_ops", "ss_prune", "ss_measure",
             "ss_probabilities", "ss_add_register", "ss_remove_register",
             "ss_nnz", "ss_export", "ss_sync", "ss_rebind_arena", "ss_set_option", "ss_stats",
@@ -169,7 +170,11 @@ class State:
     """A sparse state on one GPU, held in a caller-owned torch arena."""
 
     def __init__(self, regs, ninst: int = 1, eps: float = 1e-14, cap_entries: int = 1 << 16,
-                 table_bytes: int = 1 << 20, device=None, stream=None, arena_bytes: Optional[int] = None):
+                 table_bytes: int = 1 << 20, device=None, stream=None, arena_bytes: Optional[int] = None,
+                 noalloc: bool = False):
+        """noalloc: create through ss_create_state_noalloc (scratch in the
+        library's own device array; the torch buffer holds tables and entries
+        only, sized here like a full arena)."""
         import torch
         self.torch = torch
         self.regs = list(regs)
@@ -181,10 +186,11 @@ class State:
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p(0)
-        _check(lib.ss_create_state(_regs(self.regs), len(self.regs), ninst, float(eps),
-                                   ctypes.c_void_p(self.arena.data_ptr()), int(arena_bytes), int(table_bytes),
-                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
-               "ss_create_state")
+        create = lib.ss_create_state_noalloc if noalloc else lib.ss_create_state
+        _check(create(_regs(self.regs), len(self.regs), ninst, float(eps),
+                      ctypes.c_void_p(self.arena.data_ptr()), int(arena_bytes), int(table_bytes),
+                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "ss_create_state_noalloc" if noalloc else "ss_create_state")
         self.h = h
         self.table_ids = []
         self.table_bytes = int(table_bytes)

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -230,6 +231,8 @@ struct ss_state {
   bool rolled_back = false;       // the last synchronisation rolled back a launch
   uint64_t rb_op = 0;             // ... whose op index (batched: round) this is
   uint32_t dev_err = 0;           // kernel-side error bits seen at the last read-back
+  bool static_scratch = false;    // scratch in the library's device array (ss_create_state_noalloc)
+  int static_dev = -1;            // ... of this device
   DevMeta* hmeta = nullptr;       // pinned read-back block
   PermOp* hops = nullptr;         // pinned op staging (kMaxOpsPerCall)
   uint32_t ops_used = 0;
@@ -2139,7 +2142,76 @@ struct ss_graph {
   std::vector<ss_state::PlanMark> plan_log;
 };
 
+// The device array behind ss_create_state_noalloc's scratch (64 MiB).
+constexpr uint64_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace {
+
+// ---------------------------------------------------------------------------
+// Scratch of the state made by ss_create_state_noalloc: the meta block, digit
+// starts, op ring, instance scratch, histograms and look-back words live in
+// this array, one copy per device, held until the process ends.  Host code
+// uses the address hipGetSymbolAddress gives for the current device, never the
+// array's name.  The host-side read-back block and op staging of that state
+// are static host arrays (no pinned allocation).
+// ---------------------------------------------------------------------------
+constexpr int kMaxDevices = 8;
+
+struct ScratchSlot {
+  char* dev = nullptr;     // device address of `scratch` on this device (0: not looked up yet)
+  bool busy = false;       // a live state uses it
+};
+ScratchSlot g_scratch[kMaxDevices];
+DevMeta g_hmeta[kMaxDevices];
+PermOp g_hops[kMaxDevices][kMaxOpsPerCall];
+std::mutex g_scratch_mu;
+
+// Carve of a state whose scratch is the device array: the scratch parts in
+// [scratch, scratch + kScratchBytes), tables and the two entry buffers in the
+// caller's memory.  Returns false when the capacity leaves no room.
+bool carve_split(uint32_t W, uint32_t ninst, uint64_t cap, uint64_t table_bytes, uint64_t* scratch_bytes,
+                 uint64_t* data_bytes, Carve* c) {
+  *c = carve(W, ninst, cap, table_bytes);
+  // scratch: meta .. uscr (offsets below c->tables), then histograms and
+  // look-back words; data: tables, buffer 0, buffer 1
+  const uint64_t head = c->tables;
+  const uint64_t hist_bytes = align_up(max_passes(W) * kRadix * 8, kAlign);
+  const uint64_t lb_bytes = align_up(c->lb_words * 8, kAlign);
+  *scratch_bytes = head + hist_bytes + lb_bytes;
+  *data_bytes = align_up(table_bytes, kAlign) + 2 * align_up(cap * entry_bytes(W), kAlign);
+  return *scratch_bytes <= kScratchBytes;
+}
+
+int setup_split(ss_state* st, char* scr, char* data, size_t data_bytes) {
+  const uint32_t W = st->L.W;
+  uint64_t lo = 0, hi = data_bytes / (2 * entry_bytes(W)) / 256 + 1;
+  uint64_t sb, db;
+  Carve c;
+  while (lo + 1 < hi) {
+    const uint64_t mid = (lo + hi) / 2;
+    if (carve_split(W, st->ninst, mid * 256, st->table_bytes, &sb, &db, &c) && db <= data_bytes) lo = mid;
+    else hi = mid;
+  }
+  const uint64_t cap = lo * 256;
+  if (cap < std::max<uint64_t>(256, st->ninst)) return SS_E_NOMEM;
+  carve_split(W, st->ninst, cap, st->table_bytes, &sb, &db, &c);
+  st->cap = cap;
+  st->cv = c;
+  st->arena = data;
+  st->arena_bytes = data_bytes;
+  st->meta = reinterpret_cast<DevMeta*>(scr + c.meta);
+  st->digit_start = reinterpret_cast<uint64_t*>(scr + c.digit_start);
+  st->dev_ops = reinterpret_cast<PermOp*>(scr + c.dev_ops);
+  st->uscr = reinterpret_cast<uint64_t*>(scr + c.uscr);
+  st->hist = reinterpret_cast<unsigned long long*>(scr + c.tables);
+  st->lb = reinterpret_cast<uint64_t*>(scr + c.tables + align_up(max_passes(W) * kRadix * 8, kAlign));
+  st->tab_base = data;
+  const uint64_t b0 = align_up(st->table_bytes, kAlign);
+  st->buf[0] = make_buf(data + b0, W, cap);
+  st->buf[1] = make_buf(data + b0 + align_up(cap * entry_bytes(W), kAlign), W, cap);
+  return SS_OK;
+}
 
 void graph_free(ss_graph* g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
@@ -2223,14 +2295,82 @@ int ss_create_state(const ss_reg* regs, uint32_t nregs, uint32_t ninst, double e
   return SS_OK;
 }
 
+int ss_create_state_noalloc(const ss_reg* regs, uint32_t nregs, uint32_t ninst, double eps, void* entries,
+                            size_t entry_bytes, uint64_t table_bytes, void* hip_stream, ss_state** out) {
+  if (!out || !entries || ((uintptr_t)entries % kAlign) || !(eps >= 0.0) || !std::isfinite(eps)) return SS_E_ARG;
+  *out = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SS_E_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return SS_E_ARG;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ScratchSlot& slot = g_scratch[dev];
+    if (!slot.dev) {
+      // once per device, with that device current
+      if (hipGetSymbolAddress(reinterpret_cast<void**>(&slot.dev), HIP_SYMBOL(scratch)) != hipSuccess || !slot.dev) {
+        slot.dev = nullptr;
+        return SS_E_HIP;
+      }
+    }
+    if (slot.busy) return SS_E_STATE;
+    slot.busy = true;
+  }
+  auto release = [&]() {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    g_scratch[dev].busy = false;
+  };
+  ss_state* st = new ss_state();
+  st->static_scratch = true;
+  st->static_dev = dev;
+  int rc = make_layout(regs, nregs, ninst, st->L);
+  if (rc) {
+    delete st;
+    release();
+    return rc;
+  }
+  st->ninst = ninst;
+  st->eps = eps;
+  st->stream = static_cast<hipStream_t>(hip_stream);
+  st->table_bytes = align_up(table_bytes, kAlign);
+  rc = setup_split(st, g_scratch[dev].dev, static_cast<char*>(entries), entry_bytes);
+  if (rc) {
+    delete st;
+    release();
+    return rc;
+  }
+  st->hmeta = &g_hmeta[dev];
+  st->hops = g_hops[dev];
+  rc = init_device(st);
+  if (rc) {
+    ss_destroy_state(st);
+    return rc;
+  }
+  std::vector<uint64_t> vals((size_t)ninst * nregs, 0ull);
+  std::vector<double> amps(2 * (size_t)ninst, 0.0);
+  for (uint32_t i = 0; i < ninst; ++i) amps[2 * i] = 1.0;
+  rc = pack_entries(st, vals.data(), amps.data(), ninst, 0, true);
+  if (!rc) rc = sync_state(st);
+  if (rc) {
+    ss_destroy_state(st);
+    return rc;
+  }
+  *out = st;
+  return SS_OK;
+}
+
 int ss_destroy_state(ss_state* st) {
   if (!st) return SS_E_STATE;
   for (ss_graph* g : st->graphs) g->st = nullptr;
   (void)hipStreamSynchronize(st->stream);
   drop_trace(st);
   for (hipEvent_t e : st->ev_pool) (void)hipEventDestroy(e);
-  if (st->hmeta) (void)hipHostFree(st->hmeta);
-  if (st->hops) (void)hipHostFree(st->hops);
+  if (st->static_scratch) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    g_scratch[st->static_dev].busy = false;
+  } else {
+    if (st->hmeta) (void)hipHostFree(st->hmeta);
+    if (st->hops) (void)hipHostFree(st->hops);
+  }
   delete st;
   return SS_OK;
 }
@@ -2747,6 +2887,7 @@ int ss_add_register(ss_state* st, uint32_t nqubits, const char* name, uint32_t* 
   const uint32_t need = ri.word + 1;
   const uint32_t W2 = need <= 1 ? 1 : (need <= 2 ? 2 : 4);
   if (W2 > st->L.W) {
+    if (st->static_scratch) return SS_E_NOMEM;   // its carve is fixed
     rc = grow_key_words(st, W2);
     if (rc) return rc;
   }
@@ -2802,6 +2943,7 @@ int ss_sync(ss_state* st, ss_result* res) {
 int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes) {
   int rc = check_state(st);
   if (rc) return rc;
+  if (st->static_scratch) return SS_E_ARG;
   if (!arena || ((uintptr_t)arena % kAlign)) return SS_E_ARG;
   rc = sync_state(st);
   if (rc) return rc;
