@@ -60,7 +60,9 @@ def summarize_profile(pdir):
     sha = hashlib.sha256(open(os.path.join(src, "kernels.hip"), "rb").read()
                          + open(os.path.join(src, "kernels_common.hpp"), "rb").read()
                          + open(os.path.join(src, "sparqs_internal.h"), "rb").read()).hexdigest()[:16]
-    base = "python3 bench.py --no-cpu-baseline --calibrate-copy"
+    # the C2 part of the default run (the other sections launch the same
+    # kernels at other sizes, which would mix into the averages)
+    base = "python3 bench.py --no-cpu-baseline --calibrate-copy --sections ''"
     out = ["# rocprofv3 kernel statistics: arithmetic-heavy sparse circuit (97-bit key, 2^20 -> 2^21 entries, "
            "1001 ops)",
            "# command (from /tmp, TMPDIR=/tmp; bench.py's default run: autotuning, warm-up, entry count, timed "
