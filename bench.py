@@ -119,7 +119,57 @@ def summarize_profile(pdir):
     lines += [f"fetch_scale: {fs:.4f}", f"write_scale: {ws:.4f}", f"sources_sha: {sha}"]
     with open(os.path.join(ROOT, "profiles", "c2_hbm_counters.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
-    print("\n".join(out + lines))
+    sq = summarize_sq(pdir, base, sha) if os.path.isdir(os.path.join(pdir, "sq")) else []
+    print("\n".join(out + lines + sq))
+
+
+def summarize_sq(pdir, base, sha):
+    """profiles/c2_perm_sq_counters.txt: SQ instruction counters of every
+    dispatch of the interpreter (<pdir>/sq: one --pmc run with
+    --kernel-trace), durations joined by dispatch id."""
+    import collections
+    import csv
+    cnt = collections.defaultdict(dict)
+    names = {}
+    for r in csv.DictReader(open(os.path.join(pdir, "sq", "sq_counter_collection.csv"))):
+        d = int(r["Dispatch_Id"])
+        cnt[d][r["Counter_Name"]] = float(r["Counter_Value"])
+        names[d] = r["Kernel_Name"].split("(")[0]
+    dur = {}
+    for r in csv.DictReader(open(os.path.join(pdir, "sq", "sq_kernel_trace.csv"))):
+        dur[int(r["Dispatch_Id"])] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    perm = collections.Counter(n for n in names.values() if "k_perm_fast<" in n)
+    if not perm:
+        return []
+    kname = perm.most_common(1)[0][0]
+    label = kname.replace("void sparqs::", "")
+    counters = "SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_BRANCH SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES " \
+               "SQ_INSTS_SMEM"
+    lines = ["# SQ instruction counters of the permutation-run interpreter: arithmetic-heavy sparse circuit "
+             "(97-bit key, 2^21 entries)",
+             "# command (from /tmp, TMPDIR=/tmp):",
+             f"#   timeout -s KILL 150 rocprofv3 --pmc {counters} --kernel-trace --output-format csv -d <dir>/sq "
+             f"-o sq -- {base} --no-tune --steps 2 --warmup 0 --graph-steps 0",
+             "# summarised by: python3 bench.py --summarize-profile <dir>",
+             f"# kernel sources sha256[:16] = {sha}",
+             f"# one row per dispatch of {label}; instruction counts are wave instructions summed over the device;",
+             "# valu_busy = VALU x 4 cycles / 1024 SIMDs / (duration x 2.4 GHz)",
+             f'{"dispatch":>8s} {"dur_us":>7s} {"VALU":>10s} {"SALU":>10s} {"BRANCH":>10s} {"LDS":>9s} '
+             f'{"SMEM":>8s} {"valu_busy":>9s}']
+    tv = td = 0.0
+    for d in sorted(k for k, n in names.items() if n == kname):
+        c = cnt[d]
+        t = dur.get(d, 0.0)
+        busy = c.get("SQ_INSTS_VALU", 0.0) * 4 / 1024 / (t * 1e-6 * 2.4e9) if t > 0 else 0.0
+        tv += c.get("SQ_INSTS_VALU", 0.0) * 4 / 1024 / 2.4e9
+        td += t * 1e-6
+        lines.append(f'{d:8d} {t:7.1f} {c.get("SQ_INSTS_VALU", 0):10.0f} {c.get("SQ_INSTS_SALU", 0):10.0f} '
+                     f'{c.get("SQ_INSTS_BRANCH", 0):10.0f} {c.get("SQ_INSTS_LDS", 0):9.0f} '
+                     f'{c.get("SQ_INSTS_SMEM", 0):8.0f} {busy:9.2f}')
+    lines.append(f"# over all rows: valu_busy (duration-weighted) = {tv / td if td else 0.0:.2f}")
+    with open(os.path.join(ROOT, "profiles", "c2_perm_sq_counters.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return lines
 
 
 def set_opts(st, opts):
