@@ -110,7 +110,8 @@ def summarize_profile(pdir):
     for label in ("k_perm_fast<2, 8, false>", "k_perm_fast<2, 4, false>", "k_perm_fast<2, 16, false>",
                   "k_pair<2, 0, 4, false>", "k_pair<2, 1, 4, false>", "k_pair<2, 1, 4, true>",
                   "k_pair<2, 0, 2, false>", "k_pair<2, 1, 2, false>", "k_expand_slots<2, 5, 4>") + tuple(
-                      "k_pair_spec<2, 0, %d, false, %d>" % (i, x) for i in (1, 2, 4) for x in (0, 1, 2)):
+                      "k_pair_spec<2, 0, %d, %s, %d>" % (i, r, x) for i in (1, 2, 4) for r in ("false", "true")
+                      for x in (0, 1, 2)):
         pk = "void sparqs::" + label
         if pk not in fe or pk not in wr:
             continue
@@ -138,10 +139,15 @@ def summarize_sq(pdir, base, sha):
     dur = {}
     for r in csv.DictReader(open(os.path.join(pdir, "sq", "sq_kernel_trace.csv"))):
         dur[int(r["Dispatch_Id"])] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-    perm = collections.Counter(n for n in names.values() if "k_perm_fast<" in n)
-    if not perm:
+    # the kernel that runs the op interpreter longest: the permutation
+    # launch, or a one-target launch with a fused run
+    busy = collections.Counter()
+    for d, n in names.items():
+        if "k_perm_fast<" in n or ("k_pair_spec<" in n and ", true, " in n):
+            busy[n] += dur.get(d, 0.0)
+    if not busy:
         return []
-    kname = perm.most_common(1)[0][0]
+    kname = busy.most_common(1)[0][0]
     label = kname.replace("void sparqs::", "")
     counters = "SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_BRANCH SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES " \
                "SQ_INSTS_SMEM"
@@ -152,10 +158,11 @@ def summarize_sq(pdir, base, sha):
              f"-o sq -- {base} --no-tune --steps 2 --warmup 0 --graph-steps 0",
              "# summarised by: python3 bench.py --summarize-profile <dir>",
              f"# kernel sources sha256[:16] = {sha}",
-             f"# one row per dispatch of {label}; instruction counts are wave instructions summed over the device;",
+             f"# one row per dispatch of {label}; instruction counts are wave instructions summed over the device",
+             "# (waves: all waves of the grid, which is sized from an upper bound of the count, so some leave at once);",
              "# valu_busy = VALU x 4 cycles / 1024 SIMDs / (duration x 2.4 GHz)",
-             f'{"dispatch":>8s} {"dur_us":>7s} {"VALU":>10s} {"SALU":>10s} {"BRANCH":>10s} {"LDS":>9s} '
-             f'{"SMEM":>8s} {"valu_busy":>9s}']
+             f'{"dispatch":>8s} {"dur_us":>7s} {"waves":>7s} {"VALU":>10s} {"SALU":>10s} {"BRANCH":>10s} '
+             f'{"LDS":>9s} {"SMEM":>8s} {"valu_busy":>9s}']
     tv = td = 0.0
     for d in sorted(k for k, n in names.items() if n == kname):
         c = cnt[d]
@@ -163,7 +170,8 @@ def summarize_sq(pdir, base, sha):
         busy = c.get("SQ_INSTS_VALU", 0.0) * 4 / 1024 / (t * 1e-6 * 2.4e9) if t > 0 else 0.0
         tv += c.get("SQ_INSTS_VALU", 0.0) * 4 / 1024 / 2.4e9
         td += t * 1e-6
-        lines.append(f'{d:8d} {t:7.1f} {c.get("SQ_INSTS_VALU", 0):10.0f} {c.get("SQ_INSTS_SALU", 0):10.0f} '
+        lines.append(f'{d:8d} {t:7.1f} {c.get("SQ_WAVES", 0):7.0f} {c.get("SQ_INSTS_VALU", 0):10.0f} '
+                     f'{c.get("SQ_INSTS_SALU", 0):10.0f} '
                      f'{c.get("SQ_INSTS_BRANCH", 0):10.0f} {c.get("SQ_INSTS_LDS", 0):9.0f} '
                      f'{c.get("SQ_INSTS_SMEM", 0):8.0f} {busy:9.2f}')
     lines.append(f"# over all rows: valu_busy (duration-weighted) = {tv / td if td else 0.0:.2f}")
@@ -925,10 +933,12 @@ def main():
     # Ry ops on grouped entries (2^21) take the speculative fixed placement
     # unless it is switched off, and the compacting launch after it then only
     # records the count
-    spec_group = dict((kv.split("=", 1)[0], int(kv.split("=", 1)[1])) for kv in args.opt).get(
-        "speculate_group", 1 << 21)
-    group_label = ("k_pair_spec<2, 0, %d, false, %d>" % (args.spec_items, args.pair_exchange)
-                   if 0 < spec_group <= 1 << 21 else "k_pair<2, 0, %d, false>" % args.group_items)
+    optd = dict((kv.split("=", 1)[0], int(kv.split("=", 1)[1])) for kv in args.opt)
+    spec_group = optd.get("speculate_group", 1 << 21)
+    # the run of non-branching ops after each Ry goes into the Ry's launch
+    fused = "true" if optd.get("fuse_runs", 4096) > 0 else "false"
+    group_label = ("k_pair_spec<2, 0, %d, %s, %d>" % (args.spec_items, fused, args.pair_exchange)
+                   if 0 < spec_group <= 1 << 21 else "k_pair<2, 0, %d, %s>" % (args.group_items, fused))
     label = {"perm": "k_perm_fast<2, %d, false>" % args.perm_entries,
              "group": group_label,
              "expand": "k_pair<2, 1, %d, false>" % args.group_items}.get(dom)
@@ -979,7 +989,9 @@ def main():
                       "pass of the same steps right after the timed one",
             "limiter": {"perm": "instruction issue of the op interpreter, not HBM: the vector pipe is busy about "
                                 "40 % of the time (SQ counters, profiles/c2_perm_sq_counters.txt)",
-                        "group": "HBM stream of the fixed-placement launch plus a count-only launch",
+                        "group": "the fused run of non-branching ops (op interpreter, instruction issue: "
+                                 "profiles/c2_perm_sq_counters.txt) on top of the HBM stream of the "
+                                 "fixed-placement launch; a count-only launch follows it",
                         "expand": "HBM stream with compaction"}.get(dom),
         },
         "hbm_gbps": achieved,

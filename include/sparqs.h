@@ -375,9 +375,10 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
  * eps > 1e-12/(15 sqrt 2), so that the prunes left out move no amplitude by
  * more than 1e-12; 0: one launch per op; results agree within 1e-12 and the
  * prune band),
- * "fuse_runs" (default 16, 0 = never: a one-target op whose next ops form a
- * run of at most that many non-branching ops applies the run to its outputs
- * in the same launch; results are identical either way),
+ * "fuse_runs" (default 4096, the longest run one launch takes; 0 = never: a
+ * one-target op whose next ops form a run of at most that many non-branching
+ * ops applies the run to its outputs in the same launch; results are
+ * identical either way),
  * "speculate_group" (as "speculate" for one-target ops on grouped entries,
  * default 2^21; there a merge or an entry without its partner defeats the
  * fixed placement, so after a wasted speculative launch the next 64

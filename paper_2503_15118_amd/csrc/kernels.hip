@@ -193,234 +193,243 @@ __global__ __launch_bounds__(kBlock) void k_perm(KeyPtrs<W> keys, double2* __res
 
 // ---------------------------------------------------------------------------
 // k_perm_fast: the same ops in 32-bit form for keys of 1 or 2 words.  One
-// switch case per (kind, half indices), so every case is straight-line code;
-// each thread carries E entries so the per-op scalar decode is shared.
+// switch case per (kind, half indices), so every case is straight-line code
+// on named registers; each thread carries E entries so the per-op decode is
+// shared.  Op records are read with scalar loads, the next one while the
+// current op runs, so a record's fields are scalar operands and the decode
+// waits on no memory round trip.
 // ---------------------------------------------------------------------------
-#define SQ_E _Pragma("unroll") for (int j = 0; j < E; ++j)
+namespace fast {
+
+// X / XORC on one half: h ^= imm
+template <int T, int E>
+__device__ __forceinline__ void xm(uint32_t (&h)[E][4], const FastOp& op) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) h[j][T] ^= op.imm;
+}
+
+// one control: bit cb of half C taken as 0 / all ones (signed one-bit
+// extract), inverted when the required value is 0
+template <int T, int C, bool NEG, int E>
+__device__ __forceinline__ void xc1(uint32_t (&h)[E][4], const FastOp& op) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)h[j][C], op.a, 1u);
+    h[j][T] ^= op.imm & (NEG ? ~m : m);
+  }
+}
+
+// two controls; cvm / cvm2 are all ones where the required value is 0
+template <int T, int C, int C2, int E>
+__device__ __forceinline__ void xc2(uint32_t (&h)[E][4], const FastOp& op) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)h[j][C], op.a, 1u) ^ op.c;
+    const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int)h[j][C2], op.b, 1u) ^ op.d;
+    h[j][T] ^= op.imm & m1 & m2;
+  }
+}
+
+// whole halves: h[D] (+|-|^)= h[S]
+enum { OP_ADD, OP_SUB, OP_XOR };
+template <int K, int D, int S, int E>
+__device__ __forceinline__ void whole(uint32_t (&h)[E][4]) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    if (K == OP_ADD) h[j][D] += h[j][S];
+    else if (K == OP_SUB) h[j][D] -= h[j][S];
+    else h[j][D] ^= h[j][S];
+  }
+}
+
+// fields: the source's low sw bits (sw = min(source width, destination
+// width) < 32: only those reach the result modulo 2^width) are shifted to
+// the destination's place and combined there; carries and borrows run only
+// upwards, so bits outside the destination field are restored by the mask
+template <int K, int D, int S, int E>
+__device__ __forceinline__ void field(uint32_t (&h)[E][4], const FastOp& op) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const uint32_t v = __builtin_amdgcn_ubfe(h[j][S], op.c, op.d) << op.a;
+    const uint32_t x = h[j][D];
+    if (K == OP_ADD) h[j][D] = ((x + v) & op.b) | (x & ~op.b);
+    else if (K == OP_SUB) h[j][D] = ((x - v) & op.b) | (x & ~op.b);
+    else h[j][D] = x ^ v;
+  }
+}
+
+template <int D, int E>
+__device__ __forceinline__ void mul_whole(uint32_t (&h)[E][4], const FastOp& op) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) h[j][D] *= op.imm;
+}
+
+// field times an odd constant modulo 2^width (width < 32)
+template <int D, int E>
+__device__ __forceinline__ void mul_field(uint32_t (&h)[E][4], const FastOp& op) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const uint32_t v = (__builtin_amdgcn_ubfe(h[j][D], op.a, op.d) * op.imm) << op.a;
+    h[j][D] = (v & op.b) | (h[j][D] & ~op.b);
+  }
+}
+
+// data field ^= table32[address field]
+template <int D, int S, int E>
+__device__ __forceinline__ void qram(uint32_t (&h)[E][4], const FastOp& op) {
+  const uint32_t* table = reinterpret_cast<const uint32_t*>(((uint64_t)op.f << 32) | op.e);
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const uint32_t t = table[(h[j][S] >> op.c) & op.d];
+    h[j][D] ^= (t << op.a) & op.b;
+  }
+}
+
+// amplitude times +i where the field is 0, -i elsewhere
+template <int D, int E>
+__device__ __forceinline__ void refl(const uint32_t (&h)[E][4], double2 (&a)[E], const FastOp& op) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const double re = a[j].x, im = a[j].y;
+    if ((h[j][D] & op.b) == 0u) {
+      a[j].x = -im;
+      a[j].y = re;
+    } else {
+      a[j].x = im;
+      a[j].y = -re;
+    }
+  }
+}
+
+template <int W, int E>
+__device__ __forceinline__ void gen(uint32_t (&h)[E][4], double2 (&a)[E], const PermOp& g) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    uint64_t k[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) k[w] = (uint64_t)h[j][2 * w] | ((uint64_t)h[j][2 * w + 1] << 32);
+    perm_apply<W>(k, a[j], g);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      h[j][2 * w] = (uint32_t)k[w];
+      h[j][2 * w + 1] = (uint32_t)(k[w] >> 32);
+    }
+  }
+}
+
+}  // namespace fast
+
+// case lists: one case per half (index x), per (target, control) pair
+// (t*4 + c), per (target, control, control) triple
+#define SQ_C4(M, B) M(B, 0) M(B, 1) M(B, 2) M(B, 3)
+#define SQ_C16(M, B) SQ_C4(M, B) SQ_C4(M, B + 4) SQ_C4(M, B + 8) SQ_C4(M, B + 12)
+#define SQ_C64(M, B) SQ_C16(M, B) SQ_C16(M, B + 16) SQ_C16(M, B + 32) SQ_C16(M, B + 48)
+#define SQ_XM(B, x) case (B) + (x): fast::xm<x, E>(h, op); break;
+#define SQ_XC1(B, x) case (B) + (x): fast::xc1<(((B) + (x) - F_XC1) >> 2) & 3, ((B) + (x) - F_XC1) & 3, false, E>(h, op); break;
+#define SQ_XC1N(B, x) case (B) + (x): fast::xc1<(((B) + (x) - F_XC1N) >> 2) & 3, ((B) + (x) - F_XC1N) & 3, true, E>(h, op); break;
+#define SQ_XC2(B, x) case (B) + (x): fast::xc2<(((B) + (x) - F_XC2) >> 4) & 3, (((B) + (x) - F_XC2) >> 2) & 3, ((B) + (x) - F_XC2) & 3, E>(h, op); break;
+#define SQ_WH(B, x, K, F0) case (B) + (x): fast::whole<K, (((B) + (x) - F0) >> 2) & 3, ((B) + (x) - F0) & 3, E>(h); break;
+#define SQ_FI(B, x, K, F0) case (B) + (x): fast::field<K, (((B) + (x) - F0) >> 2) & 3, ((B) + (x) - F0) & 3, E>(h, op); break;
+#define SQ_ADDA(B, x) SQ_WH(B, x, fast::OP_ADD, F_ADDA)
+#define SQ_SUBA(B, x) SQ_WH(B, x, fast::OP_SUB, F_SUBA)
+#define SQ_XORA(B, x) SQ_WH(B, x, fast::OP_XOR, F_XORA)
+#define SQ_ADDF(B, x) SQ_FI(B, x, fast::OP_ADD, F_ADDF)
+#define SQ_SUBF(B, x) SQ_FI(B, x, fast::OP_SUB, F_SUBF)
+#define SQ_XORF(B, x) SQ_FI(B, x, fast::OP_XOR, F_XORF)
+#define SQ_MULA(B, x) case (B) + (x): fast::mul_whole<x, E>(h, op); break;
+#define SQ_MULF(B, x) case (B) + (x): fast::mul_field<x, E>(h, op); break;
+#define SQ_QRAM(B, x) case (B) + (x): fast::qram<(((B) + (x) - F_QRAM) >> 2) & 3, ((B) + (x) - F_QRAM) & 3, E>(h, op); break;
+#define SQ_REFL(B, x) case (B) + (x): fast::refl<x, E>(h, a, op); break;
+
 template <int W, int E, bool AMP>
 __device__ __forceinline__ void fast_step(uint32_t (&h)[E][4], double2 (&a)[E], const FastOp& op,
                                           const PermOp* __restrict__ gops) {
   switch (op.code) {
-    case F_XM + 0: SQ_E h[j][0] ^= op.imm; break;
-    case F_XM + 1: SQ_E h[j][1] ^= op.imm; break;
-    case F_XM + 2: SQ_E h[j][2] ^= op.imm; break;
-    case F_XM + 3: SQ_E h[j][3] ^= op.imm; break;
-    case F_XC1 + 0: SQ_E h[j][0] ^= (((h[j][0] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 1: SQ_E h[j][0] ^= (((h[j][1] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 2: SQ_E h[j][0] ^= (((h[j][2] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 3: SQ_E h[j][0] ^= (((h[j][3] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 4: SQ_E h[j][1] ^= (((h[j][0] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 5: SQ_E h[j][1] ^= (((h[j][1] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 6: SQ_E h[j][1] ^= (((h[j][2] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 7: SQ_E h[j][1] ^= (((h[j][3] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 8: SQ_E h[j][2] ^= (((h[j][0] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 9: SQ_E h[j][2] ^= (((h[j][1] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 10: SQ_E h[j][2] ^= (((h[j][2] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 11: SQ_E h[j][2] ^= (((h[j][3] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 12: SQ_E h[j][3] ^= (((h[j][0] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 13: SQ_E h[j][3] ^= (((h[j][1] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 14: SQ_E h[j][3] ^= (((h[j][2] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC1 + 15: SQ_E h[j][3] ^= (((h[j][3] >> op.cb) & 1u) == op.cv) ? op.imm : 0u; break;
-    case F_XC2 + 0: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 1: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 2: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 3: SQ_E h[j][0] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 4: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 5: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 6: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 7: SQ_E h[j][0] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 8: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 9: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 10: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 11: SQ_E h[j][0] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 12: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 13: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 14: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 15: SQ_E h[j][0] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 16: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 17: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 18: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 19: SQ_E h[j][1] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 20: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 21: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 22: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 23: SQ_E h[j][1] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 24: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 25: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 26: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 27: SQ_E h[j][1] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 28: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 29: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 30: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 31: SQ_E h[j][1] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 32: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 33: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 34: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 35: SQ_E h[j][2] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 36: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 37: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 38: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 39: SQ_E h[j][2] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 40: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 41: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 42: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 43: SQ_E h[j][2] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 44: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 45: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 46: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 47: SQ_E h[j][2] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 48: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 49: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 50: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 51: SQ_E h[j][3] ^= ((((h[j][0] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 52: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 53: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 54: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 55: SQ_E h[j][3] ^= ((((h[j][1] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 56: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 57: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 58: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 59: SQ_E h[j][3] ^= ((((h[j][2] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 60: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][0] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 61: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][1] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 62: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][2] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_XC2 + 63: SQ_E h[j][3] ^= ((((h[j][3] >> op.cb) & 1u) == op.cv) & (((h[j][3] >> op.cb2) & 1u) == op.cv2)) ? op.imm : 0u; break;
-    case F_ADDA + 0: SQ_E h[j][0] += h[j][0]; break;
-    case F_ADDA + 1: SQ_E h[j][0] += h[j][1]; break;
-    case F_ADDA + 2: SQ_E h[j][0] += h[j][2]; break;
-    case F_ADDA + 3: SQ_E h[j][0] += h[j][3]; break;
-    case F_ADDA + 4: SQ_E h[j][1] += h[j][0]; break;
-    case F_ADDA + 5: SQ_E h[j][1] += h[j][1]; break;
-    case F_ADDA + 6: SQ_E h[j][1] += h[j][2]; break;
-    case F_ADDA + 7: SQ_E h[j][1] += h[j][3]; break;
-    case F_ADDA + 8: SQ_E h[j][2] += h[j][0]; break;
-    case F_ADDA + 9: SQ_E h[j][2] += h[j][1]; break;
-    case F_ADDA + 10: SQ_E h[j][2] += h[j][2]; break;
-    case F_ADDA + 11: SQ_E h[j][2] += h[j][3]; break;
-    case F_ADDA + 12: SQ_E h[j][3] += h[j][0]; break;
-    case F_ADDA + 13: SQ_E h[j][3] += h[j][1]; break;
-    case F_ADDA + 14: SQ_E h[j][3] += h[j][2]; break;
-    case F_ADDA + 15: SQ_E h[j][3] += h[j][3]; break;
-    case F_ADDF + 0: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) + ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 1: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) + ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 2: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) + ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 3: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) + ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 4: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) + ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 5: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) + ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 6: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) + ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 7: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) + ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 8: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) + ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 9: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) + ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 10: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) + ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 11: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) + ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 12: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) + ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 13: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) + ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 14: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) + ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_ADDF + 15: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) + ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBA + 0: SQ_E h[j][0] -= h[j][0]; break;
-    case F_SUBA + 1: SQ_E h[j][0] -= h[j][1]; break;
-    case F_SUBA + 2: SQ_E h[j][0] -= h[j][2]; break;
-    case F_SUBA + 3: SQ_E h[j][0] -= h[j][3]; break;
-    case F_SUBA + 4: SQ_E h[j][1] -= h[j][0]; break;
-    case F_SUBA + 5: SQ_E h[j][1] -= h[j][1]; break;
-    case F_SUBA + 6: SQ_E h[j][1] -= h[j][2]; break;
-    case F_SUBA + 7: SQ_E h[j][1] -= h[j][3]; break;
-    case F_SUBA + 8: SQ_E h[j][2] -= h[j][0]; break;
-    case F_SUBA + 9: SQ_E h[j][2] -= h[j][1]; break;
-    case F_SUBA + 10: SQ_E h[j][2] -= h[j][2]; break;
-    case F_SUBA + 11: SQ_E h[j][2] -= h[j][3]; break;
-    case F_SUBA + 12: SQ_E h[j][3] -= h[j][0]; break;
-    case F_SUBA + 13: SQ_E h[j][3] -= h[j][1]; break;
-    case F_SUBA + 14: SQ_E h[j][3] -= h[j][2]; break;
-    case F_SUBA + 15: SQ_E h[j][3] -= h[j][3]; break;
-    case F_SUBF + 0: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) - ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 1: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) - ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 2: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) - ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 3: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) - ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 4: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) - ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 5: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) - ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 6: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) - ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 7: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) - ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 8: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) - ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 9: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) - ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 10: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) - ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 11: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) - ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 12: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) - ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 13: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) - ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 14: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) - ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_SUBF + 15: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) - ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORA + 0: SQ_E h[j][0] ^= h[j][0]; break;
-    case F_XORA + 1: SQ_E h[j][0] ^= h[j][1]; break;
-    case F_XORA + 2: SQ_E h[j][0] ^= h[j][2]; break;
-    case F_XORA + 3: SQ_E h[j][0] ^= h[j][3]; break;
-    case F_XORA + 4: SQ_E h[j][1] ^= h[j][0]; break;
-    case F_XORA + 5: SQ_E h[j][1] ^= h[j][1]; break;
-    case F_XORA + 6: SQ_E h[j][1] ^= h[j][2]; break;
-    case F_XORA + 7: SQ_E h[j][1] ^= h[j][3]; break;
-    case F_XORA + 8: SQ_E h[j][2] ^= h[j][0]; break;
-    case F_XORA + 9: SQ_E h[j][2] ^= h[j][1]; break;
-    case F_XORA + 10: SQ_E h[j][2] ^= h[j][2]; break;
-    case F_XORA + 11: SQ_E h[j][2] ^= h[j][3]; break;
-    case F_XORA + 12: SQ_E h[j][3] ^= h[j][0]; break;
-    case F_XORA + 13: SQ_E h[j][3] ^= h[j][1]; break;
-    case F_XORA + 14: SQ_E h[j][3] ^= h[j][2]; break;
-    case F_XORA + 15: SQ_E h[j][3] ^= h[j][3]; break;
-    case F_XORF + 0: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 1: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 2: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 3: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 4: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 5: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 6: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 7: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 8: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 9: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 10: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 11: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 12: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ ((h[j][0] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 13: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ ((h[j][1] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 14: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ ((h[j][2] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_XORF + 15: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ ((h[j][3] >> op.ssh) & op.sm)) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_MULA + 0: SQ_E h[j][0] *= op.imm; break;
-    case F_MULA + 1: SQ_E h[j][1] *= op.imm; break;
-    case F_MULA + 2: SQ_E h[j][2] *= op.imm; break;
-    case F_MULA + 3: SQ_E h[j][3] *= op.imm; break;
-    case F_MULF + 0: SQ_E { const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) * op.imm) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_MULF + 1: SQ_E { const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) * op.imm) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_MULF + 2: SQ_E { const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) * op.imm) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_MULF + 3: SQ_E { const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) * op.imm) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 0: SQ_E { const uint32_t t = op.table[(h[j][0] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 1: SQ_E { const uint32_t t = op.table[(h[j][1] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 2: SQ_E { const uint32_t t = op.table[(h[j][2] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 3: SQ_E { const uint32_t t = op.table[(h[j][3] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][0] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][0] = (h[j][0] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 4: SQ_E { const uint32_t t = op.table[(h[j][0] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 5: SQ_E { const uint32_t t = op.table[(h[j][1] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 6: SQ_E { const uint32_t t = op.table[(h[j][2] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 7: SQ_E { const uint32_t t = op.table[(h[j][3] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][1] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][1] = (h[j][1] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 8: SQ_E { const uint32_t t = op.table[(h[j][0] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 9: SQ_E { const uint32_t t = op.table[(h[j][1] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 10: SQ_E { const uint32_t t = op.table[(h[j][2] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 11: SQ_E { const uint32_t t = op.table[(h[j][3] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][2] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][2] = (h[j][2] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 12: SQ_E { const uint32_t t = op.table[(h[j][0] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 13: SQ_E { const uint32_t t = op.table[(h[j][1] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 14: SQ_E { const uint32_t t = op.table[(h[j][2] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_QRAM + 15: SQ_E { const uint32_t t = op.table[(h[j][3] >> op.ssh) & op.sm]; const uint32_t nv = (((h[j][3] >> op.dsh) & op.dm) ^ t) & op.dm; h[j][3] = (h[j][3] & ~op.dms) | (nv << op.dsh); } break;
-    case F_REFL + 0: SQ_E { const double re = a[j].x, im = a[j].y; if (((h[j][0] >> op.dsh) & op.dm) == 0u) { a[j].x = -im; a[j].y = re; } else { a[j].x = im; a[j].y = -re; } } break;
-    case F_REFL + 1: SQ_E { const double re = a[j].x, im = a[j].y; if (((h[j][1] >> op.dsh) & op.dm) == 0u) { a[j].x = -im; a[j].y = re; } else { a[j].x = im; a[j].y = -re; } } break;
-    case F_REFL + 2: SQ_E { const double re = a[j].x, im = a[j].y; if (((h[j][2] >> op.dsh) & op.dm) == 0u) { a[j].x = -im; a[j].y = re; } else { a[j].x = im; a[j].y = -re; } } break;
-    case F_REFL + 3: SQ_E { const double re = a[j].x, im = a[j].y; if (((h[j][3] >> op.dsh) & op.dm) == 0u) { a[j].x = -im; a[j].y = re; } else { a[j].x = im; a[j].y = -re; } } break;
-    case F_GEN: SQ_E {
-      uint64_t k[W];
-#pragma unroll
-      for (int w = 0; w < W; ++w) k[w] = (uint64_t)h[j][2 * w] | ((uint64_t)h[j][2 * w + 1] << 32);
-      perm_apply<W>(k, a[j], gops[op.gi]);
-#pragma unroll
-      for (int w = 0; w < W; ++w) { h[j][2 * w] = (uint32_t)k[w]; h[j][2 * w + 1] = (uint32_t)(k[w] >> 32); }
-    } break;
+    SQ_C4(SQ_XM, F_XM)
+    SQ_C16(SQ_XC1, F_XC1)
+    SQ_C16(SQ_XC1N, F_XC1N)
+    SQ_C64(SQ_XC2, F_XC2)
+    SQ_C16(SQ_ADDA, F_ADDA)
+    SQ_C16(SQ_ADDF, F_ADDF)
+    SQ_C16(SQ_SUBA, F_SUBA)
+    SQ_C16(SQ_SUBF, F_SUBF)
+    SQ_C16(SQ_XORA, F_XORA)
+    SQ_C16(SQ_XORF, F_XORF)
+    SQ_C4(SQ_MULA, F_MULA)
+    SQ_C4(SQ_MULF, F_MULF)
+    SQ_C16(SQ_QRAM, F_QRAM)
+    case F_REFL + 0: if (AMP) fast::refl<0, E>(h, a, op); break;
+    case F_REFL + 1: if (AMP) fast::refl<1, E>(h, a, op); break;
+    case F_REFL + 2: if (AMP) fast::refl<2, E>(h, a, op); break;
+    case F_REFL + 3: if (AMP) fast::refl<3, E>(h, a, op); break;
+    case F_GEN: fast::gen<W, E>(h, a, gops[op.e]); break;
     default: break;
   }
 }
-#undef SQ_E
+#undef SQ_C4
+#undef SQ_C16
+#undef SQ_C64
+#undef SQ_XM
+#undef SQ_XC1
+#undef SQ_XC1N
+#undef SQ_XC2
+#undef SQ_WH
+#undef SQ_FI
+#undef SQ_ADDA
+#undef SQ_SUBA
+#undef SQ_XORA
+#undef SQ_ADDF
+#undef SQ_SUBF
+#undef SQ_XORF
+#undef SQ_MULA
+#undef SQ_MULF
+#undef SQ_QRAM
+#undef SQ_REFL
+
+// A run of non-branching ops on E entries per thread.  The record of op o+1
+// is loaded (scalar load) after op o's fields have arrived and before op o
+// runs, so its latency hides behind op o; the empty asm statement with a
+// memory clobber keeps the compiler from hoisting that load above the wait
+// for op o's record (the scalar counter cannot wait for one of two loads).
+// Two record registers alternate (the loop is unrolled twice), so no record
+// is copied between them.  The records are followed by one padding record,
+// which the last prefetch reads.  They are read through the constant address
+// space (they do not change during a launch), which makes every such read a
+// scalar load whatever else the kernel stores.
+__device__ __forceinline__ FastOp load_rec(const FastOp* p) {
+  typedef const __attribute__((address_space(4))) uint32_t ConstU32;
+  ConstU32* q = (ConstU32*)p;
+  FastOp r;
+  r.code = q[0];
+  r.imm = q[1];
+  r.a = q[2];
+  r.b = q[3];
+  r.c = q[4];
+  r.d = q[5];
+  r.e = q[6];
+  r.f = q[7];
+  return r;
+}
+
+template <int W, int E, bool AMP>
+__device__ __forceinline__ void run_ops(uint32_t (&h)[E][4], double2 (&a)[E], const FastOp* __restrict__ ops,
+                                        uint32_t nops, const PermOp* __restrict__ gops) {
+  if (nops == 0) return;
+  const FastOp* p = ops;
+  const FastOp* const last = ops + (nops - 1);
+  FastOp r0 = load_rec(p);
+  for (;;) {
+    asm volatile("" ::"s"(r0.code) : "memory");
+    const FastOp r1 = load_rec(p + 1);
+    fast_step<W, E, AMP>(h, a, r0, gops);
+    if (p == last) break;
+    asm volatile("" ::"s"(r1.code) : "memory");
+    r0 = load_rec(p + 2);
+    fast_step<W, E, AMP>(h, a, r1, gops);
+    if (p + 1 == last) break;
+    p += 2;
+  }
+}
 
 template <int W, int E, bool AMP>
 __global__ __launch_bounds__(kBlock) void k_perm_fast(KeyPtrs<W> keys, double2* __restrict__ amp, uint32_t ns,
@@ -456,19 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_perm_fast(KeyPtrs<W> keys, double2* 
       h[j][0] = h[j][1] = 0u;
     }
   }
-  // Op records are staged through LDS a chunk at a time: every wave of the
-  // workgroup reads each record at the same moment, and from global memory
-  // each such read would wait for one cache miss per op.
-  __shared__ uint4 s_ops[kOpChunk * (sizeof(FastOp) / 16)];
-  for (uint32_t c0 = 0; c0 < nops; c0 += kOpChunk) {
-    const uint32_t cn = nops - c0 < (uint32_t)kOpChunk ? nops - c0 : (uint32_t)kOpChunk;
-    __syncthreads();
-    const uint4* src = reinterpret_cast<const uint4*>(ops + c0);
-    for (uint32_t q = threadIdx.x; q < cn * (uint32_t)(sizeof(FastOp) / 16); q += kBlock) s_ops[q] = src[q];
-    __syncthreads();
-    const FastOp* lops = reinterpret_cast<const FastOp*>(s_ops);
-    for (uint32_t o = 0; o < cn; ++o) fast_step<W, E, AMP>(h, a, lops[o], gops);
-  }
+  run_ops<W, E, AMP>(h, a, ops, nops, gops);
   uint64_t orv[W], andv[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) {
@@ -489,23 +486,6 @@ __global__ __launch_bounds__(kBlock) void k_perm_fast(KeyPtrs<W> keys, double2* 
     if (AMP) amp[i] = a[j];
   }
   publish_masks<W>(meta, epoch, orv, andv, s_red);
-}
-
-// A run of non-branching ops on E entries per thread, its records staged
-// through LDS (`s_ops`, kOpChunk records) a chunk at a time.  Every thread of
-// the workgroup calls it (it synchronises the workgroup).
-template <int W, int E>
-__device__ __forceinline__ void run_ops_lds(uint32_t (&h)[E][4], double2 (&a)[E], const FastOp* __restrict__ ops,
-                                            uint32_t nops, const PermOp* __restrict__ gops, uint4* s_ops) {
-  for (uint32_t c0 = 0; c0 < nops; c0 += kOpChunk) {
-    const uint32_t cn = nops - c0 < (uint32_t)kOpChunk ? nops - c0 : (uint32_t)kOpChunk;
-    __syncthreads();
-    const uint4* src = reinterpret_cast<const uint4*>(ops + c0);
-    for (uint32_t q = threadIdx.x; q < cn * (uint32_t)(sizeof(FastOp) / 16); q += kBlock) s_ops[q] = src[q];
-    __syncthreads();
-    const FastOp* lops = reinterpret_cast<const FastOp*>(s_ops);
-    for (uint32_t o = 0; o < cn; ++o) fast_step<W, E, true>(h, a, lops[o], gops);
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1314,13 +1294,13 @@ __device__ __forceinline__ void pair_write(KeyPtrs<W>& out_keys, double2* __rest
 // written at pos[it] (the upper child of an item that keeps both at pos + 1).
 // Pass 0 takes the lower kept child of every item, pass 1 the upper child of
 // items that keep both (in group mode: an entry without its partner whose
-// matrix mixes).  Every thread of the workgroup calls it (it synchronises the
-// workgroup, reusing `s_stage` for the op records).
+// matrix mixes); a wave runs pass 1 only when one of its lanes has such a
+// child.
 template <int W, int ITEMS>
 __device__ __forceinline__ void run_children(const GroupOp& op, const uint64_t (&key)[ITEMS][W],
                                              const double2 (&out)[ITEMS][2], const uint32_t (&keepm)[ITEMS],
                                              const uint64_t (&pos)[ITEMS], const FastOp* __restrict__ rops,
-                                             uint32_t rn, const PermOp* __restrict__ rgops, uint64_t* s_stage,
+                                             uint32_t rn, const PermOp* __restrict__ rgops,
                                              KeyPtrs<W> out_keys, double2* __restrict__ out_amp, uint64_t cap,
                                              uint64_t (&orv)[W], uint64_t (&andv)[W]) {
   static_assert(W <= 2, "runs are fused for keys of at most 2 words");
@@ -1351,9 +1331,9 @@ __device__ __forceinline__ void run_children(const GroupOp& op, const uint64_t (
   double2 a0[ITEMS], a1[ITEMS];
   bool has0[ITEMS], has1[ITEMS];
   (void)load(0, h0, a0, has0);
-  run_ops_lds<W, ITEMS>(h0, a0, rops, rn, rgops, reinterpret_cast<uint4*>(s_stage));
-  const bool two = __syncthreads_or(load(1, h1, a1, has1)) != 0;
-  if (two) run_ops_lds<W, ITEMS>(h1, a1, rops, rn, rgops, reinterpret_cast<uint4*>(s_stage));
+  run_ops<W, ITEMS, true>(h0, a0, rops, rn, rgops);
+  const bool two = __ballot(load(1, h1, a1, has1)) != 0ull;
+  if (two) run_ops<W, ITEMS, true>(h1, a1, rops, rn, rgops);
   // Both children of an item are written together: at an even position the
   // key words of the pair go out as one 16-byte store per word, so a wave's
   // stores cover whole lines instead of every other word.
@@ -1412,8 +1392,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_spec(KeyPtrs<W> in_keys, const 
   constexpr uint32_t TILE = kBlock * ITEMS;
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   constexpr uint32_t kStageWords = MODE == MODE_GROUP && NB != 2 ? (W + 2) * (TILE + 2) : 1;
-  constexpr uint32_t kRunWords = RUN ? kOpChunk * (uint32_t)sizeof(FastOp) / 8 : 1;
-  __shared__ __align__(16) uint64_t s_stage[kStageWords > kRunWords ? kStageWords : kRunWords];
+  __shared__ __align__(16) uint64_t s_stage[kStageWords];
   if (launch_prologue(meta, epoch)) return;
   // cooling down after a wasted speculation: the compacting launch does the op
   if (*reinterpret_cast<volatile unsigned int*>(&meta->spec_cool[MODE]) != 0u) {
@@ -1455,7 +1434,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_spec(KeyPtrs<W> in_keys, const 
     andv[w] = ~0ull;
   }
   if constexpr (RUN)
-    run_children<W, ITEMS>(op, key, out, keepm, pos, rops, rn, rgops, s_stage, out_keys, out_amp, cap,
+    run_children<W, ITEMS>(op, key, out, keepm, pos, rops, rn, rgops, out_keys, out_amp, cap,
                                  orv, andv);
   else
     pair_write<W, ITEMS>(out_keys, out_amp, cap, op, key, out, keepm, pos, orv, andv);
@@ -1486,8 +1465,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
   // each side, for the partner test; with RUN the same space then stages the
   // run's op records
   constexpr uint32_t kStageWords = MODE == MODE_GROUP ? (W + 2) * (TILE + 2) : 1;
-  constexpr uint32_t kRunWords = RUN ? kOpChunk * (uint32_t)sizeof(FastOp) / 8 : 1;
-  __shared__ __align__(16) uint64_t s_stage[kStageWords > kRunWords ? kStageWords : kRunWords];
+  __shared__ __align__(16) uint64_t s_stage[kStageWords];
   uint64_t n;
   if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
   if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&meta->upd, (unsigned long long)(n * op.upd));
@@ -1559,7 +1537,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
   if constexpr (RUN) {
     // The tile's prefix is published (the look-back above), so later tiles do
     // not wait for this work.
-    run_children<W, ITEMS>(op, key, out, keepm, pos, rops, rn, rgops, s_stage, out_keys, out_amp, cap,
+    run_children<W, ITEMS>(op, key, out, keepm, pos, rops, rn, rgops, out_keys, out_amp, cap,
                                  orv, andv);
   } else {
     pair_write<W, ITEMS>(out_keys, out_amp, cap, op, key, out, keepm, pos, orv, andv);
@@ -1720,8 +1698,9 @@ __global__ __launch_bounds__(kBlock) void k_perm_batched(KeyPtrs<W> keys, double
       const uint32_t start = __builtin_amdgcn_readfirstlane(rr.start);
       const uint32_t len = __builtin_amdgcn_readfirstlane(rr.len);
       for (uint32_t o = start; o < start + len; ++o) {
-        if (W <= 2) fast_step<W, 1, AMP>(h, a, ops[o], gops);
-        else perm_apply<W>(k, a[0], gops[ops[o].gi]);
+        const FastOp rec = load_rec(ops + o);
+        if (W <= 2) fast_step<W, 1, AMP>(h, a, rec, gops);
+        else perm_apply<W>(k, a[0], gops[rec.e]);
       }
     }
   }
@@ -2381,11 +2360,7 @@ __global__ __launch_bounds__(kBlock) void k_runs_tile(KeyPtrs<W> keys, const dou
   }
   __syncthreads();
   double cv = 0.0;
-  uint32_t cf = 0;
-  for (uint32_t j = 0; j < wv; ++j) {
-    cv = s_f[j] ? s_v[j] : cv + s_v[j];
-    cf |= s_f[j];
-  }
+  for (uint32_t j = 0; j < wv; ++j) cv = s_f[j] ? s_v[j] : cv + s_v[j];
   if (wv > 0 && !fl) v = cv + v;
   if (e < n) part[e] = v;
   const uint64_t last = ((uint64_t)blockIdx.x + 1) * kBlock < n ? ((uint64_t)blockIdx.x + 1) * kBlock - 1 : n - 1;

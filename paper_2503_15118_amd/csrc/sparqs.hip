@@ -270,7 +270,7 @@ struct ss_state {
   // at most this many ops (0: never).  A long run is issue-bound and runs
   // faster in its own launch (8 entries per lane, higher occupancy); a short
   // one costs little more than a read and a write of the state.
-  uint32_t fuse_runs = 16;
+  uint32_t fuse_runs = kRunChunk;
   uint32_t xcd_order = 0;        // 1 when workgroups spread round-robin over 8 XCDs
   int tile_order_opt = 1;        // option: 1 use XCD tickets when possible, 0 one counter
   uint64_t stats[8]{};
@@ -1085,7 +1085,7 @@ HalfField half_of(const RegInfo& r) {
 FastOp encode_fast(const ss_state* st, const ss_op& op, uint32_t gi) {
   FastOp f{};
   f.code = F_GEN;
-  f.gi = gi;
+  f.e = gi;
   const RegInfo& d = st->L.regs[op.reg];
   const HalfField hd = half_of(d);
   auto ctl_bit = [&](const ss_ctl& c, uint32_t& half, uint32_t& bit) {
@@ -1114,17 +1114,16 @@ FastOp encode_fast(const ss_state* st, const ss_op& op, uint32_t gi) {
       } else if (op.nctl == 1) {
         uint32_t hc, cb;
         ctl_bit(op.ctl[0], hc, cb);
-        f.cb = cb;
-        f.cv = op.ctl[0].value;
-        f.code = F_XC1 + half * 4 + hc;
+        f.a = cb;
+        f.code = (op.ctl[0].value ? F_XC1 : F_XC1N) + half * 4 + hc;
       } else if (op.nctl == 2) {
         uint32_t hc, cb, hc2, cb2;
         ctl_bit(op.ctl[0], hc, cb);
         ctl_bit(op.ctl[1], hc2, cb2);
-        f.cb = cb;
-        f.cv = op.ctl[0].value;
-        f.cb2 = cb2;
-        f.cv2 = op.ctl[1].value;
+        f.a = cb;
+        f.b = cb2;
+        f.c = op.ctl[0].value ? 0u : ~0u;
+        f.d = op.ctl[1].value ? 0u : ~0u;
         f.code = F_XC2 + half * 16 + hc * 4 + hc2;
       }
       return f;
@@ -1133,9 +1132,8 @@ FastOp encode_fast(const ss_state* st, const ss_op& op, uint32_t gi) {
       break;
   }
   if (op.nctl != 0 || !hd.ok) return f;
-  f.dsh = hd.sh;
-  f.dm = hd.mask;
-  f.dms = hd.mask << hd.sh;
+  f.a = hd.sh;
+  f.b = hd.mask << hd.sh;
   const bool dwhole = hd.mask == 0xFFFFFFFFu;
   switch (op.kind) {
     case SS_ADD:
@@ -1143,8 +1141,10 @@ FastOp encode_fast(const ss_state* st, const ss_op& op, uint32_t gi) {
     case SS_XOR: {
       const HalfField hs = half_of(st->L.regs[op.reg2]);
       if (!hs.ok) return f;
-      f.ssh = hs.sh;
-      f.sm = hs.mask;
+      f.c = hs.sh;
+      // only the low min(widths) source bits reach a result taken modulo
+      // 2^(destination width); in a field form that count is below 32
+      f.d = std::min<uint32_t>(st->L.regs[op.reg2].width, d.width);
       const bool whole = dwhole && hs.mask == 0xFFFFFFFFu;
       const uint32_t idx = hd.half * 4 + hs.half;
       if (op.kind == SS_ADD) f.code = (whole ? F_ADDA : F_ADDF) + idx;
@@ -1154,6 +1154,7 @@ FastOp encode_fast(const ss_state* st, const ss_op& op, uint32_t gi) {
     }
     case SS_MULC:
       f.imm = (uint32_t)op.imm;
+      f.d = d.width;
       f.code = (dwhole ? F_MULA : F_MULF) + hd.half;
       return f;
     case SS_QRAM_LOAD:
@@ -1161,9 +1162,10 @@ FastOp encode_fast(const ss_state* st, const ss_op& op, uint32_t gi) {
       const TableInfo& t = st->tables[op.aux];
       const HalfField hs = half_of(st->L.regs[op.reg2]);
       if (!t.w32 || !hs.ok) return f;
-      f.ssh = hs.sh;
-      f.sm = hs.mask;
-      f.table = static_cast<const uint32_t*>(t.dev);
+      f.c = hs.sh;
+      f.d = hs.mask;
+      f.e = (uint32_t)reinterpret_cast<uintptr_t>(t.dev);
+      f.f = (uint32_t)(reinterpret_cast<uintptr_t>(t.dev) >> 32);
       f.code = F_QRAM + hd.half * 4 + hs.half;
       return f;
     }
@@ -1265,7 +1267,8 @@ int upload_chunks(ss_state* st, const ss_op* ops, std::vector<RunChunk>& chunks,
         gen.push_back(to_perm(st, op));
       }
     }
-    c.fbytes = align_up(fast.size() * sizeof(FastOp), kAlign);
+    // the interpreter's last prefetch reads one (zero) record past the run
+    c.fbytes = fast.empty() ? 0 : align_up((fast.size() + 1) * sizeof(FastOp), kAlign);
     const uint64_t bytes = c.fbytes + gen.size() * sizeof(PermOp);
     off[k - a] = blob.size();
     blob.resize(off[k - a] + align_up(std::max<uint64_t>(bytes, 1), kAlign));
@@ -1757,7 +1760,7 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
           FastOp f = W <= 2 ? encode_fast(st, op, (uint32_t)gen.size()) : FastOp{};
           if (W > 2) {
             f.code = F_GEN;
-            f.gi = (uint32_t)gen.size();
+            f.e = (uint32_t)gen.size();
           }
           if (f.code == F_GEN) gen.push_back(to_perm(st, op));
           fast.push_back(f);

@@ -16,7 +16,6 @@ constexpr int kMaxPasses = 40;      // up to 256 key bits + 5 target bits, 8 bit
 constexpr int kMaxGroupBits = 5;    // targets fused into one interference op (2^5 group)
 constexpr int kMaxExpandBits = 10;  // targets of one pure expansion (one thread per child, 2^10 children)
 constexpr int kRing = 128;          // per-launch slots (tile counter, count, key masks)
-constexpr int kOpChunk = 128;       // op records staged in LDS at a time by the interpreter
 constexpr int kXcds = 8;            // XCDs of an MI355X
 constexpr int kXcdStride = 16;      // per-XCD counters 128 bytes apart
 
@@ -109,32 +108,39 @@ struct PermOp {
 // straight-line code on named registers.
 enum FastBase : uint32_t {
   F_XM = 0,       // + h          : h ^= imm                     (X / XORC, uncontrolled)
-  F_XC1 = 4,      // + t*4 + c    : h[t] ^= imm if bit cb of h[c] == cv        (CNOT)
-  F_XC2 = 20,     // + t*16+c*4+c2: two controls                               (Toffoli)
-  F_ADDA = 84,    // + d*4 + s    : h[d] += h[s]   (both whole halves)
-  F_ADDF = 100,   // + d*4 + s    : field form
-  F_SUBA = 116,
-  F_SUBF = 132,
-  F_XORA = 148,
-  F_XORF = 164,
-  F_MULA = 180,   // + d
-  F_MULF = 184,   // + d
-  F_QRAM = 188,   // + d*4 + s    : data field ^= table32[address field]
-  F_REFL = 204,   // + d          : amplitude *= +i / -i by field == 0
-  F_GEN = 208,    // generic 64-bit form: gops[gi]
-  F_NCODES = 209
+  F_XC1 = 4,      // + t*4 + c    : h[t] ^= imm if bit cb of h[c] is 1      (CNOT)
+  F_XC1N = 20,    // + t*4 + c    : h[t] ^= imm if bit cb of h[c] is 0
+  F_XC2 = 36,     // + t*16+c*4+c2: two controls                            (Toffoli)
+  F_ADDA = 100,   // + d*4 + s    : h[d] += h[s]   (both whole halves)
+  F_ADDF = 116,   // + d*4 + s    : field form
+  F_SUBA = 132,
+  F_SUBF = 148,
+  F_XORA = 164,
+  F_XORF = 180,
+  F_MULA = 196,   // + d
+  F_MULF = 200,   // + d
+  F_QRAM = 204,   // + d*4 + s    : data field ^= table32[address field]
+  F_REFL = 220,   // + d          : amplitude *= +i / -i by field == 0
+  F_GEN = 224,    // generic 64-bit form: gops[gi]
+  F_NCODES = 225
 };
 
-struct alignas(64) FastOp {       // 64 bytes: four 16-byte LDS words
-  uint32_t code;
-  uint32_t dsh, dm;             // dst shift within its half, width mask
-  uint32_t ssh, sm;             // src shift within its half, width mask
-  uint32_t imm;                 // X/XORC mask (shifted into place), multiplier
-  uint32_t cb, cv, cb2, cv2;    // control bit positions and required values
-  uint32_t gi;                  // index into the generic op array (F_GEN)
-  uint32_t dms;                 // dm << dsh
-  const uint32_t* table;        // QRAM words (uint32)
+// One record per op, 32 bytes so that a single scalar load brings it in;
+// the meaning of a..f depends on the kind:
+//   X / XORC:   imm = mask in place
+//   one control:  a = control bit
+//   two controls: a, b = control bits; c, d = all ones where that control's
+//                 required value is 0
+//   fields (ADD/SUB/XOR, MUL, QRAM, REFL): a = destination shift, b =
+//                 destination mask in place, c = source shift, d = source bits
+//                 taken (min of both widths, < 32; MUL: destination width;
+//                 QRAM: address mask), imm = multiplier
+//   QRAM: e, f = table address (low, high word);  generic: e = record index
+struct alignas(32) FastOp {
+  uint32_t code, imm;
+  uint32_t a, b, c, d, e, f;
 };
+static_assert(sizeof(FastOp) == 32, "one 32-byte record per op");
 
 constexpr int kMaxChain = 16;       // one-target ops on one target fused into one launch
 
