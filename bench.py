@@ -257,6 +257,7 @@ def bench_batched(args, emit=True):
     # batched
     cap = 1 << args.batch_cap_log2
     bs = batch.batch_state(circ, cap_entries=cap, table_bytes=0)
+    set_opts(bs, args.opt)
     s0 = bs.stats()
     torch.cuda.synchronize()
     tb = time.perf_counter()

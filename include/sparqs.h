@@ -379,6 +379,11 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
  * one-target op whose next ops form a run of at most that many non-branching
  * ops applies the run to its outputs in the same launch; results are
  * identical either way),
+ * "retire" (1 default, 0 off: batched calls relabel the instances by the
+ * round of their last op and leave finished instances out of later rounds;
+ * the labels are restored before the call returns, also after a capacity
+ * failure, and results are identical either way; afterwards the entries are
+ * ordered by that relabelling, not by instance),
  * "speculate_group" (as "speculate" for one-target ops on grouped entries,
  * default 2^21; there a merge or an entry without its partner defeats the
  * fixed placement, so after a wasted speculative launch the next 64

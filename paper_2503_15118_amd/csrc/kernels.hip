@@ -517,8 +517,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(KeyPtrs<W> keys, uint32_t 
   extern __shared__ uint32_t s_h[];  // npass * 256
   const uint32_t np = plan.npass;
   // the entry count of slot ns (the grid comes from an upper bound; workgroups
-  // past the count add nothing)
-  const uint64_t n = meta->nring[ns & 1];
+  // past the count add nothing), on the view [base, n) of batched rounds
+  const uint64_t vb = meta->base;
+  const uint64_t n = meta->nring[ns & 1] - vb;
+  offset_keys<W>(keys, vb);
   for (uint32_t i = threadIdx.x; i < np * kRadix; i += kBlock) s_h[i] = 0;
   __syncthreads();
   const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
@@ -616,7 +618,13 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(KeyPtrs<W> in_keys, const 
   // The count is read on the device (a sort does not change it) and the grid
   // comes from an upper bound: workgroups past the count's tiles leave before
   // taking a tile ticket, so the tickets cover exactly the count's tiles.
-  const uint64_t n = meta->nring[ns & 1];
+  // Batched rounds sort the view [base, n).
+  const uint64_t vb = meta->base;
+  const uint64_t n = meta->nring[ns & 1] - vb;
+  offset_keys<W>(in_keys, vb);
+  offset_keys<W>(out_keys, vb);
+  in_amp += vb;
+  out_amp += vb;
   if (blockIdx.x == 0 && tid == 0 && (uint64_t)gridDim.x * TILE < n) raise_error(meta, kErrGrid, epoch);
   if ((uint64_t)blockIdx.x * TILE >= n) return;
 #pragma unroll
@@ -1668,7 +1676,11 @@ __global__ __launch_bounds__(kBlock) void k_perm_batched(KeyPtrs<W> keys, double
                                                          DevMeta* meta, uint32_t epoch) {
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   if (launch_prologue(meta, epoch)) return;
-  const uint64_t n = meta->nring[ns & 1];
+  // the view [base, n) of the batched rounds
+  const uint64_t vb = meta->base;
+  const uint64_t n = meta->nring[ns & 1] - vb;
+  offset_keys<W>(keys, vb);
+  amp += vb;
   if (blockIdx.x == 0 && threadIdx.x == 0 && (uint64_t)gridDim.x * kBlock < n) raise_error(meta, kErrGrid, epoch);
   if ((uint64_t)blockIdx.x * kBlock >= n) return;
   const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1742,8 +1754,13 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
   __shared__ uint32_t s_tile;
   __shared__ uint32_t s_irange[2];
   __shared__ BatchOp s_bop[kOpStage];
-  uint64_t n;
-  if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
+  uint64_t n, vb;
+  if (!emit_begin_view(meta, ns, epoch, TILE, &n, &vb)) return;
+  offset_keys<W>(in_keys, vb);
+  offset_keys<W>(out_keys, vb);
+  in_amp += vb;
+  out_amp += vb;
+  cap -= vb;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + TILE - 1) / TILE;
   if (tile_out_of_range(tile, ntiles, &meta->err)) return;
@@ -1824,8 +1841,8 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
     if (threadIdx.x == 0) {
       s_off = ex;
       if (tile == ntiles - 1) {
-        meta->nnz_out[epoch % kRing] = ex + tile_total;
-        meta->nring[(ns & 1) ^ 1] = ex + tile_total;
+        meta->nnz_out[epoch % kRing] = vb + ex + tile_total;
+        meta->nring[(ns & 1) ^ 1] = vb + ex + tile_total;
         if (ex + tile_total > cap) raise_error(meta, kErrCapacity, epoch);
       }
     }
@@ -1909,8 +1926,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_key[W * S];
   __shared__ double2 s_amp[S];
-  uint64_t n;
-  if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
+  uint64_t n, vb;
+  if (!emit_begin_view(meta, ns, epoch, TILE, &n, &vb)) return;
+  offset_keys<W>(in_keys, vb);
+  offset_keys<W>(out_keys, vb);
+  in_amp += vb;
+  out_amp += vb;
+  cap -= vb;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + TILE - 1) / TILE;
   if (tile_out_of_range(tile, ntiles, &meta->err)) return;
@@ -1982,9 +2004,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
     if (threadIdx.x == 0) {
       s_off = ex;
       if (tile == ntiles - 1) {
-        meta->nnz_out[epoch % kRing] = ex + tile_total;
-        meta->nring[(ns & 1) ^ 1] = ex + tile_total;
-        atomicMax(&meta->peak, (unsigned long long)(ex + tile_total));
+        meta->nnz_out[epoch % kRing] = vb + ex + tile_total;
+        meta->nring[(ns & 1) ^ 1] = vb + ex + tile_total;
+        atomicMax(&meta->peak, (unsigned long long)(vb + ex + tile_total));
       }
     }
   }
@@ -2011,6 +2033,116 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
     }
   }
   publish_masks<W>(meta, epoch, orv, andv, s_red);
+}
+
+// ---------------------------------------------------------------------------
+// Retiring finished instances (batched rounds).  Instances are relabelled so
+// that labels ascend with the round in which an instance runs its last op;
+// the entries are sorted by (label, key) after every round, so the finished
+// instances form a prefix that later rounds leave alone.
+// ---------------------------------------------------------------------------
+
+// Instance field := map[instance field] on every entry [0, n) (in place; the
+// view base is ignored).  With `reset_base` the retired prefix is given back
+// to the whole array (base = 0) and generation `gen` records that.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_relabel(KeyPtrs<W> keys, uint32_t ns, uint32_t iword, uint32_t ishift,
+                                                    uint64_t imask, const uint32_t* __restrict__ map,
+                                                    uint32_t reset_base, uint32_t gen, DevMeta* meta,
+                                                    uint32_t epoch) {
+  __shared__ uint64_t s_red[2 * kMaxW * 4];
+  if (launch_prologue(meta, epoch)) return;
+  const uint64_t n = meta->nring[ns & 1];
+  if (reset_base && blockIdx.x == 0 && threadIdx.x == 0) {
+    meta->base = 0;
+    meta->base_gen[gen % kBaseGens] = 0;
+  }
+  uint64_t orv[W], andv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    orv[w] = 0;
+    andv[w] = ~0ull;
+  }
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    uint64_t k[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) k[w] = keys.w[w][i];
+    const uint32_t l = map[inst_of<W>(k, iword, ishift, imask)];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      if ((uint32_t)w == iword) {
+        k[w] = (k[w] & ~(imask << ishift)) | ((uint64_t)l << ishift);
+        keys.w[w][i] = k[w];
+      }
+      orv[w] |= k[w];
+      andv[w] &= k[w];
+    }
+  }
+  publish_masks<W>(meta, epoch, orv, andv, s_red);
+}
+
+// Retire the labels below `a`: find p, the first entry of [base, n) whose
+// label is at least `a` (entries are sorted by label), and copy [base, p)
+// from the current buffer to the other one, so both hold the final prefix.
+// Every workgroup finds p itself (one wave, a 64-way search over the sorted
+// labels); workgroup 0 leaves it in retire_p for k_retire_set.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_retire_copy(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
+                                                        KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
+                                                        uint32_t ns, uint32_t iword, uint32_t ishift, uint64_t imask,
+                                                        uint32_t a, DevMeta* meta, uint32_t epoch) {
+  __shared__ uint64_t s_p;
+  if (launch_prologue(meta, epoch)) return;
+  const uint64_t base = meta->base;
+  const uint64_t n = meta->nring[ns & 1];
+  if (threadIdx.x < 64) {
+    const uint32_t lane = threadIdx.x;
+    const uint64_t* lw = in_keys.w[iword];
+    // invariant: the first entry with label >= a lies in [lo, hi] (hi = n: none)
+    uint64_t lo = base, hi = n;
+    while (hi > lo) {
+      const uint64_t len = hi - lo;
+      const uint64_t step = (len + 63) / 64;
+      const uint64_t q = lo + (uint64_t)(lane + 1) * step - 1;
+      const bool probe = q < hi;
+      const bool ge = probe && (uint32_t)((lw[q] >> ishift) & imask) >= a;
+      // labels ascend, so the probes below the first ">= a" are a prefix of the lanes
+      const uint64_t below = __ballot(probe && !ge);
+      const uint32_t f = (uint32_t)__popcll(below);
+      const uint64_t nlo = f == 0 ? lo : lo + (uint64_t)f * step;
+      const uint64_t qf = lo + (uint64_t)(f + 1) * step - 1;
+      const uint64_t nhi = (f < 64 && qf < hi) ? qf : hi;
+      if (step == 1) {
+        lo = nlo;
+        hi = nlo;
+      } else {
+        lo = nlo;
+        hi = nhi;
+      }
+    }
+    if (lane == 0) s_p = lo;
+  }
+  __syncthreads();
+  const uint64_t p = s_p;
+  if (blockIdx.x == 0 && threadIdx.x == 0) meta->retire_p = p;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = base + (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < p; i += stride) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) out_keys.w[w][i] = in_keys.w[w][i];
+    out_amp[i] = in_amp[i];
+  }
+}
+
+// base = retire_p (one thread, after every workgroup of k_retire_copy has
+// read the old base), or 0 with `zero` (the rounds are over); generation
+// `gen` records it for the host's accounting.
+static __global__ void k_retire_set(DevMeta* meta, uint32_t gen, uint32_t zero) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (*reinterpret_cast<volatile unsigned int*>(&meta->err) != 0u) return;
+  const unsigned long long b = zero ? 0ull : meta->retire_p;
+  meta->base = b;
+  meta->base_gen[gen % kBaseGens] = b;
 }
 
 // ---------------------------------------------------------------------------
@@ -2127,6 +2259,9 @@ static __global__ void k_meta_init(DevMeta* meta) {
     }
     meta->peak = 0;
     meta->upd = 0;
+    meta->base = 0;
+    meta->retire_p = 0;
+    for (int g = 0; g < kBaseGens; ++g) meta->base_gen[g] = 0;
     meta->spec_fail[0] = meta->spec_fail[1] = 0;
     meta->spec_cool[0] = meta->spec_cool[1] = 0;
     meta->nring[0] = meta->nring[1] = 0;

@@ -266,6 +266,32 @@ __device__ __forceinline__ bool emit_begin(DevMeta* meta, uint32_t ns, uint32_t 
   return (uint64_t)blockIdx.x * tile_entries < n;
 }
 
+// emit_begin on the view [base, n) of batched rounds: the count returned is
+// n - base (positions are relative to base); an empty view records the
+// unchanged total as the output count.
+__device__ __forceinline__ bool emit_begin_view(DevMeta* meta, uint32_t ns, uint32_t epoch, uint64_t tile_entries,
+                                                uint64_t* n_out, uint64_t* base_out) {
+  if (launch_prologue(meta, epoch)) return false;
+  const uint64_t base = meta->base;
+  const uint64_t n = meta->nring[ns & 1] - base;
+  *n_out = n;
+  *base_out = base;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (n == 0) {
+      meta->nring[(ns & 1) ^ 1] = base;
+      meta->nnz_out[epoch % kRing] = base;
+    }
+    if ((uint64_t)gridDim.x * tile_entries < n) raise_error(meta, kErrGrid, epoch);
+  }
+  return (uint64_t)blockIdx.x * tile_entries < n;
+}
+
+template <int W>
+__device__ __forceinline__ void offset_keys(KeyPtrs<W>& k, uint64_t off) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) k.w[w] += off;
+}
+
 // A tile id at or past the tile count cannot be handed out when only
 // workgroups inside the count take tickets; such a workgroup touches nothing.
 __device__ __forceinline__ bool tile_out_of_range(uint32_t tile, uint64_t ntiles, unsigned int* err) {

@@ -267,10 +267,15 @@ struct ss_state {
   uint32_t spec_tries[2] = {0, 0};      // speculative launches since the last read-back
   int chain = 1;                 // option: consecutive one-target ops on one target in one launch
   // option: a one-target op applies the run that follows it when the run has
-  // at most this many ops (0: never).  A long run is issue-bound and runs
-  // faster in its own launch (8 entries per lane, higher occupancy); a short
-  // one costs little more than a read and a write of the state.
+  // at most this many ops (0: never); fusing saves the run's own read and
+  // write of the state.
   uint32_t fuse_runs = kRunChunk;
+  // batched rounds: relabel instances by the round of their last op and
+  // leave the finished ones out of later rounds (option "retire")
+  bool retire_batched = true;
+  bool in_view = false;           // launches work on the view [base, n) (batched rounds)
+  uint32_t vgen = 0;              // retirement generation of the current view base
+  std::vector<uint32_t> undo_map; // instance of each label of the last batched call (empty: not relabelled)
   uint32_t xcd_order = 0;        // 1 when workgroups spread round-robin over 8 XCDs
   int tile_order_opt = 1;        // option: 1 use XCD tickets when possible, 0 one counter
   uint64_t stats[8]{};
@@ -285,6 +290,7 @@ struct ss_state {
     hipEvent_t a, b;
     uint32_t in_ep, out_ep;
     uint64_t in_n, in_per, out_per, ent_mult;
+    int64_t vgen;                 // >= 0: counts are of the view past that generation's base
   };
   std::vector<TraceRec> pending;
   uint32_t trace_old_ep = 0;      // oldest launch a pending record refers to
@@ -367,6 +373,7 @@ void trace_end(ss_state* st, int idx, uint64_t in_per, uint64_t ent_mult, uint32
   r.ent_mult = ent_mult;
   r.out_ep = out_ep;
   r.out_per = out_per;
+  r.vgen = st->in_view ? (int64_t)st->vgen : -1;
   for (uint32_t e : {r.in_ep, r.out_ep})
     if (e && (st->trace_old_ep == 0 || e < st->trace_old_ep)) st->trace_old_ep = e;
   (void)hipEventRecord(r.b, st->stream);
@@ -377,8 +384,14 @@ void trace_flush(ss_state* st) {
   const DevMeta* hm = st->hmeta;
   for (auto& r : st->pending) {
     float ms = 0.f;
-    const uint64_t n_in = r.in_ep ? hm->nnz_out[r.in_ep % kRing] : r.in_n;
-    const uint64_t n_out = r.out_ep ? hm->nnz_out[r.out_ep % kRing] : 0;
+    uint64_t n_in = r.in_ep ? hm->nnz_out[r.in_ep % kRing] : r.in_n;
+    uint64_t n_out = r.out_ep ? hm->nnz_out[r.out_ep % kRing] : 0;
+    if (r.vgen >= 0) {
+      // batched rounds: only the entries past the retired prefix were touched
+      const uint64_t b = hm->base_gen[r.vgen % kBaseGens];
+      n_in = n_in > b ? n_in - b : 0;
+      n_out = n_out > b ? n_out - b : 0;
+    }
     if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
       st->tr_sec[r.cat] += ms * 1e-3;
       st->tr_cnt[r.cat] += 1;
@@ -1712,16 +1725,159 @@ void launch_reduce_batched_w(ss_state* st, const BatchOp* bops, uint32_t ep) {
                                                          st->lb, st->meta, ep, xo(st));
 }
 
+template <int W>
+void launch_relabel_w(ss_state* st, const uint32_t* map, bool reset, uint32_t gen, uint32_t ep) {
+  const Buf& b = st->buf[st->cur];
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, (st->n_ub + kBlock - 1) / kBlock), 4096);
+  k_relabel<W><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), st->nslot, st->L.iword, st->L.ishift, st->L.imask, map,
+                                                 reset ? 1u : 0u, gen, st->meta, ep);
+}
+
+template <int W>
+void launch_retire_w(ss_state* st, uint32_t a, uint32_t gen, uint32_t ep) {
+  const Buf& in = st->buf[st->cur];
+  const Buf& out = st->buf[st->cur ^ 1];
+  constexpr uint64_t T = (uint64_t)kBlock * 4;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, (st->n_ub + T - 1) / T), 2048);
+  k_retire_copy<W><<<grid, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot, st->L.iword,
+                                                     st->L.ishift, st->L.imask, a, st->meta, ep);
+  k_retire_set<<<1, 64, 0, st->stream>>>(st->meta, gen, 0u);
+}
+
+// Relabel the instance field of every entry through `map` (label -> value);
+// with `reset` the batched view ends (base = 0).  No map: only the reset.
+int relabel_entries(ss_state* st, const std::vector<uint32_t>& map, bool reset) {
+  const uint32_t gen = reset ? ++st->vgen : st->vgen;
+  if (map.empty()) {
+    if (!reset) return SS_OK;
+    k_retire_set<<<1, 64, 0, st->stream>>>(st->meta, gen, 1u);
+    return check_launch(st);
+  }
+  char* d = nullptr;
+  int rc = ring_upload(st, map.data(), map.size() * sizeof(uint32_t), &d);
+  if (rc) return rc;
+  uint32_t ep;
+  rc = begin_launch(st, &ep);
+  if (rc) return rc;
+  const uint32_t* m = reinterpret_cast<const uint32_t*>(d);
+  switch (st->L.W) {
+    case 1: launch_relabel_w<1>(st, m, reset, gen, ep); break;
+    case 2: launch_relabel_w<2>(st, m, reset, gen, ep); break;
+    default: launch_relabel_w<4>(st, m, reset, gen, ep); break;
+  }
+  rc = check_launch(st);
+  if (rc) return rc;
+  st->masks_valid = false;
+  st->mask_ep = ep;
+  st->sup_valid = false;
+  st->grouped = false;
+  return SS_OK;
+}
+
+// For each instance, the pass of the batched loop below in which it runs its
+// last op (the loop's control depends on the op lists only).
+std::vector<uint64_t> batched_finish_passes(const ss_state* st, const ss_op* ops, const uint64_t* off) {
+  const uint32_t NI = st->ninst;
+  std::vector<uint64_t> cur(off, off + NI), end(off + 1, off + NI + 1), fin(NI, 0);
+  std::vector<uint32_t> chunk(NI, 0);
+  uint64_t pass = 0;
+  while (true) {
+    ++pass;
+    bool any_run = false, any_branch = false;
+    for (uint32_t i = 0; i < NI; ++i) {
+      if (chunk[i] != 0) continue;
+      uint64_t j = cur[i];
+      while (j < end[i] && !is_branching(st, ops[j])) ++j;
+      any_run = any_run || j > cur[i];
+      cur[i] = j;
+    }
+    for (uint32_t i = 0; i < NI; ++i) {
+      if (cur[i] >= end[i]) continue;
+      const ss_op& op = ops[cur[i]];
+      const uint32_t nq = (uint32_t)__builtin_popcountll(op.qmask & st->L.regs[op.reg].mask);
+      if ((uint64_t)(chunk[i] + 1) * kMaxGroupBits >= nq) {
+        chunk[i] = 0;
+        cur[i]++;
+      } else {
+        chunk[i]++;
+      }
+      any_branch = true;
+    }
+    for (uint32_t i = 0; i < NI; ++i)
+      if (fin[i] == 0 && cur[i] >= end[i] && chunk[i] == 0) fin[i] = pass;
+    if (!any_branch && !any_run) break;
+    bool left = false;
+    for (uint32_t i = 0; i < NI; ++i) left = left || cur[i] < end[i];
+    if (!left) break;
+  }
+  for (uint32_t i = 0; i < NI; ++i)
+    if (fin[i] == 0) fin[i] = pass;
+  return fin;
+}
+
+int batched_rounds(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* off, ss_result* res,
+                   const std::vector<uint32_t>& label, const std::vector<uint64_t>& fin);
+
 // Every instance i runs ops[off[i] .. off[i+1]).  Round r: one fused launch
 // advances each instance through its non-branching ops up to its next
 // branching op; then one expansion applies each instance's branching op (up to
 // five target qubits; wider ops take several rounds), one LSD sort orders the
 // candidates by (instance, key) and one reduce-by-key merges equal keys.
+// Instances are first relabelled so that labels ascend with the pass of their
+// last op; after each round the finished ones (a prefix of the sorted
+// entries) are retired, so later rounds move only the entries of unfinished
+// instances; at the end the labels go back.
 int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* off, ss_result* res) {
   const uint32_t NI = st->ninst;
   if (off[0] != 0 || off[NI] > nops) return SS_E_ARG;
   for (uint32_t i = 0; i < NI; ++i)
     if (off[i] > off[i + 1]) return SS_E_ARG;
+  std::vector<uint32_t> label(NI);
+  std::vector<uint64_t> fin;
+  for (uint32_t i = 0; i < NI; ++i) label[i] = i;
+  const bool retire = st->retire_batched && NI > 1 && st->L.has_inst;
+  st->undo_map.clear();
+  if (retire) {
+    fin = batched_finish_passes(st, ops, off);
+    std::vector<uint32_t> order(NI);
+    for (uint32_t i = 0; i < NI; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return fin[x] < fin[y]; });
+    bool ident = true;
+    for (uint32_t r = 0; r < NI; ++r) {
+      label[order[r]] = r;
+      ident = ident && order[r] == r;
+    }
+    if (!ident) {
+      if (st->n_ub > 0) {
+        const int rc = relabel_entries(st, label, false);
+        if (rc) return rc;
+      }
+      st->undo_map = order;
+    }
+  }
+  st->in_view = retire;
+  const int rc = batched_rounds(st, ops, nops, off, res, label, fin);
+  st->in_view = false;
+  if (retire && !st->poisoned &&
+      (rc == SS_OK || ((rc == SS_E_CAPACITY || rc == SS_E_PLAN) && st->rolled_back))) {
+    // labels back to instances, base back to 0 (also after a roll-back: the
+    // round input it returned to is still relabelled)
+    const int uc = relabel_entries(st, st->undo_map, true);
+    if (uc) return uc;
+  }
+  return rc;
+}
+
+int batched_rounds(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t* off, ss_result* res,
+                   const std::vector<uint32_t>& label, const std::vector<uint64_t>& fin) {
+  const uint32_t NI = st->ninst;
+  (void)res;
+  const bool retire = !fin.empty();
+  uint64_t pass = 0;
+  uint32_t retired = 0;           // labels below this are retired
+  std::vector<uint64_t> fin_l(retire ? NI : 0);
+  if (retire)
+    for (uint32_t i = 0; i < NI; ++i) fin_l[label[i]] = fin[i];
   std::vector<uint64_t> cur(off, off + NI), end(off + 1, off + NI + 1);
   std::vector<uint32_t> chunk(NI, 0);
   const uint32_t W = st->L.W;
@@ -1732,6 +1888,7 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
   set_mark(st, 0, false);
   st->sup_valid = false;
   while (true) {
+    ++pass;
     // --- non-branching runs -------------------------------------------------
     bool any_run = false;
     uint32_t i0 = 0;
@@ -1751,8 +1908,8 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
         // keep one launch's op tables well inside the staging ring
         const uint64_t bytes = (fast.size() + len) * sizeof(FastOp) + (gen.size() + len) * sizeof(PermOp);
         if (!fast.empty() && bytes > kOpRingBytes / 2) break;
-        runs[i].start = (uint32_t)fast.size();
-        runs[i].len = (uint32_t)len;
+        runs[label[i]].start = (uint32_t)fast.size();
+        runs[label[i]].len = (uint32_t)len;
         for (uint64_t q = 0; q < len; ++q) {
           const ss_op& op = ops[j + q];
           if (op_uses_amp(st, op)) amp = true;
@@ -1802,7 +1959,7 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
     // --- branching ops --------------------------------------------------------
     bool any_branch = false;
     for (uint32_t i = 0; i < NI; ++i) {
-      BatchOp& b = bops[i];
+      BatchOp& b = bops[label[i]];
       b = BatchOp{};
       if (cur[i] >= end[i]) continue;
       const ss_op& op = ops[cur[i]];
@@ -1889,6 +2046,23 @@ int apply_batched(ss_state* st, const ss_op* ops, uint64_t nops, const uint64_t*
     if (rc) return rc;
     after_emit(st, ep, st->n_ub, false, round);
     set_mark(st, round + 1, false);
+    // retire the instances whose last op ran in this pass: their labels are
+    // the next ones up, their entries the start of the view
+    if (retire) {
+      uint32_t a = retired;
+      while (a < NI && fin_l[a] <= pass) ++a;
+      if (a > retired) {
+        rc = begin_launch(st, &ep);
+        if (rc) return rc;
+        const uint32_t gen = ++st->vgen;
+        if (W == 1) launch_retire_w<1>(st, a, gen, ep);
+        else if (W == 2) launch_retire_w<2>(st, a, gen, ep);
+        else launch_retire_w<4>(st, a, gen, ep);
+        rc = check_launch(st);
+        if (rc) return rc;
+        retired = a;
+      }
+    }
   }
   st->grouped = false;
   return SS_OK;
@@ -2143,6 +2317,8 @@ struct ss_graph {
   uint64_t kernels = 0;
   std::vector<ss_state::EmitLog> emits;
   std::vector<ss_state::PlanMark> plan_log;
+  bool batched_view = false;      // the plan retires instances (batched rounds)
+  std::vector<uint32_t> undo_map; // its relabelling, undone after a failed replay
 };
 
 // The device array behind ss_create_state_noalloc's scratch (64 MiB).
@@ -3110,6 +3286,8 @@ int ss_graph_capture(ss_state* st, const ss_op* ops, uint64_t nops, const uint64
       g->emits = st->emits;
       g->plan_log = st->plan_log;
       g->kernels = st->stats[0] - k0;
+      g->batched_view = inst_offsets && st->retire_batched && st->ninst > 1 && st->L.has_inst;
+      g->undo_map = st->undo_map;
       hipGraph_t graph = nullptr;
       if (hipStreamEndCapture(cs, &graph) != hipSuccess && !prc) prc = SS_E_HIP;
       g->graph = graph;
@@ -3182,6 +3360,13 @@ int ss_graph_launch(ss_graph* g, ss_result* res) {
   for (int w = 0; w < kMaxW; ++w) st->gmask[w] = g->gmask_end[w];
   st->epoch = std::max(st->epoch, g->epoch_end);
   rc = sync_state(st);
+  if ((rc == SS_E_CAPACITY || rc == SS_E_PLAN) && st->rolled_back && g->batched_view && !st->poisoned) {
+    // the replay stopped inside its batched rounds, before it gave the labels
+    // and the retired prefix back: do that now
+    st->undo_map = g->undo_map;
+    const int uc = relabel_entries(st, st->undo_map, true);
+    if (uc) return uc;
+  }
   res->status = rc;
   res->failed_op = (rc == SS_E_CAPACITY || rc == SS_E_PLAN) ? st->rb_op : 0;
   res->nnz = st->n;
@@ -3223,6 +3408,9 @@ int ss_set_option(ss_state* st, const char* key, int64_t value) {
     st->speculate = (uint64_t)value;
   } else if (k == "chain") {
     st->chain = value ? 1 : 0;
+  } else if (k == "retire") {
+    if (value != 0 && value != 1) return SS_E_ARG;
+    st->retire_batched = value != 0;
   } else if (k == "fuse_runs") {
     if (value < 0 || value > (int64_t)kRunChunk) return SS_E_ARG;
     st->fuse_runs = (uint32_t)value;

@@ -16,6 +16,7 @@ constexpr int kMaxPasses = 40;      // up to 256 key bits + 5 target bits, 8 bit
 constexpr int kMaxGroupBits = 5;    // targets fused into one interference op (2^5 group)
 constexpr int kMaxExpandBits = 10;  // targets of one pure expansion (one thread per child, 2^10 children)
 constexpr int kRing = 128;          // per-launch slots (tile counter, count, key masks)
+constexpr int kBaseGens = 64;       // retirement generations kept in the meta block (batched rounds)
 constexpr int kXcds = 8;            // XCDs of an MI355X
 constexpr int kXcdStride = 16;      // per-XCD counters 128 bytes apart
 
@@ -55,6 +56,7 @@ struct DevMeta {
   unsigned long long nnz_out[kRing];         // entry count written by an emitting kernel
   unsigned long long or_mask[kRing][kMaxW];  // OR of the produced keys, per word
   unsigned long long and_mask[kRing][kMaxW]; // AND of the produced keys, per word
+  unsigned long long base_gen[kBaseGens];    // retired prefix per retirement generation (batched rounds)
   // device-only part
   double dscratch[16];
   unsigned long long uscratch[16];
@@ -62,6 +64,11 @@ struct DevMeta {
   unsigned int spec_irr[kRing];              // speculative launch: 1 met an irregular tile, kSpecSkipped skipped
   unsigned int spec_cool[2];                 // speculative launches left to skip after a wasted one, per mode
   unsigned long long xcd_ctr[kRing][kXcds * kXcdStride];  // per-XCD tickets
+  // Batched rounds retire finished instances: entries [0, base) of both
+  // entry buffers are final and the round kernels (and the sort) work on the
+  // view [base, n).  0 outside batched rounds.
+  unsigned long long base;
+  unsigned long long retire_p;               // end of the next retired block (set by k_retire_copy)
 };
 
 // A run of non-branching ops is executed from an array of these (uniform per op).
