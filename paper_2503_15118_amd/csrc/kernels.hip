@@ -626,11 +626,12 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(KeyPtrs<W> in_keys, const 
   in_amp += vb;
   out_amp += vb;
   if (blockIdx.x == 0 && tid == 0 && (uint64_t)gridDim.x * TILE < n) raise_error(meta, kErrGrid, epoch);
-  if ((uint64_t)blockIdx.x * TILE >= n) return;
+  // xo == 2: tickets in chunks per XCD (every workgroup takes one)
+  if (xo != 2 && (uint64_t)blockIdx.x * TILE >= n) return;
 #pragma unroll
   for (int w = 0; w < kBlock / 64; ++w) s_wcount[w][tid] = 0;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
-  if (tile_out_of_range(tile, (n + TILE - 1) / TILE, &meta->err)) return;
+  if (tile_out_of_range(tile, (n + TILE - 1) / TILE, &meta->err, xo)) return;
   const uint64_t base = (uint64_t)tile * TILE;
   const uint32_t tile_n = (uint32_t)min((uint64_t)TILE, n - base);
 
@@ -818,11 +819,11 @@ __global__ __launch_bounds__(kBlock) void k_group(KeyPtrs<W> in_keys, const doub
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
   uint64_t n;
-  if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
+  if (!emit_begin(meta, ns, epoch, TILE, &n, xo)) return;
   if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&meta->upd, (unsigned long long)(n * op.upd));
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + TILE - 1) / TILE;
-  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
+  if (tile_out_of_range(tile, ntiles, &meta->err, xo)) return;
 
   uint64_t key[ITEMS][W];
   double2 v[ITEMS][G];
@@ -975,11 +976,11 @@ __global__ __launch_bounds__(kBlock) void k_expand_slots(KeyPtrs<W> in_keys, con
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
   uint64_t n;
-  if (!emit_begin(meta, ns, epoch, TILE / G, &n)) return;
+  if (!emit_begin(meta, ns, epoch, TILE / G, &n, xo)) return;
   if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&meta->upd, (unsigned long long)(n * op.upd));
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n * G + TILE - 1) / TILE;
-  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
+  if (tile_out_of_range(tile, ntiles, &meta->err, xo)) return;
   uint64_t key[ITEMS][W];
   double2 v[ITEMS];
   uint32_t cnt[ITEMS];
@@ -1475,7 +1476,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
   constexpr uint32_t kStageWords = MODE == MODE_GROUP ? (W + 2) * (TILE + 2) : 1;
   __shared__ __align__(16) uint64_t s_stage[kStageWords];
   uint64_t n;
-  if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
+  if (!emit_begin(meta, ns, epoch, TILE, &n, xo)) return;
   if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&meta->upd, (unsigned long long)(n * op.upd));
   const unsigned int sflag =
       spec_ep != 0 ? *reinterpret_cast<volatile unsigned int*>(&meta->spec_irr[spec_ep % kRing]) : 0u;
@@ -1508,7 +1509,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
   }
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + TILE - 1) / TILE;
-  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
+  if (tile_out_of_range(tile, ntiles, &meta->err, xo)) return;
   const uint64_t e0 = (uint64_t)tile * TILE;
   uint64_t key[ITEMS][W];
   double2 out[ITEMS][2];
@@ -1584,10 +1585,10 @@ __global__ __launch_bounds__(kBlock) void k_filter(KeyPtrs<W> in_keys, const dou
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
   uint64_t n;
-  if (!emit_begin(meta, ns, epoch, TILE, &n)) return;
+  if (!emit_begin(meta, ns, epoch, TILE, &n, xo)) return;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + TILE - 1) / TILE;
-  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
+  if (tile_out_of_range(tile, ntiles, &meta->err, xo)) return;
   uint64_t key[ITEMS][W];
   double2 a[ITEMS];
   uint32_t cnt[ITEMS];
@@ -1755,7 +1756,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
   __shared__ uint32_t s_irange[2];
   __shared__ BatchOp s_bop[kOpStage];
   uint64_t n, vb;
-  if (!emit_begin_view(meta, ns, epoch, TILE, &n, &vb)) return;
+  if (!emit_begin_view(meta, ns, epoch, TILE, &n, &vb, xo)) return;
   offset_keys<W>(in_keys, vb);
   offset_keys<W>(out_keys, vb);
   in_amp += vb;
@@ -1763,7 +1764,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
   cap -= vb;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + TILE - 1) / TILE;
-  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
+  if (tile_out_of_range(tile, ntiles, &meta->err, xo)) return;
   const uint64_t e0 = (uint64_t)tile * TILE;
   uint64_t key[ITEMS][W];
   double2 a[ITEMS];
@@ -1927,7 +1928,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
   __shared__ uint64_t s_key[W * S];
   __shared__ double2 s_amp[S];
   uint64_t n, vb;
-  if (!emit_begin_view(meta, ns, epoch, TILE, &n, &vb)) return;
+  if (!emit_begin_view(meta, ns, epoch, TILE, &n, &vb, xo)) return;
   offset_keys<W>(in_keys, vb);
   offset_keys<W>(out_keys, vb);
   in_amp += vb;
@@ -1935,7 +1936,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
   cap -= vb;
   const uint32_t tile = take_tile(meta, epoch, &s_tile, xo);
   const uint64_t ntiles = (n + TILE - 1) / TILE;
-  if (tile_out_of_range(tile, ntiles, &meta->err)) return;
+  if (tile_out_of_range(tile, ntiles, &meta->err, xo)) return;
   const uint64_t e0 = (uint64_t)tile * TILE;
   // stage slot l = entry e0 - 1 + l (zero key, zero amplitude past n); all
   // loads first, then the LDS stores

@@ -197,12 +197,24 @@ __device__ __forceinline__ uint32_t xcc_id() {
 // contention, and a tile waits only on lower tiles, each taken by a running
 // workgroup or by one that its XCD will still start.  Otherwise one counter
 // hands out tiles in start order.
+// xcd_order 1: XCD x (workgroups spread round robin over the 8 XCDs) hands
+// out tiles x, x + 8, ... from its own counter.  2: tickets in chunks per
+// XCD: XCD x hands out, in order, the tiles whose index / kTileChunk is x
+// modulo 8, so kTileChunk consecutive tiles run on one XCD and what they share
+// (the output lines where one tile's writes end and the next one's begin, the
+// next tile's look-back words) meets in that XCD's L2.  With 2 every workgroup
+// of the grid (a multiple of 8 x kTileChunk) takes a ticket and those past the
+// tile count leave (tile_out_of_range).
 __device__ __forceinline__ uint32_t take_tile(DevMeta* meta, uint32_t epoch, uint32_t* s_tile,
                                               uint32_t xcd_order) {
   if (threadIdx.x == 0) {
     const uint32_t slot = epoch % kRing;
     uint32_t t;
-    if (xcd_order) {
+    if (xcd_order == 2) {
+      const uint32_t x = blockIdx.x % kXcds;
+      const uint32_t k = (uint32_t)atomicAdd(&meta->xcd_ctr[slot][x * kXcdStride], 1ull);
+      t = ((k / kTileChunk) * kXcds + x) * kTileChunk + k % kTileChunk;
+    } else if (xcd_order) {
       const uint32_t x = blockIdx.x % kXcds;
       t = (uint32_t)atomicAdd(&meta->xcd_ctr[slot][x * kXcdStride], 1ull) * kXcds + x;
     } else {
@@ -252,7 +264,7 @@ __device__ __forceinline__ void raise_error(DevMeta* meta, uint32_t bits, uint32
 // empty input: workgroup 0 then records an empty output, or excess).  A grid
 // smaller than the count is flagged rather than leaving entries behind.
 __device__ __forceinline__ bool emit_begin(DevMeta* meta, uint32_t ns, uint32_t epoch, uint64_t tile_entries,
-                                           uint64_t* n_out) {
+                                           uint64_t* n_out, uint32_t xcd_order) {
   if (launch_prologue(meta, epoch)) return false;
   const uint64_t n = meta->nring[ns & 1];
   *n_out = n;
@@ -263,14 +275,14 @@ __device__ __forceinline__ bool emit_begin(DevMeta* meta, uint32_t ns, uint32_t 
     }
     if ((uint64_t)gridDim.x * tile_entries < n) raise_error(meta, kErrGrid, epoch);
   }
-  return (uint64_t)blockIdx.x * tile_entries < n;
+  return xcd_order == 2 || (uint64_t)blockIdx.x * tile_entries < n;
 }
 
 // emit_begin on the view [base, n) of batched rounds: the count returned is
 // n - base (positions are relative to base); an empty view records the
 // unchanged total as the output count.
 __device__ __forceinline__ bool emit_begin_view(DevMeta* meta, uint32_t ns, uint32_t epoch, uint64_t tile_entries,
-                                                uint64_t* n_out, uint64_t* base_out) {
+                                                uint64_t* n_out, uint64_t* base_out, uint32_t xcd_order) {
   if (launch_prologue(meta, epoch)) return false;
   const uint64_t base = meta->base;
   const uint64_t n = meta->nring[ns & 1] - base;
@@ -283,7 +295,7 @@ __device__ __forceinline__ bool emit_begin_view(DevMeta* meta, uint32_t ns, uint
     }
     if ((uint64_t)gridDim.x * tile_entries < n) raise_error(meta, kErrGrid, epoch);
   }
-  return (uint64_t)blockIdx.x * tile_entries < n;
+  return xcd_order == 2 || (uint64_t)blockIdx.x * tile_entries < n;
 }
 
 template <int W>
@@ -294,9 +306,11 @@ __device__ __forceinline__ void offset_keys(KeyPtrs<W>& k, uint64_t off) {
 
 // A tile id at or past the tile count cannot be handed out when only
 // workgroups inside the count take tickets; such a workgroup touches nothing.
-__device__ __forceinline__ bool tile_out_of_range(uint32_t tile, uint64_t ntiles, unsigned int* err) {
+__device__ __forceinline__ bool tile_out_of_range(uint32_t tile, uint64_t ntiles, unsigned int* err,
+                                                  uint32_t xcd_order) {
   if (tile < ntiles) return false;
-  if (threadIdx.x == 0) atomicOr(err, kErrGrid);
+  // chunked tickets hand out every tile of the grid: those past the count leave
+  if (xcd_order != 2 && threadIdx.x == 0) atomicOr(err, kErrGrid);
   return true;
 }
 

@@ -36,6 +36,18 @@ struct LaunchCtx {
   uint32_t xo;
 };
 
+// Grid of a launch whose workgroups take tile tickets: with chunked tickets
+// (xo == 2) every workgroup takes one, so the grid is a whole number of
+// 8 x kTileChunk workgroups.
+inline uint32_t ticket_grid(uint64_t ntiles, uint32_t xo) {
+  uint64_t g = std::max<uint64_t>(1, ntiles);
+  if (xo == 2) {
+    const uint64_t q = (uint64_t)kXcds * kTileChunk;
+    g = (g + q - 1) / q * q;
+  }
+  return (uint32_t)g;
+}
+
 // One-target op with compaction (k_pair): items entries per thread (1|2|4).
 template <int W>
 void launch_pair(const LaunchCtx& c, int mode, int items, const GroupOp& g, uint32_t ep, uint32_t ep_spec,

@@ -14,13 +14,13 @@ static void multi_wki(const LaunchCtx& c, int mode, bool slots, const GroupOp& g
     // kMaxGroupBits targets come here only as pure expansions that fit)
     constexpr uint32_t kSlotTile = kBlock * 4;
     const uint64_t nslots = c.n_ub << K;
-    const uint32_t nt = (uint32_t)std::max<uint64_t>(1, (nslots + kSlotTile - 1) / kSlotTile);
+    const uint32_t nt = ticket_grid((nslots + kSlotTile - 1) / kSlotTile, c.xo);
     k_expand_slots<W, K, 4><<<nt, kBlock, 0, c.stream>>>(ik, c.in.amp, ok, c.out.amp, c.ns, c.cap, g, c.lb, c.meta,
                                                          ep, c.xo);
     return;
   }
   if constexpr (K <= kMaxGroupBits) {
-    const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (c.n_ub + kBlock * ITEMS - 1) / (kBlock * ITEMS));
+    const uint32_t ntiles = ticket_grid((c.n_ub + kBlock * ITEMS - 1) / (kBlock * ITEMS), c.xo);
     if (mode == MODE_GROUP)
       k_group<W, K, MODE_GROUP, ITEMS><<<ntiles, kBlock, 0, c.stream>>>(ik, c.in.amp, ok, c.out.amp, c.ns, c.cap, g,
                                                                         c.lb, c.meta, ep, c.xo);

@@ -8,7 +8,7 @@ namespace sparqs {
 template <int W, int ITEMS>
 static void pair_items(const LaunchCtx& c, int mode, const GroupOp& g, uint32_t ep, uint32_t ep_spec,
                        const FusedRun& run) {
-  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (c.n_ub + kBlock * ITEMS - 1) / (kBlock * ITEMS));
+  const uint32_t ntiles = ticket_grid((c.n_ub + kBlock * ITEMS - 1) / (kBlock * ITEMS), c.xo);
   // one child per entry in group mode, two in expand mode
   const uint32_t f = mode == MODE_GROUP ? 1u : 2u;
   KeyPtrs<W> ik, ok;

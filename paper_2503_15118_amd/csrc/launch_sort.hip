@@ -20,12 +20,17 @@ void launch_sort_pass(const LaunchCtx& c, int items, uint32_t ntiles, const Pass
                       const uint64_t* digit_start, uint32_t ep) {
   KeyPtrs<W> ik, ok;
   for (int w = 0; w < W; ++w) { ik.w[w] = c.in.key[w]; ok.w[w] = c.out.key[w]; }
+  // with per-XCD tickets the passes take them in chunks of consecutive tiles:
+  // a digit's run that one tile ends and the next continues then meets in
+  // one XCD's L2 (the scatter writes many such partial lines)
+  const uint32_t xo = c.xo ? 2u : 0u;
+  ntiles = ticket_grid(ntiles, xo);
   if (items == 16)
     k_sort_pass<W, 16><<<ntiles, kBlock, 0, c.stream>>>(ik, c.in.amp, ok, c.out.amp, c.ns, pd, digit_start, c.lb,
-                                                         c.meta, ep, c.xo);
+                                                         c.meta, ep, xo);
   else
     k_sort_pass<W, 8><<<ntiles, kBlock, 0, c.stream>>>(ik, c.in.amp, ok, c.out.amp, c.ns, pd, digit_start, c.lb,
-                                                        c.meta, ep, c.xo);
+                                                        c.meta, ep, xo);
 }
 
 template void launch_sort_hist<1>(const LaunchCtx&, uint32_t, const SortPlan&, unsigned long long*, uint64_t*);

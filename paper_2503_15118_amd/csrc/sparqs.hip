@@ -856,7 +856,7 @@ void launch_filter_w(ss_state* st, const FilterOp& f, uint32_t ep) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
   constexpr int ITEMS = 4;
-  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock * ITEMS - 1) / (kBlock * ITEMS));
+  const uint32_t ntiles = ticket_grid((st->n_ub + kBlock * ITEMS - 1) / (kBlock * ITEMS), xo(st));
   k_filter<W, ITEMS><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
                                                         st->cap, f, st->lb, st->meta, ep, xo(st));
 }
@@ -1708,7 +1708,7 @@ void launch_expand_batched_w(ss_state* st, const BatchOp* bops, uint32_t ep) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
   constexpr uint64_t T = (uint64_t)kBlock * kBatchItems;
-  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + T - 1) / T);
+  const uint32_t ntiles = ticket_grid((st->n_ub + T - 1) / T, xo(st));
   k_expand_batched<W, kBatchItems><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
                                                          st->cap, bops, st->L.iword, st->L.ishift, st->L.imask,
                                                          st->lb, st->meta, ep, xo(st));
@@ -1719,7 +1719,7 @@ void launch_reduce_batched_w(ss_state* st, const BatchOp* bops, uint32_t ep) {
   const Buf& in = st->buf[st->cur];
   const Buf& out = st->buf[st->cur ^ 1];
   constexpr uint64_t T = (uint64_t)kBlock * kBatchItems;
-  const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (st->n_ub + T - 1) / T);
+  const uint32_t ntiles = ticket_grid((st->n_ub + T - 1) / T, xo(st));
   k_reduce_batched<W, kBatchItems><<<ntiles, kBlock, 0, st->stream>>>(kp<W>(in), in.amp, kp<W>(out), out.amp, st->nslot,
                                                          st->cap, bops, st->L.iword, st->L.ishift, st->L.imask,
                                                          st->lb, st->meta, ep, xo(st));
@@ -3392,8 +3392,9 @@ int ss_set_option(ss_state* st, const char* key, int64_t value) {
     st->sort_items = (int)value;
   } else if (k == "tile_order") {
     // 1: per-XCD tickets when the device spreads workgroups round-robin (one
-    // stream); 0: one ticket counter (states driven concurrently on several
-    // streams of one GPU must use 0)
+    // stream; radix passes take them in chunks of consecutive tiles); 0: one
+    // ticket counter (states driven concurrently on several streams of one
+    // GPU must use 0)
     st->tile_order_opt = value ? 1 : 0;
   } else if (k == "perm_entries") {
     if (value != 4 && value != 8 && value != 16) return SS_E_ARG;

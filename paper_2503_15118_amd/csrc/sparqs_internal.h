@@ -18,6 +18,7 @@ constexpr int kMaxExpandBits = 10;  // targets of one pure expansion (one thread
 constexpr int kRing = 128;          // per-launch slots (tile counter, count, key masks)
 constexpr int kBaseGens = 64;       // retirement generations kept in the meta block (batched rounds)
 constexpr int kXcds = 8;            // XCDs of an MI355X
+constexpr uint32_t kTileChunk = 8;  // consecutive tiles per XCD with chunked tickets
 constexpr int kXcdStride = 16;      // per-XCD counters 128 bytes apart
 
 // Lookback words: [epoch:24 | flag:2 | value:38].
