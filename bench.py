@@ -121,7 +121,37 @@ def summarize_profile(pdir):
     with open(os.path.join(ROOT, "profiles", "c2_hbm_counters.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
     sq = summarize_sq(pdir, base, sha) if os.path.isdir(os.path.join(pdir, "sq")) else []
-    print("\n".join(out + lines + sq))
+    sm = summarize_sort_merge(pdir, sha) if os.path.isdir(os.path.join(pdir, "sm")) else []
+    print("\n".join(out + lines + sq + sm))
+
+
+def summarize_sort_merge(pdir, sha):
+    """profiles/sort_merge_2e26_kernel_stats.txt: kernel statistics of the
+    sort / merge section (<pdir>/sm: --kernel-trace --stats of that section
+    alone), the radix-sort kernels and the merge launches at 2^26 entries."""
+    import csv
+    cmd = ("rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/sm -o sm -- python3 bench.py "
+           "--no-cpu-baseline --no-tune --steps 2 --warmup 1 --graph-steps 0 --sections sortmerge")
+    lines = ["# rocprofv3 kernel statistics: sort and merge of 2^26 entries (2^25 random distinct keys, an H on an "
+             "unused qubit, then the same H with grouping off: a sort of every entry on its idle bits and a merge "
+             "of each pair), W = 1 (41-bit key) and W = 2 (97-bit key), three repetitions each; the run also "
+             "steps the arithmetic-heavy circuit (small kernels of 2^21 entries mix into k_pair and the "
+             "expansions)",
+             "# command (from /tmp, TMPDIR=/tmp):",
+             f"#   {cmd}",
+             "# summarised by: python3 bench.py --summarize-profile <dir>",
+             f"# kernel sources sha256[:16] = {sha}",
+             f'{"kernel":62s} {"calls":>6s} {"avg_us":>9s} {"min_us":>9s} {"max_us":>9s} {"total_ms":>9s}']
+    for r in csv.DictReader(open(os.path.join(pdir, "sm", "sm_kernel_stats.csv"))):
+        name = r["Name"].split("(")[0][:62]
+        if not any(k in name for k in ("k_sort", "k_pair<", "k_expand")):
+            continue
+        lines.append(f'{name:62s} {int(r["Calls"]):6d} {float(r["AverageNs"]) / 1e3:9.1f} '
+                     f'{float(r["MinNs"]) / 1e3:9.1f} {float(r["MaxNs"]) / 1e3:9.1f} '
+                     f'{float(r["TotalDurationNs"]) / 1e6:9.3f}')
+    with open(os.path.join(ROOT, "profiles", "sort_merge_2e26_kernel_stats.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return lines
 
 
 def summarize_sq(pdir, base, sha):
