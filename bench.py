@@ -902,11 +902,16 @@ def main():
     sy0 = st.stats()["host_syncs"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks = []
     for _ in range(args.steps):
         step()
+        # a step ends with the planner's own waits for the device, so the
+        # host clock after it is close to the device's (a diagnostic only)
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     syncs = (st.stats()["host_syncs"] - sy0) / args.steps
+    step_ms = np.diff(np.array([t0] + marks)) * 1e3
 
     # the roofline pass: the same K steps again with a HIP event pair around
     # every launch on the state's stream (the events themselves add host and
@@ -938,16 +943,20 @@ def main():
         s0 = st.stats()["entries_updated"]
         torch.cuda.synchronize()
         g0 = time.perf_counter()
+        gmarks = []
         for _ in range(gsteps):
             st.set_entries(0, zero, one)
             g.launch()
+            gmarks.append(time.perf_counter())
         torch.cuda.synchronize()
         g1 = time.perf_counter()
+        gstep_ms = np.diff(np.array([g0] + gmarks)) * 1e3
         gent = (st.stats()["entries_updated"] - s0) / gsteps
         assert gent == entries_per_step, (gent, entries_per_step)
         assert st.nnz() == nnz_final
         graph = {"steps": gsteps, "ms_per_step": 1e3 * (g1 - g0) / gsteps,
-                 "value": gent * gsteps / (g1 - g0)}
+                 "value": gent * gsteps / (g1 - g0),
+                 "step_ms": {"median": float(np.median(gstep_ms)), "max": float(np.max(gstep_ms))}}
         g.close()
     kernels = {}
     for name, r in tr.items():
@@ -1028,6 +1037,10 @@ def main():
         "hbm_gbps": achieved,
         "gpu_kernel_ms_per_step": gpu_kernel_ms,
         "traced_ms_per_step": 1e3 * (r1 - r0) / args.steps,
+        # host clock after every timed step (each ends with the planner's
+        # waits): a single slow step shows up here as a max far above the median
+        "timed_step_ms": {"median": float(np.median(step_ms)), "max": float(np.max(step_ms)),
+                          "min": float(np.min(step_ms))},
         "host_syncs_per_step": syncs,
         "kernels": kernels,
         "graph_replay": graph,
