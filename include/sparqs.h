@@ -390,8 +390,9 @@ int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
  * fixed placement, so after a wasted speculative launch the next 64
  * eligible launches of the same mode (group or expand) skip themselves, and
  * after a read-back that sees it the next 64 eligible ops of that mode do not
- * speculate, twice as many each time this repeats), "spec_items" (1|2|4, default 4: entries per thread of the
- * speculative launch), "pair_exchange" (how a speculative group-mode launch
+ * speculate, twice as many each time this repeats), "spec_items" (1|2|4|8, default 4: entries per thread of the
+ * speculative launch; 8 applies to group-mode launches with a fused run and
+ * lane-pair partners, the others then take 4), "pair_exchange" (how a speculative group-mode launch
  * finds partners: 2, default, only at e ^ 1 through a lane-pair exchange, a
  * tile without that alignment defeating the speculation; 1 the same with
  * staging as fallback; 0 always by staging the tile's neighbours in LDS;

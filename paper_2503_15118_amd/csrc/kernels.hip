@@ -1304,8 +1304,9 @@ __device__ __forceinline__ void pair_write(KeyPtrs<W>& out_keys, double2* __rest
 // Pass 0 takes the lower kept child of every item, pass 1 the upper child of
 // items that keep both (in group mode: an entry without its partner whose
 // matrix mixes); a wave runs pass 1 only when one of its lanes has such a
-// child.
-template <int W, int ITEMS>
+// child.  ONE: no item keeps both children (group mode with every partner in
+// the neighbouring lane), so there is no pass 1.
+template <int W, int ITEMS, bool ONE = false>
 __device__ __forceinline__ void run_children(const GroupOp& op, const uint64_t (&key)[ITEMS][W],
                                              const double2 (&out)[ITEMS][2], const uint32_t (&keepm)[ITEMS],
                                              const uint64_t (&pos)[ITEMS], const FastOp* __restrict__ rops,
@@ -1341,8 +1342,8 @@ __device__ __forceinline__ void run_children(const GroupOp& op, const uint64_t (
   bool has0[ITEMS], has1[ITEMS];
   (void)load(0, h0, a0, has0);
   run_ops<W, ITEMS, true>(h0, a0, rops, rn, rgops);
-  const bool two = __ballot(load(1, h1, a1, has1)) != 0ull;
-  if (two) run_ops<W, ITEMS, true>(h1, a1, rops, rn, rgops);
+  const bool two = !ONE && __ballot(load(1, h1, a1, has1)) != 0ull;
+  if (!ONE && two) run_ops<W, ITEMS, true>(h1, a1, rops, rn, rgops);
   // Both children of an item are written together: at an even position the
   // key words of the pair go out as one 16-byte store per word, so a wave's
   // stores cover whole lines instead of every other word.
@@ -1393,7 +1394,7 @@ __device__ __forceinline__ void run_children(const GroupOp& op, const uint64_t (
 // follows the op is applied to the children before they are written, as in
 // the compacting launch (which, with RUN, then only counts its updates).
 template <int W, int MODE, int ITEMS, bool RUN, int NB>
-__global__ __launch_bounds__(kBlock) void k_pair_spec(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
+__global__ __launch_bounds__(kBlock, ITEMS >= 8 ? 4 : 1) void k_pair_spec(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                       KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
                                                       uint32_t ns, uint64_t cap, GroupOp op, uint32_t f,
                                                       DevMeta* meta, uint32_t epoch, const FastOp* __restrict__ rops,
@@ -1442,9 +1443,11 @@ __global__ __launch_bounds__(kBlock) void k_pair_spec(KeyPtrs<W> in_keys, const 
     orv[w] = 0;
     andv[w] = ~0ull;
   }
+  // group mode with lane-pair partners (NB = 2): every entry keeps only its
+  // own child
   if constexpr (RUN)
-    run_children<W, ITEMS>(op, key, out, keepm, pos, rops, rn, rgops, out_keys, out_amp, cap,
-                                 orv, andv);
+    run_children<W, ITEMS, MODE == MODE_GROUP && NB == 2>(op, key, out, keepm, pos, rops, rn, rgops, out_keys,
+                                                           out_amp, cap, orv, andv);
   else
     pair_write<W, ITEMS>(out_keys, out_amp, cap, op, key, out, keepm, pos, orv, andv);
   publish_masks<W>(meta, epoch, orv, andv, s_red);

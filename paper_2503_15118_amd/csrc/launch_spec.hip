@@ -45,6 +45,23 @@ void launch_spec(const LaunchCtx& c, int mode, int items, int nb, const GroupOp&
   switch (items) {
     case 1: spec_wi<W, 1>(c, mode, nb, g, ep_spec, run); break;
     case 4: spec_wi<W, 4>(c, mode, nb, g, ep_spec, run); break;
+    case 8:
+      // 8 entries per thread only where a run is fused and partners sit in
+      // neighbouring lanes (one pass over the children): the interpreter's
+      // dispatch is then shared by twice the entries
+      if constexpr (W <= 2) {
+        if (mode == MODE_GROUP && nb == 2 && run.n) {
+          constexpr uint32_t T = kBlock * 8;
+          const uint32_t ntiles = (uint32_t)std::max<uint64_t>(1, (c.n_ub + T - 1) / T);
+          KeyPtrs<W> ik, ok;
+          for (int w = 0; w < W; ++w) { ik.w[w] = c.in.key[w]; ok.w[w] = c.out.key[w]; }
+          k_pair_spec<W, MODE_GROUP, 8, true, 2><<<ntiles, kBlock, 0, c.stream>>>(
+              ik, c.in.amp, ok, c.out.amp, c.ns, c.cap, g, 1u, c.meta, ep_spec, run.ops, run.n, run.gops);
+          break;
+        }
+      }
+      spec_wi<W, 4>(c, mode, nb, g, ep_spec, run);
+      break;
     default: spec_wi<W, 2>(c, mode, nb, g, ep_spec, run); break;
   }
 }

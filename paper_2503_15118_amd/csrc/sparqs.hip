@@ -3421,7 +3421,7 @@ int ss_set_option(ss_state* st, const char* key, int64_t value) {
   } else if (k == "expand_slots") {
     st->expand_slots = value ? 1 : 0;
   } else if (k == "spec_items") {
-    if (value != 1 && value != 2 && value != 4) return SS_E_ARG;
+    if (value != 1 && value != 2 && value != 4 && value != 8) return SS_E_ARG;
     st->spec_items = (uint32_t)value;
   } else if (k == "speculate_group") {
     if (value < 0) return SS_E_ARG;

@@ -31,7 +31,7 @@ SPACE: Dict[str, tuple] = {
     "perm_entries": (4, 8, 16),
     "group_items": (1, 2, 4),
     "pair_exchange": (0, 1, 2),
-    "spec_items": (1, 2, 4),
+    "spec_items": (1, 2, 4, 8),
     "sort_items": (8, 16),
 }
 DEFAULTS: Dict[str, int] = {"perm_entries": 8, "group_items": 4, "pair_exchange": 2, "spec_items": 4,

@@ -230,7 +230,8 @@ def test_speculative_placement_is_exact(abi, seed):
         outs = []
         # 1: speculate at any size (expansions; grouped entries too, with each
         # way of finding partners and tile size)
-        for opts in ({"speculate": 1, "speculate_group": 1, "pair_exchange": 2, "spec_items": 4},
+        for opts in ({"speculate": 1, "speculate_group": 1, "pair_exchange": 2, "spec_items": 8},
+                     {"speculate": 1, "speculate_group": 1, "pair_exchange": 2, "spec_items": 4},
                      {"speculate": 1, "speculate_group": 1, "pair_exchange": 1, "spec_items": 2},
                      {"speculate": 1, "speculate_group": 1, "pair_exchange": 0, "spec_items": 1},
                      {"speculate": 1, "speculate_group": 0}, {"speculate": 0, "speculate_group": 0}):
