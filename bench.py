@@ -15,6 +15,8 @@ stream during the timed steps.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
 import argparse
+import contextlib
+import gc
 import json
 import os
 import sys
@@ -25,6 +27,22 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published peak
 
+
+
+@contextlib.contextmanager
+def no_gc():
+    """Run a timed region without Python's cyclic garbage collector, as timeit
+    does: a full collection of this process's heap (torch and numpy loaded,
+    some 10^5 objects) takes tens of milliseconds on the host and would land
+    in whichever timed step crosses its allocation threshold."""
+    gc.collect()
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
 
 def counter_traffic(kernel_label):
     """HBM bytes per launch of `kernel_label` from the committed rocprofv3
@@ -273,6 +291,7 @@ def bench_batched(args, emit=True):
     peak_sum = 0
     plain_ops = [_abi.to_ss_ops(c.ops) for c in circ]
     st.apply(plain_ops[0])  # warm-up
+    gc.collect()
     for c, o in zip(circ, plain_ops):
         st.set_entries(0, zero, one)
         e0 = st.stats()["entries_updated"]
@@ -289,11 +308,12 @@ def bench_batched(args, emit=True):
     bs = batch.batch_state(circ, cap_entries=cap, table_bytes=0)
     set_opts(bs, args.opt)
     s0 = bs.stats()
-    torch.cuda.synchronize()
-    tb = time.perf_counter()
-    res = bs.apply(ops, inst_offsets=off)
-    torch.cuda.synchronize()
-    bat_s = time.perf_counter() - tb
+    with no_gc():
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        res = bs.apply(ops, inst_offsets=off)
+        torch.cuda.synchronize()
+        bat_s = time.perf_counter() - tb
     stats = {k: v - s0[k] for k, v in bs.stats().items()}
     nnz_b = bs.nnz()
     # the same batch replayed from a captured HIP graph (captured once from
@@ -305,11 +325,12 @@ def bench_batched(args, emit=True):
         g = bs.capture(ops, inst_offsets=off)
         for i in range(len(circ)):
             bs.set_entries(i, zero, one)
-        torch.cuda.synchronize()
-        tg = time.perf_counter()
-        g.launch()
-        torch.cuda.synchronize()
-        graph_s = time.perf_counter() - tg
+        with no_gc():
+            torch.cuda.synchronize()
+            tg = time.perf_counter()
+            g.launch()
+            torch.cuda.synchronize()
+            graph_s = time.perf_counter() - tg
         assert bs.nnz() == nnz_b
         g.close()
         graph = {"batched_graph_s": graph_s, "batched_graph_vs_plain": seq_s / graph_s,
@@ -900,16 +921,17 @@ def main():
 
     # the timed region: K steps as a user runs them (no per-launch events)
     sy0 = st.stats()["host_syncs"]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    marks = []
-    for _ in range(args.steps):
-        step()
-        # a step ends with the planner's own waits for the device, so the
-        # host clock after it is close to the device's (a diagnostic only)
-        marks.append(time.perf_counter())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with no_gc():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        marks = []
+        for _ in range(args.steps):
+            step()
+            # a step ends with the planner's own waits for the device, so the
+            # host clock after it is close to the device's (a diagnostic only)
+            marks.append(time.perf_counter())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     syncs = (st.stats()["host_syncs"] - sy0) / args.steps
     step_ms = np.diff(np.array([t0] + marks)) * 1e3
 
@@ -918,12 +940,13 @@ def main():
     # device time between launches, so `value` is not taken from this pass)
     st.set_option("trace", 1)
     st.set_option("trace_reset", 1)
-    torch.cuda.synchronize()
-    r0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    r1 = time.perf_counter()
+    with no_gc():
+        torch.cuda.synchronize()
+        r0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        r1 = time.perf_counter()
     tr = st.trace()
     st.set_option("trace", 0)
 
@@ -942,14 +965,15 @@ def main():
             g.launch()
         s0 = st.stats()["entries_updated"]
         torch.cuda.synchronize()
-        g0 = time.perf_counter()
-        gmarks = []
-        for _ in range(gsteps):
-            st.set_entries(0, zero, one)
-            g.launch()
-            gmarks.append(time.perf_counter())
-        torch.cuda.synchronize()
-        g1 = time.perf_counter()
+        with no_gc():
+            g0 = time.perf_counter()
+            gmarks = []
+            for _ in range(gsteps):
+                st.set_entries(0, zero, one)
+                g.launch()
+                gmarks.append(time.perf_counter())
+            torch.cuda.synchronize()
+            g1 = time.perf_counter()
         gstep_ms = np.diff(np.array([g0] + gmarks)) * 1e3
         gent = (st.stats()["entries_updated"] - s0) / gsteps
         assert gent == entries_per_step, (gent, entries_per_step)
