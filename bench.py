@@ -128,7 +128,7 @@ def summarize_profile(pdir):
     for label in ("k_perm_fast<2, 8, false>", "k_perm_fast<2, 4, false>", "k_perm_fast<2, 16, false>",
                   "k_pair<2, 0, 4, false>", "k_pair<2, 1, 4, false>", "k_pair<2, 1, 4, true>",
                   "k_pair<2, 0, 2, false>", "k_pair<2, 1, 2, false>", "k_expand_slots<2, 5, 4>") + tuple(
-                      "k_pair_spec<2, 0, %d, %s, %d>" % (i, r, x) for i in (1, 2, 4) for r in ("false", "true")
+                      "k_pair_spec<2, 0, %d, %s, %d>" % (i, r, x) for i in (1, 2, 4, 8) for r in ("false", "true")
                       for x in (0, 1, 2)):
         pk = "void sparqs::" + label
         if pk not in fe or pk not in wr:
@@ -801,7 +801,7 @@ def main():
     ap.add_argument("--group-items", type=int, default=4)
     ap.add_argument("--sort-items", type=int, default=16)
     ap.add_argument("--perm-entries", type=int, default=8)
-    ap.add_argument("--spec-items", type=int, default=4)
+    ap.add_argument("--spec-items", type=int, default=8)
     ap.add_argument("--pair-exchange", type=int, default=2)
     ap.add_argument("--tile-order", type=int, default=1)
     ap.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
