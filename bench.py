@@ -44,11 +44,36 @@ def no_gc():
         if was:
             gc.enable()
 
+
+def sources_sha():
+    """Short hash of the kernel sources the committed counter summaries name."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2503_15118_amd", "csrc")
+    return hashlib.sha256(open(os.path.join(src, "kernels.hip"), "rb").read()
+                          + open(os.path.join(src, "kernels_common.hpp"), "rb").read()
+                          + open(os.path.join(src, "sparqs_internal.h"), "rb").read()).hexdigest()[:16]
+
+
+def counter_valu_busy(kernel_label):
+    """Duration-weighted vector-pipe busy fraction of `kernel_label` from the
+    committed SQ counter summary, or None when the kernel sources changed
+    since the counters were taken or the summary is of another kernel."""
+    path = os.path.join(ROOT, "profiles", "c2_perm_sq_counters.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if f"kernel sources sha256[:16] = {sources_sha()}" not in text or f"dispatch of {kernel_label};" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("# over all rows: valu_busy (duration-weighted) = "):
+            return float(line.rsplit("=", 1)[1])
+    return None
+
+
 def counter_traffic(kernel_label):
     """HBM bytes per launch of `kernel_label` from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy of known size),
     or None when the kernel sources changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "c2_hbm_counters.txt")
     if not os.path.exists(path) or kernel_label is None:
         return None
@@ -57,10 +82,7 @@ def counter_traffic(kernel_label):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2503_15118_amd", "csrc")
-    sha = hashlib.sha256(open(os.path.join(src, "kernels.hip"), "rb").read()
-                         + open(os.path.join(src, "kernels_common.hpp"), "rb").read()
-                         + open(os.path.join(src, "sparqs_internal.h"), "rb").read()).hexdigest()[:16]
+    sha = sources_sha()
     if kv.get("sources_sha") != sha or ("traffic " + kernel_label) not in kv:
         return None
     return float(kv["traffic " + kernel_label])
@@ -73,11 +95,7 @@ def summarize_profile(pdir):
     --pmc counter each)."""
     import collections
     import csv
-    import hashlib
-    src = os.path.join(ROOT, "paper_2503_15118_amd", "csrc")
-    sha = hashlib.sha256(open(os.path.join(src, "kernels.hip"), "rb").read()
-                         + open(os.path.join(src, "kernels_common.hpp"), "rb").read()
-                         + open(os.path.join(src, "sparqs_internal.h"), "rb").read()).hexdigest()[:16]
+    sha = sources_sha()
     # the C2 part of the default run (the other sections launch the same
     # kernels at other sizes, which would mix into the averages)
     base = "python3 bench.py --no-cpu-baseline --calibrate-copy --sections ''"
@@ -1007,6 +1025,7 @@ def main():
              "group": group_label,
              "expand": "k_pair<2, 1, %d, false>" % args.group_items}.get(dom)
     traffic = counter_traffic(label)
+    valu_busy = counter_valu_busy(label)
     gpu_kernel_ms = sum(k["ms_per_step"] for k in kernels.values())
 
     out = {
@@ -1048,6 +1067,12 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            # the other side of the bound: the fraction of time the vector
+            # pipe issues (SQ counters of the same kernel), well below 1 too:
+            # the launch is limited by instruction issue (the op interpreter's
+            # scalar dispatch) as much as by bytes
+            "valu_busy": valu_busy,
+            "issue_bound": True,
             "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
             "timing": "HIP event pair around every launch of the kernel on the state's stream, over a second "
                       "pass of the same steps right after the timed one",
