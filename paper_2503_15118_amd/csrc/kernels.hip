@@ -1735,15 +1735,97 @@ __global__ __launch_bounds__(kBlock) void k_perm_batched(KeyPtrs<W> keys, double
   publish_masks<W>(meta, epoch, orv, andv, s_red);
 }
 
-constexpr int kOpStage = 16;   // op records of one tile's instances staged in LDS
+// The op record of an instance in a batched round, read through pointer type
+// P: a constant address space pointer when every entry of the wave's row
+// belongs to one instance (each field one scalar load, held in scalar
+// registers), else a plain global pointer (per-lane loads).
+typedef const __attribute__((address_space(4))) BatchOp ConstBatchOp;
+
+// Children of one parent: the target bits' current values (bits) and the
+// number of children reached through nonzero elements (product over the
+// targets of the nonzero entries in column b_j); a parent whose controls fail,
+// or whose instance has no branching op this round, is copied (copy, 1 child).
+template <int W, class P>
+__device__ __forceinline__ uint32_t expand_count(P op, const uint64_t (&key)[W], uint32_t& bits, bool& copy) {
+  const uint32_t k = op->k;
+  bool ctl = true;
+  if (op->has_ctl) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) ctl = ctl && ((key[w] & op->cmask[w]) == op->cval[w]);
+  }
+  copy = k == 0 || !ctl;
+  bits = 0;
+  if (copy) return 1u;
+  const bool cplx = op->cplx != 0u;
+  uint32_t cnt = 1;
+  for (uint32_t j = 0; j < k; ++j) {
+    const uint32_t bj = (uint32_t)((sel_word<W>(key, op->tword[j]) >> op->tbit[j]) & 1ull);
+    bits |= bj << j;
+    const bool c0 = (bj ? op->m[0][1] : op->m[0][0]) != 0.0 || (cplx && (bj ? op->mi[0][1] : op->mi[0][0]) != 0.0);
+    const bool c1 = (bj ? op->m[1][1] : op->m[1][0]) != 0.0 || (cplx && (bj ? op->mi[1][1] : op->mi[1][0]) != 0.0);
+    cnt *= (uint32_t)c0 + (uint32_t)c1;
+  }
+  return cnt;
+}
+
+// Child r of one parent (the r-th of its existing children in ascending order
+// of the target bits' new values s, lowest target least significant): a
+// target whose column has two nonzero elements takes the next bit of r, one
+// with a single nonzero element its row; the amplitude is multiplied by the
+// elements stage by stage in ascending target order.  A copied parent is its
+// own only child.
+template <int W, class P>
+__device__ __forceinline__ void expand_child(P op, const uint64_t (&key)[W], double2 a, uint32_t bits, bool copy,
+                                             uint32_t r, uint64_t (&ok)[W], double2& v) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) ok[w] = key[w];
+  v = a;
+  if (copy) return;
+  const uint32_t k = op->k;
+  const bool cplx = op->cplx != 0u;
+  for (uint32_t j = 0; j < k; ++j) {
+    const uint32_t bj = (bits >> j) & 1u;
+    const double c0 = bj ? op->m[0][1] : op->m[0][0];
+    const double c1 = bj ? op->m[1][1] : op->m[1][0];
+    const double i0 = cplx ? (bj ? op->mi[0][1] : op->mi[0][0]) : 0.0;
+    const double i1 = cplx ? (bj ? op->mi[1][1] : op->mi[1][0]) : 0.0;
+    const bool nz0 = c0 != 0.0 || i0 != 0.0;
+    const bool nz1 = c1 != 0.0 || i1 != 0.0;
+    uint32_t sj;
+    if (nz0 && nz1) {
+      sj = r & 1u;
+      r >>= 1;
+    } else {
+      sj = nz1 ? 1u : 0u;
+    }
+    const double c = sj ? c1 : c0;
+    if (cplx) {
+      v = cmul(v, c, sj ? i1 : i0);
+    } else {
+      v.x = c * v.x;
+      v.y = c * v.y;
+    }
+    const uint64_t bit = 1ull << op->tbit[j];
+    const uint32_t tw = op->tword[j];
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+      if ((uint32_t)w == tw) ok[w] = sj ? (ok[w] | bit) : (ok[w] & ~bit);
+  }
+}
+
+__device__ __forceinline__ uint32_t lane_read(uint32_t lane, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(lane << 2), (int)v);
+}
+__device__ __forceinline__ uint64_t lane_read64(uint32_t lane, uint64_t v) {
+  return (uint64_t)lane_read(lane, (uint32_t)v) | ((uint64_t)lane_read(lane, (uint32_t)(v >> 32)) << 32);
+}
 
 // Branch expansion: every parent emits the children of its instance's op
-// (target bits set to s, amplitude multiplied by the matrix elements stage by
-// stage in ascending qubit order), skipping children reached through an exact
-// 0.0 element; where the controls fail, or the instance has no branching op
-// this round, the parent is copied.  Output offsets come from a look-back
-// prefix of the per-parent child counts.  ITEMS parents per thread, all loads
-// of the tile issued before any is used.
+// (expand_count / expand_child).  Output offsets come from a look-back prefix
+// of the per-parent child counts.  ITEMS parents per thread, all loads of the
+// tile issued before any is used.  Entries are ordered by instance, so almost
+// every row of 64 entries belongs to one instance, whose record the row then
+// reads with scalar loads.
 template <int W, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, const double2* __restrict__ in_amp,
                                                            KeyPtrs<W> out_keys, double2* __restrict__ out_amp,
@@ -1756,8 +1838,6 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
   __shared__ uint64_t s_lb[12];
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   __shared__ uint32_t s_tile;
-  __shared__ uint32_t s_irange[2];
-  __shared__ BatchOp s_bop[kOpStage];
   uint64_t n, vb;
   if (!emit_begin_view(meta, ns, epoch, TILE, &n, &vb, xo)) return;
   offset_keys<W>(in_keys, vb);
@@ -1769,6 +1849,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
   const uint64_t ntiles = (n + TILE - 1) / TILE;
   if (tile_out_of_range(tile, ntiles, &meta->err, xo)) return;
   const uint64_t e0 = (uint64_t)tile * TILE;
+  ConstBatchOp* const cbops = (ConstBatchOp*)bops;
   uint64_t key[ITEMS][W];
   double2 a[ITEMS];
 #pragma unroll
@@ -1783,59 +1864,22 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
       a[it] = in_amp[e];
     }
   }
-  uint32_t k[ITEMS], b[ITEMS], cnt[ITEMS], inst[ITEMS];
+  uint32_t bits[ITEMS], cnt[ITEMS], inst[ITEMS];
   bool copy[ITEMS];
-  // Entries are ordered by instance, so a tile usually spans few instances:
-  // their op records are staged in LDS (the first and the last entry of the
-  // tile bound the range); an instance outside the staged range reads its
-  // record from global memory.
-  const uint64_t e_last = (e0 + TILE < n ? e0 + TILE : n) - 1;
-#pragma unroll
-  for (int it = 0; it < ITEMS; ++it) {
-    inst[it] = inst_of<W>(key[it], iword, ishift, imask);
-    const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
-    if (e == e0) s_irange[0] = inst[it];
-    if (e == e_last) s_irange[1] = inst[it];
-  }
-  __syncthreads();
-  const uint32_t i0 = s_irange[0], i1 = s_irange[1];
-  const bool staged = i1 >= i0 && i1 - i0 < (uint32_t)kOpStage;
-  if (staged) {
-    constexpr uint32_t Q = sizeof(BatchOp) / 16;
-    const uint4* src = reinterpret_cast<const uint4*>(bops + i0);
-    uint4* dst = reinterpret_cast<uint4*>(s_bop);
-    for (uint32_t q = threadIdx.x; q < (i1 - i0 + 1) * Q; q += kBlock) dst[q] = src[q];
-  }
-  __syncthreads();
-  auto op_of = [&](uint32_t i) -> const BatchOp& {
-    return (staged && i >= i0 && i <= i1) ? s_bop[i - i0] : bops[i];
-  };
+  uint32_t uni = 0;   // bit it: the row of item it holds one instance
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
-    k[it] = 0;
-    b[it] = 0;
+    inst[it] = e < n ? inst_of<W>(key[it], iword, ishift, imask) : 0u;
+    const uint32_t u = __builtin_amdgcn_readfirstlane(inst[it]);
+    const bool one = __ballot(e < n && inst[it] != u) == 0ull;
+    uni |= (one ? 1u : 0u) << it;
+    bits[it] = 0;
     cnt[it] = 0;
     copy[it] = true;
     if (e < n) {
-      const BatchOp& op = op_of(inst[it]);
-      k[it] = op.k;
-      copy[it] = k[it] == 0 || (op.has_ctl && !controls_hold<W>(key[it], op.cmask, op.cval));
-      if (copy[it]) {
-        cnt[it] = 1;
-      } else {
-        for (uint32_t j = 0; j < k[it]; ++j)
-          b[it] |= (uint32_t)((sel_word<W>(key[it], op.tword[j]) >> op.tbit[j]) & 1ull) << j;
-        // children reachable through nonzero elements: product over stages of
-        // the number of nonzero entries in column b_j
-        cnt[it] = 1;
-        for (uint32_t j = 0; j < k[it]; ++j) {
-          const uint32_t bj = (b[it] >> j) & 1u;
-          const bool c0 = (bj ? op.m[0][1] : op.m[0][0]) != 0.0 || (op.cplx && (bj ? op.mi[0][1] : op.mi[0][0]) != 0.0);
-          const bool c1 = (bj ? op.m[1][1] : op.m[1][0]) != 0.0 || (op.cplx && (bj ? op.mi[1][1] : op.mi[1][0]) != 0.0);
-          cnt[it] *= (uint32_t)c0 + (uint32_t)c1;
-        }
-      }
+      if (one) cnt[it] = expand_count<W>(cbops + u, key[it], bits[it], copy[it]);
+      else cnt[it] = expand_count<W>(bops + inst[it], key[it], bits[it], copy[it]);
     }
   }
   uint32_t off[ITEMS];
@@ -1858,50 +1902,55 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
     orv[w] = 0;
     andv[w] = ~0ull;
   }
+  // The children of one row of 64 parents fill a contiguous output range,
+  // which the row writes 64 slots at a time, lane l slot t = base + l: its
+  // parent is the last lane whose first child is at or before t (a binary
+  // search over the row's offsets, read across lanes with ds_bpermute), its
+  // child the (t - that offset)-th; consecutive lanes write consecutive
+  // outputs.  Every lane of the wave takes part in each step.
+  const uint32_t lane = lane_id();
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
-    const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
-    if (e >= n) continue;
-    uint64_t p = s_off + off[it];
-    const BatchOp& op = op_of(inst[it]);
-    const uint32_t nchild = copy[it] ? 1u : (1u << k[it]);
-    for (uint32_t sv = 0; sv < nchild; ++sv) {
-      uint64_t ok[W];
+    const uint32_t rb = __builtin_amdgcn_readfirstlane(off[it]);
+    const uint32_t rt = (uint32_t)__builtin_amdgcn_readlane((int)(off[it] + cnt[it]), 63) - rb;
+    const uint32_t x = off[it] - rb;
+    const uint32_t cf = copy[it] ? 1u : 0u;
+    const uint64_t p0 = s_off + rb;
+    const bool one = (uni >> it) & 1u;
+    const uint32_t u = __builtin_amdgcn_readfirstlane(inst[it]);
+    for (uint32_t base = 0; base < rt; base += 64) {
+      const uint32_t t = base + lane;
+      uint32_t j = 0;
 #pragma unroll
-      for (int w = 0; w < W; ++w) ok[w] = key[it][w];
-      double2 v = a[it];
-      bool exists = true;
-      if (!copy[it]) {
-        for (uint32_t j = 0; j < k[it]; ++j) {
-          const uint32_t sj = (sv >> j) & 1u, bj = (b[it] >> j) & 1u;
-          const double c = sj ? (bj ? op.m[1][1] : op.m[1][0]) : (bj ? op.m[0][1] : op.m[0][0]);
-          if (op.cplx) {
-            const double ci = sj ? (bj ? op.mi[1][1] : op.mi[1][0]) : (bj ? op.mi[0][1] : op.mi[0][0]);
-            if (c == 0.0 && ci == 0.0) exists = false;
-            v = cmul(v, c, ci);
-          } else {
-            if (c == 0.0) exists = false;
-            v.x = c * v.x;
-            v.y = c * v.y;
-          }
-          const uint64_t bit = 1ull << op.tbit[j];
+      for (uint32_t step = 32; step; step >>= 1)
+        if (lane_read(j + step, x) <= t) j += step;
+      const uint32_t xj = lane_read(j, x);
+      uint64_t pk[W];
 #pragma unroll
-          for (int w = 0; w < W; ++w)
-            if ((uint32_t)w == op.tword[j]) ok[w] = sj ? (ok[w] | bit) : (ok[w] & ~bit);
+      for (int w = 0; w < W; ++w) pk[w] = lane_read64(j, key[it][w]);
+      double2 pa;
+      pa.x = __longlong_as_double((long long)lane_read64(j, (uint64_t)__double_as_longlong(a[it].x)));
+      pa.y = __longlong_as_double((long long)lane_read64(j, (uint64_t)__double_as_longlong(a[it].y)));
+      const uint32_t pb = lane_read(j, bits[it]);
+      const bool pc = lane_read(j, cf) != 0u;
+      const uint32_t pi = lane_read(j, inst[it]);
+      if (t < rt) {
+        uint64_t ok[W];
+        double2 v;
+        if (one) expand_child<W>(cbops + u, pk, pa, pb, pc, t - xj, ok, v);
+        else expand_child<W>(bops + pi, pk, pa, pb, pc, t - xj, ok, v);
+        const uint64_t q = p0 + t;
+        if (q < cap) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) out_keys.w[w][q] = ok[w];
+          out_amp[q] = v;
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          orv[w] |= ok[w];
+          andv[w] &= ok[w];
         }
       }
-      if (!exists) continue;
-      if (p < cap) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) out_keys.w[w][p] = ok[w];
-        out_amp[p] = v;
-      }
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        orv[w] |= ok[w];
-        andv[w] &= ok[w];
-      }
-      ++p;
     }
   }
   publish_masks<W>(meta, epoch, orv, andv, s_red);
@@ -1968,6 +2017,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
   uint64_t key[ITEMS][W];
   double2 sum[ITEMS];
   uint32_t cnt[ITEMS];
+  ConstBatchOp* const cbops = (ConstBatchOp*)bops;
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const uint32_t l = 1 + it * kBlock + threadIdx.x;
@@ -1976,6 +2026,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
     cnt[it] = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) key[it][w] = s_key[w * S + l];
+    // the row's one instance (scalar loads of its record), if it has one
+    const uint32_t inst = inst_of<W>(key[it], iword, ishift, imask);
+    const uint32_t u = __builtin_amdgcn_readfirstlane(inst);
+    const bool one = __ballot(e < n && inst != u) == 0ull;
     if (e < n) {
       bool head = true;
       if (e > 0) {
@@ -1996,8 +2050,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
           acc.y = acc.y + x.y;
         }
         sum[it] = acc;
-        const BatchOp& op = bops[inst_of<W>(key[it], iword, ishift, imask)];
-        cnt[it] = (op.prune ? keep_amp(acc.x, acc.y, op.eps2) : true) ? 1u : 0u;
+        const bool prune = one ? cbops[u].prune != 0u : bops[inst].prune != 0u;
+        const double eps2 = one ? cbops[u].eps2 : bops[inst].eps2;
+        cnt[it] = (prune ? keep_amp(acc.x, acc.y, eps2) : true) ? 1u : 0u;
       }
     }
   }
