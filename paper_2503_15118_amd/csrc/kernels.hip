@@ -1961,7 +1961,10 @@ __global__ __launch_bounds__(kBlock) void k_expand_batched(KeyPtrs<W> in_keys, c
 // sums with |a|^2 < eps^2 or a == 0.  One output per run, compacted.  A run
 // has at most 2^5 members (one branching op of up to five targets per
 // instance and round), so the tile is staged in LDS with the entry before it
-// and the kRunHalo entries after it.
+// and the kRunHalo entries after it.  Runs are long after a many-target
+// expansion (most entries are not heads), so the heads are first compacted
+// in entry order and thread t sums the runs of heads t, t + kBlock, ...: the
+// summing loops run on busy lanes, and the kept sums go out consecutively.
 constexpr uint32_t kRunHalo = 64;
 
 template <int W, int ITEMS>
@@ -1972,6 +1975,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
                                                            uint64_t* lb, DevMeta* meta, uint32_t epoch, uint32_t xo) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   constexpr uint32_t S = TILE + 1 + kRunHalo;   // staged slots: [e0 - 1, e0 + TILE + kRunHalo)
+  static_assert(S < 65536, "slot indices are 16-bit");
   __shared__ uint32_t s_wtot[ITEMS][kBlock / 64];
   __shared__ uint64_t s_off;
   __shared__ uint64_t s_lb[12];
@@ -1979,6 +1983,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_key[W * S];
   __shared__ double2 s_amp[S];
+  __shared__ uint16_t s_head[TILE];   // slot of the tile's h-th run head
   uint64_t n, vb;
   if (!emit_begin_view(meta, ns, epoch, TILE, &n, &vb, xo)) return;
   offset_keys<W>(in_keys, vb);
@@ -2014,48 +2019,62 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
     }
   }
   __syncthreads();
-  uint64_t key[ITEMS][W];
-  double2 sum[ITEMS];
-  uint32_t cnt[ITEMS];
-  ConstBatchOp* const cbops = (ConstBatchOp*)bops;
+  // run heads of the tile's entries, numbered in entry order
+  uint32_t hf[ITEMS], hoff[ITEMS];
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const uint32_t l = 1 + it * kBlock + threadIdx.x;
     const uint64_t e = e0 + l - 1;
-    sum[it] = make_double2(0.0, 0.0);
-    cnt[it] = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) key[it][w] = s_key[w * S + l];
-    // the row's one instance (scalar loads of its record), if it has one
-    const uint32_t inst = inst_of<W>(key[it], iword, ishift, imask);
-    const uint32_t u = __builtin_amdgcn_readfirstlane(inst);
-    const bool one = __ballot(e < n && inst != u) == 0ull;
+    hf[it] = 0;
     if (e < n) {
-      bool head = true;
-      if (e > 0) {
-        bool eq = true;
+      bool eq = e > 0;
 #pragma unroll
-        for (int w = 0; w < W; ++w) eq = eq && s_key[w * S + l - 1] == key[it][w];
-        head = !eq;
-      }
-      if (head) {
-        double2 acc = s_amp[l];
-        for (uint32_t m = 1; m <= kRunHalo - 1 && e + m < n; ++m) {
-          bool eq = true;
-#pragma unroll
-          for (int w = 0; w < W; ++w) eq = eq && s_key[w * S + l + m] == key[it][w];
-          if (!eq) break;
-          const double2 x = s_amp[l + m];
-          acc.x = acc.x + x.x;
-          acc.y = acc.y + x.y;
-        }
-        sum[it] = acc;
-        const bool prune = one ? cbops[u].prune != 0u : bops[inst].prune != 0u;
-        const double eps2 = one ? cbops[u].eps2 : bops[inst].eps2;
-        cnt[it] = (prune ? keep_amp(acc.x, acc.y, eps2) : true) ? 1u : 0u;
-      }
+      for (int w = 0; w < W; ++w) eq = eq && s_key[w * S + l - 1] == s_key[w * S + l];
+      hf[it] = eq ? 0u : 1u;
     }
   }
+  const uint32_t nh = (uint32_t)tile_offsets<ITEMS>(hf, hoff, s_wtot);
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it)
+    if (hf[it]) s_head[hoff[it]] = (uint16_t)(1 + it * kBlock + threadIdx.x);
+  __syncthreads();
+  // thread t: heads t + j * kBlock
+  ConstBatchOp* const cbops = (ConstBatchOp*)bops;
+  uint64_t key[ITEMS][W];
+  double2 sum[ITEMS];
+  uint32_t cnt[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const uint32_t h = j * kBlock + threadIdx.x;
+    const bool act = h < nh;
+    const uint32_t l = act ? s_head[h] : 1u;
+    const uint64_t e = e0 + l - 1;
+#pragma unroll
+    for (int w = 0; w < W; ++w) key[j][w] = act ? s_key[w * S + l] : 0ull;
+    sum[j] = make_double2(0.0, 0.0);
+    cnt[j] = 0;
+    // the wave's one instance (scalar loads of its record), if it has one
+    const uint32_t inst = inst_of<W>(key[j], iword, ishift, imask);
+    const uint32_t u = __builtin_amdgcn_readfirstlane(inst);
+    const bool one = __ballot(act && inst != u) == 0ull;
+    if (act) {
+      double2 acc = s_amp[l];
+      for (uint32_t m = 1; m <= kRunHalo - 1 && e + m < n; ++m) {
+        bool eq = true;
+#pragma unroll
+        for (int w = 0; w < W; ++w) eq = eq && s_key[w * S + l + m] == key[j][w];
+        if (!eq) break;
+        const double2 x = s_amp[l + m];
+        acc.x = acc.x + x.x;
+        acc.y = acc.y + x.y;
+      }
+      sum[j] = acc;
+      const bool prune = one ? cbops[u].prune != 0u : bops[inst].prune != 0u;
+      const double eps2 = one ? cbops[u].eps2 : bops[inst].eps2;
+      cnt[j] = (prune ? keep_amp(acc.x, acc.y, eps2) : true) ? 1u : 0u;
+    }
+  }
+  // kept sums in head order (= entry order)
   uint32_t off[ITEMS];
   const uint64_t tile_total = tile_offsets<ITEMS>(cnt, off, s_wtot);
   {
@@ -2077,18 +2096,18 @@ __global__ __launch_bounds__(kBlock) void k_reduce_batched(KeyPtrs<W> in_keys, c
     andv[w] = ~0ull;
   }
 #pragma unroll
-  for (int it = 0; it < ITEMS; ++it) {
-    if (!cnt[it]) continue;
-    const uint64_t p = s_off + off[it];
+  for (int j = 0; j < ITEMS; ++j) {
+    if (!cnt[j]) continue;
+    const uint64_t p = s_off + off[j];
     if (p < cap) {
 #pragma unroll
-      for (int w = 0; w < W; ++w) out_keys.w[w][p] = key[it][w];
-      out_amp[p] = sum[it];
+      for (int w = 0; w < W; ++w) out_keys.w[w][p] = key[j][w];
+      out_amp[p] = sum[j];
     }
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      orv[w] |= key[it][w];
-      andv[w] &= key[it][w];
+      orv[w] |= key[j][w];
+      andv[w] &= key[j][w];
     }
   }
   publish_masks<W>(meta, epoch, orv, andv, s_red);
