@@ -1670,7 +1670,9 @@ __device__ __forceinline__ uint32_t inst_of(const uint64_t (&k)[W], uint32_t iwo
 
 // Each entry runs its own instance's run of non-branching ops.  A wave takes
 // the distinct instances among its lanes one at a time, so the op index stays
-// uniform and the interpreter's dispatch stays scalar.
+// uniform and the interpreter's dispatch stays scalar.  The grid is sized
+// from the host's bound on the count, which after a round's reduction can be
+// many times the count, so it is capped and strides over the entries.
 template <int W, bool AMP>
 __global__ __launch_bounds__(kBlock) void k_perm_batched(KeyPtrs<W> keys, double2* __restrict__ amp, uint32_t ns,
                                                          const FastOp* __restrict__ ops,
@@ -1685,53 +1687,64 @@ __global__ __launch_bounds__(kBlock) void k_perm_batched(KeyPtrs<W> keys, double
   const uint64_t n = meta->nring[ns & 1] - vb;
   offset_keys<W>(keys, vb);
   amp += vb;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && (uint64_t)gridDim.x * kBlock < n) raise_error(meta, kErrGrid, epoch);
   if ((uint64_t)blockIdx.x * kBlock >= n) return;
-  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = i < n;
-  uint32_t h[1][4] = {{0u, 0u, 0u, 0u}};
-  double2 a[1] = {make_double2(0.0, 0.0)};
-  uint64_t k[W];
-#pragma unroll
-  for (int w = 0; w < W; ++w) k[w] = valid ? keys.w[w][i] : 0ull;
-  const uint32_t inst = valid ? inst_of<W>(k, iword, ishift, imask) : 0u;
-  const RunRange rr = valid ? runs[inst] : RunRange{0u, 0u};
-  if (W <= 2) {
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      h[0][2 * w] = (uint32_t)k[w];
-      h[0][2 * w + 1] = (uint32_t)(k[w] >> 32);
-    }
-  }
-  if (AMP && valid) a[0] = amp[i];
-  uint64_t pending = __ballot(valid && rr.len > 0);
-  while (pending) {
-    const uint32_t lead = (uint32_t)__builtin_ctzll(pending);
-    const uint32_t u = __builtin_amdgcn_readfirstlane(__shfl(inst, (int)lead, 64));
-    const bool mine = valid && rr.len > 0 && inst == u;
-    pending &= ~__ballot(mine);
-    if (mine) {
-      const uint32_t start = __builtin_amdgcn_readfirstlane(rr.start);
-      const uint32_t len = __builtin_amdgcn_readfirstlane(rr.len);
-      for (uint32_t o = start; o < start + len; ++o) {
-        const FastOp rec = load_rec(ops + o);
-        if (W <= 2) fast_step<W, 1, AMP>(h, a, rec, gops);
-        else perm_apply<W>(k, a[0], gops[rec.e]);
-      }
-    }
-  }
-  if (W <= 2) {
-#pragma unroll
-    for (int w = 0; w < W; ++w) k[w] = (uint64_t)h[0][2 * w] | ((uint64_t)h[0][2 * w + 1] << 32);
-  }
   uint64_t orv[W], andv[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    orv[w] = valid ? k[w] : 0ull;
-    andv[w] = valid ? k[w] : ~0ull;
-    if (valid && (write_words & (1u << w))) keys.w[w][i] = k[w];
+    orv[w] = 0ull;
+    andv[w] = ~0ull;
   }
-  if (AMP && valid) amp[i] = a[0];
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  // (the loop condition is uniform over the workgroup, which publishes its
+  // masks once at the end)
+  for (uint64_t i0 = (uint64_t)blockIdx.x * kBlock; i0 < n; i0 += stride) {
+    const uint64_t i = i0 + threadIdx.x;
+    const bool valid = i < n;
+    uint32_t h[1][4] = {{0u, 0u, 0u, 0u}};
+    double2 a[1] = {make_double2(0.0, 0.0)};
+    uint64_t k[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) k[w] = valid ? keys.w[w][i] : 0ull;
+    const uint32_t inst = valid ? inst_of<W>(k, iword, ishift, imask) : 0u;
+    const RunRange rr = valid ? runs[inst] : RunRange{0u, 0u};
+    if (W <= 2) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        h[0][2 * w] = (uint32_t)k[w];
+        h[0][2 * w + 1] = (uint32_t)(k[w] >> 32);
+      }
+    }
+    if (AMP && valid) a[0] = amp[i];
+    uint64_t pending = __ballot(valid && rr.len > 0);
+    while (pending) {
+      const uint32_t lead = (uint32_t)__builtin_ctzll(pending);
+      const uint32_t u = __builtin_amdgcn_readfirstlane(__shfl(inst, (int)lead, 64));
+      const bool mine = valid && rr.len > 0 && inst == u;
+      pending &= ~__ballot(mine);
+      if (mine) {
+        const uint32_t start = __builtin_amdgcn_readfirstlane(rr.start);
+        const uint32_t len = __builtin_amdgcn_readfirstlane(rr.len);
+        for (uint32_t o = start; o < start + len; ++o) {
+          const FastOp rec = load_rec(ops + o);
+          if (W <= 2) fast_step<W, 1, AMP>(h, a, rec, gops);
+          else perm_apply<W>(k, a[0], gops[rec.e]);
+        }
+      }
+    }
+    if (W <= 2) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) k[w] = (uint64_t)h[0][2 * w] | ((uint64_t)h[0][2 * w + 1] << 32);
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      if (valid) {
+        orv[w] |= k[w];
+        andv[w] &= k[w];
+      }
+      if (valid && (write_words & (1u << w))) keys.w[w][i] = k[w];
+    }
+    if (AMP && valid) amp[i] = a[0];
+  }
   publish_masks<W>(meta, epoch, orv, andv, s_red);
 }
 

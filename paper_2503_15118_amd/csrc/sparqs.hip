@@ -1688,11 +1688,16 @@ int pack_entries(ss_state* st, const uint64_t* values, const double* amps, uint6
 // ---------------------------------------------------------------------------
 // Batched rounds (per-instance op lists)
 // ---------------------------------------------------------------------------
+constexpr int kBatchItems = 4;           // entries per thread in the batched expand / reduce kernels
+constexpr uint64_t kBatchGridCap = 4096; // workgroups of the batched perm launch (it strides)
 template <int W>
 void launch_perm_batched_w(ss_state* st, const FastOp* f, const PermOp* g, const RunRange* runs, uint32_t ww,
                            bool amp, uint32_t ep) {
   const Buf& b = st->buf[st->cur];
-  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, (st->n_ub + kBlock - 1) / kBlock);
+  // the bound can be many times the count (it is the last expansion's count
+  // after a reduction), so the grid is capped and the kernel strides
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((st->n_ub + kBlock - 1) / kBlock,
+                                                                         kBatchGridCap));
   if (amp)
     k_perm_batched<W, true><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->nslot, f, g, runs, st->L.iword,
                                                              st->L.ishift, st->L.imask, ww, st->meta, ep);
@@ -1700,8 +1705,6 @@ void launch_perm_batched_w(ss_state* st, const FastOp* f, const PermOp* g, const
     k_perm_batched<W, false><<<grid, kBlock, 0, st->stream>>>(kp<W>(b), b.amp, st->nslot, f, g, runs, st->L.iword,
                                                               st->L.ishift, st->L.imask, ww, st->meta, ep);
 }
-
-constexpr int kBatchItems = 4;   // entries per thread in the batched expand / reduce kernels
 
 template <int W>
 void launch_expand_batched_w(ss_state* st, const BatchOp* bops, uint32_t ep) {
