@@ -158,7 +158,54 @@ def summarize_profile(pdir):
         f.write("\n".join(lines) + "\n")
     sq = summarize_sq(pdir, base, sha) if os.path.isdir(os.path.join(pdir, "sq")) else []
     sm = summarize_sort_merge(pdir, sha) if os.path.isdir(os.path.join(pdir, "sm")) else []
-    print("\n".join(out + lines + sq + sm))
+    c3 = summarize_batched(pdir, sha) if os.path.isdir(os.path.join(pdir, "c3trace")) else []
+    print("\n".join(out + lines + sq + sm + c3))
+
+
+def summarize_batched(pdir, sha):
+    """profiles/c3_batched_kernel_stats.txt: kernel statistics and HBM traffic
+    of the batched run of the 1024-instance workload (<pdir>/c3trace:
+    --kernel-trace --stats; <pdir>/c3fetch, <pdir>/c3write: one --pmc counter
+    each, scaled by the 64 MiB calibration copy of the same run)."""
+    import collections
+    import csv
+    run = ("python3 bench.py --workload c3 --no-plain --no-cpu-baseline --calibrate-copy --graph-steps 0")
+    stats = {}
+    for r in csv.DictReader(open(os.path.join(pdir, "c3trace", "c3_kernel_stats.csv"))):
+        stats[r["Name"].split("(")[0].replace("void ", "")] = r
+
+    def agg(path):
+        a = collections.defaultdict(float)
+        mx = collections.defaultdict(float)
+        for r in csv.DictReader(open(path)):
+            k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            a[k] += float(r["Counter_Value"])
+            mx[k] = max(mx[k], float(r["Counter_Value"]))
+        return a, mx
+    fe, fmx = agg(os.path.join(pdir, "c3fetch", "c3_counter_collection.csv"))
+    wr, wmx = agg(os.path.join(pdir, "c3write", "c3_counter_collection.csv"))
+    fs, ws = 65536.0 / fmx["__amd_rocclr_copyBuffer"], 65536.0 / wmx["__amd_rocclr_copyBuffer"]
+    lines = ["# rocprofv3 kernel statistics and HBM traffic: batching workload (1024 C1-form instances, 30-bit "
+             "key with the instance field, caps 2^6..2^18, 200..1000 ops), batched run only: the timed apply "
+             "and the traced apply (kernel table) of the same op lists",
+             "# commands (from /tmp, TMPDIR=/tmp):",
+             f"#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/c3trace -o c3 -- {run}",
+             f"#   timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/c3fetch -o c3 -- {run}",
+             f"#   timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/c3write -o c3 -- {run}",
+             "# summarised by: python3 bench.py --summarize-profile <dir>",
+             f"# kernel sources sha256[:16] = {sha}",
+             f"# HBM bytes = FETCH_SIZE x {fs:.3f} + WRITE_SIZE x {ws:.3f} (KiB; scales from the 64 MiB copy of "
+             "the same run), summed over the kernel's dispatches",
+             f'{"kernel":40s} {"calls":>6s} {"avg_us":>9s} {"total_ms":>9s} {"read_GB":>8s} {"write_GB":>9s}']
+    for name, r in sorted(stats.items(), key=lambda kv: -float(kv[1]["TotalDurationNs"])):
+        if "sparqs::" not in name:
+            continue
+        lines.append(f'{name.replace("sparqs::", "")[:40]:40s} {int(r["Calls"]):6d} '
+                     f'{float(r["AverageNs"]) / 1e3:9.1f} {float(r["TotalDurationNs"]) / 1e6:9.1f} '
+                     f'{fe.get(name, 0.0) * fs * 1024 / 1e9:8.1f} {wr.get(name, 0.0) * ws * 1024 / 1e9:9.1f}')
+    with open(os.path.join(ROOT, "profiles", "c3_batched_kernel_stats.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return lines
 
 
 def summarize_sort_merge(pdir, sha):
@@ -299,28 +346,31 @@ def bench_batched(args, emit=True):
                           "the first 150 ops of the first 16 instances of the batch")
     import torch
     from paper_2503_15118_amd import _abi, batch
+    if args.calibrate_copy:
+        calibration_copy()
     ops, off = batch.concat_ops(circ)
-    # plain path, one instance at a time (apply calls timed)
-    st = _abi.State(circ[0].regs, eps=circ[0].eps, cap_entries=1 << 20, table_bytes=0)
     zero = np.zeros((1, len(circ[0].regs)), dtype=np.uint64)
     one = np.array([1.0 + 0j])
-    seq_s = 0.0
-    entries = 0
-    peak_sum = 0
-    plain_ops = [_abi.to_ss_ops(c.ops) for c in circ]
-    st.apply(plain_ops[0])  # warm-up
-    gc.collect()
-    for c, o in zip(circ, plain_ops):
-        st.set_entries(0, zero, one)
-        e0 = st.stats()["entries_updated"]
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        st.apply(o)
-        torch.cuda.synchronize()
-        seq_s += time.perf_counter() - ta
-        entries += st.stats()["entries_updated"] - e0
-        peak_sum += st.nnz()
-    st.close()
+    seq_s = None
+    entries = None
+    if not args.no_plain:
+        # plain path, one instance at a time (apply calls timed)
+        st = _abi.State(circ[0].regs, eps=circ[0].eps, cap_entries=1 << 20, table_bytes=0)
+        seq_s = 0.0
+        entries = 0
+        plain_ops = [_abi.to_ss_ops(c.ops) for c in circ]
+        st.apply(plain_ops[0])  # warm-up
+        gc.collect()
+        for c, o in zip(circ, plain_ops):
+            st.set_entries(0, zero, one)
+            e0 = st.stats()["entries_updated"]
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            st.apply(o)
+            torch.cuda.synchronize()
+            seq_s += time.perf_counter() - ta
+            entries += st.stats()["entries_updated"] - e0
+        st.close()
     # batched
     cap = 1 << args.batch_cap_log2
     bs = batch.batch_state(circ, cap_entries=cap, table_bytes=0)
@@ -334,6 +384,8 @@ def bench_batched(args, emit=True):
         bat_s = time.perf_counter() - tb
     stats = {k: v - s0[k] for k, v in bs.stats().items()}
     nnz_b = bs.nnz()
+    if entries is None:
+        entries = stats["entries_updated"]
     # the same batch replayed from a captured HIP graph (captured once from
     # |0> in every instance; the replay starts from the same state)
     graph = None
@@ -351,8 +403,9 @@ def bench_batched(args, emit=True):
             graph_s = time.perf_counter() - tg
         assert bs.nnz() == nnz_b
         g.close()
-        graph = {"batched_graph_s": graph_s, "batched_graph_vs_plain": seq_s / graph_s,
-                 "batched_graph_entries_per_s": entries / graph_s}
+        graph = {"batched_graph_s": graph_s, "batched_graph_entries_per_s": entries / graph_s}
+        if seq_s is not None:
+            graph["batched_graph_vs_plain"] = seq_s / graph_s
     # kernel table: the same batch again from |0>, with a HIP event pair
     # around every launch (not part of the timing above)
     for i in range(len(circ)):
@@ -368,8 +421,8 @@ def bench_batched(args, emit=True):
         "entries_updated": int(entries),
         "sequential_plain_s": seq_s,
         "batched_s": bat_s,
-        "batched_vs_plain": seq_s / bat_s,
-        "sequential_entries_per_s": entries / seq_s,
+        "batched_vs_plain": seq_s / bat_s if seq_s else None,
+        "sequential_entries_per_s": entries / seq_s if seq_s else None,
         "batched_entries_per_s": entries / bat_s,
         "final_nnz_sum": int(res.nnz),
         "rounds_sorts": stats["sorts"],
@@ -385,6 +438,18 @@ def bench_batched(args, emit=True):
     if emit:
         print(json.dumps(out), flush=True)
     return out
+
+
+def calibration_copy():
+    """One plain device copy of 64 MiB: the reference the HBM counter
+    summaries scale FETCH_SIZE and WRITE_SIZE by."""
+    import torch
+    src = torch.ones(64 << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def _oracle_run(c):
@@ -829,6 +894,8 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache (default: per-user cache)")
     ap.add_argument("--graph-steps", type=int, default=None,
                     help="also time this many steps replayed from a captured HIP graph (default: --steps; 0: off)")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="c3: batched run only, without the one-at-a-time plain path it is compared with")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 64 MiB device copy first (reference for HBM counters)")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "m6", "m7"])
@@ -886,12 +953,7 @@ def main():
     from paper_2503_15118_amd import _abi
 
     if args.calibrate_copy:
-        src = torch.ones(64 << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copy()
 
     circ = wl.c2_circuit(args.seed)
     ops = _abi.to_ss_ops(circ.ops)
