@@ -845,6 +845,9 @@ void launch_group_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint3
     // more waves per SIMD.
     int items = st->group_items;
     if ((g.nchain || run.n) && items > 2) items = 2;
+    // after a speculative launch the compacting one usually only records the
+    // count: its cost is the dispatch of its grid, so it takes the largest tile
+    if (ep_spec) items = 4;
     launch_pair<W>(c, mode, items, g, ep, ep_spec, run);
     return;
   }
