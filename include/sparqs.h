@@ -361,9 +361,9 @@ int ss_graph_destroy(ss_graph* g);
 int ss_rebind_arena(ss_state* st, void* arena, size_t arena_bytes);
 
 /* Tuning/debug knobs: "sort_items" (8|16), "grouping" (1: reuse grouped
- * order across ops, 0: always sort), "group_items" (1|2|4, default 4; launches that carry a chain or
- * a run use at most 2, and the compacting launch after a speculative one
- * always 4), "perm_entries"
+ * order across ops, 0: always sort), "group_items" (1|2|4, default 4; group-mode launches that
+ * carry a chain or a run use at most 2, and the compacting launch after a
+ * speculative one always 4), "perm_entries"
  * (4|8|16), "tile_order" (1: per-XCD tile tickets when the device allows,
  * taken in chunks of 8 consecutive tiles by the radix passes; 0: one
  * counter; required when states run concurrently on one GPU), "speculate" (an

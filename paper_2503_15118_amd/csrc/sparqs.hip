@@ -840,11 +840,13 @@ void launch_group_w(ss_state* st, int mode, const GroupOp& g, uint32_t ep, uint3
   const LaunchCtx c = ctx(st);
   if (g.k == 1) {
     if (ep_spec) launch_spec<W>(c, mode, (int)st->spec_items, (int)st->pair_exchange, g, ep_spec, run);
-    // A chained or run-carrying launch is latency-bound (a product of up to
-    // 16 matrices, an interpreted run): at most 2 entries per thread, for
-    // more waves per SIMD.
+    // A chained or run-carrying group-mode launch is latency-bound (a
+    // product of up to 16 matrices, an interpreted run): at most 2 entries
+    // per thread, for more waves per SIMD.  Expansions keep the tuned tile
+    // (measured: the fused expansion of the arithmetic-heavy circuit is
+    // faster at 4).
     int items = st->group_items;
-    if ((g.nchain || run.n) && items > 2) items = 2;
+    if ((g.nchain || run.n) && items > 2 && mode == MODE_GROUP) items = 2;
     // after a speculative launch the compacting one usually only records the
     // count: its cost is the dispatch of its grid, so it takes the largest tile
     if (ep_spec) items = 4;
