@@ -77,6 +77,10 @@ void launch_perm(const LaunchCtx& c, int e, bool amp, const FastOp* f, uint32_t 
 template <int W>
 void launch_sort_hist(const LaunchCtx& c, uint32_t nb, const SortPlan& plan, unsigned long long* hist,
                       uint64_t* digit_start);
+// Workgroups of the histogram kernel for W-word keys that the current device
+// holds at once (occupancy at the largest histogram area x compute units);
+// 0 when the runtime cannot say.
+uint32_t sort_hist_resident(uint32_t W);
 template <int W>
 void launch_sort_pass(const LaunchCtx& c, int items, uint32_t ntiles, const PassDesc& pd,
                       const uint64_t* digit_start, uint32_t ep);

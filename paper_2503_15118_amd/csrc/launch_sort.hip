@@ -33,6 +33,22 @@ void launch_sort_pass(const LaunchCtx& c, int items, uint32_t ntiles, const Pass
                                                         c.meta, ep, xo);
 }
 
+template <int W>
+static uint32_t hist_resident_w() {
+  int dev = 0, per_cu = 0, ncu = 0;
+  const size_t lds = (size_t)((64u * W + kMaxGroupBits + kRadixBits - 1) / kRadixBits) * kRadix * 4;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sort_hist<W>, kBlock, lds) != hipSuccess ||
+      per_cu <= 0 || ncu <= 0)
+    return 0;
+  return (uint32_t)per_cu * (uint32_t)ncu;
+}
+
+uint32_t sort_hist_resident(uint32_t W) {
+  return W == 1 ? hist_resident_w<1>() : W == 2 ? hist_resident_w<2>() : hist_resident_w<4>();
+}
+
 template void launch_sort_hist<1>(const LaunchCtx&, uint32_t, const SortPlan&, unsigned long long*, uint64_t*);
 template void launch_sort_hist<2>(const LaunchCtx&, uint32_t, const SortPlan&, unsigned long long*, uint64_t*);
 template void launch_sort_hist<4>(const LaunchCtx&, uint32_t, const SortPlan&, unsigned long long*, uint64_t*);

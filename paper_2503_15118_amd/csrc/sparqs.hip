@@ -34,7 +34,7 @@ constexpr uint64_t kOpRingBytes = (uint64_t)kMaxOpsPerCall * sizeof(PermOp);
 constexpr uint32_t kRunChunk = 4096;        // ops per fused launch
 constexpr uint64_t kUploadOps = 256;        // non-branching ops whose records one copy uploads
 constexpr uint64_t kSmallSort = 1ull << 16; // at most this many entries: sort plans from the host superset
-constexpr uint32_t kHistBlocksMax = 1024;
+constexpr uint32_t kHistBlocksMax = 4096;  // further bounded by the resident count
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -277,6 +277,7 @@ struct ss_state {
   uint32_t vgen = 0;              // retirement generation of the current view base
   std::vector<uint32_t> undo_map; // instance of each label of the last batched call (empty: not relabelled)
   uint32_t xcd_order = 0;        // 1 when workgroups spread round-robin over 8 XCDs
+  uint32_t hist_res[3] = {1024, 1024, 1024};  // resident k_sort_hist workgroups, W = 1, 2, 4
   int tile_order_opt = 1;        // option: 1 use XCD tickets when possible, 0 one counter
   uint64_t stats[8]{};
   // per-launch HIP-event timing (option "trace")
@@ -786,7 +787,10 @@ int run_sort_w(ss_state* st, const SortPlan& plan) {
   if (plan.npass > max_passes(W)) return hip_fail(st);  // the histogram area is sized for this
   const int items = (W == 4) ? 8 : st->sort_items;
   const uint64_t tile = (uint64_t)kBlock * items;
-  const uint32_t nb = (uint32_t)std::min<uint64_t>(st->cv.hist_blocks, (n + 4095) / 4096);
+  // at most the workgroups the device holds at once: each takes a contiguous
+  // chunk, so a second wave of workgroups would only leave a tail
+  const uint32_t nb = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(st->cv.hist_blocks, (n + 4095) / 4096),
+                                                   st->hist_res[W == 1 ? 0 : W == 2 ? 1 : 2]);
   int tr = trace_begin(st, SS_TRACE_SORT_HIST);
   launch_sort_hist<W>(ctx(st), nb, plan, st->hist, st->digit_start);
   trace_end(st, tr, 8ull * W, 1, 0, 0);
@@ -1569,6 +1573,12 @@ int init_device(ss_state* st) {
   for (int i = 0; i < kXcds; ++i)
     for (int j = 0; j < i; ++j) rr = rr && ids[i] != ids[j];
   st->xcd_order = rr ? 1u : 0u;
+  // histogram grids: workgroups resident on the device (occupancy x CUs)
+  for (int i = 0; i < 3; ++i) {
+    const uint32_t r = sort_hist_resident(i == 0 ? 1u : i == 1 ? 2u : 4u);
+    if (r == 0) return hip_fail(st);
+    st->hist_res[i] = r;
+  }
   // device meta is fresh: empty state in slot 0, no pending launches
   st->epoch = 0;
   st->nslot = 0;
