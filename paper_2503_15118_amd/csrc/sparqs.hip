@@ -34,7 +34,8 @@ constexpr uint64_t kOpRingBytes = (uint64_t)kMaxOpsPerCall * sizeof(PermOp);
 constexpr uint32_t kRunChunk = 4096;        // ops per fused launch
 constexpr uint64_t kUploadOps = 256;        // non-branching ops whose records one copy uploads
 constexpr uint64_t kSmallSort = 1ull << 16; // at most this many entries: sort plans from the host superset
-constexpr uint32_t kHistBlocksMax = 4096;  // further bounded by the resident count
+constexpr uint32_t kHistBlocksMax = 16384;  // further bounded by kHistWaves x the resident count
+constexpr uint32_t kHistWaves = 2;         // histogram workgroups per resident slot
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -787,8 +788,10 @@ int run_sort_w(ss_state* st, const SortPlan& plan) {
   if (plan.npass > max_passes(W)) return hip_fail(st);  // the histogram area is sized for this
   const int items = (W == 4) ? 8 : st->sort_items;
   const uint64_t tile = (uint64_t)kBlock * items;
-  // at most the workgroups the device holds at once: each takes a contiguous
-  // chunk, so a second wave of workgroups would only leave a tail
+  // kHistWaves workgroups per slot the device holds at once, each taking a
+  // contiguous chunk: with more chunks than slots, a CU whose workgroups
+  // finish early takes more of them (measured at 2^26 entries: 1x 255 /
+  // 512 us, 2x 241 / 481 us, 4x 258 / 458 us for W = 1 / 2)
   const uint32_t nb = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(st->cv.hist_blocks, (n + 4095) / 4096),
                                                    st->hist_res[W == 1 ? 0 : W == 2 ? 1 : 2]);
   int tr = trace_begin(st, SS_TRACE_SORT_HIST);
@@ -1573,11 +1576,12 @@ int init_device(ss_state* st) {
   for (int i = 0; i < kXcds; ++i)
     for (int j = 0; j < i; ++j) rr = rr && ids[i] != ids[j];
   st->xcd_order = rr ? 1u : 0u;
-  // histogram grids: workgroups resident on the device (occupancy x CUs)
+  // histogram grids: a multiple of the workgroups resident on the device
+  // (occupancy x CUs)
   for (int i = 0; i < 3; ++i) {
     const uint32_t r = sort_hist_resident(i == 0 ? 1u : i == 1 ? 2u : 4u);
     if (r == 0) return hip_fail(st);
-    st->hist_res[i] = r;
+    st->hist_res[i] = kHistWaves * r;
   }
   // device meta is fresh: empty state in slot 0, no pending launches
   st->epoch = 0;
