@@ -1403,13 +1403,14 @@ __global__ __launch_bounds__(kBlock, ITEMS >= 8 ? 4 : 1) void k_pair_spec(KeyPtr
   __shared__ uint64_t s_red[2 * kMaxW * 4];
   constexpr uint32_t kStageWords = MODE == MODE_GROUP && NB != 2 ? (W + 2) * (TILE + 2) : 1;
   __shared__ __align__(16) uint64_t s_stage[kStageWords];
-  if (launch_prologue(meta, epoch)) return;
+  PrologueReads pr;
+  if (launch_prologue_reads(meta, epoch, ns, false, &meta->spec_cool[MODE], &pr)) return;
   // cooling down after a wasted speculation: the compacting launch does the op
-  if (*reinterpret_cast<volatile unsigned int*>(&meta->spec_cool[MODE]) != 0u) {
+  if (pr.flag != 0u) {
     if (blockIdx.x == 0 && threadIdx.x == 0) meta->spec_irr[epoch % kRing] = kSpecSkipped;
     return;
   }
-  const uint64_t n = meta->nring[ns & 1];
+  const uint64_t n = pr.n;
   const uint64_t e0 = (uint64_t)blockIdx.x * TILE;
   if (e0 >= n) return;
   if (blockIdx.x == 0 && threadIdx.x == 0 && (uint64_t)gridDim.x * TILE < n) raise_error(meta, kErrGrid, epoch);
@@ -1479,10 +1480,10 @@ __global__ __launch_bounds__(kBlock) void k_pair(KeyPtrs<W> in_keys, const doubl
   constexpr uint32_t kStageWords = MODE == MODE_GROUP ? (W + 2) * (TILE + 2) : 1;
   __shared__ __align__(16) uint64_t s_stage[kStageWords];
   uint64_t n;
-  if (!emit_begin(meta, ns, epoch, TILE, &n, xo)) return;
+  unsigned int sflag = 0u;
+  if (!emit_begin(meta, ns, epoch, TILE, &n, xo, spec_ep != 0 ? &meta->spec_irr[spec_ep % kRing] : nullptr, &sflag))
+    return;
   if (op.upd && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&meta->upd, (unsigned long long)(n * op.upd));
-  const unsigned int sflag =
-      spec_ep != 0 ? *reinterpret_cast<volatile unsigned int*>(&meta->spec_irr[spec_ep % kRing]) : 0u;
   if (sflag != 0u) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       if (sflag == kSpecSkipped) {

@@ -251,6 +251,47 @@ __device__ __forceinline__ bool launch_prologue(DevMeta* meta, uint32_t epoch) {
   return s_err != 0u;
 }
 
+// launch_prologue that also reads, in the same round trip as the error word,
+// the entry count of ring slot `ns`, the view base (batched rounds, when
+// `view`) and one more flag word (when `flag` is not null).  Thread 0 issues
+// the loads together (relaxed agent-scope loads: unlike volatile ones they
+// are not each waited for) and the workgroup takes the values from LDS.
+struct PrologueReads {
+  uint64_t n, base;
+  unsigned int flag;
+};
+__device__ __forceinline__ bool launch_prologue_reads(DevMeta* meta, uint32_t epoch, uint32_t ns, bool view,
+                                                      unsigned int* flag, PrologueReads* out) {
+  __shared__ unsigned int s_err2, s_flag;
+  __shared__ uint64_t s_n, s_base;
+  if (threadIdx.x == 0) {
+    if (blockIdx.x == 0) {
+      const uint32_t r = (epoch + kRing / 2) % kRing;
+      meta->counters[r] = 0;
+      meta->spec_irr[r] = 0;
+      for (int x = 0; x < kXcds; ++x) meta->xcd_ctr[r][x * kXcdStride] = 0;
+      meta->nnz_out[r] = 0;
+      for (int w = 0; w < kMaxW; ++w) {
+        meta->or_mask[r][w] = 0;
+        meta->and_mask[r][w] = ~0ull;
+      }
+    }
+    const unsigned int e = __hip_atomic_load(&meta->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t n = __hip_atomic_load(&meta->nring[ns & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t b = view ? __hip_atomic_load(&meta->base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+    const unsigned int f = flag ? __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+    s_err2 = e;
+    s_n = n;
+    s_base = b;
+    s_flag = f;
+  }
+  __syncthreads();
+  out->n = s_n;
+  out->base = s_base;
+  out->flag = s_flag;
+  return s_err2 != 0u;
+}
+
 __device__ __forceinline__ void raise_error(DevMeta* meta, uint32_t bits, uint32_t epoch) {
   atomicOr(&meta->err, bits);
   atomicCAS(&meta->err_epoch, 0u, epoch);
@@ -263,11 +304,15 @@ __device__ __forceinline__ void raise_error(DevMeta* meta, uint32_t bits, uint32
 // Returns false when the workgroup has nothing to do (an earlier error, an
 // empty input: workgroup 0 then records an empty output, or excess).  A grid
 // smaller than the count is flagged rather than leaving entries behind.
+// `flag` (optional): a word read in the prologue's round trip, into *flag_out.
 __device__ __forceinline__ bool emit_begin(DevMeta* meta, uint32_t ns, uint32_t epoch, uint64_t tile_entries,
-                                           uint64_t* n_out, uint32_t xcd_order) {
-  if (launch_prologue(meta, epoch)) return false;
-  const uint64_t n = meta->nring[ns & 1];
+                                           uint64_t* n_out, uint32_t xcd_order, unsigned int* flag = nullptr,
+                                           unsigned int* flag_out = nullptr) {
+  PrologueReads pr;
+  if (launch_prologue_reads(meta, epoch, ns, false, flag, &pr)) return false;
+  const uint64_t n = pr.n;
   *n_out = n;
+  if (flag_out) *flag_out = pr.flag;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (n == 0) {
       meta->nring[(ns & 1) ^ 1] = 0;
@@ -283,9 +328,10 @@ __device__ __forceinline__ bool emit_begin(DevMeta* meta, uint32_t ns, uint32_t 
 // unchanged total as the output count.
 __device__ __forceinline__ bool emit_begin_view(DevMeta* meta, uint32_t ns, uint32_t epoch, uint64_t tile_entries,
                                                 uint64_t* n_out, uint64_t* base_out, uint32_t xcd_order) {
-  if (launch_prologue(meta, epoch)) return false;
-  const uint64_t base = meta->base;
-  const uint64_t n = meta->nring[ns & 1] - base;
+  PrologueReads pr;
+  if (launch_prologue_reads(meta, epoch, ns, true, nullptr, &pr)) return false;
+  const uint64_t base = pr.base;
+  const uint64_t n = pr.n - base;
   *n_out = n;
   *base_out = base;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
