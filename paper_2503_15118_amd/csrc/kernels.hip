@@ -614,13 +614,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(KeyPtrs<W> in_keys, const 
   __shared__ uint32_t s_tile;
 
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (launch_prologue(meta, epoch)) return;
   // The count is read on the device (a sort does not change it) and the grid
   // comes from an upper bound: workgroups past the count's tiles leave before
   // taking a tile ticket, so the tickets cover exactly the count's tiles.
-  // Batched rounds sort the view [base, n).
-  const uint64_t vb = meta->base;
-  const uint64_t n = meta->nring[ns & 1] - vb;
+  // Batched rounds sort the view [base, n).  Both come with the prologue's
+  // round trip.
+  PrologueReads pr;
+  if (launch_prologue_reads(meta, epoch, ns, true, nullptr, &pr)) return;
+  const uint64_t vb = pr.base;
+  const uint64_t n = pr.n - vb;
   offset_keys<W>(in_keys, vb);
   offset_keys<W>(out_keys, vb);
   in_amp += vb;
